@@ -1,0 +1,196 @@
+/*
+ * eloc.h - C ABI of the MI355X (gfx950) engine for the sample-aware local
+ * energy of arXiv 2408.07625 ("Neural quantum states and peaked molecular
+ * wave functions: curse or blessing?").
+ *
+ * The engine evaluates, for a qubit Hamiltonian H = sum_l h_l P^(l)
+ * (Eq. jw_hamiltonian) and a batch U of unique sampled basis vectors,
+ *
+ *     E_loc^var(x) = sum_{x' in U} H_xx' psi(x') / psi(x)       (x in U)
+ *
+ * (Eq. local_energy restricted to U, Sec. "Streamlined local energy
+ * calculations"), and the weighted energy of Eq. variational_energy.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A Pauli term is (h_l, XY_l, YZ_l) with XY = X|Y and YZ = Y|Z as N-bit
+ *    vectors (Sec. "Hamiltonian arithmetic"); Y_l = XY_l & YZ_l.
+ *  - Bit vectors are W = ceil(N/64) uint64 words, row-major [count][W]:
+ *    qubit q lives in word q/64, bit q%64.  Bits >= N must be zero.
+ *    N <= 128 (W <= 2).
+ *  - <x|P^(l)|x'> = i^(|Y_l| + 2|x' & YZ_l|) if x ^ x' == XY_l, else 0
+ *    (Eq. pauli_melem; the phase is taken on the ket x').
+ *  - Two samples are coupled when x ^ x' equals one of the Hamiltonian's
+ *    XY masks (the unique-XY set); a coupled pair can have H_xx' == 0.
+ *    Coupled pairs are ordered pairs and include x == x' when the
+ *    Hamiltonian has a diagonal term.
+ *  - The unique-XY set is numbered in first-appearance order of the terms
+ *    as passed to eloc_set_hamiltonian ("group id").
+ *  - Complex numbers are eloc_c64 = {re, im} doubles (the layout of
+ *    complex128).  Log-amplitudes are L = log psi = log|psi| + i phase.
+ *  - "DEVICE" pointers are device memory of the context's device; "HOST"
+ *    pointers are ordinary host memory.  The caller owns every pointer it
+ *    passes; the library copies what it keeps.
+ *  - Every call returns an eloc_status (0 = OK, < 0 error) and never
+ *    throws.  eloc_last_error() gives the text of the last failure.
+ *  - Work is enqueued on the context's stream; calls return before the
+ *    GPU finishes unless documented as synchronising.  A context is not
+ *    thread-safe; use one per host thread.
+ */
+#ifndef ELOC_H
+#define ELOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eloc_ctx_s* eloc_ctx;
+typedef struct {
+    double re, im;
+} eloc_c64;
+
+enum eloc_status {
+    ELOC_OK = 0,
+    ELOC_EINVAL = -1,    /* bad argument (null pointer, size, bits >= N, bad weights) */
+    ELOC_EDUP = -2,      /* U contains the same key twice (U must be unique)          */
+    ELOC_ENOMEM = -3,    /* device allocation failed                                 */
+    ELOC_ECAPACITY = -4, /* caller buffer too small; the required size is returned   */
+    ELOC_ERANGE = -5,    /* log-amplitude spread too wide for the FP32 form          */
+    ELOC_EHIP = -6,      /* HIP runtime error                                        */
+    ELOC_ESTATE = -7     /* call order: Hamiltonian or samples not set               */
+};
+
+/* FindCoupledPairs variants (Sec. "FindCoupledPairs implementations"). */
+enum eloc_variant {
+    ELOC_TERMS = 0, /* loop over the unique XY set, look x ^ XY up in U (Alg. 2A)   */
+    ELOC_BATCH = 1, /* loop over U, look x ^ x' up in the XY set (Alg. 2B)           */
+    ELOC_TRIE = 2   /* walk prefix trees of U and of the XY set together (Alg. 2C)   */
+};
+
+/* Arithmetic of the ratio accumulation sum_x' H_xx' psi(x')/psi(x). */
+enum eloc_precision {
+    ELOC_FP64 = 0,  /* complex double throughout                                    */
+    ELOC_FP32C = 1  /* FP32 with error-free transforms (hi+lo pairs); FP64 only in
+                       the weighted energy / variance reductions                    */
+};
+
+/* Create a context on `device` enqueuing on `hip_stream` (a hipStream_t,
+ * NULL = the device's null stream).  *out receives the handle. */
+int eloc_create(eloc_ctx* out, int device, void* hip_stream);
+
+/* Free the context and every device buffer it owns (synchronises). */
+void eloc_destroy(eloc_ctx ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char* eloc_last_error(eloc_ctx ctx);
+
+/* Change the stream later work is enqueued on. */
+int eloc_set_stream(eloc_ctx ctx, void* hip_stream);
+
+/* Store the Hamiltonian (Sec. "Preparation" of the supplementary GPU notes:
+ * the unique XY set with, per XY, its contiguous run of terms).  HOST
+ * arrays: coeff[n_terms], xy[n_terms][W], yz[n_terms][W].  Equal Pauli
+ * strings may repeat (their coefficients add).  Synchronising.
+ * Errors: EINVAL (n_qubits not in 1..128, n_terms < 1, bits >= N),
+ * ENOMEM, EHIP. */
+int eloc_set_hamiltonian(eloc_ctx ctx, int n_qubits, int64_t n_terms, const double* coeff,
+                         const uint64_t* xy, const uint64_t* yz);
+
+/* Number of unique XY masks and of terms of the stored Hamiltonian. */
+int eloc_hamiltonian_info(eloc_ctx ctx, int64_t* n_groups, int64_t* n_terms, int* n_qubits);
+
+/* Store the batch U of unique samples (the sampler's output, Sec.
+ * "Sampling without replacement").  DEVICE keys_dev[n_unique][W] in any
+ * order; sample index i below always means row i of this array.
+ * Synchronising (validates the batch).  Errors: EINVAL (n_unique < 1 or
+ * >= 2^31, bits >= N), EDUP (a key repeats), ESTATE (no Hamiltonian). */
+int eloc_set_samples(eloc_ctx ctx, int64_t n_unique, const uint64_t* keys_dev);
+
+/* Forward pass.  DEVICE inputs logpsi_dev[n_unique] (complex log psi) and
+ * weights_dev[n_unique] or NULL; DEVICE outputs eloc_dev[n_unique] and
+ * stats_dev[4].  weights NULL: w = |psi|^2 renormalised over U
+ * (Eq. variational_energy); else w >= 0 with sum w > 0, renormalised by
+ * its sum (Eq. energy_estimator_via_unique with occurrence counts).
+ * stats = {Re E, Im E, Var, sum of raw weights}, E = sum w~ E_loc,
+ * Var = sum w~ |E_loc - E|^2.  Asynchronous: invalid weights or an FP32C
+ * range failure are reported by the next synchronising call
+ * (eloc_check) as EINVAL / ERANGE and the outputs are then unspecified.
+ * ELOC_FP32C requires max Re L - min Re L <= 60.
+ * Errors (immediate): EINVAL (variant/precision), ESTATE. */
+int eloc_local_energy(eloc_ctx ctx, int variant, int precision, const eloc_c64* logpsi_dev,
+                      const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev);
+
+/* Wait for the context's stream and report a deferred device-side error of
+ * the last eloc_local_energy / adjoint call (EINVAL, ERANGE).  Synchronising. */
+int eloc_check(eloc_ctx ctx);
+
+/* Number of coupled ordered pairs (x, x') in U x U, diagonal included.
+ * Synchronising. */
+int eloc_count_pairs(eloc_ctx ctx, int variant, int64_t* n_pairs_host);
+
+/* The coupled pairs themselves: DEVICE i_dev/j_dev/g_dev[capacity] receive
+ * (sample i, sample j, group id of x_i ^ x_j), sorted by (i, j) ascending
+ * (the row-major order of the paper's pair arrays, x->U and x'->U).
+ * *n_pairs_host receives the pair count; ECAPACITY if it exceeds
+ * `capacity` (nothing useful written).  Synchronising. */
+int eloc_find_pairs(eloc_ctx ctx, int variant, int64_t capacity, int32_t* i_dev, int32_t* j_dev,
+                    int32_t* g_dev, int64_t* n_pairs_host);
+
+/* MatrixElement (supplementary algorithm) for n given pairs of samples:
+ * DEVICE i_dev/j_dev[n] sample indices, h_dev[n] receives H_{x_i x_j}
+ * (0 when x_i ^ x_j is not an XY of H).  EINVAL if an index is outside U
+ * (reported by eloc_check).  Asynchronous. */
+int eloc_pair_elements(eloc_ctx ctx, int64_t n, const int32_t* i_dev, const int32_t* j_dev,
+                       eloc_c64* h_dev);
+
+/* Adjoint of the forward energy.  For a real loss with upstream
+ * grad_e = dLoss/dRe E + i dLoss/dIm E, writes DEVICE grad_logpsi_dev[n]
+ * = dLoss/dRe L + i dLoss/dIm L.  With fixed weights E is holomorphic in L:
+ *   dE/dL_y = sum_{x coupled to y} w~_x H_xy psi(y)/psi(x) - w~_y E_loc(y)
+ * (H_xy = <x|H|y>, phase on the ket y) and grad_L_y = grad_e conj(dE/dL_y);
+ * with |psi|^2 weights (weights_dev NULL) the real part gains
+ * 2 w~_y Re(conj(grad_e) (E_loc(y) - E)).  eloc_dev and stats_dev are the
+ * forward outputs for the same inputs.  Pairs are recomputed, never stored.
+ * Errors as eloc_local_energy. */
+int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
+                              const eloc_c64* logpsi_dev, const double* weights_dev,
+                              const eloc_c64* eloc_dev, const double* stats_dev, eloc_c64 grad_e,
+                              eloc_c64* grad_logpsi_dev);
+
+/* Launch-geometry override (autotuning, benchmarks): `chunks` splits the
+ * loop over the unique XY set (TERMS) or over U (BATCH) of every row into
+ * that many chunks (0 = automatic); `sig_filter` = 0 disables the exact
+ * prefilter of TERMS that skips candidates whose (even-qubit, odd-qubit)
+ * popcounts occur in no sample.  Results do not depend on either setting
+ * beyond the floating-point summation order over chunks. */
+int eloc_set_tuning(eloc_ctx ctx, int chunks, int sig_filter);
+
+/* Stage timing with HIP events on the context's stream (the per-part time
+ * breakdown of the paper's Fig. 4: sample preparation, FindCoupledPairs +
+ * MatrixElement + accumulation, reductions).  While enabled, every call
+ * records a start/end event pair around each of its stages. */
+enum eloc_stage {
+    ELOC_STAGE_SAMPLES = 0,        /* eloc_set_samples: copy, hash table, checks  */
+    ELOC_STAGE_AMPLITUDES = 1,     /* exp(L - max Re L) and its inverse           */
+    ELOC_STAGE_PAIRS = 2,          /* fused pair kernel (forward)                  */
+    ELOC_STAGE_FINISH = 3,         /* chunk sums times 1/psi(x)                    */
+    ELOC_STAGE_ENERGY = 4,         /* weighted energy and variance                 */
+    ELOC_STAGE_ADJOINT_PAIRS = 5,  /* fused pair kernel (adjoint)                  */
+    ELOC_STAGE_ADJOINT_FINISH = 6, /* adjoint row combination                      */
+    ELOC_NSTAGES = 7
+};
+int eloc_profile_enable(eloc_ctx ctx, int on);
+
+/* Totals since the last read: HOST ms_total[ELOC_NSTAGES] (milliseconds)
+ * and count[ELOC_NSTAGES] (number of timed launches).  Synchronising;
+ * resets the totals. */
+int eloc_profile_read(eloc_ctx ctx, double* ms_total, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELOC_H */

@@ -1,0 +1,272 @@
+"""Python binding of libeloc (the HIP engine for the sample-aware local
+energy E_loc^var of arXiv 2408.07625).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of include/eloc.h.  torch provides device memory and the stream.  There
+is no CPU path: if libeloc.so has not been built, importing works but every
+engine call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+import torch  # loads the HIP runtime that libeloc.so then binds to
+
+_LIB_PATH = Path(__file__).resolve().parent / "libeloc.so"
+_lib = None
+
+VARIANTS = {"terms": 0, "batch": 1, "trie": 2}
+PRECISIONS = {"fp64": 0, "fp32c": 1}
+STATUS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOMEM", -4: "ECAPACITY", -5: "ERANGE", -6: "EHIP",
+          -7: "ESTATE"}
+
+
+class ElocError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class C64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+def library() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is not built; run python -m paper_2408_07625_amd.build")
+        lib = ctypes.CDLL(str(_LIB_PATH))
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        sig = {
+            "eloc_create": (i32, [ctypes.POINTER(P), i32, P]),
+            "eloc_destroy": (None, [P]),
+            "eloc_last_error": (ctypes.c_char_p, [P]),
+            "eloc_set_stream": (i32, [P, P]),
+            "eloc_set_hamiltonian": (i32, [P, i32, i64, P, P, P]),
+            "eloc_hamiltonian_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+            "eloc_set_samples": (i32, [P, i64, P]),
+            "eloc_local_energy": (i32, [P, i32, i32, P, P, P, P]),
+            "eloc_check": (i32, [P]),
+            "eloc_count_pairs": (i32, [P, i32, ctypes.POINTER(i64)]),
+            "eloc_find_pairs": (i32, [P, i32, i64, P, P, P, ctypes.POINTER(i64)]),
+            "eloc_pair_elements": (i32, [P, i64, P, P, P]),
+            "eloc_local_energy_adjoint": (i32, [P, i32, i32, P, P, P, P, C64, P]),
+            "eloc_set_tuning": (i32, [P, i32, i32]),
+            "eloc_profile_enable": (i32, [P, i32]),
+            "eloc_profile_read": (i32, [P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    """Names the header declares that the loaded library exports."""
+    lib = library()
+    return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
+                        "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples",
+                        "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
+                        "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_set_tuning",
+                        "eloc_profile_enable", "eloc_profile_read")
+            if hasattr(lib, n)]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _variant(v):
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
+def _precision(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class Engine:
+    """One context of libeloc bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = library()
+        self.device = torch.device("cuda", device)
+        self.handle = ctypes.c_void_p()
+        # without a visible GPU the library itself reports EINVAL
+        stream = torch.cuda.current_stream(self.device).cuda_stream if torch.cuda.is_available() else 0
+        self._call(self.lib.eloc_create(ctypes.byref(self.handle), device, ctypes.c_void_p(stream)))
+        self.n_unique = 0
+        self.n_qubits = 0
+
+    def close(self):
+        if self.handle:
+            self.lib.eloc_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, rc):
+        if rc != 0:
+            msg = self.lib.eloc_last_error(self.handle) if self.handle else b""
+            raise ElocError(rc, (msg or b"").decode())
+        return rc
+
+    def _sync_stream(self):
+        self._call(self.lib.eloc_set_stream(self.handle,
+                                            ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    # -- inputs -------------------------------------------------------------
+    def set_hamiltonian(self, n_qubits: int, coeff, xy, yz):
+        c = np.ascontiguousarray(coeff, dtype=np.float64)
+        xy = np.ascontiguousarray(xy, dtype=np.uint64)
+        yz = np.ascontiguousarray(yz, dtype=np.uint64)
+        W = (n_qubits + 63) // 64
+        assert xy.shape == (c.size, W) and yz.shape == (c.size, W)
+        self._sync_stream()
+        self._call(self.lib.eloc_set_hamiltonian(self.handle, n_qubits, c.size, _np_ptr(c), _np_ptr(xy),
+                                                 _np_ptr(yz)))
+        self.n_qubits = n_qubits
+        self.n_unique = 0
+
+    def info(self):
+        g, t, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        self._call(self.lib.eloc_hamiltonian_info(self.handle, ctypes.byref(g), ctypes.byref(t), ctypes.byref(n)))
+        return {"n_groups": g.value, "n_terms": t.value, "n_qubits": n.value}
+
+    def set_samples(self, keys: torch.Tensor):
+        """keys: int64/uint64 device tensor [M, W] (bit patterns)."""
+        assert keys.is_cuda and keys.dtype in (torch.int64, torch.uint64) and keys.is_contiguous()
+        self._sync_stream()
+        self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
+        self.n_unique = keys.shape[0]
+
+    def set_tuning(self, chunks: int = 0, sig_filter: bool = True):
+        self._call(self.lib.eloc_set_tuning(self.handle, int(chunks), 1 if sig_filter else 0))
+
+    STAGES = ("samples", "amplitudes", "pairs", "finish", "energy", "adjoint_pairs", "adjoint_finish")
+
+    def profile(self, on: bool = True):
+        self._call(self.lib.eloc_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, launches)} since the last read (synchronises)."""
+        ms = np.zeros(len(self.STAGES), dtype=np.float64)
+        cnt = np.zeros(len(self.STAGES), dtype=np.int64)
+        self._call(self.lib.eloc_profile_read(self.handle, _np_ptr(ms), _np_ptr(cnt)))
+        return {s: (float(ms[k]), int(cnt[k])) for k, s in enumerate(self.STAGES)}
+
+    # -- forward ------------------------------------------------------------
+    def local_energy(self, logpsi: torch.Tensor, weights: torch.Tensor | None = None, variant="terms",
+                     precision="fp64", out: torch.Tensor | None = None, stats: torch.Tensor | None = None,
+                     check: bool = True):
+        """Returns (E_loc complex128 [M], stats float64 [4] = Re E, Im E, Var, sum w)."""
+        M = self.n_unique if self.n_unique else logpsi.shape[0]   # no batch yet: the library says ESTATE
+        if logpsi.dtype != torch.complex128 or not logpsi.is_cuda or logpsi.shape != (M,):
+            raise ValueError("logpsi must be a complex128 CUDA tensor with one entry per sample")
+        logpsi = logpsi.contiguous()
+        if weights is not None:
+            if weights.dtype != torch.float64 or not weights.is_cuda or weights.shape != (M,):
+                raise ValueError("weights must be a float64 CUDA tensor with one entry per sample")
+            weights = weights.contiguous()
+        if out is None:
+            out = torch.empty(M, dtype=torch.complex128, device=self.device)
+        if stats is None:
+            stats = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        self._call(self.lib.eloc_local_energy(self.handle, _variant(variant), _precision(precision), _ptr(logpsi),
+                                              _ptr(weights), _ptr(out), _ptr(stats)))
+        if check:
+            self.check()
+        return out, stats
+
+    def check(self):
+        self._call(self.lib.eloc_check(self.handle))
+
+    # -- pairs --------------------------------------------------------------
+    def count_pairs(self, variant="terms") -> int:
+        n = ctypes.c_int64()
+        self._sync_stream()
+        self._call(self.lib.eloc_count_pairs(self.handle, _variant(variant), ctypes.byref(n)))
+        return n.value
+
+    def find_pairs(self, variant="terms"):
+        """Canonical coupled pairs (i, j, g) sorted by (i, j), int32 device tensors."""
+        n = self.count_pairs(variant)
+        cap = max(n, 1)
+        i = torch.empty(cap, dtype=torch.int32, device=self.device)
+        j = torch.empty(cap, dtype=torch.int32, device=self.device)
+        g = torch.empty(cap, dtype=torch.int32, device=self.device)
+        got = ctypes.c_int64()
+        self._call(self.lib.eloc_find_pairs(self.handle, _variant(variant), cap, _ptr(i), _ptr(j), _ptr(g),
+                                            ctypes.byref(got)))
+        k = got.value
+        return i[:k], j[:k], g[:k]
+
+    def pair_elements(self, i: torch.Tensor, j: torch.Tensor) -> torch.Tensor:
+        assert i.dtype == torch.int32 and j.dtype == torch.int32 and i.shape == j.shape
+        i, j = i.contiguous(), j.contiguous()
+        h = torch.empty(i.shape[0], dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        self._call(self.lib.eloc_pair_elements(self.handle, i.shape[0], _ptr(i), _ptr(j), _ptr(h)))
+        self.check()
+        return h
+
+    # -- adjoint ------------------------------------------------------------
+    def adjoint(self, logpsi, eloc, stats, grad_e: complex, weights=None, variant="terms", precision="fp64",
+                out=None, check=True):
+        M = self.n_unique
+        if out is None:
+            out = torch.empty(M, dtype=torch.complex128, device=self.device)
+        ge = C64(float(np.real(grad_e)), float(np.imag(grad_e)))
+        self._sync_stream()
+        self._call(self.lib.eloc_local_energy_adjoint(self.handle, _variant(variant), _precision(precision),
+                                                      _ptr(logpsi.contiguous()),
+                                                      _ptr(None if weights is None else weights.contiguous()),
+                                                      _ptr(eloc), _ptr(stats), ge, _ptr(out)))
+        if check:
+            self.check()
+        return out
+
+
+class LocalEnergy(torch.autograd.Function):
+    """E = sum_x w~_x E_loc^var(x) as a differentiable function of log psi.
+
+    forward(logpsi, weights, engine, variant, precision) -> (E complex128
+    scalar, E_loc [M] (not differentiable), stats [4]).  Backward calls the
+    adjoint kernels; pairs are recomputed, never stored."""
+
+    @staticmethod
+    def forward(ctx, logpsi, weights, engine, variant="terms", precision="fp64"):
+        eloc, stats = engine.local_energy(logpsi, weights, variant, precision)
+        ctx.engine, ctx.variant, ctx.precision = engine, variant, precision
+        ctx.save_for_backward(logpsi, eloc, stats, *( [weights] if weights is not None else []))
+        ctx.has_w = weights is not None
+        E = torch.complex(stats[0], stats[1])
+        ctx.mark_non_differentiable(eloc, stats)
+        return E, eloc, stats
+
+    @staticmethod
+    def backward(ctx, grad_E, grad_eloc, grad_stats):
+        saved = ctx.saved_tensors
+        logpsi, eloc, stats = saved[:3]
+        weights = saved[3] if ctx.has_w else None
+        ge = complex(grad_E.item()) if grad_E is not None else 0j
+        g = ctx.engine.adjoint(logpsi, eloc, stats, ge, weights, ctx.variant, ctx.precision)
+        return g, None, None, None, None
+
+
+def local_energy(engine: Engine, logpsi, weights=None, variant="terms", precision="fp64"):
+    return LocalEnergy.apply(logpsi, weights, engine, variant, precision)

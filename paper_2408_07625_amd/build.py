@@ -1,0 +1,61 @@
+"""Build libeloc.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc.
+
+    python -m paper_2408_07625_amd.build
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+ROOT = PKG.parent
+CSRC = PKG / "csrc"
+LIB = PKG / "libeloc.so"
+SOURCES = [CSRC / "kernels.hip", CSRC / "api.cpp"]
+HEADERS = [CSRC / "internal.h", ROOT / "include" / "eloc.h"]
+
+# Packed-FP32 instructions are disabled for all HIP code (the compiler would
+# otherwise pair scalar FP32 adds/multiplies into v_pk_* forms).  Floating-
+# point contraction is off: the error-free transforms of the compensated FP32
+# path need every product rounded on its own (fused multiply-adds are written
+# out explicitly where they are wanted).
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-function"]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and Path(cand).exists():
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False) -> Path:
+    tmp = LIB.with_name(LIB.name + ".tmp")
+    cmd = [hipcc(), *FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", *map(str, SOURCES), "-o", str(tmp)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed")
+    if verbose:
+        noise = ("packed-fp32-ops", "is not a recognized feature")
+        for line in (res.stdout + res.stderr).splitlines():
+            if line.strip() and not any(n in line for n in noise):
+                print(line)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def stale() -> bool:
+    if not LIB.exists():
+        return True
+    t = LIB.stat().st_mtime
+    return any(p.stat().st_mtime > t for p in SOURCES + HEADERS)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

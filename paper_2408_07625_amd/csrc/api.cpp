@@ -1,0 +1,672 @@
+// C ABI of the engine (include/eloc.h): context, Hamiltonian ingest, sample
+// preparation and the entry points.  Device work is enqueued through the
+// launchers of kernels.hip on the context's stream.
+#include "eloc.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+
+using namespace eloc;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+uint64_t splitmix64(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int bits_for(uint64_t v) {   // smallest b with v < 2^b
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+uint64_t pow2_at_least(uint64_t v) {
+    uint64_t c = 1;
+    while (c < v) c <<= 1;
+    return c;
+}
+
+Table make_table(uint32_t* slots, uint64_t capacity, int64_t n) {
+    Table T;
+    T.slots = slots;
+    T.mask = static_cast<uint32_t>(capacity - 1);
+    T.ibits = std::max(1, bits_for(static_cast<uint64_t>(n)));   // index + 1 <= n
+    T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
+    T.fpshift = 32 + T.ibits;
+    return T;
+}
+
+}  // namespace
+
+struct eloc_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    uint64_t R[128];
+    DevBuf R_dev;
+
+    bool ham_set = false;
+    HamDev H;
+    DevBuf groups, terms, terms_f, ghash, gkeys, gslots;
+
+    bool samples_set = false;
+    SampleDev S;
+    DevBuf keys, khash, kslots, sig;
+
+    DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
+    DevBuf partial, energy_scratch, err_run, err_prep;
+    uint32_t* err_host = nullptr;
+
+    DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
+
+    int tune_chunks = 0;     // 0 = automatic
+    int tune_sig = 1;
+
+    // stage profiling: HIP events around each stage, read (and reset) by
+    // eloc_profile_read
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+};
+
+namespace {
+
+int fail(eloc_ctx c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(eloc_ctx c, hipError_t e, const char* where) {
+    return fail(c, e == hipErrorOutOfMemory ? ELOC_ENOMEM : ELOC_EHIP,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define ELOC_HIP(ctx, expr)                                 \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH; }
+
+Plan make_plan(const eloc_ctx c, int variant) {
+    Plan P;
+    const int64_t M = c->S.n;
+    const int64_t waves = (M + 63) / 64;
+    const int64_t target = 16384;
+    const int64_t span = (variant == ELOC_TERMS) ? c->H.n_groups : M;
+    int64_t chunks = c->tune_chunks > 0 ? c->tune_chunks : (target + waves - 1) / waves;
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, std::max<int64_t>(1, span / 64)));
+    int64_t per = (span + chunks - 1) / chunks;
+    chunks = (span + per - 1) / per;
+    P.chunks = static_cast<int>(chunks);
+    P.per_chunk = static_cast<int>(per);
+    P.sig_filter = c->tune_sig != 0;
+    return P;
+}
+
+int read_err(eloc_ctx c, DevBuf& word) {
+    hipError_t e = hipMemcpyAsync(c->err_host, word.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "read error word");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    return static_cast<int>(*c->err_host);
+}
+
+int map_err(eloc_ctx c, uint32_t bits) {
+    if (bits & kErrDup) return fail(c, ELOC_EDUP, "duplicate keys in the sample batch");
+    if (bits & kErrBits) return fail(c, ELOC_EINVAL, "a sample key has bits set at or above n_qubits");
+    if (bits & kErrWeights) return fail(c, ELOC_EINVAL, "weights must be finite, >= 0, with a positive sum");
+    if (bits & kErrRange)
+        return fail(c, ELOC_ERANGE, "log-amplitudes not finite, or Re log psi spread > 60 in the FP32 form");
+    if (bits & kErrIndex) return fail(c, ELOC_EINVAL, "pair index outside the sample batch");
+    return ELOC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host grouping of terms by XY in first-appearance order (growable
+// open-addressing map keyed by the XY words).
+// ---------------------------------------------------------------------------
+struct XYMap {
+    int W;
+    std::vector<uint64_t> keys;
+    std::vector<int64_t> vals;   // -1 = empty
+    size_t count = 0;
+    explicit XYMap(int w) : W(w) { resize(1024); }
+    static uint64_t mix(uint64_t h) {
+        h ^= h >> 33;
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 33;
+        h *= 0xc4ceb9fe1a85ec53ull;
+        return h ^ (h >> 33);
+    }
+    uint64_t hash(const uint64_t* k) const {
+        uint64_t h = mix(k[0]);
+        if (W == 2) h = mix(h ^ (k[1] + 0x9E3779B97F4A7C15ull));
+        return h;
+    }
+    void resize(size_t cap) {
+        std::vector<uint64_t> ok;
+        std::vector<int64_t> ov;
+        ok.swap(keys);
+        ov.swap(vals);
+        keys.assign(cap * W, 0);
+        vals.assign(cap, -1);
+        count = 0;
+        for (size_t s = 0; s < ov.size(); ++s)
+            if (ov[s] >= 0) insert(&ok[s * W], ov[s]);
+    }
+    // returns existing value or inserts v
+    int64_t find_or_insert(const uint64_t* k, int64_t v) {
+        if (2 * (count + 1) > vals.size()) resize(vals.size() * 2);
+        return insert(k, v);
+    }
+    int64_t insert(const uint64_t* k, int64_t v) {
+        const size_t mask = vals.size() - 1;
+        size_t s = hash(k) & mask;
+        for (;;) {
+            if (vals[s] < 0) {
+                for (int w = 0; w < W; ++w) keys[s * W + w] = k[w];
+                vals[s] = v;
+                ++count;
+                return v;
+            }
+            bool eq = true;
+            for (int w = 0; w < W; ++w) eq = eq && keys[s * W + w] == k[w];
+            if (eq) return vals[s];
+            s = (s + 1) & mask;
+        }
+    }
+};
+
+template <int W>
+int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
+           const uint64_t* yz) {
+    XYMap map(W);
+    std::vector<int64_t> gid(static_cast<size_t>(n_terms));
+    std::vector<int64_t> first;
+    for (int64_t l = 0; l < n_terms; ++l) {
+        const int64_t g = map.find_or_insert(xy + l * W, static_cast<int64_t>(first.size()));
+        if (g == static_cast<int64_t>(first.size())) first.push_back(l);
+        gid[static_cast<size_t>(l)] = g;
+    }
+    const int64_t G = static_cast<int64_t>(first.size());
+    if (n_terms >= (int64_t(1) << 31) || G >= (int64_t(1) << 25))
+        return fail(c, ELOC_EINVAL, "Hamiltonian too large (terms < 2^31, unique XY < 2^25)");
+    std::vector<int64_t> begin(static_cast<size_t>(G + 1), 0);
+    for (int64_t l = 0; l < n_terms; ++l) ++begin[static_cast<size_t>(gid[l] + 1)];
+    for (int64_t g = 0; g < G; ++g) begin[g + 1] += begin[g];
+    std::vector<int64_t> fillpos(begin.begin(), begin.end() - 1);
+    std::vector<TermRec<W>> terms(static_cast<size_t>(n_terms));
+    std::vector<TermRecF<W>> terms_f(static_cast<size_t>(n_terms));
+    for (int64_t l = 0; l < n_terms; ++l) {   // caller order kept inside each group
+        const int64_t p = fillpos[static_cast<size_t>(gid[l])]++;
+        TermRec<W> t;
+        TermRecF<W> tf;
+        for (int w = 0; w < W; ++w) {
+            t.yz[w] = yz[l * W + w];
+            tf.yz[w] = yz[l * W + w];
+        }
+        t.h = coeff[l];
+        tf.h_hi = static_cast<float>(coeff[l]);
+        tf.h_lo = static_cast<float>(coeff[l] - static_cast<double>(tf.h_hi));
+        terms[static_cast<size_t>(p)] = t;
+        terms_f[static_cast<size_t>(p)] = tf;
+    }
+    std::vector<GroupRec<W>> groups(static_cast<size_t>(G));
+    std::vector<uint64_t> ghash(static_cast<size_t>(G));
+    std::vector<uint64_t> gkeys(static_cast<size_t>(G * W));
+    int maxpop = 0, diag = -1;
+    for (int64_t g = 0; g < G; ++g) {
+        GroupRec<W> r;
+        const uint64_t* m = xy + first[static_cast<size_t>(g)] * W;
+        uint64_t h = 0;
+        int pc = 0;
+        for (int w = 0; w < W; ++w) {
+            r.xy[w] = m[w];
+            gkeys[static_cast<size_t>(g * W + w)] = m[w];
+            pc += __builtin_popcountll(m[w]);
+            for (uint64_t v = m[w]; v; v &= v - 1) h ^= c->R[64 * w + __builtin_ctzll(v)];
+        }
+        r.begin = static_cast<int32_t>(begin[static_cast<size_t>(g)]);
+        r.end = static_cast<int32_t>(begin[static_cast<size_t>(g + 1)]);
+        groups[static_cast<size_t>(g)] = r;
+        ghash[static_cast<size_t>(g)] = h;
+        maxpop = std::max(maxpop, pc);
+        if (pc == 0) diag = static_cast<int>(g);
+    }
+    ELOC_HIP(c, c->groups.ensure(sizeof(GroupRec<W>) * G));
+    ELOC_HIP(c, c->terms.ensure(sizeof(TermRec<W>) * n_terms));
+    ELOC_HIP(c, c->terms_f.ensure(sizeof(TermRecF<W>) * n_terms));
+    ELOC_HIP(c, c->ghash.ensure(sizeof(uint64_t) * G));
+    ELOC_HIP(c, c->gkeys.ensure(sizeof(uint64_t) * G * W));
+    const uint64_t cap = pow2_at_least(static_cast<uint64_t>(4 * G));
+    ELOC_HIP(c, c->gslots.ensure(sizeof(uint32_t) * cap));
+    ELOC_HIP(c, hipMemcpy(c->groups.p, groups.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->terms.p, terms.data(), sizeof(TermRec<W>) * n_terms, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->terms_f.p, terms_f.data(), sizeof(TermRecF<W>) * n_terms, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemsetAsync(c->gslots.p, 0, sizeof(uint32_t) * cap, c->stream));
+    Table T = make_table(c->gslots.as<uint32_t>(), cap, G);
+    ELOC_HIP(c, launch_table_insert(W, c->ghash.as<uint64_t>(), G, c->gslots.as<uint32_t>(), T, c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+
+    HamDev H;
+    H.n_qubits = n_qubits;
+    H.W = W;
+    H.n_terms = n_terms;
+    H.n_groups = G;
+    H.maxpop = maxpop;
+    H.diag_group = diag;
+    H.groups = c->groups.p;
+    H.terms = c->terms.p;
+    H.terms_f = c->terms_f.p;
+    H.group_hash = c->ghash.as<uint64_t>();
+    H.group_keys = c->gkeys.as<uint64_t>();
+    H.group_table = T;
+    c->H = H;
+    c->ham_set = true;
+    return ELOC_OK;
+}
+
+hipEvent_t pool_event(eloc_ctx c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a start event for `stage` when profiling; returns the mark index or -1.
+int prof_begin(eloc_ctx c, int stage) {
+    if (!c->prof) return -1;
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    if (!a || !b) return -1;
+    if (hipEventRecord(a, c->stream) != hipSuccess) return -1;
+    c->marks.push_back({stage, a, b});
+    return static_cast<int>(c->marks.size()) - 1;
+}
+
+void prof_end(eloc_ctx c, int mark) {
+    if (mark < 0) return;
+    (void)hipEventRecord(c->marks[static_cast<size_t>(mark)].b, c->stream);
+}
+
+int check_ready(eloc_ctx c) {
+    if (!c) return ELOC_EINVAL;
+    if (!c->ham_set) return fail(c, ELOC_ESTATE, "no Hamiltonian set");
+    if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
+    return ELOC_OK;
+}
+
+int amp_prep(eloc_ctx c, const eloc_c64* logpsi, bool fp32) {
+    const int64_t M = c->S.n;
+    ELOC_HIP(c, c->a.ensure(sizeof(double2) * M));
+    ELOC_HIP(c, c->b.ensure(sizeof(double2) * M));
+    ELOC_HIP(c, c->af.ensure(sizeof(float4) * (fp32 ? M : 1)));
+    ELOC_HIP(c, c->bf.ensure(sizeof(float4) * (fp32 ? M : 1)));
+    ELOC_HIP(c, c->shift.ensure(sizeof(double) * 2));
+    ELOC_HIP(c, c->amp_scratch.ensure(sizeof(double) * amp_scratch_len()));
+    const int pm = prof_begin(c, ELOC_STAGE_AMPLITUDES);
+    ELOC_HIP(c, launch_amp_prep(reinterpret_cast<const double2*>(logpsi), M, fp32, c->a.as<double2>(),
+                                c->b.as<double2>(), c->af.as<float4>(), c->bf.as<float4>(),
+                                c->shift.as<double>(), c->amp_scratch.as<double>(), c->err_run.as<uint32_t>(),
+                                c->stream));
+    prof_end(c, pm);
+    return ELOC_OK;
+}
+
+int count_into_offsets(eloc_ctx c, int variant, const Plan& P, int64_t* total) {
+    const int64_t n = c->S.n * P.chunks;
+    ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
+    ELOC_HIP(c, c->offsets.ensure(sizeof(int64_t) * (n + 1)));
+    ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(n)));
+    ELOC_HIP(c, launch_pairs_count(variant, c->H, c->S, P, c->counts.as<int32_t>(), c->stream));
+    ELOC_HIP(c, launch_scan_i32(c->counts.as<int32_t>(), n, c->offsets.as<int64_t>(),
+                                c->scan_scratch.as<int64_t>(), c->stream));
+    int64_t t = 0;
+    ELOC_HIP(c, hipMemcpyAsync(&t, c->offsets.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    *total = t;
+    return ELOC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported
+// ===========================================================================
+extern "C" {
+
+int eloc_create(eloc_ctx* out, int device, void* hip_stream) {
+    if (!out) return ELOC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ELOC_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return ELOC_EHIP;
+    eloc_ctx c = new eloc_ctx_s();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    uint64_t s = 0x2408076250ull;
+    for (int q = 0; q < 128; ++q) c->R[q] = splitmix64(s);
+    if (c->R_dev.ensure(sizeof(c->R)) != hipSuccess ||
+        hipMemcpy(c->R_dev.p, c->R, sizeof(c->R), hipMemcpyHostToDevice) != hipSuccess ||
+        c->err_run.ensure(sizeof(uint32_t)) != hipSuccess || c->err_prep.ensure(sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->err_run.p, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
+        eloc_destroy(c);
+        return ELOC_EHIP;
+    }
+    *out = c;
+    return ELOC_OK;
+}
+
+void eloc_destroy(eloc_ctx c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&c->R_dev, &c->groups, &c->terms, &c->terms_f, &c->ghash, &c->gkeys, &c->gslots,
+                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
+                      &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
+                      &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
+                      &c->hist, &c->hist_off, &c->hist_scratch};
+    for (DevBuf* b : bufs) b->release();
+    for (auto& m : c->marks) {
+        c->ev_pool.push_back(m.a);
+        c->ev_pool.push_back(m.b);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->err_host) (void)hipHostFree(c->err_host);
+    delete c;
+}
+
+const char* eloc_last_error(eloc_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+int eloc_set_stream(eloc_ctx c, void* hip_stream) {
+    if (!c) return ELOC_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return ELOC_OK;
+}
+
+int eloc_set_hamiltonian(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
+                         const uint64_t* yz) {
+    if (!c) return ELOC_EINVAL;
+    if (n_qubits < 1 || n_qubits > 128) return fail(c, ELOC_EINVAL, "n_qubits must be in 1..128");
+    if (n_terms < 1 || !coeff || !xy || !yz) return fail(c, ELOC_EINVAL, "empty Hamiltonian or null pointer");
+    const int W = (n_qubits + 63) / 64;
+    for (int64_t l = 0; l < n_terms; ++l) {
+        for (int w = 0; w < W; ++w) {
+            const int valid = n_qubits - 64 * w;
+            if (valid < 64) {
+                const uint64_t allowed = (1ull << valid) - 1ull;
+                if ((xy[l * W + w] | yz[l * W + w]) & ~allowed)
+                    return fail(c, ELOC_EINVAL, "a term mask has bits set at or above n_qubits");
+            }
+        }
+        if (!std::isfinite(coeff[l])) return fail(c, ELOC_EINVAL, "non-finite coefficient");
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, ELOC_EHIP, "hipSetDevice");
+    c->ham_set = false;
+    c->samples_set = false;    // sample tables depend on the qubit count
+    return W == 1 ? ingest<1>(c, n_qubits, n_terms, coeff, xy, yz) : ingest<2>(c, n_qubits, n_terms, coeff, xy, yz);
+}
+
+int eloc_hamiltonian_info(eloc_ctx c, int64_t* n_groups, int64_t* n_terms, int* n_qubits) {
+    if (!c) return ELOC_EINVAL;
+    if (!c->ham_set) return fail(c, ELOC_ESTATE, "no Hamiltonian set");
+    if (n_groups) *n_groups = c->H.n_groups;
+    if (n_terms) *n_terms = c->H.n_terms;
+    if (n_qubits) *n_qubits = c->H.n_qubits;
+    return ELOC_OK;
+}
+
+int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
+    if (!c) return ELOC_EINVAL;
+    if (!c->ham_set) return fail(c, ELOC_ESTATE, "set the Hamiltonian first");
+    if (n_unique < 1 || n_unique >= (int64_t(1) << 24) || !keys_dev)
+        return fail(c, ELOC_EINVAL, "n_unique must be in 1..2^24-1 with a key pointer");
+    const int W = c->H.W;
+    c->samples_set = false;
+    ELOC_HIP(c, c->keys.ensure(sizeof(uint64_t) * n_unique * W));
+    ELOC_HIP(c, c->khash.ensure(sizeof(uint64_t) * n_unique));
+    const uint64_t cap = pow2_at_least(static_cast<uint64_t>(4 * n_unique));
+    ELOC_HIP(c, c->kslots.ensure(sizeof(uint32_t) * cap));
+    ELOC_HIP(c, c->sig.ensure(sizeof(uint64_t) * kSigWords));
+    const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
+    ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
+                               c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, sizeof(uint32_t) * cap, c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, launch_sample_hash(W, c->keys.as<uint64_t>(), n_unique, c->R_dev.as<uint64_t>(), c->H.n_qubits,
+                                   c->khash.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+    Table T = make_table(c->kslots.as<uint32_t>(), cap, n_unique);
+    ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.as<uint32_t>(), T, c->stream));
+    SampleDev S;
+    S.n = n_unique;
+    S.keys = c->keys.as<uint64_t>();
+    S.hash = c->khash.as<uint64_t>();
+    S.table = T;
+    S.sig = c->sig.as<uint64_t>();
+    ELOC_HIP(c, launch_sample_verify(W, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+    prof_end(c, pm);
+    const int bits = read_err(c, c->err_prep);
+    if (bits < 0) return bits;
+    const int rc = map_err(c, static_cast<uint32_t>(bits));
+    if (rc != ELOC_OK) return rc;
+    c->S = S;
+    c->samples_set = true;
+    return ELOC_OK;
+}
+
+int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* logpsi_dev,
+                      const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
+    if (!logpsi_dev || !eloc_dev || !stats_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    const int64_t M = c->S.n;
+    const bool fp32 = precision == ELOC_FP32C;
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    rc = amp_prep(c, logpsi_dev, fp32);
+    if (rc) return rc;
+    const Plan P = make_plan(c, variant);
+    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
+    int pm = prof_begin(c, ELOC_STAGE_PAIRS);
+    ELOC_HIP(c, launch_pairs(false, variant, precision, c->H, c->S, P, c->a.as<double2>(), c->af.as<float4>(),
+                             c->partial.p, c->stream));
+    prof_end(c, pm);
+    pm = prof_begin(c, ELOC_STAGE_FINISH);
+    ELOC_HIP(c, launch_finish(precision, M, P, c->partial.p, c->b.as<double2>(), c->bf.as<float4>(),
+                              reinterpret_cast<double2*>(eloc_dev), c->stream));
+    prof_end(c, pm);
+    ELOC_HIP(c, c->energy_scratch.ensure(sizeof(double) * energy_scratch_len()));
+    pm = prof_begin(c, ELOC_STAGE_ENERGY);
+    ELOC_HIP(c, launch_energy(reinterpret_cast<const double2*>(eloc_dev), reinterpret_cast<const double2*>(logpsi_dev),
+                              weights_dev, c->shift.as<double>(), M, stats_dev, c->energy_scratch.as<double>(),
+                              c->err_run.as<uint32_t>(), c->stream));
+    prof_end(c, pm);
+    return ELOC_OK;
+}
+
+int eloc_check(eloc_ctx c) {
+    if (!c) return ELOC_EINVAL;
+    const int bits = read_err(c, c->err_run);
+    if (bits < 0) return bits;
+    return map_err(c, static_cast<uint32_t>(bits));
+}
+
+int eloc_count_pairs(eloc_ctx c, int variant, int64_t* n_pairs_host) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
+    const Plan P = make_plan(c, variant);
+    return count_into_offsets(c, variant, P, n_pairs_host);
+}
+
+int eloc_find_pairs(eloc_ctx c, int variant, int64_t capacity, int32_t* i_dev, int32_t* j_dev, int32_t* g_dev,
+                    int64_t* n_pairs_host) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
+    const Plan P = make_plan(c, variant);
+    int64_t total = 0;
+    rc = count_into_offsets(c, variant, P, &total);
+    if (rc) return rc;
+    *n_pairs_host = total;
+    if (total > capacity) return fail(c, ELOC_ECAPACITY, "pair capacity too small");
+    if (total == 0) return ELOC_OK;
+    if (!i_dev || !j_dev || !g_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    const int64_t M = c->S.n;
+    const int jbits = std::max(1, bits_for(static_cast<uint64_t>(M - 1)));
+    const int end_bit = 2 * jbits;
+    ELOC_HIP(c, c->pkey.ensure(sizeof(uint64_t) * total));
+    ELOC_HIP(c, c->pval.ensure(sizeof(uint32_t) * total));
+    ELOC_HIP(c, c->pkey2.ensure(sizeof(uint64_t) * total));
+    ELOC_HIP(c, c->pval2.ensure(sizeof(uint32_t) * total));
+    ELOC_HIP(c, launch_pairs_fill(variant, c->H, c->S, P, jbits, c->offsets.as<int64_t>(), c->pkey.as<uint64_t>(),
+                                  c->pval.as<uint32_t>(), c->stream));
+    const int64_t tiles = radix_tiles(total);
+    ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+    ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+    int in_alt = 0;
+    ELOC_HIP(c, launch_radix_sort_pairs(c->pkey.as<uint64_t>(), c->pval.as<uint32_t>(), c->pkey2.as<uint64_t>(),
+                                        c->pval2.as<uint32_t>(), total, end_bit, c->hist.as<uint32_t>(),
+                                        c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(), &in_alt,
+                                        c->stream));
+    const uint64_t* ks = in_alt ? c->pkey2.as<uint64_t>() : c->pkey.as<uint64_t>();
+    const uint32_t* vs = in_alt ? c->pval2.as<uint32_t>() : c->pval.as<uint32_t>();
+    ELOC_HIP(c, launch_split_pairs(ks, vs, total, jbits, i_dev, j_dev, g_dev, c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    return ELOC_OK;
+}
+
+int eloc_pair_elements(eloc_ctx c, int64_t n, const int32_t* i_dev, const int32_t* j_dev, eloc_c64* h_dev) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (n < 0) return fail(c, ELOC_EINVAL, "negative count");
+    if (n == 0) return ELOC_OK;
+    if (!i_dev || !j_dev || !h_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, launch_pair_elements(c->H, c->S, n, i_dev, j_dev, reinterpret_cast<double2*>(h_dev),
+                                     c->err_run.as<uint32_t>(), c->stream));
+    return ELOC_OK;
+}
+
+int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc_c64* logpsi_dev,
+                              const double* weights_dev, const eloc_c64* eloc_dev, const double* stats_dev,
+                              eloc_c64 grad_e, eloc_c64* grad_logpsi_dev) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
+    if (!logpsi_dev || !eloc_dev || !stats_dev || !grad_logpsi_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    const int64_t M = c->S.n;
+    const bool fp32 = precision == ELOC_FP32C;
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    rc = amp_prep(c, logpsi_dev, fp32);
+    if (rc) return rc;
+    ELOC_HIP(c, c->v.ensure(sizeof(double2) * M));
+    ELOC_HIP(c, c->vf.ensure(sizeof(float4) * (fp32 ? M : 1)));
+    ELOC_HIP(c, launch_adj_vec(c->a.as<double2>(), c->b.as<double2>(), weights_dev, M, fp32, c->v.as<double2>(),
+                               c->vf.as<float4>(), c->stream));
+    const Plan P = make_plan(c, variant);
+    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
+    int pm = prof_begin(c, ELOC_STAGE_ADJOINT_PAIRS);
+    ELOC_HIP(c, launch_pairs(true, variant, precision, c->H, c->S, P, c->v.as<double2>(), c->vf.as<float4>(),
+                             c->partial.p, c->stream));
+    prof_end(c, pm);
+    pm = prof_begin(c, ELOC_STAGE_ADJOINT_FINISH);
+    ELOC_HIP(c, launch_adj_finish(precision, M, P, c->partial.p, c->a.as<double2>(), c->af.as<float4>(),
+                                  reinterpret_cast<const double2*>(eloc_dev), weights_dev, stats_dev,
+                                  c->shift.as<double>(), make_double2(grad_e.re, grad_e.im),
+                                  reinterpret_cast<double2*>(grad_logpsi_dev), c->stream));
+    prof_end(c, pm);
+    return ELOC_OK;
+}
+
+// Launch-geometry override used by the autotuner and the benchmarks:
+// chunks = 0 restores the automatic choice; sig_filter toggles the exact
+// (even, odd) popcount prefilter of LoopOverTerms.
+int eloc_set_tuning(eloc_ctx c, int chunks, int sig_filter) {
+    if (!c || chunks < 0) return ELOC_EINVAL;
+    c->tune_chunks = chunks;
+    c->tune_sig = sig_filter;
+    return ELOC_OK;
+}
+
+int eloc_profile_enable(eloc_ctx c, int on) {
+    if (!c) return ELOC_EINVAL;
+    c->prof = on != 0;
+    return ELOC_OK;
+}
+
+int eloc_profile_read(eloc_ctx c, double* ms_total, int64_t* count) {
+    if (!c || !ms_total || !count) return ELOC_EINVAL;
+    for (int k = 0; k < ELOC_NSTAGES; ++k) {
+        ms_total[k] = 0.0;
+        count[k] = 0;
+    }
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& m : c->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess && m.stage >= 0 && m.stage < ELOC_NSTAGES) {
+            ms_total[m.stage] += ms;
+            count[m.stage] += 1;
+        }
+        c->ev_pool.push_back(m.a);
+        c->ev_pool.push_back(m.b);
+    }
+    c->marks.clear();
+    return ELOC_OK;
+}
+
+}  // extern "C"

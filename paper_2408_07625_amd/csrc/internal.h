@@ -1,0 +1,179 @@
+// Shared declarations of the HIP engine: device data layouts, the
+// membership tables and the kernel launchers used by api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace eloc {
+
+constexpr int kMaxWords = 2;     // N <= 128 qubits
+constexpr int kSigRows = 65;     // popcount of even / odd qubit positions: 0..64
+constexpr int kSigWords = 2 * kSigRows;
+
+// ---------------------------------------------------------------------------
+// Hamiltonian layout.  The unique XY set (first-appearance order) is an array
+// of GroupRec; each group owns the run [begin, end) of TermRec, whose terms
+// keep the caller's order (the paper's starts / nums arrays, as a CSR).
+// ---------------------------------------------------------------------------
+template <int W>
+struct GroupRec {
+    uint64_t xy[W];
+    int32_t begin;
+    int32_t end;
+};
+
+template <int W>
+struct TermRec {
+    uint64_t yz[W];
+    double h;
+};
+
+// FP32 form: coefficient split into hi + lo floats.
+template <int W>
+struct TermRecF {
+    uint64_t yz[W];
+    float h_hi;
+    float h_lo;
+};
+
+// ---------------------------------------------------------------------------
+// Membership tables.  Keys are looked up through a GF(2)-linear 64-bit hash
+// lin(x) = XOR of R[q] over the set bits q of x, so lin(x ^ y) =
+// lin(x) ^ lin(y): the hash of a candidate x ^ XY is one XOR of two
+// precomputed hashes.  Slots are uint32: (fingerprint << ibits) | (index + 1),
+// 0 = empty, linear probing, load factor <= 1/4.  A fingerprint match is
+// confirmed by comparing the stored key.
+// ---------------------------------------------------------------------------
+struct Table {
+    const uint32_t* slots;
+    uint32_t mask;      // capacity - 1
+    int ibits;          // bits of index+1
+    uint32_t imask;     // (1 << ibits) - 1
+    int fpshift;        // 64 - (32 - ibits)
+};
+
+template <int W>
+__device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b) {
+    bool eq = a[0] == b[0];
+    if (W == 2) eq = eq && (a[1] == b[1]);
+    return eq;
+}
+
+// Index of `key` (hash h) in the table over `keys` ([n][W]), or -1.
+template <int W>
+__device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys,
+                                          uint64_t h, const uint64_t* key) {
+    uint32_t s = static_cast<uint32_t>(h) & T.mask;
+    const uint32_t fp = static_cast<uint32_t>(h >> T.fpshift);
+    for (;;) {
+        const uint32_t v = T.slots[s];
+        if (v == 0u) return -1;
+        if ((v >> T.ibits) == fp) {
+            const int j = static_cast<int>(v & T.imask) - 1;
+            if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
+        }
+        s = (s + 1u) & T.mask;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device state handed to kernels.
+// ---------------------------------------------------------------------------
+struct HamDev {
+    int n_qubits = 0;
+    int W = 0;
+    int64_t n_terms = 0;
+    int64_t n_groups = 0;
+    int maxpop = 0;            // max popcount of an XY mask
+    int diag_group = -1;       // group whose XY is 0, or -1
+    const void* groups = nullptr;     // GroupRec<W>[G]
+    const void* terms = nullptr;      // TermRec<W>[T]
+    const void* terms_f = nullptr;    // TermRecF<W>[T]
+    const uint64_t* group_hash = nullptr;  // lin(XY_g) [G]
+    const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
+    Table group_table{};               // XY -> group id
+};
+
+struct SampleDev {
+    int64_t n = 0;
+    const uint64_t* keys = nullptr;    // [M][W] caller order
+    const uint64_t* hash = nullptr;    // lin(x_i) [M]
+    Table table{};
+    const uint64_t* sig = nullptr;     // [kSigWords] signature bitmap
+};
+
+// Amplitudes relative to the largest |psi|: a_i = exp(L_i - c), c = max Re L.
+struct AmpDev {
+    const double2* a = nullptr;        // FP64 form
+    const float4* af = nullptr;        // FP32 form: (re_hi, re_lo, im_hi, im_lo)
+    const double* shift = nullptr;     // device scalar c
+};
+
+// Launch geometry of the pair kernels.
+struct Plan {
+    int chunks = 1;            // group (or sample) chunks per row
+    int per_chunk = 0;         // groups (or samples) per chunk
+    bool sig_filter = true;
+};
+
+// Error bits latched in a device word, read by eloc_check / synchronising calls.
+enum ErrBits : uint32_t {
+    kErrDup = 1u,
+    kErrBits = 2u,
+    kErrWeights = 4u,
+    kErrRange = 8u,
+    kErrIndex = 16u,
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip).  All enqueue on `st` and return hipError_t.
+// ---------------------------------------------------------------------------
+hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
+                              int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
+hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, uint32_t* slots,
+                               const Table& T, hipStream_t st);
+hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err,
+                                hipStream_t st);
+hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,
+                           float4* af, float4* bf, double* shift, double* scratch, uint32_t* err,
+                           hipStream_t st);
+hipError_t launch_adj_vec(const double2* a, const double2* b, const double* weights, int64_t n,
+                          bool fp32, double2* v, float4* vf, hipStream_t st);
+hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& H,
+                        const SampleDev& S, const Plan& P, const double2* vec, const float4* vecf,
+                        void* partial, hipStream_t st);
+hipError_t launch_finish(int precision, int64_t n, const Plan& P, const void* partial,
+                         const double2* b, const float4* bf, double2* out, hipStream_t st);
+hipError_t launch_adj_finish(int precision, int64_t n, const Plan& P, const void* partial,
+                             const double2* a, const float4* af, const double2* eloc,
+                             const double* weights, const double* stats, const double* shift,
+                             double2 ge, double2* out, hipStream_t st);
+hipError_t launch_energy(const double2* eloc, const double2* logpsi, const double* weights,
+                         const double* shift, int64_t n, double* stats, double* scratch,
+                         uint32_t* err, hipStream_t st);
+hipError_t launch_pairs_count(int variant, const HamDev& H, const SampleDev& S, const Plan& P,
+                              int32_t* counts, hipStream_t st);
+hipError_t launch_pairs_fill(int variant, const HamDev& H, const SampleDev& S, const Plan& P,
+                             int jbits, const int64_t* offsets, uint64_t* pkey, uint32_t* pval,
+                             hipStream_t st);
+hipError_t launch_scan_i32(const int32_t* in, int64_t n, int64_t* out, int64_t* scratch,
+                           hipStream_t st);
+hipError_t launch_radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                                   uint32_t* vals_alt, int64_t n, int end_bit, uint32_t* hist,
+                                   int64_t* hist_off, int64_t* scan_scratch, int* result_in_alt,
+                                   hipStream_t st);
+hipError_t launch_split_pairs(const uint64_t* keys, const uint32_t* vals, int64_t n, int jbits,
+                              int32_t* i_out, int32_t* j_out, int32_t* g_out, hipStream_t st);
+hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n,
+                                const int32_t* i_idx, const int32_t* j_idx, double2* h_out,
+                                uint32_t* err, hipStream_t st);
+
+int64_t energy_scratch_len();
+int64_t amp_scratch_len();
+int64_t scan_scratch_len(int64_t n);
+int64_t radix_tiles(int64_t n);
+
+}  // namespace eloc

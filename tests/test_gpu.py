@@ -1,0 +1,314 @@
+"""Parity of the HIP engine (through the C ABI) with the CPU oracle.
+
+Bars: coupled pairs and group ids bit-exact; FP64 local energies within
+1e-9 Ha (the oracle and the kernels differ only in summation order; the
+observed gap is ~1e-13); the compensated FP32 form within 1e-6 Ha, the
+tolerance the accuracy target of the method states.
+"""
+import json
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from synth import configs, jw, samples  # noqa: E402
+
+TOL64 = 1e-9
+TOL32 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def eng():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_07625_amd as pe
+    e = pe.Engine(0)
+    yield e
+    e.close()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def keys_dev(keys):
+    return dev(keys.view(np.int64))
+
+
+def load(eng, ham, keys):
+    eng.set_hamiltonian(ham.n_qubits, ham.coeff, ham.xy, ham.yz)
+    eng.set_samples(keys_dev(keys))
+
+
+def oracle_pairs(ham, keys, rows=None):
+    pi, pj, pg = oracle.find_pairs(ham, keys, rows=rows)
+    return pi.astype(np.int64), pj.astype(np.int64), pg.astype(np.int64)
+
+
+def gpu_pairs(eng, variant):
+    i, j, g = eng.find_pairs(variant)
+    return i.cpu().numpy().astype(np.int64), j.cpu().numpy().astype(np.int64), g.cpu().numpy().astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+def _toy():
+    d = json.loads((Path(__file__).resolve().parent / "golden" / "toy_model.json").read_text())
+
+    def m(s):
+        return sum(1 << q for q, ch in enumerate(s) if ch == "1")
+    ham = jw.PauliHamiltonian(4, np.array([t["coeff"] for t in d["terms"]]),
+                              np.array([[m(t["XY"])] for t in d["terms"]], dtype=np.uint64),
+                              np.array([[m(t["YZ"])] for t in d["terms"]], dtype=np.uint64))
+    keys = np.array([[m(s)] for s in d["samples"]], dtype=np.uint64)
+    return d, ham, keys, np.log(np.array(d["psi"], dtype=complex))
+
+
+@pytest.mark.parametrize("variant", ["terms", "batch"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_toy_model(eng, variant, precision):
+    d, ham, keys, logpsi = _toy()
+    load(eng, ham, keys)
+    e, st = eng.local_energy(dev(logpsi), variant=variant, precision=precision)
+    np.testing.assert_allclose(e.cpu().numpy(), d["local_energy"], atol=1e-12)
+    i, j, g = gpu_pairs(eng, variant)
+    assert [j[i == r].tolist() for r in range(3)] == d["coupled"]
+    assert g.tolist() == [0, 2, 1, 2, 0, 1, 0]
+    h = eng.pair_elements(dev(i, torch.int32), dev(j, torch.int32)).cpu().numpy()
+    want = {(m["i"], m["j"]): m["h"] for m in d["matrix_elements"]}
+    np.testing.assert_allclose(h, [want[(a, b)] for a, b in zip(i, j)], atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+def check_workload(eng, w, variants=("terms", "batch"), rows=None, pairs=True):
+    load(eng, w.ham, w.keys)
+    M = w.n_unique
+    L = dev(w.logpsi)
+    W8 = None if w.weights is None else dev(w.weights)
+    if rows is None:
+        ref = oracle.local_energy(w.ham, w.keys, w.logpsi)
+        sel = np.arange(M)
+    else:
+        ref = np.concatenate([oracle.local_energy(w.ham, w.keys, w.logpsi, rows=r) for r in rows])
+        sel = np.concatenate([np.arange(a, b) for a, b in rows])
+    for variant in variants:
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, st = eng.local_energy(L, W8, variant=variant, precision=prec)
+            got = e.cpu().numpy()[sel]
+            err = np.abs(got - ref).max()
+            print(f"{w.name} {variant} {prec}: max |dE_loc| = {err:.3e}")
+            assert err <= tol, (variant, prec, err)
+            if rows is None:
+                E, var, tot = oracle.energy(ref, w.logpsi, w.weights)
+                s = st.cpu().numpy()
+                assert abs(s[0] - E.real) <= tol and abs(s[1] - E.imag) <= tol
+                assert abs(s[2] - var) <= tol * max(1.0, var)
+                np.testing.assert_allclose(s[3], tot, rtol=1e-12)
+    if pairs:
+        if rows is None:
+            ref_p = oracle_pairs(w.ham, w.keys)
+            for variant in variants:
+                got_p = gpu_pairs(eng, variant)
+                for a, b in zip(got_p, ref_p):
+                    np.testing.assert_array_equal(a, b)
+        else:
+            for variant in variants:
+                got_p = gpu_pairs(eng, variant)
+                for (a, b) in rows:
+                    ref_p = oracle_pairs(w.ham, w.keys, rows=(a, b))
+                    m = (got_p[0] >= a) & (got_p[0] < b)
+                    for x, y in zip(got_p, ref_p):
+                        np.testing.assert_array_equal(x[m], y)
+
+
+def test_small_workload(eng, small_workload):
+    check_workload(eng, small_workload)
+
+
+def test_medium_workload(eng, medium_workload):
+    w = medium_workload
+    check_workload(eng, w, rows=[(0, 700), (31000, 31333), (65536 - 517, 65536)])
+    # full-row energies, the configuration the benchmark times
+    ref = oracle.local_energy(w.ham, w.keys, w.logpsi)
+    e, st = eng.local_energy(dev(w.logpsi), variant="terms", precision="fp64")
+    assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
+    E, var, tot = oracle.energy(ref, w.logpsi)
+    s = st.cpu().numpy()
+    assert abs(s[0] - E.real) <= TOL64 and abs(s[2] - var) <= TOL64 * max(1.0, var)
+    _, npairs = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=(0, w.n_unique), with_pairs=True)
+    assert eng.count_pairs("terms") == int(npairs.sum())
+
+
+def test_large_workload_sampled(eng):
+    w = configs.large()
+    check_workload(eng, w, variants=("terms",), rows=[(0, 300), (524288, 524600), ((1 << 20) - 211, 1 << 20)],
+                   pairs=False)
+
+
+def test_wide_workload_sampled(eng):
+    """100 qubits, two words per key, occurrence-count weights."""
+    w = configs.wide()
+    rows = [(0, 100), ((1 << 18) - 77, 1 << 18)]
+    check_workload(eng, w, variants=("terms",), rows=rows, pairs=False)
+    L = dev(w.logpsi)
+    Wt = dev(w.weights)
+    e, st = eng.local_energy(L, Wt, variant="terms", precision="fp64")
+    E = complex(st[0].item(), st[1].item())
+    for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+        g = eng.adjoint(L, e, st, 1.0 + 0.5j, Wt, precision=prec).cpu().numpy()
+        for a, b in rows:
+            ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=(a, b))
+            ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, 1.0 + 0.5j, weights=w.weights,
+                                 energy_value=E, rows=(a, b))
+            err = np.abs(g[a:b] - ref).max()
+            print(f"wide adjoint {prec}: max |dG| = {err:.3e} (max |G| {np.abs(ref).max():.3e})")
+            assert err <= tol * max(1.0, np.abs(ref).max())
+
+
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("M", [1, 2, 63, 64, 65, 255, 257, 1000])
+def test_ragged_batch_sizes(eng, small_workload, M):
+    w = small_workload
+    keys = w.keys[:M].copy()
+    lp = w.logpsi[:M].copy()
+    load(eng, w.ham, keys)
+    ref = oracle.local_energy(w.ham, keys, lp)
+    for variant in ("terms", "batch"):
+        e, st = eng.local_energy(dev(lp), variant=variant)
+        assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
+        got = gpu_pairs(eng, variant)
+        for a, b in zip(got, oracle_pairs(w.ham, keys)):
+            np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("chunks", [1, 3, 17])
+def test_chunking_does_not_change_pairs(eng, small_workload, chunks):
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    ref = oracle.local_energy(w.ham, w.keys, w.logpsi)
+    for sig in (True, False):
+        eng.set_tuning(chunks, sig)
+        try:
+            for variant in ("terms", "batch"):
+                e, _ = eng.local_energy(dev(w.logpsi), variant=variant)
+                assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
+                assert eng.count_pairs(variant) == oracle.find_pairs(w.ham, w.keys)[0].size
+        finally:
+            eng.set_tuning(0, True)
+
+
+def test_random_pauli_odd_y(eng):
+    """All four letters with odd |Y|: the i^|Y| factor and the ket phase."""
+    rng = np.random.default_rng(7)
+    ham = jw.random_pauli(10, 300, rng, max_flip=3)
+    keys = np.sort(rng.choice(1024, size=400, replace=False)).astype(np.uint64)[:, None]
+    keys = keys[rng.permutation(400)]
+    lp = rng.normal(size=400) + 1j * rng.uniform(0, 6.28, size=400)
+    load(eng, ham, keys)
+    ref = oracle.local_energy(ham, keys, lp)
+    for variant in ("terms", "batch"):
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, _ = eng.local_energy(dev(lp), variant=variant, precision=prec)
+            assert np.abs(e.cpu().numpy() - ref).max() <= tol
+    i, j, g = gpu_pairs(eng, "terms")
+    h = eng.pair_elements(dev(i, torch.int32), dev(j, torch.int32)).cpu().numpy()
+    np.testing.assert_allclose(h, oracle.matrix_elements(ham, keys[i], keys[j]), atol=1e-12)
+
+
+def test_deterministic(eng, small_workload):
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    L = dev(w.logpsi)
+    for variant in ("terms", "batch"):
+        for prec in ("fp64", "fp32c"):
+            a, sa = eng.local_energy(L, variant=variant, precision=prec)
+            a = a.clone(); sa = sa.clone()
+            b, sb = eng.local_energy(L, variant=variant, precision=prec)
+            assert torch.equal(a, b) and torch.equal(sa, sb)
+
+
+def test_single_determinant(eng):
+    """U = {x}: E_loc = H_xx (Slater-Condon closed form checked in the oracle pins)."""
+    N = 28
+    ham, h, g = jw.random_jw(N, np.random.default_rng(3))
+    keys, _ = samples.excitation_batch(N, 14, 1, np.random.default_rng(4))
+    load(eng, ham, keys)
+    e, st = eng.local_energy(dev(np.array([0.2 - 0.7j])))
+    ref = oracle.local_energy(ham, keys, np.array([0.2 - 0.7j]))
+    assert abs(e.cpu().numpy()[0] - ref[0]) <= TOL64
+    assert abs(st[2].item()) < 1e-18
+
+
+# ----------------------------------------------------------------------------
+def test_errors(eng, small_workload):
+    import paper_2408_07625_amd as pe
+    w = small_workload
+    eng.set_hamiltonian(w.ham.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
+    dup = np.concatenate([w.keys[:10], w.keys[3:4]])
+    with pytest.raises(pe.ElocError) as ex:
+        eng.set_samples(keys_dev(dup))
+    assert ex.value.status == "EDUP"
+    bad = w.keys[:10].copy()
+    bad[5, 0] |= np.uint64(1 << 40)
+    with pytest.raises(pe.ElocError) as ex:
+        eng.set_samples(keys_dev(bad))
+    assert ex.value.status == "EINVAL"
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(dev(w.logpsi[:10]))
+    assert ex.value.status == "ESTATE"
+    eng.set_samples(keys_dev(w.keys[:10]))
+    negw = np.ones(10)
+    negw[2] = -1.0
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(dev(w.logpsi[:10]), dev(negw))
+    assert ex.value.status == "EINVAL"
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(dev(w.logpsi[:10]), dev(np.zeros(10)))
+    assert ex.value.status == "EINVAL"
+    wide = w.logpsi[:10].copy()
+    wide[4] -= 70.0
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(dev(wide), precision="fp32c")
+    assert ex.value.status == "ERANGE"
+    e, _ = eng.local_energy(dev(wide), precision="fp64")     # FP64 takes the wide spread
+    ref = oracle.local_energy(w.ham, w.keys[:10], wide)
+    assert np.abs(e.cpu().numpy() - ref).max() <= TOL64 * max(1.0, np.abs(ref).max())
+    with pytest.raises(pe.ElocError) as ex:
+        eng.pair_elements(dev(np.array([0, 11], dtype=np.int32)), dev(np.array([1, 1], dtype=np.int32)))
+    assert ex.value.status == "EINVAL"
+
+
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("use_counts", [False, True])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_adjoint_small(eng, small_workload, use_counts, precision):
+    import paper_2408_07625_amd as pe
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    weights = np.random.default_rng(1).integers(1, 30, size=w.n_unique).astype(float) if use_counts else None
+    ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi)
+    E, _, _ = oracle.energy(ref_e, w.logpsi, weights)
+    for variant in ("terms", "batch"):
+        for ge in (1.0, 1j, 0.3 - 0.4j):
+            ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, ge, weights=weights, energy_value=E)
+            L = dev(w.logpsi)
+            Wt = None if weights is None else dev(weights)
+            e, st = eng.local_energy(L, Wt, variant=variant, precision=precision)
+            g = eng.adjoint(L, e, st, ge, Wt, variant=variant, precision=precision).cpu().numpy()
+            tol = TOL64 if precision == "fp64" else TOL32
+            assert np.abs(g - ref).max() <= tol * max(1.0, np.abs(ref).max())
+    # through torch.autograd
+    L = dev(w.logpsi).requires_grad_(True)
+    Wt = None if weights is None else dev(weights)
+    E_t, _, _ = pe.local_energy(eng, L, Wt, "terms", precision)
+    E_t.real.backward()
+    ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, 1.0, weights=weights, energy_value=E)
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert np.abs(L.grad.cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
