@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--variant", default="terms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", action="store_true", help="time only the headline variant")
     return ap.parse_args()
 
 
@@ -108,6 +109,30 @@ def main():
               ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]),
               file=sys.stderr, flush=True)
 
+    # the other FindCoupledPairs variants, same workload and protocol
+    variants = {}
+    for var in ("terms", "batch", "trie"):
+        if var == args.variant or args.only:
+            continue
+        for prec in ("fp64", "fp32c"):
+            for _ in range(args.warmup):
+                eng.set_samples(keys)
+                eng.local_energy(L, Wt, var, prec, out=out, stats=stats, check=False)
+            eng.check()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                eng.set_samples(keys)
+                eng.local_energy(L, Wt, var, prec, out=out, stats=stats, check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            eng.check()
+            variants.setdefault(var, {})[prec] = e0.elapsed_time(e1) / args.steps
+        print(f"# variant {var}: " + ", ".join(f"{p}={v:.3f} ms/step" for p, v in variants[var].items()),
+              file=sys.stderr, flush=True)
+
     # work counts (outside the timed region)
     n_pairs = eng.count_pairs(args.variant)
     _, _, gids = eng.find_pairs(args.variant)
@@ -154,6 +179,7 @@ def main():
         "stage_ms": {p: {k: v[0] / max(v[1], 1) for k, v in results[p]["stages"].items() if v[1]}
                      for p in results},
         "roofline": roof,
+        "other_variants_ms_per_step": variants,
     }
 
     if not args.no_cpu_baseline:

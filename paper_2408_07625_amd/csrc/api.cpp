@@ -3,6 +3,7 @@
 // launchers of kernels.hip on the context's stream.
 #include "eloc.h"
 #include "internal.h"
+#include "trie.h"
 
 #include <hip/hip_runtime.h>
 
@@ -83,10 +84,14 @@ struct eloc_ctx_s {
     bool ham_set = false;
     HamDev H;
     DevBuf groups, terms, terms_f, ghash, gkeys, gslots;
+    DevBuf xyt_keys, xyt_gid, xyt_nodes;
 
     bool samples_set = false;
     SampleDev S;
     DevBuf keys, khash, kslots, sig;
+    DevBuf ut_keys, ut_perm, ut_nodes;
+    bool ut_valid = false;
+    DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
 
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
     DevBuf partial, energy_scratch, err_run, err_prep;
@@ -126,21 +131,32 @@ int hip_fail(eloc_ctx c, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
-int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH; }
+int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH || v == ELOC_TRIE; }
 
+// Launch geometry.  TERMS / BATCH: one wave per rows_per_block rows, the
+// inner loop (groups / samples) split into chunks of whole 64-lane steps so
+// that the grid has about `target` waves.  TRIE: one lane per row, one chunk
+// per XY tree.
 Plan make_plan(const eloc_ctx c, int variant) {
     Plan P;
     const int64_t M = c->S.n;
-    const int64_t waves = (M + 63) / 64;
+    P.rows_per_block = rows_per_block(variant);
+    P.sig_filter = c->tune_sig != 0;
+    if (variant == ELOC_TRIE) {
+        P.chunks = c->H.xyt.chunks;
+        P.per_chunk = c->H.xyt.chunk;
+        return P;
+    }
+    const int64_t waves = (M + P.rows_per_block - 1) / P.rows_per_block;
     const int64_t target = 16384;
     const int64_t span = (variant == ELOC_TERMS) ? c->H.n_groups : M;
+    const int64_t steps = (span + 63) / 64;
     int64_t chunks = c->tune_chunks > 0 ? c->tune_chunks : (target + waves - 1) / waves;
-    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, std::max<int64_t>(1, span / 64)));
-    int64_t per = (span + chunks - 1) / chunks;
-    chunks = (span + per - 1) / per;
-    P.chunks = static_cast<int>(chunks);
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, steps));
+    const int64_t per_steps = (steps + chunks - 1) / chunks;
+    const int64_t per = per_steps * 64;
+    P.chunks = static_cast<int>((span + per - 1) / per);
     P.per_chunk = static_cast<int>(per);
-    P.sig_filter = c->tune_sig != 0;
     return P;
 }
 
@@ -232,23 +248,39 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     const int64_t G = static_cast<int64_t>(first.size());
     if (n_terms >= (int64_t(1) << 31) || G >= (int64_t(1) << 25))
         return fail(c, ELOC_EINVAL, "Hamiltonian too large (terms < 2^31, unique XY < 2^25)");
+    // |Y| parity of each term: even terms form the real part of a group's
+    // run, odd terms the imaginary part; i^|Y| = (-1)^floor(|Y|/2) i^(|Y| mod 2)
+    std::vector<int> ny(static_cast<size_t>(n_terms));
+    for (int64_t l = 0; l < n_terms; ++l) {
+        int k = 0;
+        for (int w = 0; w < W; ++w) k += __builtin_popcountll(xy[l * W + w] & yz[l * W + w]);
+        ny[static_cast<size_t>(l)] = k;
+    }
+    std::vector<int64_t> n_even(static_cast<size_t>(G), 0), n_all(static_cast<size_t>(G), 0);
+    for (int64_t l = 0; l < n_terms; ++l) {
+        ++n_all[static_cast<size_t>(gid[l])];
+        if ((ny[static_cast<size_t>(l)] & 1) == 0) ++n_even[static_cast<size_t>(gid[l])];
+    }
     std::vector<int64_t> begin(static_cast<size_t>(G + 1), 0);
-    for (int64_t l = 0; l < n_terms; ++l) ++begin[static_cast<size_t>(gid[l] + 1)];
-    for (int64_t g = 0; g < G; ++g) begin[g + 1] += begin[g];
-    std::vector<int64_t> fillpos(begin.begin(), begin.end() - 1);
+    for (int64_t g = 0; g < G; ++g) begin[g + 1] = begin[g] + n_all[static_cast<size_t>(g)];
+    std::vector<int64_t> pos_even(begin.begin(), begin.end() - 1), pos_odd(static_cast<size_t>(G));
+    for (int64_t g = 0; g < G; ++g) pos_odd[static_cast<size_t>(g)] = begin[g] + n_even[static_cast<size_t>(g)];
     std::vector<TermRec<W>> terms(static_cast<size_t>(n_terms));
     std::vector<TermRecF<W>> terms_f(static_cast<size_t>(n_terms));
-    for (int64_t l = 0; l < n_terms; ++l) {   // caller order kept inside each group
-        const int64_t p = fillpos[static_cast<size_t>(gid[l])]++;
+    for (int64_t l = 0; l < n_terms; ++l) {   // caller order kept inside each part
+        const size_t g = static_cast<size_t>(gid[l]);
+        const int k = ny[static_cast<size_t>(l)];
+        const int64_t p = (k & 1) ? pos_odd[g]++ : pos_even[g]++;
+        const double h = ((k >> 1) & 1) ? -coeff[l] : coeff[l];
         TermRec<W> t;
         TermRecF<W> tf;
         for (int w = 0; w < W; ++w) {
             t.yz[w] = yz[l * W + w];
             tf.yz[w] = yz[l * W + w];
         }
-        t.h = coeff[l];
-        tf.h_hi = static_cast<float>(coeff[l]);
-        tf.h_lo = static_cast<float>(coeff[l] - static_cast<double>(tf.h_hi));
+        t.h = h;
+        tf.h_hi = static_cast<float>(h);
+        tf.h_lo = static_cast<float>(h - static_cast<double>(tf.h_hi));
         terms[static_cast<size_t>(p)] = t;
         terms_f[static_cast<size_t>(p)] = tf;
     }
@@ -268,12 +300,37 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
             for (uint64_t v = m[w]; v; v &= v - 1) h ^= c->R[64 * w + __builtin_ctzll(v)];
         }
         r.begin = static_cast<int32_t>(begin[static_cast<size_t>(g)]);
+        r.mid = static_cast<int32_t>(begin[static_cast<size_t>(g)] + n_even[static_cast<size_t>(g)]);
         r.end = static_cast<int32_t>(begin[static_cast<size_t>(g + 1)]);
+        r.pad = 0;
         groups[static_cast<size_t>(g)] = r;
         ghash[static_cast<size_t>(g)] = h;
         maxpop = std::max(maxpop, pc);
         if (pc == 0) diag = static_cast<int>(g);
     }
+    // XY prefix trees: masks sorted ascending, cut into chunks of xy_chunk
+    std::vector<int32_t> order(static_cast<size_t>(G));
+    for (int64_t g = 0; g < G; ++g) order[static_cast<size_t>(g)] = static_cast<int32_t>(g);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t ka = gkeys[static_cast<size_t>(a) * W + w], kb = gkeys[static_cast<size_t>(b) * W + w];
+            if (ka != kb) return ka < kb;
+        }
+        return false;
+    });
+    std::vector<uint64_t> xsorted(static_cast<size_t>(G * W));
+    for (int64_t i = 0; i < G; ++i)
+        for (int w = 0; w < W; ++w)
+            xsorted[static_cast<size_t>(i * W + w)] = gkeys[static_cast<size_t>(order[static_cast<size_t>(i)]) * W + w];
+    const int64_t xy_chunks_target = 16;
+    const int64_t xy_chunk = std::max<int64_t>(2, (G + xy_chunks_target - 1) / xy_chunks_target);
+    const int64_t xy_chunks = (G + xy_chunk - 1) / xy_chunk;
+    ELOC_HIP(c, c->xyt_keys.ensure(sizeof(uint64_t) * G * W));
+    ELOC_HIP(c, c->xyt_gid.ensure(sizeof(int32_t) * G));
+    ELOC_HIP(c, c->xyt_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, xy_chunks * (xy_chunk - 1))));
+    ELOC_HIP(c, hipMemcpy(c->xyt_keys.p, xsorted.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->xyt_gid.p, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice));
+    ELOC_HIP(c, launch_trie_build(W, c->xyt_keys.as<uint64_t>(), G, xy_chunk, c->xyt_nodes.as<TNode>(), c->stream));
     ELOC_HIP(c, c->groups.ensure(sizeof(GroupRec<W>) * G));
     ELOC_HIP(c, c->terms.ensure(sizeof(TermRec<W>) * n_terms));
     ELOC_HIP(c, c->terms_f.ensure(sizeof(TermRecF<W>) * n_terms));
@@ -304,6 +361,11 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.group_hash = c->ghash.as<uint64_t>();
     H.group_keys = c->gkeys.as<uint64_t>();
     H.group_table = T;
+    H.xyt.keys = c->xyt_keys.as<uint64_t>();
+    H.xyt.gid = c->xyt_gid.as<int32_t>();
+    H.xyt.nodes = c->xyt_nodes.as<TNode>();
+    H.xyt.chunk = static_cast<int>(xy_chunk);
+    H.xyt.chunks = static_cast<int>(xy_chunks);
     c->H = H;
     c->ham_set = true;
     return ELOC_OK;
@@ -340,6 +402,42 @@ int check_ready(eloc_ctx c) {
     if (!c->ham_set) return fail(c, ELOC_ESTATE, "no Hamiltonian set");
     if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
     return ELOC_OK;
+}
+
+// Sorted copy of U with its radix tree, built on first use by LoopOverTrie
+// after every eloc_set_samples.
+int ensure_utrie(eloc_ctx c) {
+    if (c->ut_valid) return ELOC_OK;
+    const int64_t M = c->S.n;
+    const int W = c->H.W;
+    const int64_t tiles = radix_tiles(M);
+    ELOC_HIP(c, c->ut_keys.ensure(sizeof(uint64_t) * M * W));
+    ELOC_HIP(c, c->ut_perm.ensure(sizeof(int32_t) * M));
+    ELOC_HIP(c, c->ut_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, M - 1)));
+    ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * M));
+    ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * M));
+    ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * M));
+    ELOC_HIP(c, c->s_val2.ensure(sizeof(uint32_t) * M));
+    ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+    ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+    SortScratch ss{c->s_key.as<uint64_t>(), c->s_val.as<uint32_t>(), c->s_key2.as<uint64_t>(),
+                   c->s_val2.as<uint32_t>(), c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(),
+                   c->hist_scratch.as<int64_t>()};
+    const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
+    ELOC_HIP(c, launch_sort_keys(W, c->H.n_qubits, c->keys.as<uint64_t>(), M, ss, c->ut_keys.as<uint64_t>(),
+                                 c->ut_perm.as<int32_t>(), c->stream));
+    ELOC_HIP(c, launch_trie_build(W, c->ut_keys.as<uint64_t>(), M, M, c->ut_nodes.as<TNode>(), c->stream));
+    prof_end(c, pm);
+    c->S.ut.keys = c->ut_keys.as<uint64_t>();
+    c->S.ut.perm = c->ut_perm.as<int32_t>();
+    c->S.ut.nodes = c->ut_nodes.as<TNode>();
+    c->ut_valid = true;
+    return ELOC_OK;
+}
+
+int prepare_variant(eloc_ctx c, int variant) {
+    return variant == ELOC_TRIE ? ensure_utrie(c) : ELOC_OK;
 }
 
 int amp_prep(eloc_ctx c, const eloc_c64* logpsi, bool fp32) {
@@ -413,7 +511,8 @@ void eloc_destroy(eloc_ctx c) {
                       &c->keys, &c->khash, &c->kslots, &c->sig, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
-                      &c->hist, &c->hist_off, &c->hist_scratch};
+                      &c->hist, &c->hist_off, &c->hist_scratch, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes,
+                      &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2};
     for (DevBuf* b : bufs) b->release();
     for (auto& m : c->marks) {
         c->ev_pool.push_back(m.a);
@@ -499,6 +598,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     const int rc = map_err(c, static_cast<uint32_t>(bits));
     if (rc != ELOC_OK) return rc;
     c->S = S;
+    c->ut_valid = false;
     c->samples_set = true;
     return ELOC_OK;
 }
@@ -512,6 +612,8 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
     if (!logpsi_dev || !eloc_dev || !stats_dev) return fail(c, ELOC_EINVAL, "null pointer");
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
+    rc = prepare_variant(c, variant);
+    if (rc) return rc;
     ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     rc = amp_prep(c, logpsi_dev, fp32);
     if (rc) return rc;
@@ -546,6 +648,8 @@ int eloc_count_pairs(eloc_ctx c, int variant, int64_t* n_pairs_host) {
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
+    rc = prepare_variant(c, variant);
+    if (rc) return rc;
     const Plan P = make_plan(c, variant);
     return count_into_offsets(c, variant, P, n_pairs_host);
 }
@@ -556,6 +660,8 @@ int eloc_find_pairs(eloc_ctx c, int variant, int64_t capacity, int32_t* i_dev, i
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
+    rc = prepare_variant(c, variant);
+    if (rc) return rc;
     const Plan P = make_plan(c, variant);
     int64_t total = 0;
     rc = count_into_offsets(c, variant, P, &total);
@@ -611,6 +717,8 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
     if (!logpsi_dev || !eloc_dev || !stats_dev || !grad_logpsi_dev) return fail(c, ELOC_EINVAL, "null pointer");
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
+    rc = prepare_variant(c, variant);
+    if (rc) return rc;
     ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     rc = amp_prep(c, logpsi_dev, fp32);
     if (rc) return rc;

@@ -15,14 +15,21 @@ constexpr int kSigWords = 2 * kSigRows;
 
 // ---------------------------------------------------------------------------
 // Hamiltonian layout.  The unique XY set (first-appearance order) is an array
-// of GroupRec; each group owns the run [begin, end) of TermRec, whose terms
-// keep the caller's order (the paper's starts / nums arrays, as a CSR).
+// of GroupRec; each group owns the run [begin, end) of TermRec (the paper's
+// starts / nums arrays, as a CSR).  Inside a run the terms with an even
+// |Y| = |XY & YZ| come first ([begin, mid), real matrix-element part), then
+// those with odd |Y| ([mid, end), imaginary part), each in caller order.
+// The stored coefficient already carries the sign of i^|Y|:
+// h' = h (-1)^floor(|Y|/2), so <x|P|x'> h = h' (-1)^|x' & YZ| (times i for
+// the odd part).
 // ---------------------------------------------------------------------------
 template <int W>
 struct GroupRec {
     uint64_t xy[W];
     int32_t begin;
+    int32_t mid;
     int32_t end;
+    int32_t pad;
 };
 
 template <int W>
@@ -31,7 +38,7 @@ struct TermRec {
     double h;
 };
 
-// FP32 form: coefficient split into hi + lo floats.
+// FP32 form: signed coefficient split into hi + lo floats.
 template <int W>
 struct TermRecF {
     uint64_t yz[W];
@@ -82,6 +89,25 @@ __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __rest
 // ---------------------------------------------------------------------------
 // Device state handed to kernels.
 // ---------------------------------------------------------------------------
+struct TNode;
+
+// Prefix trees (sorted keys + radix-tree nodes).  XY trees are built per
+// chunk of `chunk` consecutive sorted masks: chunk c owns leaves
+// [c * chunk, min(G, (c + 1) * chunk)) and nodes from c * (chunk - 1).
+struct XYTrieDev {
+    const uint64_t* keys = nullptr;   // [G][W] sorted
+    const int32_t* gid = nullptr;     // group id of each sorted mask
+    const TNode* nodes = nullptr;
+    int chunk = 0;
+    int chunks = 0;
+};
+
+struct UTrieDev {
+    const uint64_t* keys = nullptr;   // [M][W] sorted
+    const int32_t* perm = nullptr;    // sample index of each sorted key
+    const TNode* nodes = nullptr;     // [M - 1]
+};
+
 struct HamDev {
     int n_qubits = 0;
     int W = 0;
@@ -95,6 +121,7 @@ struct HamDev {
     const uint64_t* group_hash = nullptr;  // lin(XY_g) [G]
     const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
     Table group_table{};               // XY -> group id
+    XYTrieDev xyt{};
 };
 
 struct SampleDev {
@@ -103,6 +130,7 @@ struct SampleDev {
     const uint64_t* hash = nullptr;    // lin(x_i) [M]
     Table table{};
     const uint64_t* sig = nullptr;     // [kSigWords] signature bitmap
+    UTrieDev ut{};                     // valid once built for this batch
 };
 
 // Amplitudes relative to the largest |psi|: a_i = exp(L_i - c), c = max Re L.
@@ -117,6 +145,7 @@ struct Plan {
     int chunks = 1;            // group (or sample) chunks per row
     int per_chunk = 0;         // groups (or samples) per chunk
     bool sig_filter = true;
+    int rows_per_block = 1;    // rows owned by one workgroup
 };
 
 // Error bits latched in a device word, read by eloc_check / synchronising calls.
@@ -170,6 +199,21 @@ hipError_t launch_split_pairs(const uint64_t* keys, const uint32_t* vals, int64_
 hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n,
                                 const int32_t* i_idx, const int32_t* j_idx, double2* h_out,
                                 uint32_t* err, hipStream_t st);
+
+struct SortScratch {
+    uint64_t* key;
+    uint32_t* val;
+    uint64_t* key2;
+    uint32_t* val2;
+    uint32_t* hist;
+    int64_t* hist_off;
+    int64_t* scan;
+};
+hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, const SortScratch& S,
+                            uint64_t* sorted, int32_t* perm, hipStream_t st);
+hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
+                             hipStream_t st);
+int rows_per_block(int variant);
 
 int64_t energy_scratch_len();
 int64_t amp_scratch_len();

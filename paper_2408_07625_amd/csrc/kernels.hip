@@ -1,22 +1,10 @@
-// HIP kernels for gfx950 (CDNA4, wave64) of the sample-aware local energy.
-//
-// Work decomposition of the pair kernels: one lane per sample row x (the
-// row's key, its linear hash and its accumulator stay in registers), the
-// grid's y dimension splits the loop over the unique XY set (LoopOverTerms)
-// or over U (LoopOverBatch) into chunks so that a launch has enough waves to
-// cover the chip.  Each (row, chunk) writes one partial sum; a second kernel
-// adds the chunks in a fixed order, so results are bitwise reproducible and
-// no floating-point atomics are used.
-//
-// LoopOverTerms (Alg. 2A): the chunk's XY masks are wave-uniform, so the
-// group record, the group hash and the group's term run are scalar loads;
-// x' = x ^ XY is looked up in the sample table.  LoopOverBatch (Alg. 2B): the
-// chunk's sample keys are wave-uniform; x ^ x' is rejected when its popcount
-// exceeds the largest XY popcount, otherwise looked up in the XY table.
-//
-// MatrixElement (supplementary algorithm, Eq. pauli_melem): for a term with
-// mask YZ the factor is i^(|XY & YZ|) (-1)^(|ket & YZ|), so a term adds +-h to
-// the real or the imaginary part; only additions are rounded.
+// HIP kernels for gfx950 (CDNA4, wave64) around the pair kernels of
+// pairs.hip: sample preparation (linear hash, membership table, duplicate
+// and bit checks), amplitudes relative to the largest |psi|, per-row
+// combination of chunk partials, the weighted energy / variance reductions,
+// an exclusive scan, a stable LSD radix sort, and the parallel construction
+// of the prefix trees used by LoopOverTrie.
+#include "device.h"
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -28,331 +16,6 @@ namespace eloc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint64_t kEven = 0x5555555555555555ull;
-constexpr uint64_t kOdd = 0xAAAAAAAAAAAAAAAAull;
-
-__device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }
-
-template <int W>
-__device__ __forceinline__ bool sig_ok(const uint64_t* sig, const uint64_t* k) {
-    int pa = 0, pb = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        pa += popc64(k[w] & kEven);
-        pb += popc64(k[w] & kOdd);
-    }
-    return (sig[2 * pa + (pb >> 6)] >> (pb & 63)) & 1ull;
-}
-
-// ---------------------------------------------------------------------------
-// Compensated FP32 arithmetic (error-free transforms).
-//   TwoSum: Knuth, TAOCP vol. 2;  TwoProduct via fused multiply-add;
-//   accumulation as in Ogita, Rump, Oishi, "Accurate sum and dot product",
-//   SIAM J. Sci. Comput. 26(6), 2005 (Sum2 / Dot2): the running sum s and
-// the running sum c of all rounding errors are kept separately.
-// ---------------------------------------------------------------------------
-struct F2 {      // value = s + c
-    float s, c;
-};
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-__device__ __forceinline__ void acc_add(F2& acc, float hi, float lo) {
-    float s, e;
-    two_sum(acc.s, hi, s, e);
-    acc.s = s;
-    acc.c += e + lo;
-}
-
-// (x.s + x.c) * (y.s + y.c) as hi + lo, exact in the leading product.
-__device__ __forceinline__ void df_mul(F2 x, F2 y, float& hi, float& lo) {
-    hi = x.s * y.s;
-    lo = fmaf(x.s, y.s, -hi);
-    lo = fmaf(x.s, y.c, lo);
-    lo = fmaf(x.c, y.s, lo);
-}
-
-struct AccD {
-    double re = 0.0, im = 0.0;
-};
-struct AccF {
-    F2 re{0.f, 0.f}, im{0.f, 0.f};
-};
-
-// ---------------------------------------------------------------------------
-// MatrixElement over a run of terms.  `xy` is the group's mask, `ket` the key
-// the phase is evaluated on.
-// ---------------------------------------------------------------------------
-template <int W>
-__device__ __forceinline__ void melem_f64(const TermRec<W>* __restrict__ terms, int b, int e,
-                                          const uint64_t* xy, const uint64_t* ket, double& hr,
-                                          double& hi) {
-    hr = 0.0;
-    hi = 0.0;
-    for (int t = b; t < e; ++t) {
-        const TermRec<W> tr = terms[t];
-        int ny = 0, pc = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            ny += popc64(xy[w] & tr.yz[w]);
-            pc += popc64(ket[w] & tr.yz[w]);
-        }
-        const double v = (((ny >> 1) ^ pc) & 1) ? -tr.h : tr.h;
-        if (ny & 1)
-            hi += v;
-        else
-            hr += v;
-    }
-}
-
-template <int W>
-__device__ __forceinline__ void melem_f32(const TermRecF<W>* __restrict__ terms, int b, int e,
-                                          const uint64_t* xy, const uint64_t* ket, F2& hr,
-                                          F2& hi) {
-    hr = F2{0.f, 0.f};
-    hi = F2{0.f, 0.f};
-    for (int t = b; t < e; ++t) {
-        const TermRecF<W> tr = terms[t];
-        int ny = 0, pc = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            ny += popc64(xy[w] & tr.yz[w]);
-            pc += popc64(ket[w] & tr.yz[w]);
-        }
-        const bool neg = ((ny >> 1) ^ pc) & 1;
-        const float vh = neg ? -tr.h_hi : tr.h_hi;
-        const float vl = neg ? -tr.h_lo : tr.h_lo;
-        if (ny & 1)
-            acc_add(hi, vh, vl);
-        else
-            acc_add(hr, vh, vl);
-    }
-}
-
-// acc += H * v (complex).
-__device__ __forceinline__ void mac(AccD& acc, double hr, double hi, double2 v) {
-    acc.re = fma(hr, v.x, fma(-hi, v.y, acc.re));
-    acc.im = fma(hr, v.y, fma(hi, v.x, acc.im));
-}
-
-__device__ __forceinline__ void mac(AccF& acc, F2 hr, F2 hi, float4 v) {
-    const F2 vr{v.x, v.y}, vi{v.z, v.w};
-    float p, q;
-    df_mul(hr, vr, p, q);
-    acc_add(acc.re, p, q);
-    df_mul(hi, vi, p, q);
-    acc_add(acc.re, -p, -q);
-    df_mul(hr, vi, p, q);
-    acc_add(acc.im, p, q);
-    df_mul(hi, vr, p, q);
-    acc_add(acc.im, p, q);
-}
-
-// ---------------------------------------------------------------------------
-// Kernel arguments shared by the pair kernels.
-// ---------------------------------------------------------------------------
-struct PairArgs {
-    const void* groups;
-    const uint64_t* ghash;
-    const void* terms;
-    const void* terms_f;
-    const uint64_t* gkeys;
-    Table gtable;
-    int n_groups;
-    int maxpop;
-    const uint64_t* keys;
-    const uint64_t* khash;
-    Table ktable;
-    const uint64_t* sig;
-    int sig_filter;
-    int64_t M;
-    int per_chunk;
-};
-
-PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
-    PairArgs a;
-    a.groups = H.groups;
-    a.ghash = H.group_hash;
-    a.terms = H.terms;
-    a.terms_f = H.terms_f;
-    a.gkeys = H.group_keys;
-    a.gtable = H.group_table;
-    a.n_groups = static_cast<int>(H.n_groups);
-    a.maxpop = H.maxpop;
-    a.keys = S.keys;
-    a.khash = S.hash;
-    a.ktable = S.table;
-    a.sig = S.sig;
-    a.sig_filter = P.sig_filter ? 1 : 0;
-    a.M = S.n;
-    a.per_chunk = P.per_chunk;
-    return a;
-}
-
-// Visit every coupled pair (row, j) of the row owned by this lane inside the
-// chunk; on_hit(g, xy_of_group, xprime, j, term_begin, term_end).
-template <int W, class OnHit>
-__device__ __forceinline__ void visit_terms(const PairArgs& A, const uint64_t* __restrict__ sig_lds,
-                                            bool live, const uint64_t (&x)[W], uint64_t hx,
-                                            int chunk, OnHit&& on_hit) {
-    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
-    const uint64_t* __restrict__ ghash = A.ghash;
-    const int g0 = chunk * A.per_chunk;
-    const int g1 = min(A.n_groups, g0 + A.per_chunk);
-    for (int g = g0; g < g1; ++g) {
-        const GroupRec<W> gr = groups[g];
-        const uint64_t gh = ghash[g];
-        uint64_t xp[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) xp[w] = x[w] ^ gr.xy[w];
-        bool cand = live;
-        if (A.sig_filter) cand = cand && sig_ok<W>(sig_lds, xp);
-        if (cand) {
-            const int j = table_find<W>(A.ktable, A.keys, hx ^ gh, xp);
-            if (j >= 0) on_hit(g, gr.xy, xp, j, gr.begin, gr.end);
-        }
-    }
-}
-
-template <int W, class OnHit>
-__device__ __forceinline__ void visit_batch(const PairArgs& A, bool live, const uint64_t (&x)[W],
-                                            uint64_t hx, int chunk, OnHit&& on_hit) {
-    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
-    const uint64_t* __restrict__ keys = A.keys;
-    const uint64_t* __restrict__ khash = A.khash;
-    const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
-    const int64_t j1 = min(A.M, j0 + A.per_chunk);
-    for (int64_t j = j0; j < j1; ++j) {
-        uint64_t xj[W], m[W];
-        int pc = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            xj[w] = keys[j * W + w];
-            m[w] = x[w] ^ xj[w];
-            pc += popc64(m[w]);
-        }
-        if (live && pc <= A.maxpop) {
-            const int g = table_find<W>(A.gtable, A.gkeys, hx ^ khash[j], m);
-            if (g >= 0) {
-                const GroupRec<W> gr = groups[g];
-                on_hit(g, gr.xy, xj, static_cast<int>(j), gr.begin, gr.end);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Fused pair kernel: FindCoupledPairs + MatrixElement + row accumulation.
-//   forward (ADJ = false): acc_x = sum_{x' coupled} H_xx' a_x'   (ket x')
-//   adjoint (ADJ = true):  acc_y = sum_{x coupled}  H_xy v_x     (ket y)
-// `vec` is a (forward) or v = w / a (adjoint).
-// ---------------------------------------------------------------------------
-template <int W, int VARIANT, int PREC, bool ADJ>
-__global__ __launch_bounds__(kBlock) void k_pairs(PairArgs A, const double2* __restrict__ vec,
-                                                  const float4* __restrict__ vecf,
-                                                  void* __restrict__ partial) {
-    __shared__ uint64_t sig_lds[kSigWords];
-    if (VARIANT == 0) {
-        for (int t = threadIdx.x; t < kSigWords; t += kBlock) sig_lds[t] = A.sig[t];
-        __syncthreads();
-    }
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const bool live = row < A.M;
-    const int chunk = blockIdx.y;
-    uint64_t x[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = live ? A.keys[row * W + w] : 0ull;
-    const uint64_t hx = live ? A.khash[row] : 0ull;
-
-    if (PREC == 0) {
-        const TermRec<W>* __restrict__ terms = static_cast<const TermRec<W>*>(A.terms);
-        AccD acc;
-        auto hit = [&](int, const uint64_t* gxy, const uint64_t* xp, int j, int b, int e) {
-            double hr, hi;
-            melem_f64<W>(terms, b, e, gxy, ADJ ? x : xp, hr, hi);
-            mac(acc, hr, hi, vec[j]);
-        };
-        if (VARIANT == 0)
-            visit_terms<W>(A, sig_lds, live, x, hx, chunk, hit);
-        else
-            visit_batch<W>(A, live, x, hx, chunk, hit);
-        if (live) static_cast<double2*>(partial)[chunk * A.M + row] = make_double2(acc.re, acc.im);
-    } else {
-        const TermRecF<W>* __restrict__ terms = static_cast<const TermRecF<W>*>(A.terms_f);
-        AccF acc;
-        auto hit = [&](int, const uint64_t* gxy, const uint64_t* xp, int j, int b, int e) {
-            F2 hr, hi;
-            melem_f32<W>(terms, b, e, gxy, ADJ ? x : xp, hr, hi);
-            mac(acc, hr, hi, vecf[j]);
-        };
-        if (VARIANT == 0)
-            visit_terms<W>(A, sig_lds, live, x, hx, chunk, hit);
-        else
-            visit_batch<W>(A, live, x, hx, chunk, hit);
-        if (live)
-            static_cast<float4*>(partial)[chunk * A.M + row] =
-                make_float4(acc.re.s, acc.re.c, acc.im.s, acc.im.c);
-    }
-}
-
-// Count coupled pairs per (row, chunk): counts[row * chunks + chunk].
-template <int W, int VARIANT>
-__global__ __launch_bounds__(kBlock) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
-    __shared__ uint64_t sig_lds[kSigWords];
-    if (VARIANT == 0) {
-        for (int t = threadIdx.x; t < kSigWords; t += kBlock) sig_lds[t] = A.sig[t];
-        __syncthreads();
-    }
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const bool live = row < A.M;
-    const int chunk = blockIdx.y;
-    uint64_t x[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = live ? A.keys[row * W + w] : 0ull;
-    const uint64_t hx = live ? A.khash[row] : 0ull;
-    int n = 0;
-    auto hit = [&](int, const uint64_t*, const uint64_t*, int, int, int) { ++n; };
-    if (VARIANT == 0)
-        visit_terms<W>(A, sig_lds, live, x, hx, chunk, hit);
-    else
-        visit_batch<W>(A, live, x, hx, chunk, hit);
-    if (live) counts[row * chunks + chunk] = n;
-}
-
-// Write the pairs of (row, chunk) at offsets[row * chunks + chunk]:
-// key = (row << jbits) | j, value = group id.
-template <int W, int VARIANT>
-__global__ __launch_bounds__(kBlock) void k_fill(PairArgs A, int chunks, int jbits,
-                                                 const int64_t* __restrict__ offsets,
-                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-    __shared__ uint64_t sig_lds[kSigWords];
-    if (VARIANT == 0) {
-        for (int t = threadIdx.x; t < kSigWords; t += kBlock) sig_lds[t] = A.sig[t];
-        __syncthreads();
-    }
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const bool live = row < A.M;
-    const int chunk = blockIdx.y;
-    uint64_t x[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = live ? A.keys[row * W + w] : 0ull;
-    const uint64_t hx = live ? A.khash[row] : 0ull;
-    int64_t pos = live ? offsets[row * chunks + chunk] : 0;
-    auto hit = [&](int g, const uint64_t*, const uint64_t*, int j, int, int) {
-        pkey[pos] = (static_cast<uint64_t>(row) << jbits) | static_cast<uint64_t>(j);
-        pval[pos] = static_cast<uint32_t>(g);
-        ++pos;
-    };
-    if (VARIANT == 0)
-        visit_terms<W>(A, sig_lds, live, x, hx, chunk, hit);
-    else
-        visit_batch<W>(A, live, x, hx, chunk, hit);
-}
-
 // ---------------------------------------------------------------------------
 // Sample preparation.
 // ---------------------------------------------------------------------------
@@ -888,56 +551,49 @@ __global__ __launch_bounds__(kBlock) void k_split_pairs(const uint64_t* __restri
     pg[t] = static_cast<int32_t>(vals[t]);
 }
 
-// MatrixElement for given sample pairs (ket x_j).
+// ---------------------------------------------------------------------------
+// Prefix trees: sorted keys with a permutation, then one thread per internal
+// node of each segment's radix tree (segment s = leaves [s * per, ...)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_iota(uint32_t* __restrict__ v, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) v[i] = static_cast<uint32_t>(i);
+}
+
+// out[i] = keys[(perm ? perm[i] : i) * W + w]
+__global__ __launch_bounds__(kBlock) void k_gather_word(const uint64_t* __restrict__ keys, int W, int w,
+                                                        const uint32_t* __restrict__ perm, int64_t n,
+                                                        uint64_t* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = perm ? static_cast<int64_t>(perm[i]) : i;
+    out[i] = keys[src * W + w];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_keys(const uint64_t* __restrict__ keys, int W,
+                                                        const uint32_t* __restrict__ perm, int64_t n,
+                                                        uint64_t* __restrict__ out, int32_t* __restrict__ perm_out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = perm[i];
+    for (int w = 0; w < W; ++w) out[i * W + w] = keys[src * W + w];
+    perm_out[i] = static_cast<int32_t>(src);
+}
+
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_pair_elements(PairArgs A, int64_t n, const int32_t* __restrict__ pi,
-                                                          const int32_t* __restrict__ pj,
-                                                          double2* __restrict__ out, uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(kBlock) void k_trie_build(const uint64_t* __restrict__ K, int64_t n_total, int64_t per,
+                                                       int64_t segs, TNode* __restrict__ nodes) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int64_t i = pi[t], j = pj[t];
-    if (i < 0 || j < 0 || i >= A.M || j >= A.M) {
-        atomicOr(err, static_cast<uint32_t>(kErrIndex));
-        out[t] = make_double2(0.0, 0.0);
-        return;
-    }
-    uint64_t xi[W], xj[W], m[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        xi[w] = A.keys[i * W + w];
-        xj[w] = A.keys[j * W + w];
-        m[w] = xi[w] ^ xj[w];
-    }
-    const int g = table_find<W>(A.gtable, A.gkeys, A.khash[i] ^ A.khash[j], m);
-    double hr = 0.0, hi = 0.0;
-    if (g >= 0) {
-        const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
-        melem_f64<W>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.end, gr.xy, xj, hr, hi);
-    }
-    out[t] = make_double2(hr, hi);
+    const int64_t s = t / (per - 1);
+    const int64_t i = t % (per - 1);
+    if (s >= segs) return;
+    const int64_t base = s * per;
+    const int64_t n = min(per, n_total - base);
+    if (i >= n - 1) return;
+    nodes[s * (per - 1) + i] = trie_node<W>(K + base * W, n, i);
 }
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
-
-template <int W, int VARIANT, int PREC, bool ADJ>
-hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const double2* vec, const float4* vecf,
-                          void* partial, hipStream_t st) {
-    dim3 grid(blocks_for(A.M), static_cast<unsigned>(P.chunks));
-    hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ>), grid, dim3(kBlock), 0, st, A, vec, vecf, partial);
-    return hipGetLastError();
-}
-
-template <bool ADJ>
-hipError_t dispatch_pairs(int W, int variant, int precision, const PairArgs& A, const Plan& P,
-                          const double2* vec, const float4* vecf, void* partial, hipStream_t st) {
-#define ELOC_CASE(w, v, p)                                                               \
-    if (W == w && variant == v && precision == p)                                       \
-        return launch_pairs_t<w, v, p, ADJ>(A, P, vec, vecf, partial, st);
-    ELOC_CASE(1, 0, 0) ELOC_CASE(1, 0, 1) ELOC_CASE(1, 1, 0) ELOC_CASE(1, 1, 1)
-    ELOC_CASE(2, 0, 0) ELOC_CASE(2, 0, 1) ELOC_CASE(2, 1, 0) ELOC_CASE(2, 1, 1)
-#undef ELOC_CASE
-    return hipErrorInvalidValue;
-}
 
 }  // namespace
 
@@ -983,13 +639,6 @@ hipError_t launch_adj_vec(const double2* a, const double2* b, const double* weig
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& H, const SampleDev& S,
-                        const Plan& P, const double2* vec, const float4* vecf, void* partial, hipStream_t st) {
-    const PairArgs A = make_args(H, S, P);
-    if (adjoint) return dispatch_pairs<true>(H.W, variant, precision, A, P, vec, vecf, partial, st);
-    return dispatch_pairs<false>(H.W, variant, precision, A, P, vec, vecf, partial, st);
-}
-
 hipError_t launch_finish(int precision, int64_t n, const Plan& P, const void* partial, const double2* b,
                          const float4* bf, double2* out, hipStream_t st) {
     if (precision == 0)
@@ -1027,32 +676,6 @@ hipError_t launch_energy(const double2* eloc, const double2* logpsi, const doubl
 
 int64_t energy_scratch_len() { return 3 * kRedBlocks + 4; }
 int64_t amp_scratch_len() { return 2 * kRedBlocks; }
-
-hipError_t launch_pairs_count(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int32_t* counts,
-                              hipStream_t st) {
-    const PairArgs A = make_args(H, S, P);
-    dim3 grid(blocks_for(S.n), static_cast<unsigned>(P.chunks));
-    if (H.W == 1 && variant == 0) hipLaunchKernelGGL((k_count<1, 0>), grid, dim3(kBlock), 0, st, A, P.chunks, counts);
-    else if (H.W == 1) hipLaunchKernelGGL((k_count<1, 1>), grid, dim3(kBlock), 0, st, A, P.chunks, counts);
-    else if (variant == 0) hipLaunchKernelGGL((k_count<2, 0>), grid, dim3(kBlock), 0, st, A, P.chunks, counts);
-    else hipLaunchKernelGGL((k_count<2, 1>), grid, dim3(kBlock), 0, st, A, P.chunks, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_pairs_fill(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int jbits,
-                             const int64_t* offsets, uint64_t* pkey, uint32_t* pval, hipStream_t st) {
-    const PairArgs A = make_args(H, S, P);
-    dim3 grid(blocks_for(S.n), static_cast<unsigned>(P.chunks));
-    if (H.W == 1 && variant == 0)
-        hipLaunchKernelGGL((k_fill<1, 0>), grid, dim3(kBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
-    else if (H.W == 1)
-        hipLaunchKernelGGL((k_fill<1, 1>), grid, dim3(kBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
-    else if (variant == 0)
-        hipLaunchKernelGGL((k_fill<2, 0>), grid, dim3(kBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
-    else
-        hipLaunchKernelGGL((k_fill<2, 1>), grid, dim3(kBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
-    return hipGetLastError();
-}
 
 int64_t scan_scratch_len(int64_t n) {
     int64_t total = 0;
@@ -1103,14 +726,47 @@ hipError_t launch_split_pairs(const uint64_t* keys, const uint32_t* vals, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pi,
-                                const int32_t* pj, double2* out, uint32_t* err, hipStream_t st) {
-    Plan P;
-    const PairArgs A = make_args(H, S, P);
-    if (H.W == 1)
-        hipLaunchKernelGGL(k_pair_elements<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, A, n, pi, pj, out, err);
+
+hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
+                             hipStream_t st) {
+    if (per < 2 || n_total < 2) return hipSuccess;
+    const int64_t segs = (n_total + per - 1) / per;
+    const int64_t threads = segs * (per - 1);
+    if (W == 1)
+        hipLaunchKernelGGL(k_trie_build<1>, dim3(blocks_for(threads)), dim3(kBlock), 0, st, keys, n_total, per, segs,
+                           nodes);
     else
-        hipLaunchKernelGGL(k_pair_elements<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, A, n, pi, pj, out, err);
+        hipLaunchKernelGGL(k_trie_build<2>, dim3(blocks_for(threads)), dim3(kBlock), 0, st, keys, n_total, per, segs,
+                           nodes);
+    return hipGetLastError();
+}
+
+// Sort keys[n][W] ascending (word W-1 most significant; only the low n_bits
+// bits can be set) into sorted[n][W] with perm[i] = source row.
+hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, const SortScratch& S,
+                            uint64_t* sorted, int32_t* perm, hipStream_t st) {
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(kBlock), 0, st, S.val, n);
+    hipLaunchKernelGGL(k_gather_word, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, W, 0,
+                       static_cast<const uint32_t*>(nullptr), n, S.key);
+    int alt = 0;
+    hipError_t e = launch_radix_sort_pairs(S.key, S.val, S.key2, S.val2, n, W == 1 ? n_bits : 64, S.hist, S.hist_off,
+                                           S.scan, &alt, st);
+    if (e != hipSuccess) return e;
+    uint32_t* pv = alt ? S.val2 : S.val;
+    if (W == 2) {
+        uint32_t* other = alt ? S.val : S.val2;
+        uint64_t* k2 = alt ? S.key : S.key2;
+        uint64_t* k3 = alt ? S.key2 : S.key;
+        (void)k3;
+        hipLaunchKernelGGL(k_gather_word, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, W, 1, pv, n, k2);
+        int alt2 = 0;
+        // second pass: sort by the high word, carrying the permutation (stable)
+        e = launch_radix_sort_pairs(k2, pv, alt ? S.key2 : S.key, other, n, n_bits - 64, S.hist, S.hist_off, S.scan,
+                                    &alt2, st);
+        if (e != hipSuccess) return e;
+        pv = alt2 ? other : pv;
+    }
+    hipLaunchKernelGGL(k_gather_keys, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, W, pv, n, sorted, perm);
     return hipGetLastError();
 }
 

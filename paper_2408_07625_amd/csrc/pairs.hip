@@ -1,0 +1,635 @@
+// Pair kernels for gfx950: FindCoupledPairs (three variants) fused with
+// MatrixElement and the ratio accumulation, plus the pair count / emission
+// kernels that share the same enumeration.
+//
+// LoopOverTerms (Alg. 2A) and LoopOverBatch (Alg. 2B): a workgroup is one
+// wave that owns kRows sample rows.  The rows' keys and linear hashes are
+// wave-uniform (scalar registers); the lanes sweep the inner dimension - 64
+// XY groups (TERMS) or 64 samples x' (BATCH) per step - so every lane has
+// kRows independent table probes in flight.  Coupled pairs found in a step
+// are compacted into an LDS queue with ballot + mbcnt.  Short term runs are
+// evaluated 64 pairs at a time, one pair per lane; runs longer than kLongRun
+// (the diagonal group, single excitations) are evaluated by the whole wave,
+// 64 terms per step.  Each lane keeps one accumulator per row in registers;
+// the per-row totals are formed at the end by a fixed-order butterfly over
+// the lanes, so results are bitwise reproducible without atomics.
+//
+// LoopOverTrie (Alg. 2C, trees of Alg. 3): one lane per row walks the
+// radix tree of U together with the radix tree of one chunk of the XY set
+// (trie.h) and evaluates each pair it reaches.
+//
+// The grid's y dimension splits the inner loop into chunks; every
+// (row, chunk) writes one partial sum that a second kernel adds in chunk
+// order.
+#include "device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eloc {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRows = 8;                 // rows per wave (TERMS / BATCH)
+constexpr int kLongRun = 16;             // longer term runs are split over the wave
+constexpr int kQCap = kWave + kRows * kWave;
+constexpr int kTrieBlock = 256;
+
+struct PairArgs {
+    const void* groups;
+    const uint64_t* ghash;
+    const void* terms;
+    const void* terms_f;
+    const uint64_t* gkeys;
+    Table gtable;
+    int n_groups;
+    int maxpop;
+    const uint64_t* keys;
+    const uint64_t* khash;
+    Table ktable;
+    const uint64_t* sig;
+    int sig_filter;
+    int64_t M;
+    int per_chunk;
+    // prefix trees
+    const uint64_t* u_keys;
+    const int32_t* u_perm;
+    const TNode* u_nodes;
+    const uint64_t* xy_keys;
+    const int32_t* xy_gid;
+    const TNode* xy_nodes;
+    int xy_chunk;
+};
+
+PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
+    PairArgs a;
+    a.groups = H.groups;
+    a.ghash = H.group_hash;
+    a.terms = H.terms;
+    a.terms_f = H.terms_f;
+    a.gkeys = H.group_keys;
+    a.gtable = H.group_table;
+    a.n_groups = static_cast<int>(H.n_groups);
+    a.maxpop = H.maxpop;
+    a.keys = S.keys;
+    a.khash = S.hash;
+    a.ktable = S.table;
+    a.sig = S.sig;
+    a.sig_filter = P.sig_filter ? 1 : 0;
+    a.M = S.n;
+    a.per_chunk = P.per_chunk;
+    a.u_keys = S.ut.keys;
+    a.u_perm = S.ut.perm;
+    a.u_nodes = S.ut.nodes;
+    a.xy_keys = H.xyt.keys;
+    a.xy_gid = H.xyt.gid;
+    a.xy_nodes = H.xyt.nodes;
+    a.xy_chunk = H.xyt.chunk;
+    return a;
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return static_cast<int>(__builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
+}
+
+// Continue a linear probe whose first slot value v (at slot s) is loaded.
+template <int W>
+__device__ __forceinline__ int resolve(const Table& T, const uint64_t* __restrict__ keys, uint32_t v, uint32_t s,
+                                       uint32_t fp, const uint64_t* key) {
+    while (v != 0u) {
+        if ((v >> T.ibits) == fp) {
+            const int j = static_cast<int>(v & T.imask) - 1;
+            if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
+        }
+        s = (s + 1u) & T.mask;
+        v = T.slots[s];
+    }
+    return -1;
+}
+
+template <int W>
+struct Rows {
+    int n;
+    int64_t row0;
+    uint64_t x[kRows][W];
+    uint64_t hx[kRows];
+};
+
+template <int W>
+__device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W>& R, uint64_t* rowkey) {
+    R.row0 = static_cast<int64_t>(blockIdx.x) * kRows;
+    R.n = static_cast<int>(min(static_cast<int64_t>(kRows), A.M - R.row0));
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const int64_t row = min(R.row0 + r, A.M - 1);
+#pragma unroll
+        for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
+        R.hx[r] = A.khash[row];
+    }
+    if (threadIdx.x < kRows * W) {
+        const int64_t row = min(R.row0 + threadIdx.x / W, A.M - 1);
+        rowkey[threadIdx.x] = A.keys[row * W + threadIdx.x % W];
+    }
+}
+
+// LoopOverTerms: lanes over 64 groups of the chunk per step.
+template <int W, class Sink>
+__device__ __forceinline__ void find_terms(const PairArgs& A, const uint64_t* __restrict__ sig, const Rows<W>& R,
+                                           int chunk, Sink& sink) {
+    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const int g0 = chunk * A.per_chunk;
+    const int g1 = min(A.n_groups, g0 + A.per_chunk);
+    for (int base = g0; base < g1; base += kWave) {
+        const int g = base + static_cast<int>(threadIdx.x);
+        const bool valid = g < g1;
+        const int gg = valid ? g : g0;
+        const GroupRec<W> gr = groups[gg];
+        const uint64_t gh = A.ghash[gg];
+        uint64_t xp[kRows][W];
+        uint32_t v[kRows], s[kRows], fp[kRows];
+        bool c[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) xp[r][w] = R.x[r][w] ^ gr.xy[w];
+            c[r] = valid && r < R.n;
+            if (A.sig_filter) c[r] = c[r] && sig_ok<W>(sig, xp[r]);
+            const uint64_t h = R.hx[r] ^ gh;
+            s[r] = static_cast<uint32_t>(h) & A.ktable.mask;
+            fp[r] = static_cast<uint32_t>(h >> A.ktable.fpshift);
+            v[r] = c[r] ? A.ktable.slots[s[r]] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int j = c[r] ? resolve<W>(A.ktable, A.keys, v[r], s[r], fp[r], xp[r]) : -1;
+            sink.hit(r, j >= 0, g, j, gr.end - gr.begin);
+        }
+        sink.flush();
+    }
+}
+
+// LoopOverBatch: lanes over 64 samples x' of the chunk per step.
+template <int W, class Sink>
+__device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
+    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
+    const int64_t j1 = min(A.M, j0 + A.per_chunk);
+    for (int64_t base = j0; base < j1; base += kWave) {
+        const int64_t j = base + threadIdx.x;
+        const bool valid = j < j1;
+        const int64_t jj = valid ? j : j0;
+        uint64_t xj[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
+        const uint64_t hj = A.khash[jj];
+        uint64_t m[kRows][W];
+        uint32_t v[kRows], s[kRows], fp[kRows];
+        bool c[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            int pc = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                m[r][w] = R.x[r][w] ^ xj[w];
+                pc += popc64(m[r][w]);
+            }
+            c[r] = valid && r < R.n && pc <= A.maxpop;
+            const uint64_t h = R.hx[r] ^ hj;
+            s[r] = static_cast<uint32_t>(h) & A.gtable.mask;
+            fp[r] = static_cast<uint32_t>(h >> A.gtable.fpshift);
+            v[r] = c[r] ? A.gtable.slots[s[r]] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int g = c[r] ? resolve<W>(A.gtable, A.gkeys, v[r], s[r], fp[r], m[r]) : -1;
+            int run = 0;
+            if (g >= 0) {
+                const GroupRec<W>& gr = groups[g];
+                run = gr.end - gr.begin;
+            }
+            sink.hit(r, g >= 0, g, static_cast<int>(j), run);
+        }
+        sink.flush();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sinks: what happens to the pairs a wave finds.
+// ---------------------------------------------------------------------------
+template <int W, int PREC, bool ADJ>
+struct AccSink {
+    using P = Prec<PREC>;
+    using Acc = typename P::Acc;
+    using Vec = typename P::Vec;
+    using Term = typename P::template Term<W>;
+
+    const GroupRec<W>* groups;
+    const Term* terms;
+    const Vec* vec;
+    uint2* q;
+    uint2* lq;
+    const uint64_t* rowkey;
+    int qn = 0;
+    int ln = 0;
+    Acc acc[kRows];
+
+    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int run) {
+        const bool lng = h && run > kLongRun;
+        const bool sht = h && !lng;
+        const uint64_t ms = __ballot(sht);
+        const uint64_t ml = __ballot(lng);
+        const uint2 e = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
+                                   static_cast<uint32_t>(j));
+        if (sht) q[qn + lanes_below(ms)] = e;
+        if (lng) q[kQCap + ln + lanes_below(ml)] = e;
+        qn += __popcll(ms);
+        ln += __popcll(ml);
+    }
+
+    // acc[r] += v with r a lane value: every row adds v or an exact zero,
+    // which keeps the accumulators in registers (no indexed array).
+    __device__ __forceinline__ void add_row(int r, const Acc& v) {
+#pragma unroll
+        for (int rr = 0; rr < kRows; ++rr) acc_plus(acc[rr], masked(v, rr == r));
+    }
+
+    // one pair per lane, entries [o, o + n) of the short queue
+    __device__ __forceinline__ void drain_short(int o, int n) {
+        if (static_cast<int>(threadIdx.x) < n) {
+            const uint2 e = q[o + threadIdx.x];
+            const int r = static_cast<int>(e.x & 15u);
+            const int g = static_cast<int>(e.x >> 4);
+            const GroupRec<W> gr = groups[g];
+            uint64_t ket[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
+            typename P::H hr, hi;
+            melem<W>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
+            Acc v;
+            P::madd(v, hr, hi, vec[e.y]);
+            add_row(r, v);
+        }
+    }
+
+    // the whole wave on each long run, 64 terms per step
+    __device__ __forceinline__ void drain_long(int n) {
+        for (int k = 0; k < n; ++k) {
+            const uint32_t ex = __builtin_amdgcn_readfirstlane(q[kQCap + k].x);
+            const uint32_t ey = __builtin_amdgcn_readfirstlane(q[kQCap + k].y);
+            const int r = static_cast<int>(ex & 15u);
+            const GroupRec<W> gr = groups[ex >> 4];
+            uint64_t ket[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
+            typename P::H hr, hi;
+            melem<W>(terms, gr.begin, gr.mid, gr.end, static_cast<int>(threadIdx.x), kWave, ket, hr, hi);
+            Acc v;
+            P::madd(v, hr, hi, vec[ey]);
+            add_row(r, v);
+        }
+    }
+
+    __device__ __forceinline__ void flush() {
+        if (qn >= kWave) {
+            __syncthreads();
+            int o = 0;
+            for (; qn - o >= kWave; o += kWave) drain_short(o, kWave);
+            __syncthreads();
+            const int rest = qn - o;
+            uint2 t = make_uint2(0u, 0u);
+            if (static_cast<int>(threadIdx.x) < rest) t = q[o + threadIdx.x];
+            __syncthreads();
+            if (static_cast<int>(threadIdx.x) < rest) q[threadIdx.x] = t;
+            qn = rest;
+        }
+        if (ln >= kWave) {
+            __syncthreads();
+            drain_long(ln);
+            __syncthreads();
+            ln = 0;
+        }
+    }
+
+    __device__ __forceinline__ void finish() {
+        __syncthreads();
+        drain_short(0, qn);
+        drain_long(ln);
+        qn = 0;
+        ln = 0;
+    }
+};
+
+struct CountSink {
+    int cnt[kRows];
+    __device__ __forceinline__ void hit(int r, bool h, int, int, int) { cnt[r] += __popcll(__ballot(h)); }
+    __device__ __forceinline__ void flush() {}
+};
+
+struct FillSink {
+    int64_t pos[kRows];
+    int64_t row0;
+    int jbits;
+    uint64_t* pkey;
+    uint32_t* pval;
+    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
+        const uint64_t m = __ballot(h);
+        if (h) {
+            const int64_t p = pos[r] + lanes_below(m);
+            pkey[p] = (static_cast<uint64_t>(row0 + r) << jbits) | static_cast<uint64_t>(j);
+            pval[p] = static_cast<uint32_t>(g);
+        }
+        pos[r] += __popcll(m);
+    }
+    __device__ __forceinline__ void flush() {}
+};
+
+template <int W, int VARIANT, class Sink>
+__device__ __forceinline__ void find(const PairArgs& A, const uint64_t* sig, const Rows<W>& R, int chunk,
+                                     Sink& sink) {
+    if (VARIANT == 0)
+        find_terms<W>(A, sig, R, chunk, sink);
+    else
+        find_batch<W>(A, R, chunk, sink);
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward / adjoint kernel (TERMS, BATCH).
+//   forward: acc_x = sum_{x'} H_xx' vec_x'  (ket x', vec = a)
+//   adjoint: acc_y = sum_{x}  H_xy vec_x    (ket y,  vec = w / a)
+// ---------------------------------------------------------------------------
+template <int W, int VARIANT, int PREC, bool ADJ>
+__global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restrict__ vec,
+                                                 void* __restrict__ partial) {
+    __shared__ uint64_t sig[kSigWords];
+    __shared__ uint64_t rowkey[kRows * W];
+    __shared__ uint2 q[2 * kQCap];
+    if (VARIANT == 0)
+        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
+    Rows<W> R;
+    load_rows<W>(A, R, rowkey);
+    __syncthreads();
+    using P = Prec<PREC>;
+    AccSink<W, PREC, ADJ> sink;
+    sink.groups = static_cast<const GroupRec<W>*>(A.groups);
+    sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
+    sink.vec = static_cast<const typename P::Vec*>(vec);
+    sink.q = q;
+    sink.rowkey = rowkey;
+    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+    sink.finish();
+    const int64_t out0 = static_cast<int64_t>(blockIdx.y) * A.M + R.row0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        wave_sum(sink.acc[r]);
+        if (static_cast<int>(threadIdx.x) == r && r < R.n) store_acc(partial, out0 + r, sink.acc[r]);
+    }
+}
+
+template <int W, int VARIANT>
+__global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
+    __shared__ uint64_t sig[kSigWords];
+    __shared__ uint64_t rowkey[kRows * W];
+    if (VARIANT == 0)
+        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
+    Rows<W> R;
+    load_rows<W>(A, R, rowkey);
+    __syncthreads();
+    CountSink sink;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
+    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+        if (static_cast<int>(threadIdx.x) == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
+}
+
+template <int W, int VARIANT>
+__global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
+                                                uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+    __shared__ uint64_t sig[kSigWords];
+    __shared__ uint64_t rowkey[kRows * W];
+    if (VARIANT == 0)
+        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
+    Rows<W> R;
+    load_rows<W>(A, R, rowkey);
+    __syncthreads();
+    FillSink sink;
+    sink.row0 = R.row0;
+    sink.jbits = jbits;
+    sink.pkey = pkey;
+    sink.pval = pval;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+        sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
+    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+}
+
+// ---------------------------------------------------------------------------
+// LoopOverTrie: one lane per row, walk U tree x XY chunk tree.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void trie_views(const PairArgs& A, int chunk, TrieView& U, TrieView& V, int64_t& vbase) {
+    U.keys = A.u_keys;
+    U.nodes = A.u_nodes;
+    U.n = A.M;
+    vbase = static_cast<int64_t>(chunk) * A.xy_chunk;
+    V.keys = A.xy_keys + vbase * W;
+    V.nodes = A.xy_nodes + static_cast<int64_t>(chunk) * (A.xy_chunk - 1);
+    V.n = min(static_cast<int64_t>(A.xy_chunk), static_cast<int64_t>(A.n_groups) - vbase);
+}
+
+template <int W, int PREC, bool ADJ>
+__global__ __launch_bounds__(kTrieBlock) void k_pairs_trie(PairArgs A, const void* __restrict__ vec,
+                                                           void* __restrict__ partial) {
+    using P = Prec<PREC>;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
+    if (row >= A.M) return;
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
+    TrieView U, V;
+    int64_t vbase;
+    trie_views<W>(A, blockIdx.y, U, V, vbase);
+    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const auto* __restrict__ terms =
+        static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
+    const auto* __restrict__ v = static_cast<const typename P::Vec*>(vec);
+    typename P::Acc acc;
+    trie_walk<W>(x, U, V, [&](int32_t ul, int32_t vl) {
+        const GroupRec<W> gr = groups[A.xy_gid[vbase + vl]];
+        const uint64_t* ket = ADJ ? x : (U.keys + static_cast<int64_t>(ul) * W);
+        typename P::H hr, hi;
+        melem<W>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
+        P::madd(acc, hr, hi, v[A.u_perm[ul]]);
+    });
+    store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + row, acc);
+}
+
+template <int W>
+__global__ __launch_bounds__(kTrieBlock) void k_count_trie(PairArgs A, int chunks, int32_t* __restrict__ counts) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
+    if (row >= A.M) return;
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
+    TrieView U, V;
+    int64_t vbase;
+    trie_views<W>(A, blockIdx.y, U, V, vbase);
+    int n = 0;
+    trie_walk<W>(x, U, V, [&](int32_t, int32_t) { ++n; });
+    counts[row * chunks + blockIdx.y] = n;
+}
+
+template <int W>
+__global__ __launch_bounds__(kTrieBlock) void k_fill_trie(PairArgs A, int chunks, int jbits,
+                                                          const int64_t* __restrict__ offsets,
+                                                          uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
+    if (row >= A.M) return;
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
+    TrieView U, V;
+    int64_t vbase;
+    trie_views<W>(A, blockIdx.y, U, V, vbase);
+    int64_t pos = offsets[row * chunks + blockIdx.y];
+    trie_walk<W>(x, U, V, [&](int32_t ul, int32_t vl) {
+        pkey[pos] = (static_cast<uint64_t>(row) << jbits) | static_cast<uint64_t>(A.u_perm[ul]);
+        pval[pos] = static_cast<uint32_t>(A.xy_gid[vbase + vl]);
+        ++pos;
+    });
+}
+
+// MatrixElement for given sample pairs (ket x_j).
+template <int W>
+__global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, const int32_t* __restrict__ pi,
+                                                       const int32_t* __restrict__ pj, double2* __restrict__ out,
+                                                       uint32_t* __restrict__ err) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = pi[t], j = pj[t];
+    if (i < 0 || j < 0 || i >= A.M || j >= A.M) {
+        atomicOr(err, static_cast<uint32_t>(kErrIndex));
+        out[t] = make_double2(0.0, 0.0);
+        return;
+    }
+    uint64_t xj[W], m[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        xj[w] = A.keys[j * W + w];
+        m[w] = A.keys[i * W + w] ^ xj[w];
+    }
+    const uint64_t h = A.khash[i] ^ A.khash[j];
+    const uint32_t s = static_cast<uint32_t>(h) & A.gtable.mask;
+    const int g = resolve<W>(A.gtable, A.gkeys, A.gtable.slots[s], s, static_cast<uint32_t>(h >> A.gtable.fpshift), m);
+    double hr = 0.0, hi = 0.0;
+    if (g >= 0) {
+        const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
+        melem<W>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.mid, gr.end, 0, 1, xj, hr, hi);
+    }
+    out[t] = make_double2(hr, hi);
+}
+
+inline unsigned div_up(int64_t n, int64_t d) { return static_cast<unsigned>((n + d - 1) / d); }
+
+template <int W, int VARIANT, int PREC, bool ADJ>
+hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
+    if (VARIANT == 2) {
+        dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+    } else {
+        dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ>), grid, dim3(kWave), 0, st, A, vec, partial);
+    }
+    return hipGetLastError();
+}
+
+template <int W, int VARIANT, bool ADJ>
+hipError_t dispatch_prec(int precision, const PairArgs& A, const Plan& P, const void* vec, void* partial,
+                         hipStream_t st) {
+    return precision == 0 ? launch_pairs_t<W, VARIANT, 0, ADJ>(A, P, vec, partial, st)
+                          : launch_pairs_t<W, VARIANT, 1, ADJ>(A, P, vec, partial, st);
+}
+
+template <int W, bool ADJ>
+hipError_t dispatch_variant(int variant, int precision, const PairArgs& A, const Plan& P, const void* vec,
+                            void* partial, hipStream_t st) {
+    if (variant == 0) return dispatch_prec<W, 0, ADJ>(precision, A, P, vec, partial, st);
+    if (variant == 1) return dispatch_prec<W, 1, ADJ>(precision, A, P, vec, partial, st);
+    return dispatch_prec<W, 2, ADJ>(precision, A, P, vec, partial, st);
+}
+
+}  // namespace
+
+int rows_per_block(int variant) { return variant == 2 ? kTrieBlock : kRows; }
+
+hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& H, const SampleDev& S, const Plan& P,
+                        const double2* vec, const float4* vecf, void* partial, hipStream_t st) {
+    const PairArgs A = make_args(H, S, P);
+    const void* v = precision == 0 ? static_cast<const void*>(vec) : static_cast<const void*>(vecf);
+    if (H.W == 1)
+        return adjoint ? dispatch_variant<1, true>(variant, precision, A, P, v, partial, st)
+                       : dispatch_variant<1, false>(variant, precision, A, P, v, partial, st);
+    return adjoint ? dispatch_variant<2, true>(variant, precision, A, P, v, partial, st)
+                   : dispatch_variant<2, false>(variant, precision, A, P, v, partial, st);
+}
+
+template <int W>
+static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t* counts, hipStream_t st) {
+    if (variant == 2) {
+        dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL(k_count_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, counts);
+    } else {
+        dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
+        if (variant == 0)
+            hipLaunchKernelGGL((k_count<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+        else
+            hipLaunchKernelGGL((k_count<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+    }
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbits, const int64_t* offsets,
+                         uint64_t* pkey, uint32_t* pval, hipStream_t st) {
+    if (variant == 2) {
+        dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL(k_fill_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+    } else {
+        dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
+        if (variant == 0)
+            hipLaunchKernelGGL((k_fill<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+        else
+            hipLaunchKernelGGL((k_fill<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_count(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int32_t* counts,
+                              hipStream_t st) {
+    const PairArgs A = make_args(H, S, P);
+    return H.W == 1 ? count_w<1>(variant, A, P, counts, st) : count_w<2>(variant, A, P, counts, st);
+}
+
+hipError_t launch_pairs_fill(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int jbits,
+                             const int64_t* offsets, uint64_t* pkey, uint32_t* pval, hipStream_t st) {
+    const PairArgs A = make_args(H, S, P);
+    return H.W == 1 ? fill_w<1>(variant, A, P, jbits, offsets, pkey, pval, st)
+                    : fill_w<2>(variant, A, P, jbits, offsets, pkey, pval, st);
+}
+
+hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pi, const int32_t* pj,
+                                double2* out, uint32_t* err, hipStream_t st) {
+    Plan P;
+    const PairArgs A = make_args(H, S, P);
+    if (H.W == 1)
+        hipLaunchKernelGGL(k_pair_elements<1>, dim3(div_up(n, 256)), dim3(256), 0, st, A, n, pi, pj, out, err);
+    else
+        hipLaunchKernelGGL(k_pair_elements<2>, dim3(div_up(n, 256)), dim3(256), 0, st, A, n, pi, pj, out, err);
+    return hipGetLastError();
+}
+
+}  // namespace eloc

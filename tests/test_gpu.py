@@ -71,7 +71,7 @@ def _toy():
     return d, ham, keys, np.log(np.array(d["psi"], dtype=complex))
 
 
-@pytest.mark.parametrize("variant", ["terms", "batch"])
+@pytest.mark.parametrize("variant", ["terms", "batch", "trie"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_toy_model(eng, variant, precision):
     d, ham, keys, logpsi = _toy()
@@ -87,7 +87,7 @@ def test_toy_model(eng, variant, precision):
 
 
 # ----------------------------------------------------------------------------
-def check_workload(eng, w, variants=("terms", "batch"), rows=None, pairs=True):
+def check_workload(eng, w, variants=("terms", "batch", "trie"), rows=None, pairs=True):
     load(eng, w.ham, w.keys)
     M = w.n_unique
     L = dev(w.logpsi)
@@ -180,7 +180,7 @@ def test_ragged_batch_sizes(eng, small_workload, M):
     lp = w.logpsi[:M].copy()
     load(eng, w.ham, keys)
     ref = oracle.local_energy(w.ham, keys, lp)
-    for variant in ("terms", "batch"):
+    for variant in ("terms", "batch", "trie"):
         e, st = eng.local_energy(dev(lp), variant=variant)
         assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
         got = gpu_pairs(eng, variant)
@@ -213,10 +213,14 @@ def test_random_pauli_odd_y(eng):
     lp = rng.normal(size=400) + 1j * rng.uniform(0, 6.28, size=400)
     load(eng, ham, keys)
     ref = oracle.local_energy(ham, keys, lp)
-    for variant in ("terms", "batch"):
+    for variant in ("terms", "batch", "trie"):
         for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
             e, _ = eng.local_energy(dev(lp), variant=variant, precision=prec)
             assert np.abs(e.cpu().numpy() - ref).max() <= tol
+    ref_p = oracle_pairs(ham, keys)
+    for variant in ("batch", "trie"):
+        for a, b in zip(gpu_pairs(eng, variant), ref_p):
+            np.testing.assert_array_equal(a, b)
     i, j, g = gpu_pairs(eng, "terms")
     h = eng.pair_elements(dev(i, torch.int32), dev(j, torch.int32)).cpu().numpy()
     np.testing.assert_allclose(h, oracle.matrix_elements(ham, keys[i], keys[j]), atol=1e-12)
@@ -226,7 +230,7 @@ def test_deterministic(eng, small_workload):
     w = small_workload
     load(eng, w.ham, w.keys)
     L = dev(w.logpsi)
-    for variant in ("terms", "batch"):
+    for variant in ("terms", "batch", "trie"):
         for prec in ("fp64", "fp32c"):
             a, sa = eng.local_energy(L, variant=variant, precision=prec)
             a = a.clone(); sa = sa.clone()
@@ -295,7 +299,7 @@ def test_adjoint_small(eng, small_workload, use_counts, precision):
     weights = np.random.default_rng(1).integers(1, 30, size=w.n_unique).astype(float) if use_counts else None
     ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi)
     E, _, _ = oracle.energy(ref_e, w.logpsi, weights)
-    for variant in ("terms", "batch"):
+    for variant in ("terms", "batch", "trie"):
         for ge in (1.0, 1j, 0.3 - 0.4j):
             ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, ge, weights=weights, energy_value=E)
             L = dev(w.logpsi)
