@@ -62,13 +62,15 @@ uint64_t pow2_at_least(uint64_t v) {
     return c;
 }
 
-Table make_table(uint32_t* slots, uint64_t capacity, int64_t n) {
+Table make_table(uint32_t* slots, uint64_t capacity, int64_t n, uint64_t salt) {
     Table T;
     T.slots = slots;
     T.mask = static_cast<uint32_t>(capacity - 1);
     T.ibits = std::max(1, bits_for(static_cast<uint64_t>(n)));   // index + 1 <= n
     T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
     T.fpshift = 32 + T.ibits;
+    T.altshift = bits_for(capacity - 1);
+    T.salt = salt;
     return T;
 }
 
@@ -96,11 +98,15 @@ struct eloc_ctx_s {
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
     DevBuf partial, energy_scratch, err_run, err_prep;
     uint32_t* err_host = nullptr;
+    uint64_t* sig_host = nullptr;    // pinned copy of the signature bitmap
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
     int tune_chunks = 0;     // 0 = automatic
     int tune_sig = 1;
+    bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
+    int sig_pa = 0, sig_n = 0;
+    uint64_t salt_state = 0x5EED2408ull;
 
     // stage profiling: HIP events around each stage, read (and reset) by
     // eloc_profile_read
@@ -141,7 +147,9 @@ Plan make_plan(const eloc_ctx c, int variant) {
     Plan P;
     const int64_t M = c->S.n;
     P.rows_per_block = rows_per_block(variant);
-    P.sig_filter = c->tune_sig != 0;
+    P.sig_filter = c->tune_sig != 0 && c->sig_one;
+    P.sig_pa = c->sig_pa;
+    P.sig_n = c->sig_n;
     if (variant == ELOC_TRIE) {
         P.chunks = c->H.xyt.chunks;
         P.per_chunk = c->H.xyt.chunk;
@@ -233,6 +241,25 @@ struct XYMap {
         }
     }
 };
+
+// Fill a cuckoo table with keys 0..n-1 (hashes `hash`); a new salt is drawn
+// if an insertion does not settle.
+int build_table(eloc_ctx c, const uint64_t* hash, int64_t n, uint32_t* slots, uint64_t cap, Table* out) {
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        const uint64_t salt = splitmix64(c->salt_state);
+        Table T = make_table(slots, cap, n, salt);
+        ELOC_HIP(c, hipMemsetAsync(slots, 0, sizeof(uint32_t) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+        ELOC_HIP(c, launch_table_insert(0, hash, n, slots, T, c->err_prep.as<uint32_t>(), c->stream));
+        const int bits = read_err(c, c->err_prep);
+        if (bits < 0) return bits;
+        if (!(static_cast<uint32_t>(bits) & kErrTable)) {
+            *out = T;
+            return ELOC_OK;
+        }
+    }
+    return fail(c, ELOC_EHIP, "membership table could not be built");
+}
 
 template <int W>
 int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
@@ -343,10 +370,9 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->terms_f.p, terms_f.data(), sizeof(TermRecF<W>) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
-    ELOC_HIP(c, hipMemsetAsync(c->gslots.p, 0, sizeof(uint32_t) * cap, c->stream));
-    Table T = make_table(c->gslots.as<uint32_t>(), cap, G);
-    ELOC_HIP(c, launch_table_insert(W, c->ghash.as<uint64_t>(), G, c->gslots.as<uint32_t>(), T, c->stream));
-    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    Table T;
+    int rc = build_table(c, c->ghash.as<uint64_t>(), G, c->gslots.as<uint32_t>(), cap, &T);
+    if (rc) return rc;
 
     HamDev H;
     H.n_qubits = n_qubits;
@@ -494,7 +520,9 @@ int eloc_create(eloc_ctx* out, int device, void* hip_stream) {
         hipMemcpy(c->R_dev.p, c->R, sizeof(c->R), hipMemcpyHostToDevice) != hipSuccess ||
         c->err_run.ensure(sizeof(uint32_t)) != hipSuccess || c->err_prep.ensure(sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->err_run.p, 0, sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->sig_host), sizeof(uint64_t) * kSigWords, hipHostMallocDefault) !=
+            hipSuccess) {
         eloc_destroy(c);
         return ELOC_EHIP;
     }
@@ -520,6 +548,7 @@ void eloc_destroy(eloc_ctx c) {
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->err_host) (void)hipHostFree(c->err_host);
+    if (c->sig_host) (void)hipHostFree(c->sig_host);
     delete c;
 }
 
@@ -578,25 +607,50 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
     ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
                                c->stream));
-    ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, sizeof(uint32_t) * cap, c->stream));
-    ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
     ELOC_HIP(c, launch_sample_hash(W, c->keys.as<uint64_t>(), n_unique, c->R_dev.as<uint64_t>(), c->H.n_qubits,
                                    c->khash.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
-    Table T = make_table(c->kslots.as<uint32_t>(), cap, n_unique);
-    ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.as<uint32_t>(), T, c->stream));
     SampleDev S;
     S.n = n_unique;
     S.keys = c->keys.as<uint64_t>();
     S.hash = c->khash.as<uint64_t>();
-    S.table = T;
     S.sig = c->sig.as<uint64_t>();
-    ELOC_HIP(c, launch_sample_verify(W, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+    // table insert + verification, one read-back; a fresh salt only if a
+    // cuckoo insertion did not settle
+    uint32_t bits = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (attempt == 8) return fail(c, ELOC_EHIP, "membership table could not be built");
+        S.table = make_table(c->kslots.as<uint32_t>(), cap, n_unique, splitmix64(c->salt_state));
+        ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, sizeof(uint32_t) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
+        ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.as<uint32_t>(), S.table,
+                                        c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_sample_verify(W, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(c->err_host, c->err_prep.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(c->sig_host, c->sig.p, sizeof(uint64_t) * kSigWords, hipMemcpyDeviceToHost,
+                                   c->stream));
+        ELOC_HIP(c, hipStreamSynchronize(c->stream));
+        bits = *c->err_host;
+        // a key that did not settle also fails its own lookup (duplicate
+        // flag): rebuild and verify again; bad bits are final
+        if (!(bits & kErrTable) || (bits & kErrBits)) break;
+        ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+    }
     prof_end(c, pm);
-    const int bits = read_err(c, c->err_prep);
-    if (bits < 0) return bits;
-    const int rc = map_err(c, static_cast<uint32_t>(bits));
+    const int rc = map_err(c, bits);
     if (rc != ELOC_OK) return rc;
+    // a single (even, odd) popcount signature over U enables the exact
+    // prefilter of LoopOverTerms
+    int nsig = 0;
+    for (int k = 0; k < kSigWords; ++k) nsig += __builtin_popcountll(c->sig_host[k]);
+    c->sig_one = nsig == 1;
+    for (int k = 0; c->sig_one && k < kSigWords; ++k)
+        if (c->sig_host[k]) {
+            const int pa = k / 2;
+            const int pb = (k % 2) * 64 + __builtin_ctzll(c->sig_host[k]);
+            c->sig_pa = pa;
+            c->sig_n = pa + pb;
+        }
     c->S = S;
     c->ut_valid = false;
     c->samples_set = true;

@@ -50,17 +50,34 @@ struct TermRecF {
 // Membership tables.  Keys are looked up through a GF(2)-linear 64-bit hash
 // lin(x) = XOR of R[q] over the set bits q of x, so lin(x ^ y) =
 // lin(x) ^ lin(y): the hash of a candidate x ^ XY is one XOR of two
-// precomputed hashes.  Slots are uint32: (fingerprint << ibits) | (index + 1),
-// 0 = empty, linear probing, load factor <= 1/4.  A fingerprint match is
-// confirmed by comparing the stored key.
+// precomputed hashes.  The table is a two-choice cuckoo table of uint32
+// slots holding (fingerprint << ibits) | (index + 1), 0 = empty, load factor
+// <= 1/4: a key sits in one of its two slots, so a lookup is exactly two
+// independent loads, and a fingerprint match is confirmed by comparing the
+// stored key.  Slot bits, alternate-slot bits and fingerprint bits are
+// disjoint fields of (hash ^ salt).
 // ---------------------------------------------------------------------------
 struct Table {
     const uint32_t* slots;
     uint32_t mask;      // capacity - 1
-    int ibits;          // bits of index+1
+    int ibits;          // bits of index + 1
     uint32_t imask;     // (1 << ibits) - 1
-    int fpshift;        // 64 - (32 - ibits)
+    int fpshift;        // fingerprint = top 32 - ibits bits
+    int altshift;       // log2(capacity)
+    uint64_t salt;
 };
+
+__host__ __device__ __forceinline__ uint32_t slot1(const Table& T, uint64_t h) {
+    return static_cast<uint32_t>(h ^ T.salt) & T.mask;
+}
+__host__ __device__ __forceinline__ uint32_t slot2(const Table& T, uint64_t h) {
+    const uint64_t k = h ^ T.salt;
+    return (static_cast<uint32_t>(k) ^ (static_cast<uint32_t>(k >> T.altshift) | 1u)) & T.mask;
+}
+// never 0, so an empty slot (0) cannot match
+__host__ __device__ __forceinline__ uint32_t fingerprint(const Table& T, uint64_t h) {
+    return static_cast<uint32_t>((h ^ T.salt) >> T.fpshift) | 1u;
+}
 
 template <int W>
 __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b) {
@@ -73,17 +90,18 @@ __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b)
 template <int W>
 __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys,
                                           uint64_t h, const uint64_t* key) {
-    uint32_t s = static_cast<uint32_t>(h) & T.mask;
-    const uint32_t fp = static_cast<uint32_t>(h >> T.fpshift);
-    for (;;) {
-        const uint32_t v = T.slots[s];
-        if (v == 0u) return -1;
-        if ((v >> T.ibits) == fp) {
-            const int j = static_cast<int>(v & T.imask) - 1;
-            if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
-        }
-        s = (s + 1u) & T.mask;
+    const uint32_t fp = fingerprint(T, h);
+    const uint32_t v1 = T.slots[slot1(T, h)];
+    const uint32_t v2 = T.slots[slot2(T, h)];
+    if ((v1 >> T.ibits) == fp) {
+        const int j = static_cast<int>(v1 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
     }
+    if ((v2 >> T.ibits) == fp) {
+        const int j = static_cast<int>(v2 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
+    }
+    return -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -144,7 +162,9 @@ struct AmpDev {
 struct Plan {
     int chunks = 1;            // group (or sample) chunks per row
     int per_chunk = 0;         // groups (or samples) per chunk
-    bool sig_filter = true;
+    bool sig_filter = true;    // U has one (even, odd) popcount signature and the filter is on
+    int sig_pa = 0;            // that signature: popcount on even qubits
+    int sig_n = 0;             //                 total popcount
     int rows_per_block = 1;    // rows owned by one workgroup
 };
 
@@ -155,6 +175,7 @@ enum ErrBits : uint32_t {
     kErrWeights = 4u,
     kErrRange = 8u,
     kErrIndex = 16u,
+    kErrTable = 32u,   // cuckoo insertion did not settle; rebuild with another salt
 };
 
 // ---------------------------------------------------------------------------
@@ -163,7 +184,7 @@ enum ErrBits : uint32_t {
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
                               int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
 hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, uint32_t* slots,
-                               const Table& T, hipStream_t st);
+                               const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err,
                                 hipStream_t st);
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,

@@ -47,15 +47,27 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
     if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
 }
 
+// Cuckoo insertion: place the value in one of its two slots, evicting the
+// occupant to its other slot; give up (error flag) after kMaxKicks moves.
+constexpr int kMaxKicks = 256;
+
 __global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n,
-                                                         uint32_t* __restrict__ slots, Table T) {
+                                                         uint32_t* __restrict__ slots, Table T,
+                                                         uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint64_t h = hash[i];
-    uint32_t s = static_cast<uint32_t>(h) & T.mask;
-    const uint32_t fp = static_cast<uint32_t>(h >> T.fpshift);
-    const uint32_t v = (fp << T.ibits) | static_cast<uint32_t>(i + 1);
-    while (atomicCAS(slots + s, 0u, v) != 0u) s = (s + 1u) & T.mask;
+    uint64_t h = hash[i];
+    uint32_t v = (fingerprint(T, h) << T.ibits) | static_cast<uint32_t>(i + 1);
+    uint32_t s = slot1(T, h);
+    for (int k = 0; k < kMaxKicks; ++k) {
+        const uint32_t old = atomicExch(slots + s, v);
+        if (old == 0u) return;
+        v = old;
+        h = hash[(old & T.imask) - 1u];
+        const uint32_t a = slot1(T, h);
+        s = (s == a) ? slot2(T, h) : a;
+    }
+    atomicOr(err, static_cast<uint32_t>(kErrTable));
 }
 
 // Duplicate check (every key must find itself) and the signature bitmap of
@@ -610,8 +622,8 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
 }
 
 hipError_t launch_table_insert(int, const uint64_t* hash, int64_t n, uint32_t* slots, const Table& T,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, T);
+                               uint32_t* err, hipStream_t st) {
+    hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, T, err);
     return hipGetLastError();
 }
 

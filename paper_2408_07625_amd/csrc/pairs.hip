@@ -49,8 +49,8 @@ struct PairArgs {
     const uint64_t* keys;
     const uint64_t* khash;
     Table ktable;
-    const uint64_t* sig;
-    int sig_filter;
+    int sig_pa;
+    int sig_n;
     int64_t M;
     int per_chunk;
     // prefix trees
@@ -76,8 +76,8 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.keys = S.keys;
     a.khash = S.hash;
     a.ktable = S.table;
-    a.sig = S.sig;
-    a.sig_filter = P.sig_filter ? 1 : 0;
+    a.sig_pa = P.sig_pa;
+    a.sig_n = P.sig_n;
     a.M = S.n;
     a.per_chunk = P.per_chunk;
     a.u_keys = S.ut.keys;
@@ -95,19 +95,20 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
-// Continue a linear probe whose first slot value v (at slot s) is loaded.
+// Second half of a cuckoo lookup: the two slot values are loaded.
 template <int W>
-__device__ __forceinline__ int resolve(const Table& T, const uint64_t* __restrict__ keys, uint32_t v, uint32_t s,
-                                       uint32_t fp, const uint64_t* key) {
-    while (v != 0u) {
-        if ((v >> T.ibits) == fp) {
-            const int j = static_cast<int>(v & T.imask) - 1;
-            if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
-        }
-        s = (s + 1u) & T.mask;
-        v = T.slots[s];
+__device__ __forceinline__ int settle(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1, uint32_t v2,
+                                      uint32_t fp, const uint64_t* key) {
+    int j = -1;
+    if ((v1 >> T.ibits) == fp) {
+        const int j1 = static_cast<int>(v1 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
     }
-    return -1;
+    if (j < 0 && (v2 >> T.ibits) == fp) {
+        const int j2 = static_cast<int>(v2 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
+    }
+    return j;
 }
 
 template <int W>
@@ -135,11 +136,14 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W>& R, uint64_
     }
 }
 
-// LoopOverTerms: lanes over 64 groups of the chunk per step.
-template <int W, class Sink>
-__device__ __forceinline__ void find_terms(const PairArgs& A, const uint64_t* __restrict__ sig, const Rows<W>& R,
-                                           int chunk, Sink& sink) {
+// LoopOverTerms: lanes over 64 groups of the chunk per step.  With SIG the
+// candidate must have U's single (even-qubit, total) popcount signature.
+// Rows past the end of U are clamped copies of the last row; their results
+// are discarded by the caller.
+template <int W, int SIG, class Sink>
+__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const Table& T = A.ktable;
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     for (int base = g0; base < g1; base += kWave) {
@@ -149,22 +153,28 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const uint64_t* __
         const GroupRec<W> gr = groups[gg];
         const uint64_t gh = A.ghash[gg];
         uint64_t xp[kRows][W];
-        uint32_t v[kRows], s[kRows], fp[kRows];
-        bool c[kRows];
+        uint32_t v1[kRows], v2[kRows], fp[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
+            bool ok = valid;
+            int pa = 0, n = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) xp[r][w] = R.x[r][w] ^ gr.xy[w];
-            c[r] = valid && r < R.n;
-            if (A.sig_filter) c[r] = c[r] && sig_ok<W>(sig, xp[r]);
+            for (int w = 0; w < W; ++w) {
+                xp[r][w] = R.x[r][w] ^ gr.xy[w];
+                if (SIG) {
+                    pa += popc64(xp[r][w] & kEven);
+                    n += popc64(xp[r][w]);
+                }
+            }
+            if (SIG) ok = ok && pa == A.sig_pa && n == A.sig_n;
             const uint64_t h = R.hx[r] ^ gh;
-            s[r] = static_cast<uint32_t>(h) & A.ktable.mask;
-            fp[r] = static_cast<uint32_t>(h >> A.ktable.fpshift);
-            v[r] = c[r] ? A.ktable.slots[s[r]] : 0u;
+            fp[r] = fingerprint(T, h);
+            v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
+            v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            const int j = c[r] ? resolve<W>(A.ktable, A.keys, v[r], s[r], fp[r], xp[r]) : -1;
+            const int j = settle<W>(T, A.keys, v1[r], v2[r], fp[r], xp[r]);
             sink.hit(r, j >= 0, g, j, gr.end - gr.begin);
         }
         sink.flush();
@@ -175,6 +185,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const uint64_t* __
 template <int W, class Sink>
 __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const Table& T = A.gtable;
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
     const int64_t j1 = min(A.M, j0 + A.per_chunk);
     for (int64_t base = j0; base < j1; base += kWave) {
@@ -186,8 +197,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, 
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
         const uint64_t hj = A.khash[jj];
         uint64_t m[kRows][W];
-        uint32_t v[kRows], s[kRows], fp[kRows];
-        bool c[kRows];
+        uint32_t v1[kRows], v2[kRows], fp[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             int pc = 0;
@@ -196,15 +206,15 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, 
                 m[r][w] = R.x[r][w] ^ xj[w];
                 pc += popc64(m[r][w]);
             }
-            c[r] = valid && r < R.n && pc <= A.maxpop;
+            const bool ok = valid && pc <= A.maxpop;
             const uint64_t h = R.hx[r] ^ hj;
-            s[r] = static_cast<uint32_t>(h) & A.gtable.mask;
-            fp[r] = static_cast<uint32_t>(h >> A.gtable.fpshift);
-            v[r] = c[r] ? A.gtable.slots[s[r]] : 0u;
+            fp[r] = fingerprint(T, h);
+            v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
+            v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            const int g = c[r] ? resolve<W>(A.gtable, A.gkeys, v[r], s[r], fp[r], m[r]) : -1;
+            const int g = settle<W>(T, A.gkeys, v1[r], v2[r], fp[r], m[r]);
             int run = 0;
             if (g >= 0) {
                 const GroupRec<W>& gr = groups[g];
@@ -331,12 +341,13 @@ struct CountSink {
 struct FillSink {
     int64_t pos[kRows];
     int64_t row0;
+    int n;          // rows of this wave inside U; the rest are clamped copies
     int jbits;
     uint64_t* pkey;
     uint32_t* pval;
     __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
         const uint64_t m = __ballot(h);
-        if (h) {
+        if (h && r < n) {
             const int64_t p = pos[r] + lanes_below(m);
             pkey[p] = (static_cast<uint64_t>(row0 + r) << jbits) | static_cast<uint64_t>(j);
             pval[p] = static_cast<uint32_t>(g);
@@ -346,11 +357,13 @@ struct FillSink {
     __device__ __forceinline__ void flush() {}
 };
 
+// VARIANT: 0 TERMS without signature filter, 3 TERMS with it, 1 BATCH.
 template <int W, int VARIANT, class Sink>
-__device__ __forceinline__ void find(const PairArgs& A, const uint64_t* sig, const Rows<W>& R, int chunk,
-                                     Sink& sink) {
+__device__ __forceinline__ void find(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
     if (VARIANT == 0)
-        find_terms<W>(A, sig, R, chunk, sink);
+        find_terms<W, 0>(A, R, chunk, sink);
+    else if (VARIANT == 3)
+        find_terms<W, 1>(A, R, chunk, sink);
     else
         find_batch<W>(A, R, chunk, sink);
 }
@@ -363,11 +376,8 @@ __device__ __forceinline__ void find(const PairArgs& A, const uint64_t* sig, con
 template <int W, int VARIANT, int PREC, bool ADJ>
 __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                  void* __restrict__ partial) {
-    __shared__ uint64_t sig[kSigWords];
     __shared__ uint64_t rowkey[kRows * W];
     __shared__ uint2 q[2 * kQCap];
-    if (VARIANT == 0)
-        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
     Rows<W> R;
     load_rows<W>(A, R, rowkey);
     __syncthreads();
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
     sink.vec = static_cast<const typename P::Vec*>(vec);
     sink.q = q;
     sink.rowkey = rowkey;
-    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+    find<W, VARIANT>(A, R, blockIdx.y, sink);
     sink.finish();
     const int64_t out0 = static_cast<int64_t>(blockIdx.y) * A.M + R.row0;
 #pragma unroll
@@ -390,17 +400,14 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
 
 template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
-    __shared__ uint64_t sig[kSigWords];
     __shared__ uint64_t rowkey[kRows * W];
-    if (VARIANT == 0)
-        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
     Rows<W> R;
     load_rows<W>(A, R, rowkey);
     __syncthreads();
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
-    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+    find<W, VARIANT>(A, R, blockIdx.y, sink);
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         if (static_cast<int>(threadIdx.x) == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
@@ -409,22 +416,20 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
 template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-    __shared__ uint64_t sig[kSigWords];
     __shared__ uint64_t rowkey[kRows * W];
-    if (VARIANT == 0)
-        for (int t = threadIdx.x; t < kSigWords; t += kWave) sig[t] = A.sig[t];
     Rows<W> R;
     load_rows<W>(A, R, rowkey);
     __syncthreads();
     FillSink sink;
     sink.row0 = R.row0;
+    sink.n = R.n;
     sink.jbits = jbits;
     sink.pkey = pkey;
     sink.pval = pval;
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
-    find<W, VARIANT>(A, sig, R, blockIdx.y, sink);
+    find<W, VARIANT>(A, R, blockIdx.y, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,9 +527,7 @@ __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, co
         xj[w] = A.keys[j * W + w];
         m[w] = A.keys[i * W + w] ^ xj[w];
     }
-    const uint64_t h = A.khash[i] ^ A.khash[j];
-    const uint32_t s = static_cast<uint32_t>(h) & A.gtable.mask;
-    const int g = resolve<W>(A.gtable, A.gkeys, A.gtable.slots[s], s, static_cast<uint32_t>(h >> A.gtable.fpshift), m);
+    const int g = table_find<W>(A.gtable, A.gkeys, A.khash[i] ^ A.khash[j], m);
     double hr = 0.0, hi = 0.0;
     if (g >= 0) {
         const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
@@ -537,7 +540,7 @@ inline unsigned div_up(int64_t n, int64_t d) { return static_cast<unsigned>((n +
 
 template <int W, int VARIANT, int PREC, bool ADJ>
 hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
-    if (VARIANT == 2) {
+    if constexpr (VARIANT == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
     } else {
@@ -557,6 +560,7 @@ hipError_t dispatch_prec(int precision, const PairArgs& A, const Plan& P, const 
 template <int W, bool ADJ>
 hipError_t dispatch_variant(int variant, int precision, const PairArgs& A, const Plan& P, const void* vec,
                             void* partial, hipStream_t st) {
+    if (variant == 0 && P.sig_filter) return dispatch_prec<W, 3, ADJ>(precision, A, P, vec, partial, st);
     if (variant == 0) return dispatch_prec<W, 0, ADJ>(precision, A, P, vec, partial, st);
     if (variant == 1) return dispatch_prec<W, 1, ADJ>(precision, A, P, vec, partial, st);
     return dispatch_prec<W, 2, ADJ>(precision, A, P, vec, partial, st);
@@ -584,7 +588,9 @@ static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t
         hipLaunchKernelGGL(k_count_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, counts);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        if (variant == 0)
+        if (variant == 0 && P.sig_filter)
+            hipLaunchKernelGGL((k_count<W, 3>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+        else if (variant == 0)
             hipLaunchKernelGGL((k_count<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
         else
             hipLaunchKernelGGL((k_count<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
@@ -600,7 +606,9 @@ static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbit
         hipLaunchKernelGGL(k_fill_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        if (variant == 0)
+        if (variant == 0 && P.sig_filter)
+            hipLaunchKernelGGL((k_fill<W, 3>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+        else if (variant == 0)
             hipLaunchKernelGGL((k_fill<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
         else
             hipLaunchKernelGGL((k_fill<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
