@@ -160,13 +160,19 @@ int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
                               const eloc_c64* eloc_dev, const double* stats_dev, eloc_c64 grad_e,
                               eloc_c64* grad_logpsi_dev);
 
-/* Launch-geometry override (autotuning, benchmarks): `chunks` splits the
- * loop over the unique XY set (TERMS) or over U (BATCH) of every row into
- * that many chunks (0 = automatic); `sig_filter` = 0 disables the exact
- * prefilter of TERMS that skips candidates whose (even-qubit, odd-qubit)
- * popcounts occur in no sample.  Results do not depend on either setting
- * beyond the floating-point summation order over chunks. */
-int eloc_set_tuning(eloc_ctx ctx, int chunks, int sig_filter);
+/* Launch geometry of the pair kernels (autotuning, benchmarks).  Results do
+ * not depend on these settings beyond the floating-point summation order of
+ * the chunk partial sums. */
+typedef struct {
+    int chunks;        /* split of the loop over the unique XY set (TERMS) or over
+                          U (BATCH) of every row; 0 = automatic                  */
+    int sig_filter;    /* 1: skip TERMS candidates whose (even-qubit, total)
+                          popcounts differ from U's when U has a single such
+                          signature (exact); 0: off                             */
+    int rows_per_wave; /* rows one wave owns: 4 or 8 (0 = 8)                    */
+} eloc_tuning;
+int eloc_set_tuning(eloc_ctx ctx, const eloc_tuning* tuning);
+int eloc_get_tuning(eloc_ctx ctx, eloc_tuning* tuning);
 
 /* Stage timing with HIP events on the context's stream (the per-part time
  * breakdown of the paper's Fig. 4: sample preparation, FindCoupledPairs +

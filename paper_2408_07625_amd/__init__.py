@@ -34,6 +34,10 @@ class C64(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int)]
+
+
 def library() -> ctypes.CDLL:
     global _lib
     if _lib is None:
@@ -55,7 +59,8 @@ def library() -> ctypes.CDLL:
             "eloc_find_pairs": (i32, [P, i32, i64, P, P, P, ctypes.POINTER(i64)]),
             "eloc_pair_elements": (i32, [P, i64, P, P, P]),
             "eloc_local_energy_adjoint": (i32, [P, i32, i32, P, P, P, P, C64, P]),
-            "eloc_set_tuning": (i32, [P, i32, i32]),
+            "eloc_set_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
+            "eloc_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
             "eloc_profile_enable": (i32, [P, i32]),
             "eloc_profile_read": (i32, [P, P, P]),
         }
@@ -73,7 +78,7 @@ def exported_symbols() -> list[str]:
     return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
                         "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples",
                         "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
-                        "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_set_tuning",
+                        "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_set_tuning", "eloc_get_tuning",
                         "eloc_profile_enable", "eloc_profile_read")
             if hasattr(lib, n)]
 
@@ -153,8 +158,14 @@ class Engine:
         self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
         self.n_unique = keys.shape[0]
 
-    def set_tuning(self, chunks: int = 0, sig_filter: bool = True):
-        self._call(self.lib.eloc_set_tuning(self.handle, int(chunks), 1 if sig_filter else 0))
+    def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 8):
+        t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave))
+        self._call(self.lib.eloc_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._call(self.lib.eloc_get_tuning(self.handle, ctypes.byref(t)))
+        return {"chunks": t.chunks, "sig_filter": bool(t.sig_filter), "rows_per_wave": t.rows_per_wave}
 
     STAGES = ("samples", "amplitudes", "pairs", "finish", "energy", "adjoint_pairs", "adjoint_finish")
 

@@ -104,6 +104,7 @@ struct eloc_ctx_s {
 
     int tune_chunks = 0;     // 0 = automatic
     int tune_sig = 1;
+    int tune_rows = 8;
     bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
     int sig_pa = 0, sig_n = 0;
     uint64_t salt_state = 0x5EED2408ull;
@@ -146,7 +147,7 @@ int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH || v == ELO
 Plan make_plan(const eloc_ctx c, int variant) {
     Plan P;
     const int64_t M = c->S.n;
-    P.rows_per_block = rows_per_block(variant);
+    P.rows_per_block = rows_per_block(variant, c->tune_rows);
     P.sig_filter = c->tune_sig != 0 && c->sig_one;
     P.sig_pa = c->sig_pa;
     P.sig_n = c->sig_n;
@@ -795,13 +796,20 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
     return ELOC_OK;
 }
 
-// Launch-geometry override used by the autotuner and the benchmarks:
-// chunks = 0 restores the automatic choice; sig_filter toggles the exact
-// (even, odd) popcount prefilter of LoopOverTerms.
-int eloc_set_tuning(eloc_ctx c, int chunks, int sig_filter) {
-    if (!c || chunks < 0) return ELOC_EINVAL;
-    c->tune_chunks = chunks;
-    c->tune_sig = sig_filter;
+int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
+    if (!c || !t || t->chunks < 0 || (t->rows_per_wave != 0 && t->rows_per_wave != 4 && t->rows_per_wave != 8))
+        return c ? fail(c, ELOC_EINVAL, "bad tuning") : ELOC_EINVAL;
+    c->tune_chunks = t->chunks;
+    c->tune_sig = t->sig_filter;
+    c->tune_rows = t->rows_per_wave == 0 ? 8 : t->rows_per_wave;
+    return ELOC_OK;
+}
+
+int eloc_get_tuning(eloc_ctx c, eloc_tuning* t) {
+    if (!c || !t) return ELOC_EINVAL;
+    t->chunks = c->tune_chunks;
+    t->sig_filter = c->tune_sig;
+    t->rows_per_wave = c->tune_rows;
     return ELOC_OK;
 }
 

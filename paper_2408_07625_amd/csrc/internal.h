@@ -234,7 +234,7 @@ hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, 
                             uint64_t* sorted, int32_t* perm, hipStream_t st);
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
                              hipStream_t st);
-int rows_per_block(int variant);
+int rows_per_block(int variant, int requested);
 
 int64_t energy_scratch_len();
 int64_t amp_scratch_len();

@@ -34,7 +34,6 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kRows = 8;                 // rows per wave (TERMS / BATCH)
 constexpr int kLongRun = 16;             // longer term runs are split over the wave
-constexpr int kQCap = kWave + kRows * kWave;
 constexpr int kTrieBlock = 256;
 
 struct PairArgs {
@@ -111,26 +110,27 @@ __device__ __forceinline__ int settle(const Table& T, const uint64_t* __restrict
     return j;
 }
 
-template <int W>
+template <int W, int NR>
 struct Rows {
+    static constexpr int kN = NR;
     int n;
     int64_t row0;
-    uint64_t x[kRows][W];
-    uint64_t hx[kRows];
+    uint64_t x[NR][W];
+    uint64_t hx[NR];
 };
 
-template <int W>
-__device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W>& R, uint64_t* rowkey) {
-    R.row0 = static_cast<int64_t>(blockIdx.x) * kRows;
-    R.n = static_cast<int>(min(static_cast<int64_t>(kRows), A.M - R.row0));
+template <int W, int NR>
+__device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey) {
+    R.row0 = static_cast<int64_t>(blockIdx.x) * NR;
+    R.n = static_cast<int>(min(static_cast<int64_t>(NR), A.M - R.row0));
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int64_t row = min(R.row0 + r, A.M - 1);
 #pragma unroll
         for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
         R.hx[r] = A.khash[row];
     }
-    if (threadIdx.x < kRows * W) {
+    if (threadIdx.x < NR * W) {
         const int64_t row = min(R.row0 + threadIdx.x / W, A.M - 1);
         rowkey[threadIdx.x] = A.keys[row * W + threadIdx.x % W];
     }
@@ -140,22 +140,22 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W>& R, uint64_
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
 // are discarded by the caller.
-template <int W, int SIG, class Sink>
-__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
+template <int W, int SIG, int NR, class Sink>
+__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.ktable;
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
+    const int lane = static_cast<int>(threadIdx.x);
+    GroupRec<W> gr = groups[min(g0 + lane, g1 - 1)];
+    uint64_t gh = A.ghash[min(g0 + lane, g1 - 1)];
     for (int base = g0; base < g1; base += kWave) {
-        const int g = base + static_cast<int>(threadIdx.x);
+        const int g = base + lane;
         const bool valid = g < g1;
-        const int gg = valid ? g : g0;
-        const GroupRec<W> gr = groups[gg];
-        const uint64_t gh = A.ghash[gg];
-        uint64_t xp[kRows][W];
-        uint32_t v1[kRows], v2[kRows], fp[kRows];
+        uint64_t xp[NR][W];
+        uint32_t v1[NR], v2[NR], fp[NR];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < NR; ++r) {
             bool ok = valid;
             int pa = 0, n = 0;
 #pragma unroll
@@ -172,18 +172,29 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W>& R, 
             v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
             v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
         }
+        // next step's groups, requested after this step's probes
+        GroupRec<W> ngr = gr;
+        uint64_t ngh = gh;
+        if (base + kWave < g1) {
+            const int ng = min(base + kWave + lane, g1 - 1);
+            ngr = groups[ng];
+            ngh = A.ghash[ng];
+        }
+        const int run = gr.end - gr.begin;
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int j = settle<W>(T, A.keys, v1[r], v2[r], fp[r], xp[r]);
-            sink.hit(r, j >= 0, g, j, gr.end - gr.begin);
+            sink.hit(r, j >= 0, g, j, run);
         }
         sink.flush();
+        gr = ngr;
+        gh = ngh;
     }
 }
 
 // LoopOverBatch: lanes over 64 samples x' of the chunk per step.
-template <int W, class Sink>
-__device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
+template <int W, int NR, class Sink>
+__device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.gtable;
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
@@ -196,10 +207,10 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, 
 #pragma unroll
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
         const uint64_t hj = A.khash[jj];
-        uint64_t m[kRows][W];
-        uint32_t v1[kRows], v2[kRows], fp[kRows];
+        uint64_t m[NR][W];
+        uint32_t v1[NR], v2[NR], fp[NR];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < NR; ++r) {
             int pc = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
@@ -213,7 +224,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, 
             v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
         }
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int g = settle<W>(T, A.gkeys, v1[r], v2[r], fp[r], m[r]);
             int run = 0;
             if (g >= 0) {
@@ -229,7 +240,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W>& R, 
 // ---------------------------------------------------------------------------
 // Sinks: what happens to the pairs a wave finds.
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool ADJ>
+template <int W, int PREC, bool ADJ, int NR>
 struct AccSink {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
@@ -239,56 +250,32 @@ struct AccSink {
     const GroupRec<W>* groups;
     const Term* terms;
     const Vec* vec;
-    uint2* q;
-    uint2* lq;
-    const uint64_t* rowkey;
+    uint2* q;               // LDS hit queue [kWave + NR * kWave]
+    uint2* lq;              // LDS long runs met while draining [kWave]
+    Acc* acc;               // LDS accumulators [NR][kWave]; lane l owns column l
+    const uint64_t* rowkey; // LDS row keys [NR][W]
     int qn = 0;
-    int ln = 0;
-    Acc acc[kRows];
 
-    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int run) {
-        const bool lng = h && run > kLongRun;
-        const bool sht = h && !lng;
-        const uint64_t ms = __ballot(sht);
-        const uint64_t ml = __ballot(lng);
-        const uint2 e = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
-                                   static_cast<uint32_t>(j));
-        if (sht) q[qn + lanes_below(ms)] = e;
-        if (lng) q[kQCap + ln + lanes_below(ml)] = e;
-        qn += __popcll(ms);
-        ln += __popcll(ml);
+    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
+        const uint64_t m = __ballot(h);
+        if (h)
+            q[qn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
+                                                static_cast<uint32_t>(j));
+        qn += __popcll(m);
     }
 
-    // acc[r] += v with r a lane value: every row adds v or an exact zero,
-    // which keeps the accumulators in registers (no indexed array).
-    __device__ __forceinline__ void add_row(int r, const Acc& v) {
-#pragma unroll
-        for (int rr = 0; rr < kRows; ++rr) acc_plus(acc[rr], masked(v, rr == r));
-    }
-
-    // one pair per lane, entries [o, o + n) of the short queue
-    __device__ __forceinline__ void drain_short(int o, int n) {
-        if (static_cast<int>(threadIdx.x) < n) {
-            const uint2 e = q[o + threadIdx.x];
-            const int r = static_cast<int>(e.x & 15u);
-            const int g = static_cast<int>(e.x >> 4);
-            const GroupRec<W> gr = groups[g];
-            uint64_t ket[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
-            typename P::H hr, hi;
-            melem<W>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
-            Acc v;
-            P::madd(v, hr, hi, vec[e.y]);
-            add_row(r, v);
-        }
+    __device__ __forceinline__ void add(int r, const Acc& v) {
+        Acc& a = acc[r * kWave + threadIdx.x];
+        Acc t = a;
+        acc_plus(t, v);
+        a = t;
     }
 
     // the whole wave on each long run, 64 terms per step
     __device__ __forceinline__ void drain_long(int n) {
         for (int k = 0; k < n; ++k) {
-            const uint32_t ex = __builtin_amdgcn_readfirstlane(q[kQCap + k].x);
-            const uint32_t ey = __builtin_amdgcn_readfirstlane(q[kQCap + k].y);
+            const uint32_t ex = __builtin_amdgcn_readfirstlane(lq[k].x);
+            const uint32_t ey = __builtin_amdgcn_readfirstlane(lq[k].y);
             const int r = static_cast<int>(ex & 15u);
             const GroupRec<W> gr = groups[ex >> 4];
             uint64_t ket[W];
@@ -298,7 +285,39 @@ struct AccSink {
             melem<W>(terms, gr.begin, gr.mid, gr.end, static_cast<int>(threadIdx.x), kWave, ket, hr, hi);
             Acc v;
             P::madd(v, hr, hi, vec[ey]);
-            add_row(r, v);
+            add(r, v);
+        }
+    }
+
+    // entries [o, o + n) of the queue, one pair per lane; runs longer than
+    // kLongRun are set aside and done by the whole wave
+    __device__ __forceinline__ void drain(int o, int n) {
+        const bool mine = static_cast<int>(threadIdx.x) < n;
+        uint2 e = make_uint2(0u, 0u);
+        GroupRec<W> gr{};
+        bool lng = false;
+        if (mine) {
+            e = q[o + threadIdx.x];
+            gr = groups[e.x >> 4];
+            lng = gr.end - gr.begin > kLongRun;
+        }
+        const uint64_t ml = __ballot(mine && lng);
+        if (mine && lng) lq[lanes_below(ml)] = e;
+        if (mine && !lng) {
+            const int r = static_cast<int>(e.x & 15u);
+            uint64_t ket[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
+            typename P::H hr, hi;
+            melem<W>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
+            Acc v;
+            P::madd(v, hr, hi, vec[e.y]);
+            add(r, v);
+        }
+        if (ml) {
+            __syncthreads();
+            drain_long(__popcll(ml));
+            __syncthreads();
         }
     }
 
@@ -306,7 +325,7 @@ struct AccSink {
         if (qn >= kWave) {
             __syncthreads();
             int o = 0;
-            for (; qn - o >= kWave; o += kWave) drain_short(o, kWave);
+            for (; qn - o >= kWave; o += kWave) drain(o, kWave);
             __syncthreads();
             const int rest = qn - o;
             uint2 t = make_uint2(0u, 0u);
@@ -315,20 +334,13 @@ struct AccSink {
             if (static_cast<int>(threadIdx.x) < rest) q[threadIdx.x] = t;
             qn = rest;
         }
-        if (ln >= kWave) {
-            __syncthreads();
-            drain_long(ln);
-            __syncthreads();
-            ln = 0;
-        }
     }
 
     __device__ __forceinline__ void finish() {
         __syncthreads();
-        drain_short(0, qn);
-        drain_long(ln);
+        if (qn) drain(0, qn);
         qn = 0;
-        ln = 0;
+        __syncthreads();
     }
 };
 
@@ -358,14 +370,14 @@ struct FillSink {
 };
 
 // VARIANT: 0 TERMS without signature filter, 3 TERMS with it, 1 BATCH.
-template <int W, int VARIANT, class Sink>
-__device__ __forceinline__ void find(const PairArgs& A, const Rows<W>& R, int chunk, Sink& sink) {
-    if (VARIANT == 0)
-        find_terms<W, 0>(A, R, chunk, sink);
-    else if (VARIANT == 3)
-        find_terms<W, 1>(A, R, chunk, sink);
+template <int W, int VARIANT, int NR, class Sink>
+__device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+    if constexpr (VARIANT == 0)
+        find_terms<W, 0, NR>(A, R, chunk, sink);
+    else if constexpr (VARIANT == 3)
+        find_terms<W, 1, NR>(A, R, chunk, sink);
     else
-        find_batch<W>(A, R, chunk, sink);
+        find_batch<W, NR>(A, R, chunk, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -373,41 +385,50 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W>& R, int ch
 //   forward: acc_x = sum_{x'} H_xx' vec_x'  (ket x', vec = a)
 //   adjoint: acc_y = sum_{x}  H_xy vec_x    (ket y,  vec = w / a)
 // ---------------------------------------------------------------------------
-template <int W, int VARIANT, int PREC, bool ADJ>
+template <int W, int VARIANT, int PREC, bool ADJ, int NR>
 __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                  void* __restrict__ partial) {
-    __shared__ uint64_t rowkey[kRows * W];
-    __shared__ uint2 q[2 * kQCap];
-    Rows<W> R;
-    load_rows<W>(A, R, rowkey);
-    __syncthreads();
     using P = Prec<PREC>;
-    AccSink<W, PREC, ADJ> sink;
+    using Acc = typename P::Acc;
+    __shared__ uint64_t rowkey[NR * W];
+    __shared__ uint2 q[kWave + NR * kWave];
+    __shared__ uint2 lq[kWave];
+    static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
+    __shared__ double2 acc_raw[NR * kWave];
+    Acc* acc = reinterpret_cast<Acc*>(acc_raw);
+    Rows<W, NR> R;
+    load_rows<W, NR>(A, R, rowkey);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r * kWave + threadIdx.x] = Acc{};
+    __syncthreads();
+    AccSink<W, PREC, ADJ, NR> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec);
     sink.q = q;
+    sink.lq = lq;
+    sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, NR>(A, R, blockIdx.y, sink);
     sink.finish();
-    const int64_t out0 = static_cast<int64_t>(blockIdx.y) * A.M + R.row0;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        wave_sum(sink.acc[r]);
-        if (static_cast<int>(threadIdx.x) == r && r < R.n) store_acc(partial, out0 + r, sink.acc[r]);
+    // per-row totals: lane r adds the 64 lane columns of row r in order
+    if (static_cast<int>(threadIdx.x) < R.n) {
+        Acc t{};
+        for (int l = 0; l < kWave; ++l) acc_plus(t, acc[threadIdx.x * kWave + l]);
+        store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + R.row0 + threadIdx.x, t);
     }
 }
 
 template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRows * W];
-    Rows<W> R;
-    load_rows<W>(A, R, rowkey);
+    Rows<W, kRows> R;
+    load_rows<W, kRows>(A, R, rowkey);
     __syncthreads();
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
-    find<W, VARIANT>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows>(A, R, blockIdx.y, sink);
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         if (static_cast<int>(threadIdx.x) == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
@@ -417,8 +438,8 @@ template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRows * W];
-    Rows<W> R;
-    load_rows<W>(A, R, rowkey);
+    Rows<W, kRows> R;
+    load_rows<W, kRows>(A, R, rowkey);
     __syncthreads();
     FillSink sink;
     sink.row0 = R.row0;
@@ -429,7 +450,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
-    find<W, VARIANT>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows>(A, R, blockIdx.y, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -543,9 +564,12 @@ hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, voi
     if constexpr (VARIANT == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+    } else if (P.rows_per_block == 4) {
+        dim3 grid(div_up(A.M, 4), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4>), grid, dim3(kWave), 0, st, A, vec, partial);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ>), grid, dim3(kWave), 0, st, A, vec, partial);
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();
 }
@@ -568,7 +592,10 @@ hipError_t dispatch_variant(int variant, int precision, const PairArgs& A, const
 
 }  // namespace
 
-int rows_per_block(int variant) { return variant == 2 ? kTrieBlock : kRows; }
+int rows_per_block(int variant, int requested) {
+    if (variant == 2) return kTrieBlock;
+    return requested == 4 ? 4 : kRows;
+}
 
 hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& H, const SampleDev& S, const Plan& P,
                         const double2* vec, const float4* vecf, void* partial, hipStream_t st) {

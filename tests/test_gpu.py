@@ -188,20 +188,20 @@ def test_ragged_batch_sizes(eng, small_workload, M):
             np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("chunks", [1, 3, 17])
-def test_chunking_does_not_change_pairs(eng, small_workload, chunks):
+@pytest.mark.parametrize("chunks,rows", [(1, 8), (3, 4), (17, 8)])
+def test_chunking_does_not_change_pairs(eng, small_workload, chunks, rows):
     w = small_workload
     load(eng, w.ham, w.keys)
     ref = oracle.local_energy(w.ham, w.keys, w.logpsi)
     for sig in (True, False):
-        eng.set_tuning(chunks, sig)
+        eng.set_tuning(chunks, sig, rows)
         try:
             for variant in ("terms", "batch"):
                 e, _ = eng.local_energy(dev(w.logpsi), variant=variant)
                 assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
                 assert eng.count_pairs(variant) == oracle.find_pairs(w.ham, w.keys)[0].size
         finally:
-            eng.set_tuning(0, True)
+            eng.set_tuning(0, True, 8)
 
 
 def test_random_pauli_odd_y(eng):
