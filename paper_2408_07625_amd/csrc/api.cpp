@@ -62,8 +62,9 @@ uint64_t pow2_at_least(uint64_t v) {
     return c;
 }
 
-Table make_table(uint32_t* slots, uint64_t capacity, int64_t n, uint64_t salt) {
+Table make_table(uint32_t* slots, uint32_t* stash, uint64_t capacity, int64_t n, uint64_t salt) {
     Table T;
+    T.stash = stash;
     T.slots = slots;
     T.mask = static_cast<uint32_t>(capacity - 1);
     T.ibits = std::max(1, bits_for(static_cast<uint64_t>(n)));   // index + 1 <= n
@@ -85,12 +86,12 @@ struct eloc_ctx_s {
 
     bool ham_set = false;
     HamDev H;
-    DevBuf groups, terms, terms_f, ghash, gkeys, gslots;
+    DevBuf groups, terms, terms_f, ghash, gkeys, gslots, gstash;
     DevBuf xyt_keys, xyt_gid, xyt_nodes;
 
     bool samples_set = false;
     SampleDev S;
-    DevBuf keys, khash, kslots, sig;
+    DevBuf keys, khash, kslots, kstash, sig;
     DevBuf ut_keys, ut_perm, ut_nodes;
     bool ut_valid = false;
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
@@ -245,13 +246,15 @@ struct XYMap {
 
 // Fill a cuckoo table with keys 0..n-1 (hashes `hash`); a new salt is drawn
 // if an insertion does not settle.
-int build_table(eloc_ctx c, const uint64_t* hash, int64_t n, uint32_t* slots, uint64_t cap, Table* out) {
+int build_table(eloc_ctx c, const uint64_t* hash, int64_t n, uint32_t* slots, uint32_t* stash, uint64_t cap,
+                Table* out) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         const uint64_t salt = splitmix64(c->salt_state);
-        Table T = make_table(slots, cap, n, salt);
+        Table T = make_table(slots, stash, cap, n, salt);
         ELOC_HIP(c, hipMemsetAsync(slots, 0, sizeof(uint32_t) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(stash, 0, sizeof(uint32_t) * (1 + kStash), c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
-        ELOC_HIP(c, launch_table_insert(0, hash, n, slots, T, c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_table_insert(0, hash, n, slots, stash, T, c->err_prep.as<uint32_t>(), c->stream));
         const int bits = read_err(c, c->err_prep);
         if (bits < 0) return bits;
         if (!(static_cast<uint32_t>(bits) & kErrTable)) {
@@ -371,8 +374,9 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->terms_f.p, terms_f.data(), sizeof(TermRecF<W>) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
+    ELOC_HIP(c, c->gstash.ensure(sizeof(uint32_t) * (1 + kStash)));
     Table T;
-    int rc = build_table(c, c->ghash.as<uint64_t>(), G, c->gslots.as<uint32_t>(), cap, &T);
+    int rc = build_table(c, c->ghash.as<uint64_t>(), G, c->gslots.as<uint32_t>(), c->gstash.as<uint32_t>(), cap, &T);
     if (rc) return rc;
 
     HamDev H;
@@ -540,7 +544,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->keys, &c->khash, &c->kslots, &c->sig, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
-                      &c->hist, &c->hist_off, &c->hist_scratch, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes,
+                      &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes,
                       &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2};
     for (DevBuf* b : bufs) b->release();
     for (auto& m : c->marks) {
@@ -604,6 +608,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     ELOC_HIP(c, c->khash.ensure(sizeof(uint64_t) * n_unique));
     const uint64_t cap = pow2_at_least(static_cast<uint64_t>(4 * n_unique));
     ELOC_HIP(c, c->kslots.ensure(sizeof(uint32_t) * cap));
+    ELOC_HIP(c, c->kstash.ensure(sizeof(uint32_t) * (1 + kStash)));
     ELOC_HIP(c, c->sig.ensure(sizeof(uint64_t) * kSigWords));
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
     ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
@@ -621,11 +626,13 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     uint32_t bits = 0;
     for (int attempt = 0;; ++attempt) {
         if (attempt == 8) return fail(c, ELOC_EHIP, "membership table could not be built");
-        S.table = make_table(c->kslots.as<uint32_t>(), cap, n_unique, splitmix64(c->salt_state));
+        S.table = make_table(c->kslots.as<uint32_t>(), c->kstash.as<uint32_t>(), cap, n_unique,
+                             splitmix64(c->salt_state));
         ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, sizeof(uint32_t) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(uint32_t) * (1 + kStash), c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
-        ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.as<uint32_t>(), S.table,
-                                        c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.as<uint32_t>(),
+                                        c->kstash.as<uint32_t>(), S.table, c->err_prep.as<uint32_t>(), c->stream));
         ELOC_HIP(c, launch_sample_verify(W, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->err_host, c->err_prep.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->sig_host, c->sig.p, sizeof(uint64_t) * kSigWords, hipMemcpyDeviceToHost,

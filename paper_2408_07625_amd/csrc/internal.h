@@ -55,8 +55,13 @@ struct TermRecF {
 // <= 1/4: a key sits in one of its two slots, so a lookup is exactly two
 // independent loads, and a fingerprint match is confirmed by comparing the
 // stored key.  Slot bits, alternate-slot bits and fingerprint bits are
-// disjoint fields of (hash ^ salt).
+// disjoint fields of (hash ^ salt).  A key whose insertion does not settle
+// goes to a small stash (A. Kirsch, M. Mitzenmacher, U. Wieder, "More robust
+// hashing: cuckoo hashing with a stash", 2009) that lookups scan only when
+// it is non-empty.
 // ---------------------------------------------------------------------------
+constexpr int kStash = 32;
+
 struct Table {
     const uint32_t* slots;
     uint32_t mask;      // capacity - 1
@@ -65,6 +70,7 @@ struct Table {
     int fpshift;        // fingerprint = top 32 - ibits bits
     int altshift;       // log2(capacity)
     uint64_t salt;
+    const uint32_t* stash;   // [1 + kStash]: count, then slot values
 };
 
 __host__ __device__ __forceinline__ uint32_t slot1(const Table& T, uint64_t h) {
@@ -86,22 +92,38 @@ __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b)
     return eq;
 }
 
-// Index of `key` (hash h) in the table over `keys` ([n][W]), or -1.
+// Second half of a lookup: the two slot values v1, v2 are loaded; `nstash`
+// is the stash count (wave-uniform).  Index of the key in `keys`, or -1.
+template <int W>
+__device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1,
+                                            uint32_t v2, uint32_t fp, const uint64_t* key, int nstash) {
+    int j = -1;
+    if ((v1 >> T.ibits) == fp) {
+        const int j1 = static_cast<int>(v1 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
+    }
+    if (j < 0 && (v2 >> T.ibits) == fp) {
+        const int j2 = static_cast<int>(v2 & T.imask) - 1;
+        if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
+    }
+    if (nstash > 0) {
+        for (int k = 0; k < nstash && k < kStash; ++k) {
+            const uint32_t v = T.stash[1 + k];
+            if (j < 0 && (v >> T.ibits) == fp) {
+                const int js = static_cast<int>(v & T.imask) - 1;
+                if (keys_equal<W>(keys + static_cast<size_t>(js) * W, key)) j = js;
+            }
+        }
+    }
+    return j;
+}
+
 template <int W>
 __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys,
                                           uint64_t h, const uint64_t* key) {
     const uint32_t fp = fingerprint(T, h);
-    const uint32_t v1 = T.slots[slot1(T, h)];
-    const uint32_t v2 = T.slots[slot2(T, h)];
-    if ((v1 >> T.ibits) == fp) {
-        const int j = static_cast<int>(v1 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
-    }
-    if ((v2 >> T.ibits) == fp) {
-        const int j = static_cast<int>(v2 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j) * W, key)) return j;
-    }
-    return -1;
+    return table_settle<W>(T, keys, T.slots[slot1(T, h)], T.slots[slot2(T, h)], fp, key,
+                           static_cast<int>(T.stash[0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +206,7 @@ enum ErrBits : uint32_t {
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
                               int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
 hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, uint32_t* slots,
-                               const Table& T, uint32_t* err, hipStream_t st);
+                               uint32_t* stash, const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err,
                                 hipStream_t st);
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,

@@ -52,8 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
 constexpr int kMaxKicks = 256;
 
 __global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n,
-                                                         uint32_t* __restrict__ slots, Table T,
-                                                         uint32_t* __restrict__ err) {
+                                                         uint32_t* __restrict__ slots, uint32_t* __restrict__ stash,
+                                                         Table T, uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
     uint64_t h = hash[i];
@@ -67,7 +67,11 @@ __global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restr
         const uint32_t a = slot1(T, h);
         s = (s == a) ? slot2(T, h) : a;
     }
-    atomicOr(err, static_cast<uint32_t>(kErrTable));
+    const uint32_t k = atomicAdd(stash, 1u);
+    if (k < static_cast<uint32_t>(kStash))
+        stash[1 + k] = v;
+    else
+        atomicOr(err, static_cast<uint32_t>(kErrTable));
 }
 
 // Duplicate check (every key must find itself) and the signature bitmap of
@@ -621,9 +625,9 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_table_insert(int, const uint64_t* hash, int64_t n, uint32_t* slots, const Table& T,
-                               uint32_t* err, hipStream_t st) {
-    hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, T, err);
+hipError_t launch_table_insert(int, const uint64_t* hash, int64_t n, uint32_t* slots, uint32_t* stash,
+                               const Table& T, uint32_t* err, hipStream_t st) {
+    hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
     return hipGetLastError();
 }
 

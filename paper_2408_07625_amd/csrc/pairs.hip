@@ -50,6 +50,8 @@ struct PairArgs {
     Table ktable;
     int sig_pa;
     int sig_n;
+    int kstash;      // stash counts, read at kernel start
+    int gstash;
     int64_t M;
     int per_chunk;
     // prefix trees
@@ -94,22 +96,6 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
-// Second half of a cuckoo lookup: the two slot values are loaded.
-template <int W>
-__device__ __forceinline__ int settle(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1, uint32_t v2,
-                                      uint32_t fp, const uint64_t* key) {
-    int j = -1;
-    if ((v1 >> T.ibits) == fp) {
-        const int j1 = static_cast<int>(v1 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
-    }
-    if (j < 0 && (v2 >> T.ibits) == fp) {
-        const int j2 = static_cast<int>(v2 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
-    }
-    return j;
-}
-
 template <int W, int NR>
 struct Rows {
     static constexpr int kN = NR;
@@ -118,6 +104,11 @@ struct Rows {
     uint64_t x[NR][W];
     uint64_t hx[NR];
 };
+
+__device__ __forceinline__ void read_stash_counts(PairArgs& A) {
+    A.kstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.ktable.stash[0]));
+    A.gstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.gtable.stash[0]));
+}
 
 template <int W, int NR>
 __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey) {
@@ -147,8 +138,18 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     const int lane = static_cast<int>(threadIdx.x);
-    GroupRec<W> gr = groups[min(g0 + lane, g1 - 1)];
-    uint64_t gh = A.ghash[min(g0 + lane, g1 - 1)];
+    // the step's group fields live in plain registers (mask words, run
+    // length, hash); the next step's are requested after this step's probes
+    uint64_t gxy[W];
+    int run;
+    uint64_t gh;
+    {
+        const GroupRec<W>& gr = groups[min(g0 + lane, g1 - 1)];
+#pragma unroll
+        for (int w = 0; w < W; ++w) gxy[w] = gr.xy[w];
+        run = gr.end - gr.begin;
+        gh = A.ghash[min(g0 + lane, g1 - 1)];
+    }
     for (int base = g0; base < g1; base += kWave) {
         const int g = base + lane;
         const bool valid = g < g1;
@@ -160,7 +161,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             int pa = 0, n = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-                xp[r][w] = R.x[r][w] ^ gr.xy[w];
+                xp[r][w] = R.x[r][w] ^ gxy[w];
                 if (SIG) {
                     pa += popc64(xp[r][w] & kEven);
                     n += popc64(xp[r][w]);
@@ -172,22 +173,28 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
             v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
         }
-        // next step's groups, requested after this step's probes
-        GroupRec<W> ngr = gr;
+        uint64_t nxy[W];
+        int nrun = run;
         uint64_t ngh = gh;
+#pragma unroll
+        for (int w = 0; w < W; ++w) nxy[w] = gxy[w];
         if (base + kWave < g1) {
             const int ng = min(base + kWave + lane, g1 - 1);
-            ngr = groups[ng];
+            const GroupRec<W>& gr = groups[ng];
+#pragma unroll
+            for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
+            nrun = gr.end - gr.begin;
             ngh = A.ghash[ng];
         }
-        const int run = gr.end - gr.begin;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int j = settle<W>(T, A.keys, v1[r], v2[r], fp[r], xp[r]);
+            const int j = table_settle<W>(T, A.keys, v1[r], v2[r], fp[r], xp[r], A.kstash);
             sink.hit(r, j >= 0, g, j, run);
         }
         sink.flush();
-        gr = ngr;
+#pragma unroll
+        for (int w = 0; w < W; ++w) gxy[w] = nxy[w];
+        run = nrun;
         gh = ngh;
     }
 }
@@ -225,7 +232,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int g = settle<W>(T, A.gkeys, v1[r], v2[r], fp[r], m[r]);
+            const int g = table_settle<W>(T, A.gkeys, v1[r], v2[r], fp[r], m[r], A.gstash);
             int run = 0;
             if (g >= 0) {
                 const GroupRec<W>& gr = groups[g];
@@ -396,6 +403,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kWave];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
+    read_stash_counts(A);
     Rows<W, NR> R;
     load_rows<W, NR>(A, R, rowkey);
 #pragma unroll
@@ -422,6 +430,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
 template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRows * W];
+    read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey);
     __syncthreads();
@@ -438,6 +447,7 @@ template <int W, int VARIANT>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRows * W];
+    read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey);
     __syncthreads();
