@@ -36,6 +36,9 @@
  *  - Work is enqueued on the context's stream; calls return before the
  *    GPU finishes unless documented as synchronising.  A context is not
  *    thread-safe; use one per host thread.
+ *  - Many problems at once: the eloc_batch_* calls at the end evaluate a
+ *    set of (Hamiltonian, U) problems of uneven size in one persistent
+ *    launch replayed from a HIP graph.
  */
 #ifndef ELOC_H
 #define ELOC_H
@@ -60,7 +63,8 @@ enum eloc_status {
     ELOC_ECAPACITY = -4, /* caller buffer too small; the required size is returned   */
     ELOC_ERANGE = -5,    /* log-amplitude spread too wide for the FP32 form          */
     ELOC_EHIP = -6,      /* HIP runtime error                                        */
-    ELOC_ESTATE = -7     /* call order: Hamiltonian or samples not set               */
+    ELOC_ESTATE = -7,    /* call order: Hamiltonian or samples not set               */
+    ELOC_EAGAIN = -8     /* a hash table overflowed and was rebuilt; repeat the call  */
 };
 
 /* FindCoupledPairs variants (Sec. "FindCoupledPairs implementations"). */
@@ -106,7 +110,7 @@ int eloc_hamiltonian_info(eloc_ctx ctx, int64_t* n_groups, int64_t* n_terms, int
  * "Sampling without replacement").  DEVICE keys_dev[n_unique][W] in any
  * order; sample index i below always means row i of this array.
  * Synchronising (validates the batch).  Errors: EINVAL (n_unique < 1 or
- * >= 2^31, bits >= N), EDUP (a key repeats), ESTATE (no Hamiltonian). */
+ * >= 2^24, bits >= N), EDUP (a key repeats), ESTATE (no Hamiltonian). */
 int eloc_set_samples(eloc_ctx ctx, int64_t n_unique, const uint64_t* keys_dev);
 
 /* Forward pass.  DEVICE inputs logpsi_dev[n_unique] (complex log psi) and
@@ -194,6 +198,102 @@ int eloc_profile_enable(eloc_ctx ctx, int on);
  * and count[ELOC_NSTAGES] (number of timed launches).  Synchronising;
  * resets the totals. */
 int eloc_profile_read(eloc_ctx ctx, double* ms_total, int64_t* count);
+
+
+/* ===========================================================================
+ * Batched evaluation: many problems (H_k, U_k) of uneven size in one
+ * pipeline.  Per problem the result is the forward pass above
+ * (E_loc^var over U_k and the weighted statistics); the pair stage of all
+ * problems is one persistent kernel whose workgroups take work items
+ * (problem, row tile, chunk of the inner loop) from an atomic counter, and
+ * the whole pipeline (sample tables, amplitudes, pairs, row sums,
+ * reductions) is captured once per precision into a HIP graph and replayed
+ * by eloc_batch_run.  Every problem uses LoopOverTerms or LoopOverBatch as
+ * the schedule decides; pairs and phases are those of the single-problem
+ * calls, and E_loc equals the single-problem result with the same chunking
+ * and rows per wave bit for bit.
+ * ======================================================================== */
+typedef struct eloc_batch_s* eloc_batch;
+
+/* One problem.  HOST: coeff[n_terms], xy[n_terms][W_k], yz[n_terms][W_k]
+ * with W_k = ceil(n_qubits / 64), read during eloc_batch_create only.
+ * DEVICE (read / written by every eloc_batch_run, so they must stay valid
+ * and keep their sizes while the batch exists): keys_dev[n_unique][W_k]
+ * (unique, any order), logpsi_dev[n_unique], weights_dev[n_unique] or
+ * NULL (|psi|^2 weights), outputs eloc_dev[n_unique] and stats_dev[4] as
+ * in eloc_local_energy. */
+typedef struct {
+    int n_qubits;
+    int64_t n_terms;
+    const double* coeff;
+    const uint64_t* xy;
+    const uint64_t* yz;
+    int64_t n_unique;
+    const uint64_t* keys_dev;
+    const eloc_c64* logpsi_dev;
+    const double* weights_dev;
+    eloc_c64* eloc_dev;
+    double* stats_dev;
+} eloc_problem;
+
+/* Schedule of the persistent pair kernel. */
+typedef struct {
+    int rows_per_wave;       /* 4 or 8 rows owned by one wave per work item        */
+    int blocks_per_cu;       /* resident workgroups per compute unit; 0 = as many
+                                as fit                                              */
+    int64_t item_candidates; /* target candidates (row x inner index) per item;
+                                sets the chunk length of every problem             */
+    int order;               /* 0: problems with most candidates first; 1: as given */
+    double batch_ratio;      /* LoopOverBatch for problems with n_unique <=
+                                batch_ratio * |unique XY|, else LoopOverTerms      */
+} eloc_batch_schedule;
+
+/* Ingest n problems (1..256) on `device`, work enqueued on `hip_stream`.
+ * Synchronising.  Errors: EINVAL (as eloc_set_hamiltonian / set_samples,
+ * with the problem index in the message), ENOMEM, EHIP.  Unless out is NULL
+ * or n / probs are invalid, *out receives a handle even on failure, usable
+ * for eloc_batch_last_error and eloc_batch_destroy only. */
+int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, const eloc_problem* probs);
+void eloc_batch_destroy(eloc_batch batch);
+const char* eloc_batch_last_error(eloc_batch batch);
+int eloc_batch_set_stream(eloc_batch batch, void* hip_stream);
+
+/* Evaluate every problem from the current contents of its DEVICE inputs.
+ * Asynchronous; the first call of a precision captures the graph.  Input
+ * errors (bits >= N, duplicate keys, bad weights, FP32C range) are
+ * reported by eloc_batch_check. */
+int eloc_batch_run(eloc_batch batch, int precision);
+
+/* 1: replay the captured graph (default); 0: launch the same kernels one by
+ * one on the stream (for comparison). */
+int eloc_batch_set_graph(eloc_batch batch, int on);
+
+/* Wait for the stream and report the first problem (*bad_problem, -1 if
+ * none) whose last run failed: EINVAL, EDUP, ERANGE as in the
+ * single-problem calls, or EAGAIN when its sample table overflowed (it is
+ * rebuilt with a new salt by this call; run again).  Synchronising. */
+int eloc_batch_check(eloc_batch batch, int* bad_problem);
+
+/* HOST counts_host[n]: coupled ordered pairs of every problem found by the
+ * last run.  Synchronising. */
+int eloc_batch_pair_counts(eloc_batch batch, int64_t* counts_host);
+
+/* Per-problem view of the schedule: unique XY count, term count, variant
+ * used (ELOC_TERMS / ELOC_BATCH) and chunks per row. */
+int eloc_batch_problem_info(eloc_batch batch, int k, int64_t* n_groups, int64_t* n_terms, int* variant,
+                            int* chunks);
+
+int eloc_batch_get_schedule(eloc_batch batch, eloc_batch_schedule* schedule);
+int eloc_batch_set_schedule(eloc_batch batch, const eloc_batch_schedule* schedule);
+
+/* Autotuner: times the pipeline (eager launches, best of two after a warm
+ * run) over a coordinate search of the schedule - rows per wave x
+ * candidates per item, then the LoopOverBatch ratio, workgroups per CU and
+ * problem order - and keeps the fastest.  The inputs must hold valid data.
+ * cache_path (HOST string or NULL): a text file of earlier choices keyed
+ * by device, precision and problem sizes; a hit skips the timing
+ * (*from_cache = 1), a new choice is written to it.  Synchronising. */
+int eloc_batch_tune(eloc_batch batch, int precision, const char* cache_path, int* from_cache);
 
 #ifdef __cplusplus
 }

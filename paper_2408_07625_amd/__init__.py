@@ -20,7 +20,7 @@ _lib = None
 VARIANTS = {"terms": 0, "batch": 1, "trie": 2}
 PRECISIONS = {"fp64": 0, "fp32c": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOMEM", -4: "ECAPACITY", -5: "ERANGE", -6: "EHIP",
-          -7: "ESTATE"}
+          -7: "ESTATE", -8: "EAGAIN"}
 
 
 class ElocError(RuntimeError):
@@ -36,6 +36,18 @@ class C64(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int), ("n_terms", ctypes.c_int64), ("coeff", ctypes.c_void_p),
+                ("xy", ctypes.c_void_p), ("yz", ctypes.c_void_p), ("n_unique", ctypes.c_int64),
+                ("keys_dev", ctypes.c_void_p), ("logpsi_dev", ctypes.c_void_p), ("weights_dev", ctypes.c_void_p),
+                ("eloc_dev", ctypes.c_void_p), ("stats_dev", ctypes.c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("rows_per_wave", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
+                ("item_candidates", ctypes.c_int64), ("order", ctypes.c_int), ("batch_ratio", ctypes.c_double)]
 
 
 def library() -> ctypes.CDLL:
@@ -63,6 +75,19 @@ def library() -> ctypes.CDLL:
             "eloc_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
             "eloc_profile_enable": (i32, [P, i32]),
             "eloc_profile_read": (i32, [P, P, P]),
+            "eloc_batch_create": (i32, [ctypes.POINTER(P), i32, P, i32, P]),
+            "eloc_batch_destroy": (None, [P]),
+            "eloc_batch_last_error": (ctypes.c_char_p, [P]),
+            "eloc_batch_set_stream": (i32, [P, P]),
+            "eloc_batch_run": (i32, [P, i32]),
+            "eloc_batch_set_graph": (i32, [P, i32]),
+            "eloc_batch_check": (i32, [P, ctypes.POINTER(i32)]),
+            "eloc_batch_pair_counts": (i32, [P, P]),
+            "eloc_batch_problem_info": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                              ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "eloc_batch_get_schedule": (i32, [P, ctypes.POINTER(Schedule)]),
+            "eloc_batch_set_schedule": (i32, [P, ctypes.POINTER(Schedule)]),
+            "eloc_batch_tune": (i32, [P, i32, ctypes.c_char_p, ctypes.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -79,7 +104,10 @@ def exported_symbols() -> list[str]:
                         "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples",
                         "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
                         "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_set_tuning", "eloc_get_tuning",
-                        "eloc_profile_enable", "eloc_profile_read")
+                        "eloc_profile_enable", "eloc_profile_read", "eloc_batch_create", "eloc_batch_destroy",
+                        "eloc_batch_last_error", "eloc_batch_set_stream", "eloc_batch_run", "eloc_batch_set_graph",
+                        "eloc_batch_check", "eloc_batch_pair_counts", "eloc_batch_problem_info",
+                        "eloc_batch_get_schedule", "eloc_batch_set_schedule", "eloc_batch_tune")
             if hasattr(lib, n)]
 
 
@@ -281,3 +309,120 @@ class LocalEnergy(torch.autograd.Function):
 
 def local_energy(engine: Engine, logpsi, weights=None, variant="terms", precision="fp64"):
     return LocalEnergy.apply(logpsi, weights, engine, variant, precision)
+
+
+class Batch:
+    """Many (Hamiltonian, U) problems evaluated by one batched launch.
+
+    problems: sequence of dicts with n_qubits, coeff, xy, yz (host arrays as
+    for Engine.set_hamiltonian), keys (int64 device tensor [M, W_k]), logpsi
+    (complex128 device tensor [M]) and optionally weights (float64 device
+    tensor [M]).  The device tensors are kept referenced: every run reads
+    their current contents, so new samples of the same sizes are passed by
+    writing into them (self.inputs[k]).  Outputs: self.eloc[k] (complex128
+    [M_k]) and self.stats[k] (float64 [4]) per problem."""
+
+    def __init__(self, problems, device: int = 0):
+        self.lib = library()
+        self.device = torch.device("cuda", device)
+        self.handle = ctypes.c_void_p()
+        self._host = []
+        self.inputs, self.eloc, self.stats = [], [], []
+        arr = (Problem * len(problems))()
+        for k, p in enumerate(problems):
+            c = np.ascontiguousarray(p["coeff"], dtype=np.float64)
+            xy = np.ascontiguousarray(p["xy"], dtype=np.uint64)
+            yz = np.ascontiguousarray(p["yz"], dtype=np.uint64)
+            keys = p["keys"]
+            if not (keys.is_cuda and keys.dtype in (torch.int64, torch.uint64) and keys.is_contiguous()):
+                raise ValueError(f"problem {k}: keys must be a contiguous int64 CUDA tensor")
+            lp = p["logpsi"]
+            if lp.dtype != torch.complex128 or not lp.is_cuda or lp.shape != (keys.shape[0],) or \
+                    not lp.is_contiguous():
+                raise ValueError(f"problem {k}: logpsi must be a contiguous complex128 CUDA tensor [M]")
+            w = p.get("weights")
+            if w is not None and (w.dtype != torch.float64 or not w.is_cuda or w.shape != (keys.shape[0],) or
+                                  not w.is_contiguous()):
+                raise ValueError(f"problem {k}: weights must be a contiguous float64 CUDA tensor [M]")
+            e = torch.empty(keys.shape[0], dtype=torch.complex128, device=self.device)
+            s = torch.empty(4, dtype=torch.float64, device=self.device)
+            self.eloc.append(e)
+            self.stats.append(s)
+            self._host += [c, xy, yz]
+            self.inputs.append({"keys": keys, "logpsi": lp, "weights": w})
+            arr[k] = Problem(int(p["n_qubits"]), c.size, _np_ptr(c).value, _np_ptr(xy).value, _np_ptr(yz).value,
+                             keys.shape[0], keys.data_ptr(), lp.data_ptr(), None if w is None else w.data_ptr(),
+                             e.data_ptr(), s.data_ptr())
+        stream = torch.cuda.current_stream(self.device).cuda_stream if torch.cuda.is_available() else 0
+        rc = self.lib.eloc_batch_create(ctypes.byref(self.handle), device, ctypes.c_void_p(stream), len(problems),
+                                        ctypes.cast(arr, ctypes.c_void_p))
+        self._call(rc)
+        self.n = len(problems)
+        self._host = []   # copied by create; the device tensors in self.inputs must live on
+
+    def close(self):
+        if self.handle:
+            self.lib.eloc_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, rc, bad=None):
+        if rc != 0:
+            msg = (self.lib.eloc_batch_last_error(self.handle) or b"").decode() if self.handle else ""
+            err = ElocError(rc, msg)
+            err.problem = None if bad is None else bad.value
+            raise err
+        return rc
+
+    def _sync_stream(self):
+        self._call(self.lib.eloc_batch_set_stream(
+            self.handle, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def run(self, precision="fp32c", check: bool = True):
+        self._sync_stream()
+        self._call(self.lib.eloc_batch_run(self.handle, _precision(precision)))
+        if check:
+            self.check()
+        return self.eloc, self.stats
+
+    def check(self):
+        bad = ctypes.c_int(-1)
+        self._call(self.lib.eloc_batch_check(self.handle, ctypes.byref(bad)), bad)
+
+    def set_graph(self, on: bool):
+        self._call(self.lib.eloc_batch_set_graph(self.handle, 1 if on else 0))
+
+    def pair_counts(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int64)
+        self._call(self.lib.eloc_batch_pair_counts(self.handle, _np_ptr(out)))
+        return out
+
+    def problem_info(self, k: int) -> dict:
+        g, t, v, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        self._call(self.lib.eloc_batch_problem_info(self.handle, k, ctypes.byref(g), ctypes.byref(t),
+                                                    ctypes.byref(v), ctypes.byref(c)))
+        return {"n_groups": g.value, "n_terms": t.value, "variant": "batch" if v.value == 1 else "terms",
+                "chunks": c.value}
+
+    def get_schedule(self) -> dict:
+        s = Schedule()
+        self._call(self.lib.eloc_batch_get_schedule(self.handle, ctypes.byref(s)))
+        return {"rows_per_wave": s.rows_per_wave, "blocks_per_cu": s.blocks_per_cu,
+                "item_candidates": s.item_candidates, "order": s.order, "batch_ratio": s.batch_ratio}
+
+    def set_schedule(self, rows_per_wave=8, blocks_per_cu=0, item_candidates=1 << 17, order=0, batch_ratio=1.0):
+        s = Schedule(int(rows_per_wave), int(blocks_per_cu), int(item_candidates), int(order), float(batch_ratio))
+        self._call(self.lib.eloc_batch_set_schedule(self.handle, ctypes.byref(s)))
+
+    def tune(self, precision="fp32c", cache_path=None) -> tuple[dict, bool]:
+        """Autotune the schedule (synchronising); returns (schedule, taken from the cache)."""
+        self._sync_stream()
+        hit = ctypes.c_int(0)
+        path = None if cache_path is None else str(cache_path).encode()
+        self._call(self.lib.eloc_batch_tune(self.handle, _precision(precision), path, ctypes.byref(hit)))
+        return self.get_schedule(), bool(hit.value)

@@ -14,8 +14,9 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libeloc.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "pairs.hip", CSRC / "api.cpp"]
-HEADERS = [CSRC / "internal.h", CSRC / "device.h", CSRC / "trie.h", ROOT / "include" / "eloc.h"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "pairs.hip", CSRC / "batch.hip", CSRC / "api.cpp", CSRC / "batch.cpp"]
+HEADERS = [CSRC / "internal.h", CSRC / "device.h", CSRC / "trie.h", CSRC / "ham.h", CSRC / "host.h",
+           ROOT / "include" / "eloc.h"]
 
 # Packed-FP32 instructions are disabled for all HIP code (the compiler would
 # otherwise pair scalar FP32 adds/multiplies into v_pk_* forms).  Floating-

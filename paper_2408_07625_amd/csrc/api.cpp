@@ -2,6 +2,8 @@
 // preparation and the entry points.  Device work is enqueued through the
 // launchers of kernels.hip on the context's stream.
 #include "eloc.h"
+#include "ham.h"
+#include "host.h"
 #include "internal.h"
 #include "trie.h"
 
@@ -18,62 +20,6 @@
 using namespace eloc;
 
 namespace {
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t n) {
-        if (n <= bytes && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (n == 0) n = 16;
-        hipError_t e = hipMalloc(&p, n);
-        if (e == hipSuccess) bytes = n;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T>
-    T* as() const {
-        return static_cast<T*>(p);
-    }
-};
-
-uint64_t splitmix64(uint64_t& s) {
-    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-int bits_for(uint64_t v) {   // smallest b with v < 2^b
-    int b = 0;
-    while (b < 64 && (v >> b) != 0) ++b;
-    return b;
-}
-
-uint64_t pow2_at_least(uint64_t v) {
-    uint64_t c = 1;
-    while (c < v) c <<= 1;
-    return c;
-}
-
-Table make_table(uint32_t* slots, uint32_t* stash, uint64_t capacity, int64_t n, uint64_t salt) {
-    Table T;
-    T.stash = stash;
-    T.slots = slots;
-    T.mask = static_cast<uint32_t>(capacity - 1);
-    T.ibits = std::max(1, bits_for(static_cast<uint64_t>(n)));   // index + 1 <= n
-    T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
-    T.fpshift = 32 + T.ibits;
-    T.altshift = bits_for(capacity - 1);
-    T.salt = salt;
-    return T;
-}
 
 }  // namespace
 
@@ -188,62 +134,6 @@ int map_err(eloc_ctx c, uint32_t bits) {
     return ELOC_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Host grouping of terms by XY in first-appearance order (growable
-// open-addressing map keyed by the XY words).
-// ---------------------------------------------------------------------------
-struct XYMap {
-    int W;
-    std::vector<uint64_t> keys;
-    std::vector<int64_t> vals;   // -1 = empty
-    size_t count = 0;
-    explicit XYMap(int w) : W(w) { resize(1024); }
-    static uint64_t mix(uint64_t h) {
-        h ^= h >> 33;
-        h *= 0xff51afd7ed558ccdull;
-        h ^= h >> 33;
-        h *= 0xc4ceb9fe1a85ec53ull;
-        return h ^ (h >> 33);
-    }
-    uint64_t hash(const uint64_t* k) const {
-        uint64_t h = mix(k[0]);
-        if (W == 2) h = mix(h ^ (k[1] + 0x9E3779B97F4A7C15ull));
-        return h;
-    }
-    void resize(size_t cap) {
-        std::vector<uint64_t> ok;
-        std::vector<int64_t> ov;
-        ok.swap(keys);
-        ov.swap(vals);
-        keys.assign(cap * W, 0);
-        vals.assign(cap, -1);
-        count = 0;
-        for (size_t s = 0; s < ov.size(); ++s)
-            if (ov[s] >= 0) insert(&ok[s * W], ov[s]);
-    }
-    // returns existing value or inserts v
-    int64_t find_or_insert(const uint64_t* k, int64_t v) {
-        if (2 * (count + 1) > vals.size()) resize(vals.size() * 2);
-        return insert(k, v);
-    }
-    int64_t insert(const uint64_t* k, int64_t v) {
-        const size_t mask = vals.size() - 1;
-        size_t s = hash(k) & mask;
-        for (;;) {
-            if (vals[s] < 0) {
-                for (int w = 0; w < W; ++w) keys[s * W + w] = k[w];
-                vals[s] = v;
-                ++count;
-                return v;
-            }
-            bool eq = true;
-            for (int w = 0; w < W; ++w) eq = eq && keys[s * W + w] == k[w];
-            if (eq) return vals[s];
-            s = (s + 1) & mask;
-        }
-    }
-};
-
 // Fill a cuckoo table with keys 0..n-1 (hashes `hash`); a new salt is drawn
 // if an insertion does not settle.
 int build_table(eloc_ctx c, const uint64_t* hash, int64_t n, uint32_t* slots, uint32_t* stash, uint64_t cap,
@@ -268,91 +158,18 @@ int build_table(eloc_ctx c, const uint64_t* hash, int64_t n, uint32_t* slots, ui
 template <int W>
 int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
            const uint64_t* yz) {
-    XYMap map(W);
-    std::vector<int64_t> gid(static_cast<size_t>(n_terms));
-    std::vector<int64_t> first;
-    for (int64_t l = 0; l < n_terms; ++l) {
-        const int64_t g = map.find_or_insert(xy + l * W, static_cast<int64_t>(first.size()));
-        if (g == static_cast<int64_t>(first.size())) first.push_back(l);
-        gid[static_cast<size_t>(l)] = g;
-    }
-    const int64_t G = static_cast<int64_t>(first.size());
-    if (n_terms >= (int64_t(1) << 31) || G >= (int64_t(1) << 25))
-        return fail(c, ELOC_EINVAL, "Hamiltonian too large (terms < 2^31, unique XY < 2^25)");
-    // |Y| parity of each term: even terms form the real part of a group's
-    // run, odd terms the imaginary part; i^|Y| = (-1)^floor(|Y|/2) i^(|Y| mod 2)
-    std::vector<int> ny(static_cast<size_t>(n_terms));
-    for (int64_t l = 0; l < n_terms; ++l) {
-        int k = 0;
-        for (int w = 0; w < W; ++w) k += __builtin_popcountll(xy[l * W + w] & yz[l * W + w]);
-        ny[static_cast<size_t>(l)] = k;
-    }
-    std::vector<int64_t> n_even(static_cast<size_t>(G), 0), n_all(static_cast<size_t>(G), 0);
-    for (int64_t l = 0; l < n_terms; ++l) {
-        ++n_all[static_cast<size_t>(gid[l])];
-        if ((ny[static_cast<size_t>(l)] & 1) == 0) ++n_even[static_cast<size_t>(gid[l])];
-    }
-    std::vector<int64_t> begin(static_cast<size_t>(G + 1), 0);
-    for (int64_t g = 0; g < G; ++g) begin[g + 1] = begin[g] + n_all[static_cast<size_t>(g)];
-    std::vector<int64_t> pos_even(begin.begin(), begin.end() - 1), pos_odd(static_cast<size_t>(G));
-    for (int64_t g = 0; g < G; ++g) pos_odd[static_cast<size_t>(g)] = begin[g] + n_even[static_cast<size_t>(g)];
-    std::vector<TermRec<W>> terms(static_cast<size_t>(n_terms));
-    std::vector<TermRecF<W>> terms_f(static_cast<size_t>(n_terms));
-    for (int64_t l = 0; l < n_terms; ++l) {   // caller order kept inside each part
-        const size_t g = static_cast<size_t>(gid[l]);
-        const int k = ny[static_cast<size_t>(l)];
-        const int64_t p = (k & 1) ? pos_odd[g]++ : pos_even[g]++;
-        const double h = ((k >> 1) & 1) ? -coeff[l] : coeff[l];
-        TermRec<W> t;
-        TermRecF<W> tf;
-        for (int w = 0; w < W; ++w) {
-            t.yz[w] = yz[l * W + w];
-            tf.yz[w] = yz[l * W + w];
-        }
-        t.h = h;
-        tf.h_hi = static_cast<float>(h);
-        tf.h_lo = static_cast<float>(h - static_cast<double>(tf.h_hi));
-        terms[static_cast<size_t>(p)] = t;
-        terms_f[static_cast<size_t>(p)] = tf;
-    }
-    std::vector<GroupRec<W>> groups(static_cast<size_t>(G));
-    std::vector<uint64_t> ghash(static_cast<size_t>(G));
-    std::vector<uint64_t> gkeys(static_cast<size_t>(G * W));
-    int maxpop = 0, diag = -1;
-    for (int64_t g = 0; g < G; ++g) {
-        GroupRec<W> r;
-        const uint64_t* m = xy + first[static_cast<size_t>(g)] * W;
-        uint64_t h = 0;
-        int pc = 0;
-        for (int w = 0; w < W; ++w) {
-            r.xy[w] = m[w];
-            gkeys[static_cast<size_t>(g * W + w)] = m[w];
-            pc += __builtin_popcountll(m[w]);
-            for (uint64_t v = m[w]; v; v &= v - 1) h ^= c->R[64 * w + __builtin_ctzll(v)];
-        }
-        r.begin = static_cast<int32_t>(begin[static_cast<size_t>(g)]);
-        r.mid = static_cast<int32_t>(begin[static_cast<size_t>(g)] + n_even[static_cast<size_t>(g)]);
-        r.end = static_cast<int32_t>(begin[static_cast<size_t>(g + 1)]);
-        r.pad = 0;
-        groups[static_cast<size_t>(g)] = r;
-        ghash[static_cast<size_t>(g)] = h;
-        maxpop = std::max(maxpop, pc);
-        if (pc == 0) diag = static_cast<int>(g);
-    }
-    // XY prefix trees: masks sorted ascending, cut into chunks of xy_chunk
-    std::vector<int32_t> order(static_cast<size_t>(G));
-    for (int64_t g = 0; g < G; ++g) order[static_cast<size_t>(g)] = static_cast<int32_t>(g);
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        for (int w = W - 1; w >= 0; --w) {
-            const uint64_t ka = gkeys[static_cast<size_t>(a) * W + w], kb = gkeys[static_cast<size_t>(b) * W + w];
-            if (ka != kb) return ka < kb;
-        }
-        return false;
-    });
-    std::vector<uint64_t> xsorted(static_cast<size_t>(G * W));
-    for (int64_t i = 0; i < G; ++i)
-        for (int w = 0; w < W; ++w)
-            xsorted[static_cast<size_t>(i * W + w)] = gkeys[static_cast<size_t>(order[static_cast<size_t>(i)]) * W + w];
+    HostHam<W> hh;
+    const std::string why = build_host_ham<W>(c->R, n_terms, coeff, xy, yz, hh);
+    if (!why.empty()) return fail(c, ELOC_EINVAL, why);
+    const int64_t G = hh.G;
+    const std::vector<GroupRec<W>>& groups = hh.groups;
+    const std::vector<TermRec<W>>& terms = hh.terms;
+    const std::vector<TermRecF<W>>& terms_f = hh.terms_f;
+    const std::vector<uint64_t>& ghash = hh.ghash;
+    const std::vector<uint64_t>& gkeys = hh.gkeys;
+    const std::vector<int32_t>& order = hh.order;
+    const std::vector<uint64_t>& xsorted = hh.xsorted;
+    const int maxpop = hh.maxpop, diag = hh.diag;
     const int64_t xy_chunks_target = 16;
     const int64_t xy_chunk = std::max<int64_t>(2, (G + xy_chunks_target - 1) / xy_chunks_target);
     const int64_t xy_chunks = (G + xy_chunk - 1) / xy_chunk;

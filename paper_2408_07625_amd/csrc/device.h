@@ -228,6 +228,33 @@ __device__ __forceinline__ void wave_sum(AccF& a) {
     }
 }
 
+// A complex double as FP32 hi + lo pairs (re_hi, re_lo, im_hi, im_lo).
+__device__ __forceinline__ float4 split_c(double re, double im) {
+    const float rh = static_cast<float>(re);
+    const float ih = static_cast<float>(im);
+    return make_float4(rh, static_cast<float>(re - static_cast<double>(rh)), ih,
+                       static_cast<float>(im - static_cast<double>(ih)));
+}
+
+// Block-wide sums of K doubles over NT threads (fixed tree, deterministic);
+// every thread ends with the totals.
+template <int K, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[K], double (*lds)[NT]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (static_cast<int>(threadIdx.x) < s) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) lds[k][threadIdx.x] += lds[k][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = lds[k][0];
+    __syncthreads();
+}
+
 __device__ __forceinline__ void store_acc(void* partial, int64_t idx, const AccD& a) {
     static_cast<double2*>(partial)[idx] = make_double2(a.re, a.im);
 }

@@ -126,6 +126,32 @@ __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __rest
                            static_cast<int>(T.stash[0]));
 }
 
+// Cuckoo insertion of value i + 1 (hash hash[i]): place it in one of its two
+// slots, evicting the occupant to its other slot; after kMaxKicks moves the
+// value in hand goes to the stash, or the error bit is set if that is full.
+constexpr int kMaxKicks = 256;
+
+__device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ hash, int64_t i,
+                                                 uint32_t* __restrict__ slots, uint32_t* __restrict__ stash,
+                                                 const Table& T, uint32_t* __restrict__ err, uint32_t err_bit) {
+    uint64_t h = hash[i];
+    uint32_t v = (fingerprint(T, h) << T.ibits) | static_cast<uint32_t>(i + 1);
+    uint32_t s = slot1(T, h);
+    for (int k = 0; k < kMaxKicks; ++k) {
+        const uint32_t old = atomicExch(slots + s, v);
+        if (old == 0u) return;
+        v = old;
+        h = hash[(old & T.imask) - 1u];
+        const uint32_t a = slot1(T, h);
+        s = (s == a) ? slot2(T, h) : a;
+    }
+    const uint32_t k = atomicAdd(stash, 1u);
+    if (k < static_cast<uint32_t>(kStash))
+        stash[1 + k] = v;
+    else
+        atomicOr(err, err_bit);
+}
+
 // ---------------------------------------------------------------------------
 // Device state handed to kernels.
 // ---------------------------------------------------------------------------
@@ -201,6 +227,91 @@ enum ErrBits : uint32_t {
 };
 
 // ---------------------------------------------------------------------------
+// Batched launch: many (Hamiltonian, U) problems in one pipeline.  Samples of
+// all problems share one global index space (problem k owns [s0, s0 + M));
+// a per-problem descriptor holds the offsets into the concatenated buffers
+// and the caller's own input / output pointers.  The pair kernel is
+// persistent: work items (problem, row tile, chunk) are taken from one
+// atomic counter in the order of the schedule.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 256;   // problems per batch (four lane registers of item starts)
+constexpr int kBTile = 2048;     // samples per reduction tile
+
+struct BatchProb {
+    // Hamiltonian (run and group indices local to the problem)
+    const void* groups;
+    const uint64_t* ghash;
+    const void* terms;
+    const void* terms_f;
+    const uint64_t* gkeys;
+    Table gtable;
+    int32_t n_groups;
+    int32_t maxpop;
+    int32_t n_qubits;
+    int32_t variant;       // 0 LoopOverTerms, 1 LoopOverBatch
+    // samples
+    int64_t s0;
+    int64_t M;
+    Table ktable;          // index values local to the problem
+    uint32_t* kslots;      // writable views of ktable's arrays
+    uint32_t* kstash;
+    // schedule
+    int32_t chunks;
+    int32_t per_chunk;
+    int64_t item0;         // first work item of the problem
+    int64_t items;
+    int64_t pbase;         // first partial of the problem; partial (c, row) at pbase + c * M + row
+    int32_t rt0;           // reduction tiles [rt0, rt0 + rtn)
+    int32_t rtn;
+    // caller buffers (device)
+    const uint64_t* keys_in;   // [M][w_in]
+    int32_t w_in;
+    int32_t pad;
+    const double2* logpsi;
+    const double* weights;     // null: |psi|^2 weights
+    double2* eloc;
+    double* stats;             // [4]
+};
+
+struct RTile {
+    int32_t prob;
+    int32_t pad;
+    int64_t begin;   // global sample range
+    int64_t end;
+};
+
+struct BatchDev {
+    const BatchProb* probs;
+    int n;
+    int W;
+    const int32_t* pid;        // [S] problem of every global sample
+    int64_t S;
+    const RTile* tiles;
+    int n_tiles;
+    const int32_t* sched;      // problems in schedule order (item0 ascending)
+    int64_t total_items;
+    const uint64_t* R;         // linear hash words [64 W]
+    uint64_t* keys;            // [S][W] copy of the caller keys (zero-padded words)
+    uint64_t* khash;           // [S]
+    uint32_t* slots;           // all key-table slots (cleared per run)
+    int64_t n_slots;
+    uint32_t* stash;           // [n][1 + kStash]
+    uint32_t* err;             // [n] error bits
+    uint32_t* sigmin;          // [n] min / max of (even popcount << 8 | popcount) over U_k
+    uint32_t* sigmax;
+    double* shift;             // [n] max Re L
+    double* scal;              // [n][3] E re, E im, sum w
+    double* part;              // [n_tiles][3] reduction partials
+    unsigned long long* pairs; // [n] coupled pairs found
+    unsigned int* work;        // work-item counter
+    double2* a;
+    double2* b;
+    float4* af;
+    float4* bf;
+    void* partial;
+};
+
+// ---------------------------------------------------------------------------
 // Launchers (kernels.hip).  All enqueue on `st` and return hipError_t.
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
@@ -257,6 +368,13 @@ hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, 
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
                              hipStream_t st);
 int rows_per_block(int variant, int requested);
+
+// Batched pipeline (batch.hip; the persistent pair kernel in pairs.hip).
+hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
+hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st);
+hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st);
+int batch_blocks_per_cu(int W, int precision, int rows);
+
 
 int64_t energy_scratch_len();
 int64_t amp_scratch_len();

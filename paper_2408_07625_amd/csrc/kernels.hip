@@ -47,31 +47,12 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
     if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
 }
 
-// Cuckoo insertion: place the value in one of its two slots, evicting the
-// occupant to its other slot; give up (error flag) after kMaxKicks moves.
-constexpr int kMaxKicks = 256;
-
 __global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n,
                                                          uint32_t* __restrict__ slots, uint32_t* __restrict__ stash,
                                                          Table T, uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    uint64_t h = hash[i];
-    uint32_t v = (fingerprint(T, h) << T.ibits) | static_cast<uint32_t>(i + 1);
-    uint32_t s = slot1(T, h);
-    for (int k = 0; k < kMaxKicks; ++k) {
-        const uint32_t old = atomicExch(slots + s, v);
-        if (old == 0u) return;
-        v = old;
-        h = hash[(old & T.imask) - 1u];
-        const uint32_t a = slot1(T, h);
-        s = (s == a) ? slot2(T, h) : a;
-    }
-    const uint32_t k = atomicAdd(stash, 1u);
-    if (k < static_cast<uint32_t>(kStash))
-        stash[1 + k] = v;
-    else
-        atomicOr(err, static_cast<uint32_t>(kErrTable));
+    table_insert_one(hash, i, slots, stash, T, err, static_cast<uint32_t>(kErrTable));
 }
 
 // Duplicate check (every key must find itself) and the signature bitmap of
@@ -103,26 +84,6 @@ __global__ __launch_bounds__(kBlock) void k_sample_verify(const uint64_t* __rest
         if (lsig[t]) atomicOr(reinterpret_cast<unsigned long long*>(sig + t), lsig[t]);
 }
 
-// ---------------------------------------------------------------------------
-// Block reductions (fixed tree, deterministic).
-// ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double (*lds)[kBlock]) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) lds[k][threadIdx.x] += lds[k][threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = lds[k][0];
-    __syncthreads();
-}
-
 constexpr int kRedBlocks = 256;   // fixed partition of reductions over U
 
 __global__ __launch_bounds__(kBlock) void k_minmax_partial(const double2* __restrict__ L, int64_t n,
@@ -149,13 +110,6 @@ __global__ __launch_bounds__(kBlock) void k_minmax_partial(const double2* __rest
         part[2 * blockIdx.x] = lds[0][0];
         part[2 * blockIdx.x + 1] = lds[1][0];
     }
-}
-
-__device__ __forceinline__ float4 split_c(double re, double im) {
-    const float rh = static_cast<float>(re);
-    const float ih = static_cast<float>(im);
-    return make_float4(rh, static_cast<float>(re - static_cast<double>(rh)), ih,
-                       static_cast<float>(im - static_cast<double>(ih)));
 }
 
 // a = exp(L - c), b = exp(c - L) (FP64 and, if fp32, hi/lo float pairs).
@@ -342,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_p1(const double2* __restrict_
         v[2] += w * e.y;
     }
     if (bad) atomicOr(err, static_cast<uint32_t>(kErrWeights));
-    block_sum<3>(v, lds);
+    block_sum<3, kBlock>(v, lds);
     if (threadIdx.x == 0) {
         part[3 * blockIdx.x] = v[0];
         part[3 * blockIdx.x + 1] = v[1];
@@ -362,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_mid(const double* __restrict_
         v[1] += part[3 * k + 1];
         v[2] += part[3 * k + 2];
     }
-    block_sum<3>(v, lds);
+    block_sum<3, kBlock>(v, lds);
     if (threadIdx.x == 0) {
         const double tot = v[0];
         if (!(tot > 0.0) || !isfinite(tot)) atomicOr(err, static_cast<uint32_t>(kErrWeights));
@@ -393,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_p2(const double2* __restrict_
         const double dr = e.x - er, di = e.y - ei;
         v[0] += w * (dr * dr + di * di);
     }
-    block_sum<1>(v, lds);
+    block_sum<1, kBlock>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
@@ -403,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_p3(const double* __restrict__
     __shared__ double lds[1][kBlock];
     double v[1] = {0.0};
     for (int k = threadIdx.x; k < kRedBlocks; k += kBlock) v[0] += part[k];
-    block_sum<1>(v, lds);
+    block_sum<1, kBlock>(v, lds);
     if (threadIdx.x == 0) stats[2] = v[0] / scal[2];
 }
 

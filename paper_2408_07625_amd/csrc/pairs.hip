@@ -111,8 +111,8 @@ __device__ __forceinline__ void read_stash_counts(PairArgs& A) {
 }
 
 template <int W, int NR>
-__device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey) {
-    R.row0 = static_cast<int64_t>(blockIdx.x) * NR;
+__device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey, int64_t tile) {
+    R.row0 = tile * NR;
     R.n = static_cast<int>(min(static_cast<int64_t>(NR), A.M - R.row0));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -262,6 +262,8 @@ struct AccSink {
     Acc* acc;               // LDS accumulators [NR][kWave]; lane l owns column l
     const uint64_t* rowkey; // LDS row keys [NR][W]
     int qn = 0;
+    int nrows = 0;          // rows inside U (the rest are clamped copies)
+    int64_t hits = 0;       // coupled pairs of those rows
 
     __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
         const uint64_t m = __ballot(h);
@@ -269,6 +271,7 @@ struct AccSink {
             q[qn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
                                                 static_cast<uint32_t>(j));
         qn += __popcll(m);
+        if (r < nrows) hits += __popcll(m);
     }
 
     __device__ __forceinline__ void add(int r, const Acc& v) {
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
     read_stash_counts(A);
     Rows<W, NR> R;
-    load_rows<W, NR>(A, R, rowkey);
+    load_rows<W, NR>(A, R, rowkey, blockIdx.x);
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r * kWave + threadIdx.x] = Acc{};
     __syncthreads();
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
     __shared__ uint64_t rowkey[kRows * W];
     read_stash_counts(A);
     Rows<W, kRows> R;
-    load_rows<W, kRows>(A, R, rowkey);
+    load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
     __syncthreads();
     CountSink sink;
 #pragma unroll
@@ -449,7 +452,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
     __shared__ uint64_t rowkey[kRows * W];
     read_stash_counts(A);
     Rows<W, kRows> R;
-    load_rows<W, kRows>(A, R, rowkey);
+    load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
     __syncthreads();
     FillSink sink;
     sink.row0 = R.row0;
@@ -461,6 +464,100 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
     for (int r = 0; r < kRows; ++r)
         sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
     find<W, VARIANT, kRows>(A, R, blockIdx.y, sink);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernel.  Each workgroup (one wave) takes work items
+// from the batch's atomic counter until the schedule is exhausted; item t
+// belongs to the problem whose [item0, item0 + items) holds it (found by a
+// ballot over the item starts, kept in four lane registers), and is the
+// (row tile, chunk) pair u / chunks, u % chunks of that problem.  The item
+// body is the forward row kernel above with the problem's own tables,
+// variant and signature filter; a row's chunk partials land at the
+// problem's partial offset.  Every wave leaves the loop when the counter
+// passes the last item.
+// ---------------------------------------------------------------------------
+template <int W, int PREC, int NR>
+__global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void* __restrict__ vec_all,
+                                                         void* __restrict__ partial_all) {
+    using P = Prec<PREC>;
+    using Acc = typename P::Acc;
+    __shared__ uint64_t rowkey[NR * W];
+    __shared__ uint2 q[kWave + NR * kWave];
+    __shared__ uint2 lq[kWave];
+    static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
+    __shared__ double2 acc_raw[NR * kWave];
+    Acc* acc = reinterpret_cast<Acc*>(acc_raw);
+    const int lane = static_cast<int>(threadIdx.x);
+    constexpr int kSlices = kMaxBatch / kWave;
+    int64_t istart[kSlices];
+#pragma unroll
+    for (int c = 0; c < kSlices; ++c) {
+        const int p = c * kWave + lane;
+        istart[c] = p < B.n ? B.probs[B.sched[p]].item0 : INT64_MAX;
+    }
+    for (;;) {
+        unsigned int t0 = 0u;
+        if (lane == 0) t0 = atomicAdd(B.work, 1u);
+        const int64_t t = static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(t0)));
+        if (t >= B.total_items) break;
+        int pos = -1;
+#pragma unroll
+        for (int c = 0; c < kSlices; ++c) pos += __popcll(__ballot(istart[c] <= t));
+        const int k = B.sched[pos];
+        const BatchProb& D = B.probs[k];
+        PairArgs A;
+        A.groups = D.groups;
+        A.ghash = D.ghash;
+        A.terms = D.terms;
+        A.terms_f = D.terms_f;
+        A.gkeys = D.gkeys;
+        A.gtable = D.gtable;
+        A.n_groups = D.n_groups;
+        A.maxpop = D.maxpop;
+        A.keys = B.keys + D.s0 * W;
+        A.khash = B.khash + D.s0;
+        A.ktable = D.ktable;
+        A.M = D.M;
+        A.per_chunk = D.per_chunk;
+        const uint32_t smin = B.sigmin[k], smax = B.sigmax[k];
+        const bool sig = smin == smax;
+        A.sig_pa = static_cast<int>(smin >> 8);
+        A.sig_n = static_cast<int>(smin & 255u);
+        read_stash_counts(A);
+        const int64_t u = t - D.item0;
+        const int64_t tile = u / D.chunks;
+        const int chunk = static_cast<int>(u - tile * D.chunks);
+        Rows<W, NR> R;
+        load_rows<W, NR>(A, R, rowkey, tile);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r * kWave + lane] = Acc{};
+        __syncthreads();
+        AccSink<W, PREC, false, NR> sink;
+        sink.groups = static_cast<const GroupRec<W>*>(A.groups);
+        sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
+        sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
+        sink.q = q;
+        sink.lq = lq;
+        sink.acc = acc;
+        sink.rowkey = rowkey;
+        sink.nrows = R.n;
+        if (D.variant == 1)
+            find_batch<W, NR>(A, R, chunk, sink);
+        else if (sig)
+            find_terms<W, 1, NR>(A, R, chunk, sink);
+        else
+            find_terms<W, 0, NR>(A, R, chunk, sink);
+        sink.finish();
+        if (lane < R.n) {
+            Acc s{};
+            for (int l = 0; l < kWave; ++l) acc_plus(s, acc[lane * kWave + l]);
+            auto* part = static_cast<double2*>(partial_all) + D.pbase;
+            store_acc(part, static_cast<int64_t>(chunk) * D.M + R.row0 + lane, s);
+        }
+        if (lane == 0) atomicAdd(B.pairs + k, static_cast<unsigned long long>(sink.hits));
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -616,6 +713,42 @@ hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& 
                        : dispatch_variant<1, false>(variant, precision, A, P, v, partial, st);
     return adjoint ? dispatch_variant<2, true>(variant, precision, A, P, v, partial, st)
                    : dispatch_variant<2, false>(variant, precision, A, P, v, partial, st);
+}
+
+template <int W, int PREC, int NR>
+static void batch_kernel_ptr(const void** f) {
+    *f = reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR>);
+}
+
+static const void* batch_kernel(int W, int precision, int rows) {
+    const void* f = nullptr;
+    const int key = (W == 1 ? 0 : 4) + (precision == 0 ? 0 : 2) + (rows == 4 ? 0 : 1);
+    switch (key) {
+        case 0: batch_kernel_ptr<1, 0, 4>(&f); break;
+        case 1: batch_kernel_ptr<1, 0, 8>(&f); break;
+        case 2: batch_kernel_ptr<1, 1, 4>(&f); break;
+        case 3: batch_kernel_ptr<1, 1, 8>(&f); break;
+        case 4: batch_kernel_ptr<2, 0, 4>(&f); break;
+        case 5: batch_kernel_ptr<2, 0, 8>(&f); break;
+        case 6: batch_kernel_ptr<2, 1, 4>(&f); break;
+        default: batch_kernel_ptr<2, 1, 8>(&f); break;
+    }
+    return f;
+}
+
+int batch_blocks_per_cu(int W, int precision, int rows) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, precision, rows), kWave, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st) {
+    const void* vec = precision == 0 ? static_cast<const void*>(B.a) : static_cast<const void*>(B.af);
+    void* part = B.partial;
+    void* args[] = {const_cast<BatchDev*>(&B), &vec, &part};
+    return hipLaunchKernel(batch_kernel(B.W, precision, rows), dim3(static_cast<unsigned>(blocks)), dim3(kWave),
+                           args, 0, st);
 }
 
 template <int W>
