@@ -11,7 +11,10 @@ rank <= 4 excitations), JW Hamiltonian from seeded random integrals; inputs
 are resident in device memory before timing starts.
 
 Prints one JSON line.  value = coupled pairs/s of the compensated-FP32 form;
-the plain FP64 form is reported beside it.
+the plain FP64 form is reported beside it.  The "batched" object times the
+64-problem batched launch (qubit counts 16..40, unique batches 10^3..10^5,
+one persistent launch replayed from a HIP graph, autotuned schedule)
+against the same problems run as 64 sequential single launches.
 """
 from __future__ import annotations
 
@@ -48,6 +51,7 @@ def parse():
     ap.add_argument("--variant", default="terms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", action="store_true", help="time only the headline variant")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-launch measurement")
     return ap.parse_args()
 
 
@@ -199,8 +203,91 @@ def main():
                                    "sample": f"all {M} rows of the workload, one forward pass "
                                              f"({cpu_s:.2f} s wall)",
                                    "samples_per_s": M / cpu_s}
+    if not args.no_batched:
+        rec["batched"] = bench_batched(args)
     print(json.dumps(rec))
     eng.close()
+
+
+def bench_batched(args):
+    """The batched launch over 64 problems against 64 sequential launches."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    from synth import configs
+
+    t0 = time.perf_counter()
+    ws = configs.batched()
+    probs = [{"n_qubits": w.n_qubits, "coeff": w.ham.coeff, "xy": w.ham.xy, "yz": w.ham.yz,
+              "keys": torch.from_numpy(w.keys.view(np.int64)).cuda(), "logpsi": torch.from_numpy(w.logpsi).cuda()}
+             for w in ws]
+    b = pe.Batch(probs)
+    S = sum(w.n_unique for w in ws)
+    print(f"# batched: {len(ws)} problems, {S} samples, {sum(w.ham.n_terms for w in ws)} terms "
+          f"(set up in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    schedule, _ = b.tune("fp32c")
+    tune_s = time.perf_counter() - t0
+    print(f"# batched: tuned in {tune_s:.1f} s: {schedule}", file=sys.stderr, flush=True)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {"workload": f"{len(ws)} problems: {min(w.n_qubits for w in ws)}..{max(w.n_qubits for w in ws)} qubits, "
+                       f"{S} unique samples in all ({min(w.n_unique for w in ws)}..{max(w.n_unique for w in ws)} "
+                       f"per problem), |psi|^2 weights",
+           "schedule": schedule, "tune_s": tune_s}
+    for prec in ("fp32c", "fp64"):
+        b.set_graph(True)
+        ms = timed(lambda: b.run(prec, check=False), args.steps)
+        b.check()
+        pairs = int(b.pair_counts().sum())
+        b.set_graph(False)
+        ms_eager = timed(lambda: b.run(prec, check=False), args.steps)
+        b.check()
+        b.set_graph(True)
+        out[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "samples_per_s": S / (ms * 1e-3),
+                     "eager_ms_per_step": ms_eager}
+        out["coupled_pairs"] = pairs
+        print(f"# batched {prec}: graph {ms:.3f} ms, eager {ms_eager:.3f} ms, {pairs} pairs",
+              file=sys.stderr, flush=True)
+    # the same problems one by one: one context each (Hamiltonian ingested
+    # once), each step sets the samples and runs the forward pass
+    engines = []
+    for k, w in enumerate(ws):
+        e = pe.Engine(0)
+        e.set_hamiltonian(w.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
+        info = b.problem_info(k)
+        engines.append((e, info["variant"], probs[k]["keys"], probs[k]["logpsi"],
+                        torch.empty(w.n_unique, dtype=torch.complex128, device="cuda"),
+                        torch.empty(4, dtype=torch.float64, device="cuda")))
+
+    def sequential(prec):
+        for e, var, keys, L, o, s in engines:
+            e.set_samples(keys)
+            e.local_energy(L, None, var, prec, out=o, stats=s, check=False)
+
+    for prec in ("fp32c", "fp64"):
+        ms = timed(lambda: sequential(prec), max(1, args.steps // 4))
+        out[prec]["sequential_ms_per_step"] = ms
+        out[prec]["speedup_vs_sequential"] = ms / out[prec]["ms_per_step"]
+        print(f"# sequential {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    out["fp32c_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
+    for e, *_ in engines:
+        e.close()
+    b.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -104,8 +104,8 @@ BatchDev dev_view(const eloc_batch b) {
     B.slots = b->kslots.as<uint32_t>();
     int64_t ns = 0;
     for (uint64_t c : b->kcap) ns += static_cast<int64_t>(c);
-    B.n_slots = ns;
-    B.stash = b->kstash.as<uint32_t>();
+    B.n_slot_words = ns * static_cast<int64_t>(slot_bytes(b->W) / sizeof(uint32_t));
+    B.stash = b->kstash.as<Stash>();
     B.err = b->err_dev.as<uint32_t>();
     B.sigmin = b->sigmin.as<uint32_t>();
     B.sigmax = b->sigmax.as<uint32_t>();
@@ -220,14 +220,14 @@ int run(eloc_batch b, int precision) {
 
 // Group membership tables (LoopOverBatch), built once; a new salt is drawn if
 // an insertion does not settle.
-int build_group_table(eloc_batch b, const uint64_t* hash, int64_t n, uint32_t* slots, uint32_t* stash, uint64_t cap,
+int build_group_table(eloc_batch b, const uint64_t* hash, int64_t n, void* slots, Stash* stash, uint64_t cap,
                       Table* out) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         Table T = make_table(slots, stash, cap, n, splitmix64(b->salt_state));
-        BATCH_HIP(b, hipMemset(slots, 0, sizeof(uint32_t) * cap));
-        BATCH_HIP(b, hipMemset(stash, 0, sizeof(uint32_t) * (1 + kStash)));
+        BATCH_HIP(b, hipMemset(slots, 0, slot_bytes(b->W) * cap));
+        BATCH_HIP(b, hipMemset(stash, 0, sizeof(Stash)));
         BATCH_HIP(b, hipMemset(b->err_dev.p, 0, sizeof(uint32_t)));
-        BATCH_HIP(b, launch_table_insert(0, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
+        BATCH_HIP(b, launch_table_insert(b->W, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
         BATCH_HIP(b, hipMemcpy(b->err_host, b->err_dev.p, sizeof(uint32_t), hipMemcpyDeviceToHost));
         if (!(b->err_host[0] & kErrTable)) {
             *out = T;
@@ -266,9 +266,9 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         kcoff[static_cast<size_t>(k)] = kc;
         nt += h.n_terms;
         ng += h.G;
-        gc[static_cast<size_t>(k)] = pow2_at_least(static_cast<uint64_t>(4 * h.G));
+        gc[static_cast<size_t>(k)] = table_capacity(h.G);
         gcap += static_cast<int64_t>(gc[static_cast<size_t>(k)]);
-        b->kcap[static_cast<size_t>(k)] = pow2_at_least(static_cast<uint64_t>(4 * probs[k].n_unique));
+        b->kcap[static_cast<size_t>(k)] = table_capacity(probs[k].n_unique);
         kc += static_cast<int64_t>(b->kcap[static_cast<size_t>(k)]);
     }
     BATCH_HIP(b, b->groups.ensure(sizeof(GroupRec<W>) * ng));
@@ -276,10 +276,10 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
     BATCH_HIP(b, b->gkeys.ensure(sizeof(uint64_t) * ng * W));
     BATCH_HIP(b, b->terms.ensure(sizeof(TermRec<W>) * nt));
     BATCH_HIP(b, b->terms_f.ensure(sizeof(TermRecF<W>) * nt));
-    BATCH_HIP(b, b->gslots.ensure(sizeof(uint32_t) * gcap));
-    BATCH_HIP(b, b->gstash.ensure(sizeof(uint32_t) * (1 + kStash) * n));
-    BATCH_HIP(b, b->kslots.ensure(sizeof(uint32_t) * kc));
-    BATCH_HIP(b, b->kstash.ensure(sizeof(uint32_t) * (1 + kStash) * n));
+    BATCH_HIP(b, b->gslots.ensure(slot_bytes(W) * gcap));
+    BATCH_HIP(b, b->gstash.ensure(sizeof(Stash) * n));
+    BATCH_HIP(b, b->kslots.ensure(slot_bytes(W) * kc));
+    BATCH_HIP(b, b->kstash.ensure(sizeof(Stash) * n));
     auto* groups = b->groups.as<GroupRec<W>>();
     auto* terms = b->terms.as<TermRec<W>>();
     auto* terms_f = b->terms_f.as<TermRecF<W>>();
@@ -301,8 +301,8 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         D.terms = terms + to;
         D.terms_f = terms_f + to;
         D.gkeys = b->gkeys.as<uint64_t>() + go * W;
-        uint32_t* gs = b->gslots.as<uint32_t>() + gcoff[static_cast<size_t>(k)];
-        uint32_t* gst = b->gstash.as<uint32_t>() + static_cast<size_t>(k) * (1 + kStash);
+        void* gs = b->gslots.as<char>() + slot_bytes(W) * static_cast<size_t>(gcoff[static_cast<size_t>(k)]);
+        Stash* gst = b->gstash.as<Stash>() + k;
         const int rc = build_group_table(b, D.ghash, h.G, gs, gst, gc[static_cast<size_t>(k)], &D.gtable);
         if (rc) return rc;
         D.n_groups = static_cast<int32_t>(h.G);
@@ -311,8 +311,8 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         I.n_terms = h.n_terms;
         I.G = h.G;
         I.maxpop = h.maxpop;
-        D.kslots = b->kslots.as<uint32_t>() + kcoff[static_cast<size_t>(k)];
-        D.kstash = b->kstash.as<uint32_t>() + static_cast<size_t>(k) * (1 + kStash);
+        D.kslots = b->kslots.as<char>() + slot_bytes(W) * static_cast<size_t>(kcoff[static_cast<size_t>(k)]);
+        D.kstash = b->kstash.as<Stash>() + k;
         D.ktable = make_table(D.kslots, D.kstash, b->kcap[static_cast<size_t>(k)], I.M, splitmix64(b->salt_state));
     }
     return ELOC_OK;
@@ -431,8 +431,7 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
     b->device = device;
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->n = n;
-    uint64_t s = 0x2408076250ull;
-    for (int q = 0; q < 128; ++q) b->R[q] = splitmix64(s);
+    make_hash_words(b->R);
     if (hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || b->n_cu < 1)
         return bfail(b, ELOC_EHIP, "compute unit count");
     if (hipHostMalloc(reinterpret_cast<void**>(&b->err_host), sizeof(uint32_t) * kMaxBatch, hipHostMallocDefault) !=

@@ -26,9 +26,9 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock
 __global__ __launch_bounds__(kBlock) void k_bt_clear(BatchDev B) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    for (int64_t i = t0; i < B.n_slots; i += stride) B.slots[i] = 0u;
-    for (int64_t i = t0; i < static_cast<int64_t>(B.n) * (1 + kStash); i += stride) B.stash[i] = 0u;
+    for (int64_t i = t0; i < B.n_slot_words; i += stride) B.slots[i] = 0u;
     if (t0 < B.n) {
+        B.stash[t0].count = 0u;
         B.err[t0] = 0u;
         B.sigmin[t0] = 0xFFFFFFFFu;
         B.sigmax[t0] = 0u;
@@ -95,13 +95,14 @@ __global__ __launch_bounds__(kBlock) void k_bt_hash(BatchDev B) {
     }
 }
 
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_bt_insert(BatchDev B) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= B.S) return;
     const int k = B.pid[i];
     const BatchProb& P = B.probs[k];
-    table_insert_one(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
-                     static_cast<uint32_t>(kErrTable));
+    table_insert_one<W>(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
+                        static_cast<uint32_t>(kErrTable));
 }
 
 // every key must find itself (U unique)
@@ -299,16 +300,16 @@ __global__ __launch_bounds__(kBlock) void k_bt_energy4(BatchDev B) {
 }  // namespace
 
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st) {
-    const int64_t clear_n = B.n_slots > B.S ? B.n_slots : B.S;
+    const int64_t clear_n = B.n_slot_words > B.S ? B.n_slot_words : B.S;
     const unsigned clear_blocks = blocks_for(clear_n) < 4096u ? blocks_for(clear_n) : 4096u;
     hipLaunchKernelGGL(k_bt_clear, dim3(clear_blocks), dim3(kBlock), 0, st, B);
     if (B.W == 1) {
         hipLaunchKernelGGL(k_bt_hash<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_bt_insert<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
         hipLaunchKernelGGL(k_bt_verify<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
     } else {
         hipLaunchKernelGGL(k_bt_hash<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_bt_insert<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
         hipLaunchKernelGGL(k_bt_verify<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
     }
     hipLaunchKernelGGL(k_bt_minmax, dim3(static_cast<unsigned>(B.n_tiles)), dim3(kBlock), 0, st, B);

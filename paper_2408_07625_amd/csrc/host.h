@@ -55,7 +55,7 @@ inline uint64_t pow2_at_least(uint64_t v) {
     return c;
 }
 
-inline Table make_table(uint32_t* slots, uint32_t* stash, uint64_t capacity, int64_t n, uint64_t salt) {
+inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n, uint64_t salt) {
     Table T;
     T.stash = stash;
     T.slots = slots;
@@ -63,9 +63,38 @@ inline Table make_table(uint32_t* slots, uint32_t* stash, uint64_t capacity, int
     T.ibits = std::max(1, bits_for(static_cast<uint64_t>(n)));   // index + 1 <= n
     T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
     T.fpshift = 32 + T.ibits;
-    T.altshift = bits_for(capacity - 1);
+    T.capbits = bits_for(capacity - 1);
     T.salt = salt;
     return T;
+}
+
+// Slots of a membership table for n keys: capacity (a power of two, load
+// <= 1/4) and bytes per slot for keys of W words.
+inline uint64_t table_capacity(int64_t n) { return pow2_at_least(static_cast<uint64_t>(4 * std::max<int64_t>(n, 1))); }
+inline size_t slot_bytes(int W) { return W == 1 ? sizeof(uint64_t) : sizeof(uint32_t); }
+
+// The 128 words R of the linear hash.  The first 64 are drawn until they are
+// linearly independent over GF(2), so that the hash is a bijection of
+// one-word keys (what makes one-word lookups exact without a key compare).
+inline void make_hash_words(uint64_t R[128]) {
+    uint64_t s = 0x2408076250ull;
+    uint64_t basis[64] = {};   // basis[b]: reduced vector with leading bit b
+    int q = 0;
+    while (q < 64) {
+        const uint64_t v = splitmix64(s);
+        uint64_t r = v;
+        for (int b = 63; b >= 0 && r; --b) {
+            if (!((r >> b) & 1ull)) continue;
+            if (basis[b]) {
+                r ^= basis[b];
+            } else {
+                basis[b] = r;
+                break;
+            }
+        }
+        if (r) R[q++] = v;
+    }
+    for (; q < 128; ++q) R[q] = splitmix64(s);
 }
 
 }  // namespace eloc

@@ -50,40 +50,58 @@ struct TermRecF {
 // Membership tables.  Keys are looked up through a GF(2)-linear 64-bit hash
 // lin(x) = XOR of R[q] over the set bits q of x, so lin(x ^ y) =
 // lin(x) ^ lin(y): the hash of a candidate x ^ XY is one XOR of two
-// precomputed hashes.  The table is a two-choice cuckoo table of uint32
-// slots holding (fingerprint << ibits) | (index + 1), 0 = empty, load factor
-// <= 1/4: a key sits in one of its two slots, so a lookup is exactly two
-// independent loads, and a fingerprint match is confirmed by comparing the
-// stored key.  Slot bits, alternate-slot bits and fingerprint bits are
-// disjoint fields of (hash ^ salt).  A key whose insertion does not settle
-// goes to a small stash (A. Kirsch, M. Mitzenmacher, U. Wieder, "More robust
-// hashing: cuckoo hashing with a stash", 2009) that lookups scan only when
-// it is non-empty.
+// precomputed hashes.  The table is a two-choice cuckoo table (load factor
+// <= 1/4): a key sits in one of its two slots, so a lookup is exactly two
+// independent loads.  With hs = lin(x) ^ salt and c = log2(capacity), slot 1
+// is the low c bits of hs and slot 2 is slot 1 XOR ((hs >> c) | 1).
+//
+// One-word keys (N <= 64): R[0..63] are linearly independent, so lin is a
+// bijection of 64-bit words and equal hashes mean equal keys.  A 64-bit slot
+// stores (hs >> c) << (ibits + 1) | which << ibits | (index + 1): its
+// position and contents give back all of hs, so a lookup is exact with no
+// further load (which = 1 marks a key sitting in its slot 2).
+//
+// Two-word keys: 32-bit slots hold (fingerprint << ibits) | (index + 1),
+// fingerprint = bits of hs above bit 32 + ibits (never 0), and a match is
+// confirmed by comparing the stored key.
+//
+// Slots are 0 when empty.  A key whose insertion does not settle goes to a
+// small stash (A. Kirsch, M. Mitzenmacher, U. Wieder, "More robust hashing:
+// cuckoo hashing with a stash", 2009), scanned only when it is non-empty.
 // ---------------------------------------------------------------------------
 constexpr int kStash = 32;
 
+struct Stash {
+    uint32_t count;
+    uint32_t pad;
+    uint32_t idx[kStash];     // key index
+    uint64_t hs[kStash];      // salted hash of that key
+};
+
 struct Table {
-    const uint32_t* slots;
+    const void* slots;  // uint64 (one-word keys) or uint32 (two-word keys)
     uint32_t mask;      // capacity - 1
     int ibits;          // bits of index + 1
     uint32_t imask;     // (1 << ibits) - 1
-    int fpshift;        // fingerprint = top 32 - ibits bits
-    int altshift;       // log2(capacity)
+    int fpshift;        // two-word keys: fingerprint = hs >> fpshift
+    int capbits;        // log2(capacity)
     uint64_t salt;
-    const uint32_t* stash;   // [1 + kStash]: count, then slot values
+    const Stash* stash;
 };
 
-__host__ __device__ __forceinline__ uint32_t slot1(const Table& T, uint64_t h) {
-    return static_cast<uint32_t>(h ^ T.salt) & T.mask;
+__host__ __device__ __forceinline__ uint32_t slot1(const Table& T, uint64_t hs) {
+    return static_cast<uint32_t>(hs) & T.mask;
 }
-__host__ __device__ __forceinline__ uint32_t slot2(const Table& T, uint64_t h) {
-    const uint64_t k = h ^ T.salt;
-    return (static_cast<uint32_t>(k) ^ (static_cast<uint32_t>(k >> T.altshift) | 1u)) & T.mask;
+__host__ __device__ __forceinline__ uint32_t slot2(const Table& T, uint64_t hs) {
+    return (static_cast<uint32_t>(hs) ^ (static_cast<uint32_t>(hs >> T.capbits) | 1u)) & T.mask;
 }
-// never 0, so an empty slot (0) cannot match
-__host__ __device__ __forceinline__ uint32_t fingerprint(const Table& T, uint64_t h) {
-    return static_cast<uint32_t>((h ^ T.salt) >> T.fpshift) | 1u;
+// two-word keys; never 0, so an empty slot cannot match
+__host__ __device__ __forceinline__ uint32_t fingerprint(const Table& T, uint64_t hs) {
+    return static_cast<uint32_t>(hs >> T.fpshift) | 1u;
 }
+// one-word keys: what (slot >> ibits) holds for a key of salted hash hs in
+// its slot 1 (| 1 in its slot 2)
+__host__ __device__ __forceinline__ uint64_t tag(const Table& T, uint64_t hs) { return (hs >> T.capbits) << 1; }
 
 template <int W>
 __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b) {
@@ -92,64 +110,118 @@ __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b)
     return eq;
 }
 
-// Second half of a lookup: the two slot values v1, v2 are loaded; `nstash`
-// is the stash count (wave-uniform).  Index of the key in `keys`, or -1.
+// Slot values of a lookup: 64-bit words for one-word keys, else 32-bit.
 template <int W>
-__device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1,
-                                            uint32_t v2, uint32_t fp, const uint64_t* key, int nstash) {
+struct SlotT {
+    using type = uint32_t;
+};
+template <>
+struct SlotT<1> {
+    using type = uint64_t;
+};
+
+template <int W>
+__device__ __forceinline__ typename SlotT<W>::type load_slot(const Table& T, uint32_t s) {
+    return static_cast<const typename SlotT<W>::type*>(T.slots)[s];
+}
+
+// Second half of a lookup of a key with salted hash hs, given its two slot
+// values; `nstash` is the stash count (wave-uniform).  Index of the key in
+// `keys`, or -1.
+__device__ __forceinline__ int table_settle1(const Table& T, uint64_t v1, uint64_t v2, uint64_t hs, int nstash) {
+    const uint64_t t = tag(T, hs);
+    int j = -1;
+    if ((v1 >> T.ibits) == t) j = static_cast<int>(v1 & T.imask) - 1;
+    if ((v2 >> T.ibits) == (t | 1u)) j = static_cast<int>(v2 & T.imask) - 1;
+    for (int k = 0; k < nstash && k < kStash; ++k)
+        if (T.stash->hs[k] == hs) j = static_cast<int>(T.stash->idx[k]);
+    return j;
+}
+
+__device__ __forceinline__ int table_settle2(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1,
+                                             uint32_t v2, uint64_t hs, const uint64_t* key, int nstash) {
+    const uint32_t fp = fingerprint(T, hs);
     int j = -1;
     if ((v1 >> T.ibits) == fp) {
         const int j1 = static_cast<int>(v1 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
+        if (keys_equal<2>(keys + static_cast<size_t>(j1) * 2, key)) j = j1;
     }
     if (j < 0 && (v2 >> T.ibits) == fp) {
         const int j2 = static_cast<int>(v2 & T.imask) - 1;
-        if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
+        if (keys_equal<2>(keys + static_cast<size_t>(j2) * 2, key)) j = j2;
     }
-    if (nstash > 0) {
-        for (int k = 0; k < nstash && k < kStash; ++k) {
-            const uint32_t v = T.stash[1 + k];
-            if (j < 0 && (v >> T.ibits) == fp) {
-                const int js = static_cast<int>(v & T.imask) - 1;
-                if (keys_equal<W>(keys + static_cast<size_t>(js) * W, key)) j = js;
-            }
+    for (int k = 0; k < nstash && k < kStash; ++k) {
+        if (j < 0 && T.stash->hs[k] == hs) {
+            const int js = static_cast<int>(T.stash->idx[k]);
+            if (keys_equal<2>(keys + static_cast<size_t>(js) * 2, key)) j = js;
         }
     }
     return j;
 }
 
 template <int W>
-__device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys,
-                                          uint64_t h, const uint64_t* key) {
-    const uint32_t fp = fingerprint(T, h);
-    return table_settle<W>(T, keys, T.slots[slot1(T, h)], T.slots[slot2(T, h)], fp, key,
-                           static_cast<int>(T.stash[0]));
+__device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys,
+                                            typename SlotT<W>::type v1, typename SlotT<W>::type v2, uint64_t hs,
+                                            const uint64_t* key, int nstash) {
+    if constexpr (W == 1)
+        return table_settle1(T, v1, v2, hs, nstash);
+    else
+        return table_settle2(T, keys, v1, v2, hs, key, nstash);
 }
 
-// Cuckoo insertion of value i + 1 (hash hash[i]): place it in one of its two
+// Full lookup of a key with (unsalted) hash h.
+template <int W>
+__device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys, uint64_t h,
+                                          const uint64_t* key) {
+    const uint64_t hs = h ^ T.salt;
+    return table_settle<W>(T, keys, load_slot<W>(T, slot1(T, hs)), load_slot<W>(T, slot2(T, hs)), hs, key,
+                           static_cast<int>(T.stash->count));
+}
+
+// Cuckoo insertion of key i (hash hash[i]): place it in one of its two
 // slots, evicting the occupant to its other slot; after kMaxKicks moves the
-// value in hand goes to the stash, or the error bit is set if that is full.
+// key in hand goes to the stash, or the error bit is set if that is full.
 constexpr int kMaxKicks = 256;
 
-__device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ hash, int64_t i,
-                                                 uint32_t* __restrict__ slots, uint32_t* __restrict__ stash,
-                                                 const Table& T, uint32_t* __restrict__ err, uint32_t err_bit) {
-    uint64_t h = hash[i];
-    uint32_t v = (fingerprint(T, h) << T.ibits) | static_cast<uint32_t>(i + 1);
-    uint32_t s = slot1(T, h);
-    for (int k = 0; k < kMaxKicks; ++k) {
-        const uint32_t old = atomicExch(slots + s, v);
-        if (old == 0u) return;
-        v = old;
-        h = hash[(old & T.imask) - 1u];
-        const uint32_t a = slot1(T, h);
-        s = (s == a) ? slot2(T, h) : a;
+template <int W>
+__device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ hash, int64_t i, void* slots_v,
+                                                 Stash* __restrict__ stash, const Table& T,
+                                                 uint32_t* __restrict__ err, uint32_t err_bit) {
+    uint64_t hs = hash[i] ^ T.salt;
+    int64_t held = i;   // index of the key in hand
+    if constexpr (W == 1) {
+        auto* slots = static_cast<unsigned long long*>(slots_v);
+        unsigned long long v = ((hs >> T.capbits) << (T.ibits + 1)) | static_cast<unsigned long long>(i + 1);
+        uint32_t s = slot1(T, hs);
+        for (int k = 0; k < kMaxKicks; ++k) {
+            const unsigned long long old = atomicExch(slots + s, v);
+            if (old == 0ull) return;
+            // the evicted key moves to its other slot (same XOR in both directions)
+            s ^= (static_cast<uint32_t>(old >> (T.ibits + 1)) | 1u) & T.mask;
+            v = old ^ (1ull << T.ibits);
+        }
+        held = static_cast<int64_t>(v & T.imask) - 1;
+    } else {
+        auto* slots = static_cast<uint32_t*>(slots_v);
+        uint32_t v = (fingerprint(T, hs) << T.ibits) | static_cast<uint32_t>(i + 1);
+        uint32_t s = slot1(T, hs);
+        for (int k = 0; k < kMaxKicks; ++k) {
+            const uint32_t old = atomicExch(slots + s, v);
+            if (old == 0u) return;
+            v = old;
+            const uint64_t ho = hash[(old & T.imask) - 1u] ^ T.salt;
+            const uint32_t a = slot1(T, ho);
+            s = (s == a) ? slot2(T, ho) : a;
+        }
+        held = static_cast<int64_t>(v & T.imask) - 1;
     }
-    const uint32_t k = atomicAdd(stash, 1u);
-    if (k < static_cast<uint32_t>(kStash))
-        stash[1 + k] = v;
-    else
+    const uint32_t k = atomicAdd(&stash->count, 1u);
+    if (k < static_cast<uint32_t>(kStash)) {
+        stash->idx[k] = static_cast<uint32_t>(held);
+        stash->hs[k] = hash[held] ^ T.salt;
+    } else {
         atomicOr(err, err_bit);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -253,8 +325,8 @@ struct BatchProb {
     int64_t s0;
     int64_t M;
     Table ktable;          // index values local to the problem
-    uint32_t* kslots;      // writable views of ktable's arrays
-    uint32_t* kstash;
+    void* kslots;          // writable views of ktable's arrays
+    Stash* kstash;
     // schedule
     int32_t chunks;
     int32_t per_chunk;
@@ -294,8 +366,8 @@ struct BatchDev {
     uint64_t* keys;            // [S][W] copy of the caller keys (zero-padded words)
     uint64_t* khash;           // [S]
     uint32_t* slots;           // all key-table slots (cleared per run)
-    int64_t n_slots;
-    uint32_t* stash;           // [n][1 + kStash]
+    int64_t n_slot_words;      // their size in 32-bit words
+    Stash* stash;              // [n]
     uint32_t* err;             // [n] error bits
     uint32_t* sigmin;          // [n] min / max of (even popcount << 8 | popcount) over U_k
     uint32_t* sigmax;
@@ -316,8 +388,8 @@ struct BatchDev {
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
                               int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
-hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, uint32_t* slots,
-                               uint32_t* stash, const Table& T, uint32_t* err, hipStream_t st);
+hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
+                               const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err,
                                 hipStream_t st);
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,

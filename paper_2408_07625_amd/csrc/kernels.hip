@@ -47,12 +47,13 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
     if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
 }
 
-__global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n,
-                                                         uint32_t* __restrict__ slots, uint32_t* __restrict__ stash,
-                                                         Table T, uint32_t* __restrict__ err) {
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n, void* slots,
+                                                         Stash* __restrict__ stash, Table T,
+                                                         uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    table_insert_one(hash, i, slots, stash, T, err, static_cast<uint32_t>(kErrTable));
+    table_insert_one<W>(hash, i, slots, stash, T, err, static_cast<uint32_t>(kErrTable));
 }
 
 // Duplicate check (every key must find itself) and the signature bitmap of
@@ -579,9 +580,12 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_table_insert(int, const uint64_t* hash, int64_t n, uint32_t* slots, uint32_t* stash,
-                               const Table& T, uint32_t* err, hipStream_t st) {
-    hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
+hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, void* slots, Stash* stash, const Table& T,
+                               uint32_t* err, hipStream_t st) {
+    if (W == 1)
+        hipLaunchKernelGGL(k_table_insert<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
+    else
+        hipLaunchKernelGGL(k_table_insert<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
     return hipGetLastError();
 }
 

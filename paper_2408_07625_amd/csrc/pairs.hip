@@ -106,8 +106,8 @@ struct Rows {
 };
 
 __device__ __forceinline__ void read_stash_counts(PairArgs& A) {
-    A.kstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.ktable.stash[0]));
-    A.gstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.gtable.stash[0]));
+    A.kstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.ktable.stash->count));
+    A.gstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.gtable.stash->count));
 }
 
 template <int W, int NR>
@@ -154,7 +154,8 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         const int g = base + lane;
         const bool valid = g < g1;
         uint64_t xp[NR][W];
-        uint32_t v1[NR], v2[NR], fp[NR];
+        typename SlotT<W>::type v1[NR], v2[NR];
+        uint64_t hs[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             bool ok = valid;
@@ -168,10 +169,9 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
                 }
             }
             if (SIG) ok = ok && pa == A.sig_pa && n == A.sig_n;
-            const uint64_t h = R.hx[r] ^ gh;
-            fp[r] = fingerprint(T, h);
-            v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
-            v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
+            hs[r] = (R.hx[r] ^ T.salt) ^ gh;
+            v1[r] = ok ? load_slot<W>(T, slot1(T, hs[r])) : 0u;
+            v2[r] = ok ? load_slot<W>(T, slot2(T, hs[r])) : 0u;
         }
         uint64_t nxy[W];
         int nrun = run;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int j = table_settle<W>(T, A.keys, v1[r], v2[r], fp[r], xp[r], A.kstash);
+            const int j = table_settle<W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash);
             sink.hit(r, j >= 0, g, j, run);
         }
         sink.flush();
@@ -215,7 +215,8 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
         const uint64_t hj = A.khash[jj];
         uint64_t m[NR][W];
-        uint32_t v1[NR], v2[NR], fp[NR];
+        typename SlotT<W>::type v1[NR], v2[NR];
+        uint64_t hs[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             int pc = 0;
@@ -225,14 +226,13 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
                 pc += popc64(m[r][w]);
             }
             const bool ok = valid && pc <= A.maxpop;
-            const uint64_t h = R.hx[r] ^ hj;
-            fp[r] = fingerprint(T, h);
-            v1[r] = ok ? T.slots[slot1(T, h)] : 0u;
-            v2[r] = ok ? T.slots[slot2(T, h)] : 0u;
+            hs[r] = (R.hx[r] ^ T.salt) ^ hj;
+            v1[r] = ok ? load_slot<W>(T, slot1(T, hs[r])) : 0u;
+            v2[r] = ok ? load_slot<W>(T, slot2(T, hs[r])) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int g = table_settle<W>(T, A.gkeys, v1[r], v2[r], fp[r], m[r], A.gstash);
+            const int g = table_settle<W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash);
             int run = 0;
             if (g >= 0) {
                 const GroupRec<W>& gr = groups[g];
