@@ -28,6 +28,37 @@ from pathlib import Path
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
+PROFILES = ROOT / "profiles"
+PAIR_SOURCES = [ROOT / "paper_2408_07625_amd" / "csrc" / f for f in ("pairs.hip", "device.h", "internal.h")]
+
+
+def pair_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in PAIR_SOURCES:
+        h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch of the pair kernel from a committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = PROFILES / name
+    if not path.exists():
+        return None
+    fields = {}
+    for line in path.read_text().splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_hash") != pair_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 # Algorithmic lane-op counts per unit of work of the fused pair kernel (W
 # 64-bit words per key); see the design notes for the derivation.
 def ops_per_candidate(W):
@@ -52,6 +83,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", action="store_true", help="time only the headline variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-launch measurement")
+    ap.add_argument("--calibrate-mib", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB (reads and writes it once), "
+                         "the reference kernel for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -161,7 +195,8 @@ def main():
     ops = candidates * ops_per_candidate(W) + term_evals * ops_per_term(W) + n_pairs * OPS_PER_PAIR
     achieved = ops / pair_avg_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-            "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": measured_traffic(f"k_pairs_{w.name}_{args.variant}_fp32c_traffic.md"),
             "kernel": "k_pairs (fused FindCoupledPairs + MatrixElement + accumulation)",
             "kernel_ms": pair_avg_s * 1e3,
             "ops_per_launch": ops}
@@ -205,6 +240,14 @@ def main():
                                    "samples_per_s": M / cpu_s}
     if not args.no_batched:
         rec["batched"] = bench_batched(args)
+    if args.calibrate_mib:
+        n = args.calibrate_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        rec["calibration_copy_bytes"] = 2 * n * 8
     print(json.dumps(rec))
     eng.close()
 

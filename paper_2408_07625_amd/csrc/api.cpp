@@ -136,15 +136,15 @@ int map_err(eloc_ctx c, uint32_t bits) {
 
 // Fill a cuckoo table with keys 0..n-1 (hashes `hash`); a new salt is drawn
 // if an insertion does not settle.
-int build_table(eloc_ctx c, int W, const uint64_t* hash, int64_t n, void* slots, Stash* stash, uint64_t cap,
+int build_table(eloc_ctx c, int tk, const uint64_t* hash, int64_t n, void* slots, Stash* stash, uint64_t cap,
                 Table* out) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         const uint64_t salt = splitmix64(c->salt_state);
         Table T = make_table(slots, stash, cap, n, salt);
-        ELOC_HIP(c, hipMemsetAsync(slots, 0, slot_bytes(W) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(slots, 0, slot_bytes(tk) * cap, c->stream));
         ELOC_HIP(c, hipMemsetAsync(stash, 0, sizeof(Stash), c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
-        ELOC_HIP(c, launch_table_insert(W, hash, n, slots, stash, T, c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_table_insert(tk, hash, n, slots, stash, T, c->err_prep.as<uint32_t>(), c->stream));
         const int bits = read_err(c, c->err_prep);
         if (bits < 0) return bits;
         if (!(static_cast<uint32_t>(bits) & kErrTable)) {
@@ -185,7 +185,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, c->ghash.ensure(sizeof(uint64_t) * G));
     ELOC_HIP(c, c->gkeys.ensure(sizeof(uint64_t) * G * W));
     const uint64_t cap = table_capacity(G);
-    ELOC_HIP(c, c->gslots.ensure(slot_bytes(W) * cap));
+    const int tk = table_kind(W, n_qubits <= 32);
+    ELOC_HIP(c, c->gslots.ensure(slot_bytes(tk) * cap));
     ELOC_HIP(c, hipMemcpy(c->groups.p, groups.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->terms.p, terms.data(), sizeof(TermRec<W>) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->terms_f.p, terms_f.data(), sizeof(TermRecF<W>) * n_terms, hipMemcpyHostToDevice));
@@ -193,12 +194,13 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
     ELOC_HIP(c, c->gstash.ensure(sizeof(Stash)));
     Table T;
-    int rc = build_table(c, W, c->ghash.as<uint64_t>(), G, c->gslots.p, c->gstash.as<Stash>(), cap, &T);
+    int rc = build_table(c, tk, c->ghash.as<uint64_t>(), G, c->gslots.p, c->gstash.as<Stash>(), cap, &T);
     if (rc) return rc;
 
     HamDev H;
     H.n_qubits = n_qubits;
     H.W = W;
+    H.narrow = n_qubits <= 32;
     H.n_terms = n_terms;
     H.n_groups = G;
     H.maxpop = maxpop;
@@ -423,7 +425,8 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     ELOC_HIP(c, c->keys.ensure(sizeof(uint64_t) * n_unique * W));
     ELOC_HIP(c, c->khash.ensure(sizeof(uint64_t) * n_unique));
     const uint64_t cap = table_capacity(n_unique);
-    ELOC_HIP(c, c->kslots.ensure(slot_bytes(W) * cap));
+    const int tk = table_kind(W, c->H.narrow);
+    ELOC_HIP(c, c->kslots.ensure(slot_bytes(tk) * cap));
     ELOC_HIP(c, c->kstash.ensure(sizeof(Stash)));
     ELOC_HIP(c, c->sig.ensure(sizeof(uint64_t) * kSigWords));
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
@@ -444,12 +447,13 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
         if (attempt == 8) return fail(c, ELOC_EHIP, "membership table could not be built");
         S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), cap, n_unique,
                              splitmix64(c->salt_state));
-        ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(W) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(tk) * cap, c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(Stash), c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
-        ELOC_HIP(c, launch_table_insert(W, c->khash.as<uint64_t>(), n_unique, c->kslots.p, c->kstash.as<Stash>(),
+        ELOC_HIP(c, launch_table_insert(tk, c->khash.as<uint64_t>(), n_unique, c->kslots.p, c->kstash.as<Stash>(),
                                         S.table, c->err_prep.as<uint32_t>(), c->stream));
-        ELOC_HIP(c, launch_sample_verify(W, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_sample_verify(W, c->H.narrow, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(),
+                                         c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->err_host, c->err_prep.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->sig_host, c->sig.p, sizeof(uint64_t) * kSigWords, hipMemcpyDeviceToHost,
                                    c->stream));

@@ -43,6 +43,8 @@ struct eloc_batch_s {
     std::string err;
     int n = 0;
     int W = 1;
+    bool narrow = true;   // every problem has at most 32 qubits
+    int tk = kTabNarrow;  // membership-table format
     int n_cu = 0;
     int64_t S = 0;
     uint64_t salt_state = 0xBA7C4ED5ull;
@@ -92,6 +94,7 @@ BatchDev dev_view(const eloc_batch b) {
     B.probs = b->probs.as<BatchProb>();
     B.n = b->n;
     B.W = b->W;
+    B.narrow = b->narrow;
     B.pid = b->pid.as<int32_t>();
     B.S = b->S;
     B.tiles = b->tiles_dev.as<RTile>();
@@ -104,7 +107,7 @@ BatchDev dev_view(const eloc_batch b) {
     B.slots = b->kslots.as<uint32_t>();
     int64_t ns = 0;
     for (uint64_t c : b->kcap) ns += static_cast<int64_t>(c);
-    B.n_slot_words = ns * static_cast<int64_t>(slot_bytes(b->W) / sizeof(uint32_t));
+    B.n_slot_words = ns * static_cast<int64_t>(slot_bytes(b->tk) / sizeof(uint32_t));
     B.stash = b->kstash.as<Stash>();
     B.err = b->err_dev.as<uint32_t>();
     B.sigmin = b->sigmin.as<uint32_t>();
@@ -175,7 +178,7 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
 
 int launch_blocks(eloc_batch b, int precision) {
     int per_cu = b->schedule.blocks_per_cu;
-    const int fit = batch_blocks_per_cu(b->W, precision, b->schedule.rows_per_wave);
+    const int fit = batch_blocks_per_cu(b->W, b->narrow, precision, b->schedule.rows_per_wave);
     if (per_cu <= 0 || (fit > 0 && per_cu > fit)) per_cu = fit > 0 ? fit : 1;
     return std::max(1, per_cu * b->n_cu);
 }
@@ -224,10 +227,10 @@ int build_group_table(eloc_batch b, const uint64_t* hash, int64_t n, void* slots
                       Table* out) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         Table T = make_table(slots, stash, cap, n, splitmix64(b->salt_state));
-        BATCH_HIP(b, hipMemset(slots, 0, slot_bytes(b->W) * cap));
+        BATCH_HIP(b, hipMemset(slots, 0, slot_bytes(b->tk) * cap));
         BATCH_HIP(b, hipMemset(stash, 0, sizeof(Stash)));
         BATCH_HIP(b, hipMemset(b->err_dev.p, 0, sizeof(uint32_t)));
-        BATCH_HIP(b, launch_table_insert(b->W, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
+        BATCH_HIP(b, launch_table_insert(b->tk, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
         BATCH_HIP(b, hipMemcpy(b->err_host, b->err_dev.p, sizeof(uint32_t), hipMemcpyDeviceToHost));
         if (!(b->err_host[0] & kErrTable)) {
             *out = T;
@@ -276,9 +279,9 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
     BATCH_HIP(b, b->gkeys.ensure(sizeof(uint64_t) * ng * W));
     BATCH_HIP(b, b->terms.ensure(sizeof(TermRec<W>) * nt));
     BATCH_HIP(b, b->terms_f.ensure(sizeof(TermRecF<W>) * nt));
-    BATCH_HIP(b, b->gslots.ensure(slot_bytes(W) * gcap));
+    BATCH_HIP(b, b->gslots.ensure(slot_bytes(b->tk) * gcap));
     BATCH_HIP(b, b->gstash.ensure(sizeof(Stash) * n));
-    BATCH_HIP(b, b->kslots.ensure(slot_bytes(W) * kc));
+    BATCH_HIP(b, b->kslots.ensure(slot_bytes(b->tk) * kc));
     BATCH_HIP(b, b->kstash.ensure(sizeof(Stash) * n));
     auto* groups = b->groups.as<GroupRec<W>>();
     auto* terms = b->terms.as<TermRec<W>>();
@@ -301,7 +304,7 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         D.terms = terms + to;
         D.terms_f = terms_f + to;
         D.gkeys = b->gkeys.as<uint64_t>() + go * W;
-        void* gs = b->gslots.as<char>() + slot_bytes(W) * static_cast<size_t>(gcoff[static_cast<size_t>(k)]);
+        void* gs = b->gslots.as<char>() + slot_bytes(b->tk) * static_cast<size_t>(gcoff[static_cast<size_t>(k)]);
         Stash* gst = b->gstash.as<Stash>() + k;
         const int rc = build_group_table(b, D.ghash, h.G, gs, gst, gc[static_cast<size_t>(k)], &D.gtable);
         if (rc) return rc;
@@ -311,7 +314,7 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         I.n_terms = h.n_terms;
         I.G = h.G;
         I.maxpop = h.maxpop;
-        D.kslots = b->kslots.as<char>() + slot_bytes(W) * static_cast<size_t>(kcoff[static_cast<size_t>(k)]);
+        D.kslots = b->kslots.as<char>() + slot_bytes(b->tk) * static_cast<size_t>(kcoff[static_cast<size_t>(k)]);
         D.kstash = b->kstash.as<Stash>() + k;
         D.ktable = make_table(D.kslots, D.kstash, b->kcap[static_cast<size_t>(k)], I.M, splitmix64(b->salt_state));
     }
@@ -460,6 +463,7 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
             if (!std::isfinite(p.coeff[l])) return bfail(b, ELOC_EINVAL, pre + "non-finite coefficient");
         }
         W = std::max(W, wk);
+        b->narrow = b->narrow && p.n_qubits <= 32;
         ProbInfo& I = b->info[static_cast<size_t>(k)];
         I.n_qubits = p.n_qubits;
         I.M = p.n_unique;
@@ -476,6 +480,7 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
         S += p.n_unique;
     }
     b->W = W;
+    b->tk = table_kind(W, b->narrow);
     b->S = S;
     // reduction tiles and the sample -> problem map
     std::vector<int32_t> pid(static_cast<size_t>(S));
@@ -644,7 +649,7 @@ int eloc_batch_tune(eloc_batch b, int precision, const char* cache_path, int* fr
         if (t.batch_ratio != best.batch_ratio) rc = trial(t);
     }
     {
-        const int fit = batch_blocks_per_cu(b->W, precision, best.rows_per_wave);
+        const int fit = batch_blocks_per_cu(b->W, b->narrow, precision, best.rows_per_wave);
         for (int bpc : {fit / 2, fit}) {
             if (rc || bpc < 1) continue;
             eloc_batch_schedule t = best;

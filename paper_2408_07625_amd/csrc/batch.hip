@@ -95,18 +95,18 @@ __global__ __launch_bounds__(kBlock) void k_bt_hash(BatchDev B) {
     }
 }
 
-template <int W>
+template <int TK>
 __global__ __launch_bounds__(kBlock) void k_bt_insert(BatchDev B) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= B.S) return;
     const int k = B.pid[i];
     const BatchProb& P = B.probs[k];
-    table_insert_one<W>(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
+    table_insert_one<TK>(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
                         static_cast<uint32_t>(kErrTable));
 }
 
 // every key must find itself (U unique)
-template <int W>
+template <int W, int TK>
 __global__ __launch_bounds__(kBlock) void k_bt_verify(BatchDev B) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= B.S) return;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_bt_verify(BatchDev B) {
     uint64_t key[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) key[w] = B.keys[i * W + w];
-    const int j = table_find<W>(P.ktable, B.keys + P.s0 * W, B.khash[i], key);
+    const int j = table_find<TK, W>(P.ktable, B.keys + P.s0 * W, B.khash[i], key);
     if (j != static_cast<int>(i - P.s0)) atomicOr(B.err + k, static_cast<uint32_t>(kErrDup));
 }
 
@@ -303,14 +303,19 @@ hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st) {
     const int64_t clear_n = B.n_slot_words > B.S ? B.n_slot_words : B.S;
     const unsigned clear_blocks = blocks_for(clear_n) < 4096u ? blocks_for(clear_n) : 4096u;
     hipLaunchKernelGGL(k_bt_clear, dim3(clear_blocks), dim3(kBlock), 0, st, B);
-    if (B.W == 1) {
-        hipLaunchKernelGGL(k_bt_hash<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_verify<1>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
+    const dim3 grid(blocks_for(B.S)), block(kBlock);
+    if (B.W == 2) {
+        hipLaunchKernelGGL(k_bt_hash<2>, grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_insert<kTabVerify>, grid, block, 0, st, B);
+        hipLaunchKernelGGL((k_bt_verify<2, kTabVerify>), grid, block, 0, st, B);
+    } else if (B.narrow) {
+        hipLaunchKernelGGL(k_bt_hash<1>, grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_insert<kTabNarrow>, grid, block, 0, st, B);
+        hipLaunchKernelGGL((k_bt_verify<1, kTabNarrow>), grid, block, 0, st, B);
     } else {
-        hipLaunchKernelGGL(k_bt_hash<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_bt_verify<2>, dim3(blocks_for(B.S)), dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_bt_hash<1>, grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_insert<kTabWide>, grid, block, 0, st, B);
+        hipLaunchKernelGGL((k_bt_verify<1, kTabWide>), grid, block, 0, st, B);
     }
     hipLaunchKernelGGL(k_bt_minmax, dim3(static_cast<unsigned>(B.n_tiles)), dim3(kBlock), 0, st, B);
     hipLaunchKernelGGL(k_bt_shift, dim3(blocks_for(B.n)), dim3(kBlock), 0, st, B, fp32 ? 1 : 0);

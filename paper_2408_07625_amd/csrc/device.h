@@ -121,46 +121,53 @@ __device__ __forceinline__ void mac(AccF& acc, F2 hr, F2 hi, float4 v) {
 // run: real part from [b, m), imaginary part from [m, e); each term adds
 // h' (-1)^|ket & YZ|.  Terms are visited with stride `step` from offset
 // `off` (step 1: one lane evaluates the whole run; step 64: the wave splits
-// it).
+// it).  NW: keys of at most 32 qubits (the parity needs the low word only).
 // ---------------------------------------------------------------------------
-template <int W>
-__device__ __forceinline__ double term_f64(const TermRec<W>& tr, const uint64_t* ket) {
-    int pc = 0;
+template <int W, bool NW>
+__device__ __forceinline__ int ket_parity(const uint64_t* yz, const uint64_t* ket) {
+    if constexpr (NW) {
+        return __popc(static_cast<uint32_t>(ket[0]) & static_cast<uint32_t>(yz[0])) & 1;
+    } else {
+        int pc = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) pc += popc64(ket[w] & tr.yz[w]);
-    return (pc & 1) ? -tr.h : tr.h;
+        for (int w = 0; w < W; ++w) pc += popc64(ket[w] & yz[w]);
+        return pc & 1;
+    }
 }
 
-template <int W>
+template <int W, bool NW = false>
+__device__ __forceinline__ double term_f64(const TermRec<W>& tr, const uint64_t* ket) {
+    return ket_parity<W, NW>(tr.yz, ket) ? -tr.h : tr.h;
+}
+
+template <int W, bool NW = false>
 __device__ __forceinline__ void melem(const TermRec<W>* __restrict__ terms, int b, int m, int e, int off, int step,
                                       const uint64_t* ket, double& hr, double& hi) {
     hr = 0.0;
     hi = 0.0;
-    for (int t = b + off; t < m; t += step) hr += term_f64<W>(terms[t], ket);
-    for (int t = m + off; t < e; t += step) hi += term_f64<W>(terms[t], ket);
+    for (int t = b + off; t < m; t += step) hr += term_f64<W, NW>(terms[t], ket);
+    for (int t = m + off; t < e; t += step) hi += term_f64<W, NW>(terms[t], ket);
 }
 
-template <int W>
+template <int W, bool NW = false>
 __device__ __forceinline__ void term_f32(const TermRecF<W>& tr, const uint64_t* ket, float& vh, float& vl) {
-    int pc = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) pc += popc64(ket[w] & tr.yz[w]);
-    vh = (pc & 1) ? -tr.h_hi : tr.h_hi;
-    vl = (pc & 1) ? -tr.h_lo : tr.h_lo;
+    const bool odd = ket_parity<W, NW>(tr.yz, ket);
+    vh = odd ? -tr.h_hi : tr.h_hi;
+    vl = odd ? -tr.h_lo : tr.h_lo;
 }
 
-template <int W>
+template <int W, bool NW = false>
 __device__ __forceinline__ void melem(const TermRecF<W>* __restrict__ terms, int b, int m, int e, int off, int step,
                                       const uint64_t* ket, F2& hr, F2& hi) {
     hr = F2{0.f, 0.f};
     hi = F2{0.f, 0.f};
     float vh, vl;
     for (int t = b + off; t < m; t += step) {
-        term_f32<W>(terms[t], ket, vh, vl);
+        term_f32<W, NW>(terms[t], ket, vh, vl);
         acc_add(hr, vh, vl);
     }
     for (int t = m + off; t < e; t += step) {
-        term_f32<W>(terms[t], ket, vh, vl);
+        term_f32<W, NW>(terms[t], ket, vh, vl);
         acc_add(hi, vh, vl);
     }
 }

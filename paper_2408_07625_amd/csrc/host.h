@@ -68,31 +68,44 @@ inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n,
     return T;
 }
 
-// Slots of a membership table for n keys: capacity (a power of two, load
-// <= 1/4) and bytes per slot for keys of W words.
+// Slots of a membership table for n keys: a power of two, load <= 1/4.
 inline uint64_t table_capacity(int64_t n) { return pow2_at_least(static_cast<uint64_t>(4 * std::max<int64_t>(n, 1))); }
-inline size_t slot_bytes(int W) { return W == 1 ? sizeof(uint64_t) : sizeof(uint32_t); }
 
-// The 128 words R of the linear hash.  The first 64 are drawn until they are
-// linearly independent over GF(2), so that the hash is a bijection of
-// one-word keys (what makes one-word lookups exact without a key compare).
+// Adds v to a GF(2) basis (basis[b]: reduced vector with leading bit b);
+// false if v depends on it.
+template <class T, int B>
+inline bool gf2_insert(T (&basis)[B], T v) {
+    for (int b = B - 1; b >= 0 && v; --b) {
+        if (!((v >> b) & 1u)) continue;
+        if (!basis[b]) {
+            basis[b] = v;
+            return true;
+        }
+        v ^= basis[b];
+    }
+    return false;
+}
+
+// The 128 words R of the linear hash.  R[0..31] are drawn until their low
+// 32 bits are linearly independent over GF(2), and R[0..63] until they are
+// independent as 64-bit words: the low half of the hash is then a bijection
+// of keys of up to 32 qubits and the whole hash a bijection of one-word
+// keys, which makes those lookups exact without a key compare.
 inline void make_hash_words(uint64_t R[128]) {
     uint64_t s = 0x2408076250ull;
-    uint64_t basis[64] = {};   // basis[b]: reduced vector with leading bit b
+    uint32_t b32[32] = {};
+    uint64_t b64[64] = {};
     int q = 0;
+    while (q < 32) {
+        const uint64_t v = splitmix64(s);
+        if (gf2_insert(b32, static_cast<uint32_t>(v))) {
+            (void)gf2_insert(b64, v);   // independent: its low half already is
+            R[q++] = v;
+        }
+    }
     while (q < 64) {
         const uint64_t v = splitmix64(s);
-        uint64_t r = v;
-        for (int b = 63; b >= 0 && r; --b) {
-            if (!((r >> b) & 1ull)) continue;
-            if (basis[b]) {
-                r ^= basis[b];
-            } else {
-                basis[b] = r;
-                break;
-            }
-        }
-        if (r) R[q++] = v;
+        if (gf2_insert(b64, v)) R[q++] = v;
     }
     for (; q < 128; ++q) R[q] = splitmix64(s);
 }

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace eloc {
 
@@ -52,18 +53,22 @@ struct TermRecF {
 // lin(x) ^ lin(y): the hash of a candidate x ^ XY is one XOR of two
 // precomputed hashes.  The table is a two-choice cuckoo table (load factor
 // <= 1/4): a key sits in one of its two slots, so a lookup is exactly two
-// independent loads.  With hs = lin(x) ^ salt and c = log2(capacity), slot 1
+// independent loads.  With hs the salted hash and c = log2(capacity), slot 1
 // is the low c bits of hs and slot 2 is slot 1 XOR ((hs >> c) | 1).
 //
-// One-word keys (N <= 64): R[0..63] are linearly independent, so lin is a
-// bijection of 64-bit words and equal hashes mean equal keys.  A 64-bit slot
-// stores (hs >> c) << (ibits + 1) | which << ibits | (index + 1): its
-// position and contents give back all of hs, so a lookup is exact with no
-// further load (which = 1 marks a key sitting in its slot 2).
-//
-// Two-word keys: 32-bit slots hold (fingerprint << ibits) | (index + 1),
-// fingerprint = bits of hs above bit 32 + ibits (never 0), and a match is
-// confirmed by comparing the stored key.
+// Three formats, by key width:
+//  * narrow (N <= 32): hs = low 32 bits of lin(x) ^ salt.  The low halves
+//    of R[0..31] are linearly independent, so this is a bijection of 32-bit
+//    keys; a 32-bit slot stores (hs >> c) << (ibits + 1) | which << ibits |
+//    (index + 1).  Its position and contents give back all of hs, so equal
+//    contents mean equal keys: a lookup is exact with no further load
+//    (which = 1 marks a key sitting in its slot 2).
+//  * wide (33 <= N <= 64): the same with the full 64-bit hash (R[0..63]
+//    independent) and 64-bit slots.
+//  * two words (N > 64): hs = lin(x) ^ salt; 32-bit slots hold
+//    (fingerprint << ibits) | (index + 1), fingerprint = bits of hs above
+//    bit 32 + ibits (never 0), and a match is confirmed by comparing the
+//    stored key.
 //
 // Slots are 0 when empty.  A key whose insertion does not settle goes to a
 // small stash (A. Kirsch, M. Mitzenmacher, U. Wieder, "More robust hashing:
@@ -71,15 +76,37 @@ struct TermRecF {
 // ---------------------------------------------------------------------------
 constexpr int kStash = 32;
 
+enum TableKind : int { kTabNarrow = 0, kTabWide = 1, kTabVerify = 2 };
+
+constexpr int table_kind(int W, bool narrow) { return W == 2 ? kTabVerify : (narrow ? kTabNarrow : kTabWide); }
+
+template <int TK>
+struct TabT {
+    using slot = uint32_t;
+    using hash = uint64_t;
+};
+template <>
+struct TabT<kTabNarrow> {
+    using slot = uint32_t;
+    using hash = uint32_t;
+};
+template <>
+struct TabT<kTabWide> {
+    using slot = uint64_t;
+    using hash = uint64_t;
+};
+
+inline size_t slot_bytes(int TK) { return TK == kTabWide ? sizeof(uint64_t) : sizeof(uint32_t); }
+
 struct Stash {
     uint32_t count;
     uint32_t pad;
     uint32_t idx[kStash];     // key index
-    uint64_t hs[kStash];      // salted hash of that key
+    uint64_t hs[kStash];      // salted hash of that key (narrow: low 32 bits)
 };
 
 struct Table {
-    const void* slots;  // uint64 (one-word keys) or uint32 (two-word keys)
+    const void* slots;  // TabT<kind>::slot [capacity]
     uint32_t mask;      // capacity - 1
     int ibits;          // bits of index + 1
     uint32_t imask;     // (1 << ibits) - 1
@@ -89,19 +116,22 @@ struct Table {
     const Stash* stash;
 };
 
-__host__ __device__ __forceinline__ uint32_t slot1(const Table& T, uint64_t hs) {
+template <int TK>
+__host__ __device__ __forceinline__ typename TabT<TK>::hash salted(const Table& T, uint64_t h) {
+    return static_cast<typename TabT<TK>::hash>(h ^ T.salt);
+}
+template <class HT>
+__host__ __device__ __forceinline__ uint32_t slot1(const Table& T, HT hs) {
     return static_cast<uint32_t>(hs) & T.mask;
 }
-__host__ __device__ __forceinline__ uint32_t slot2(const Table& T, uint64_t hs) {
+template <class HT>
+__host__ __device__ __forceinline__ uint32_t slot2(const Table& T, HT hs) {
     return (static_cast<uint32_t>(hs) ^ (static_cast<uint32_t>(hs >> T.capbits) | 1u)) & T.mask;
 }
 // two-word keys; never 0, so an empty slot cannot match
 __host__ __device__ __forceinline__ uint32_t fingerprint(const Table& T, uint64_t hs) {
     return static_cast<uint32_t>(hs >> T.fpshift) | 1u;
 }
-// one-word keys: what (slot >> ibits) holds for a key of salted hash hs in
-// its slot 1 (| 1 in its slot 2)
-__host__ __device__ __forceinline__ uint64_t tag(const Table& T, uint64_t hs) { return (hs >> T.capbits) << 1; }
 
 template <int W>
 __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b) {
@@ -110,72 +140,53 @@ __device__ __forceinline__ bool keys_equal(const uint64_t* a, const uint64_t* b)
     return eq;
 }
 
-// Slot values of a lookup: 64-bit words for one-word keys, else 32-bit.
-template <int W>
-struct SlotT {
-    using type = uint32_t;
-};
-template <>
-struct SlotT<1> {
-    using type = uint64_t;
-};
-
-template <int W>
-__device__ __forceinline__ typename SlotT<W>::type load_slot(const Table& T, uint32_t s) {
-    return static_cast<const typename SlotT<W>::type*>(T.slots)[s];
+template <int TK>
+__device__ __forceinline__ typename TabT<TK>::slot load_slot(const Table& T, uint32_t s) {
+    return static_cast<const typename TabT<TK>::slot*>(T.slots)[s];
 }
 
 // Second half of a lookup of a key with salted hash hs, given its two slot
 // values; `nstash` is the stash count (wave-uniform).  Index of the key in
-// `keys`, or -1.
-__device__ __forceinline__ int table_settle1(const Table& T, uint64_t v1, uint64_t v2, uint64_t hs, int nstash) {
-    const uint64_t t = tag(T, hs);
+// `keys` (two-word format only), or -1.
+template <int TK, int W>
+__device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys,
+                                            typename TabT<TK>::slot v1, typename TabT<TK>::slot v2,
+                                            typename TabT<TK>::hash hs, const uint64_t* key, int nstash) {
+    using ST = typename TabT<TK>::slot;
     int j = -1;
-    if ((v1 >> T.ibits) == t) j = static_cast<int>(v1 & T.imask) - 1;
-    if ((v2 >> T.ibits) == (t | 1u)) j = static_cast<int>(v2 & T.imask) - 1;
-    for (int k = 0; k < nstash && k < kStash; ++k)
-        if (T.stash->hs[k] == hs) j = static_cast<int>(T.stash->idx[k]);
-    return j;
-}
-
-__device__ __forceinline__ int table_settle2(const Table& T, const uint64_t* __restrict__ keys, uint32_t v1,
-                                             uint32_t v2, uint64_t hs, const uint64_t* key, int nstash) {
-    const uint32_t fp = fingerprint(T, hs);
-    int j = -1;
-    if ((v1 >> T.ibits) == fp) {
-        const int j1 = static_cast<int>(v1 & T.imask) - 1;
-        if (keys_equal<2>(keys + static_cast<size_t>(j1) * 2, key)) j = j1;
-    }
-    if (j < 0 && (v2 >> T.ibits) == fp) {
-        const int j2 = static_cast<int>(v2 & T.imask) - 1;
-        if (keys_equal<2>(keys + static_cast<size_t>(j2) * 2, key)) j = j2;
-    }
-    for (int k = 0; k < nstash && k < kStash; ++k) {
-        if (j < 0 && T.stash->hs[k] == hs) {
-            const int js = static_cast<int>(T.stash->idx[k]);
-            if (keys_equal<2>(keys + static_cast<size_t>(js) * 2, key)) j = js;
+    if constexpr (TK != kTabVerify) {
+        const ST t = static_cast<ST>((hs >> T.capbits) << 1);
+        if ((v1 >> T.ibits) == t) j = static_cast<int>(v1 & T.imask) - 1;
+        if ((v2 >> T.ibits) == (t | 1u)) j = static_cast<int>(v2 & T.imask) - 1;
+        for (int k = 0; k < nstash && k < kStash; ++k)
+            if (T.stash->hs[k] == static_cast<uint64_t>(hs)) j = static_cast<int>(T.stash->idx[k]);
+    } else {
+        const uint32_t fp = fingerprint(T, hs);
+        if ((v1 >> T.ibits) == fp) {
+            const int j1 = static_cast<int>(v1 & T.imask) - 1;
+            if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
+        }
+        if (j < 0 && (v2 >> T.ibits) == fp) {
+            const int j2 = static_cast<int>(v2 & T.imask) - 1;
+            if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
+        }
+        for (int k = 0; k < nstash && k < kStash; ++k) {
+            if (j < 0 && T.stash->hs[k] == hs) {
+                const int js = static_cast<int>(T.stash->idx[k]);
+                if (keys_equal<W>(keys + static_cast<size_t>(js) * W, key)) j = js;
+            }
         }
     }
     return j;
 }
 
-template <int W>
-__device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys,
-                                            typename SlotT<W>::type v1, typename SlotT<W>::type v2, uint64_t hs,
-                                            const uint64_t* key, int nstash) {
-    if constexpr (W == 1)
-        return table_settle1(T, v1, v2, hs, nstash);
-    else
-        return table_settle2(T, keys, v1, v2, hs, key, nstash);
-}
-
 // Full lookup of a key with (unsalted) hash h.
-template <int W>
+template <int TK, int W>
 __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __restrict__ keys, uint64_t h,
                                           const uint64_t* key) {
-    const uint64_t hs = h ^ T.salt;
-    return table_settle<W>(T, keys, load_slot<W>(T, slot1(T, hs)), load_slot<W>(T, slot2(T, hs)), hs, key,
-                           static_cast<int>(T.stash->count));
+    const auto hs = salted<TK>(T, h);
+    return table_settle<TK, W>(T, keys, load_slot<TK>(T, slot1(T, hs)), load_slot<TK>(T, slot2(T, hs)), hs, key,
+                               static_cast<int>(T.stash->count));
 }
 
 // Cuckoo insertion of key i (hash hash[i]): place it in one of its two
@@ -183,22 +194,23 @@ __device__ __forceinline__ int table_find(const Table& T, const uint64_t* __rest
 // key in hand goes to the stash, or the error bit is set if that is full.
 constexpr int kMaxKicks = 256;
 
-template <int W>
+template <int TK>
 __device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ hash, int64_t i, void* slots_v,
                                                  Stash* __restrict__ stash, const Table& T,
                                                  uint32_t* __restrict__ err, uint32_t err_bit) {
-    uint64_t hs = hash[i] ^ T.salt;
+    const auto hs = salted<TK>(T, hash[i]);
     int64_t held = i;   // index of the key in hand
-    if constexpr (W == 1) {
-        auto* slots = static_cast<unsigned long long*>(slots_v);
-        unsigned long long v = ((hs >> T.capbits) << (T.ibits + 1)) | static_cast<unsigned long long>(i + 1);
+    if constexpr (TK != kTabVerify) {
+        using ST = std::conditional_t<TK == kTabWide, unsigned long long, uint32_t>;
+        auto* slots = static_cast<ST*>(slots_v);
+        ST v = static_cast<ST>(((static_cast<ST>(hs) >> T.capbits) << (T.ibits + 1)) | static_cast<ST>(i + 1));
         uint32_t s = slot1(T, hs);
         for (int k = 0; k < kMaxKicks; ++k) {
-            const unsigned long long old = atomicExch(slots + s, v);
-            if (old == 0ull) return;
-            // the evicted key moves to its other slot (same XOR in both directions)
+            const ST old = atomicExch(slots + s, v);
+            if (old == 0) return;
+            // the evicted key moves to its other slot (the same XOR in both directions)
             s ^= (static_cast<uint32_t>(old >> (T.ibits + 1)) | 1u) & T.mask;
-            v = old ^ (1ull << T.ibits);
+            v = old ^ (static_cast<ST>(1) << T.ibits);
         }
         held = static_cast<int64_t>(v & T.imask) - 1;
     } else {
@@ -218,7 +230,7 @@ __device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ ha
     const uint32_t k = atomicAdd(&stash->count, 1u);
     if (k < static_cast<uint32_t>(kStash)) {
         stash->idx[k] = static_cast<uint32_t>(held);
-        stash->hs[k] = hash[held] ^ T.salt;
+        stash->hs[k] = static_cast<uint64_t>(salted<TK>(T, hash[held]));
     } else {
         atomicOr(err, err_bit);
     }
@@ -249,6 +261,7 @@ struct UTrieDev {
 struct HamDev {
     int n_qubits = 0;
     int W = 0;
+    bool narrow = false;       // n_qubits <= 32: narrow table format, 32-bit bit work
     int64_t n_terms = 0;
     int64_t n_groups = 0;
     int maxpop = 0;            // max popcount of an XY mask
@@ -356,6 +369,7 @@ struct BatchDev {
     const BatchProb* probs;
     int n;
     int W;
+    bool narrow;               // every problem has at most 32 qubits
     const int32_t* pid;        // [S] problem of every global sample
     int64_t S;
     const RTile* tiles;
@@ -388,9 +402,9 @@ struct BatchDev {
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
                               int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
-hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
+hipError_t launch_table_insert(int table_kind, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
                                const Table& T, uint32_t* err, hipStream_t st);
-hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err,
+hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t* sig, uint32_t* err,
                                 hipStream_t st);
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,
                            float4* af, float4* bf, double* shift, double* scratch, uint32_t* err,
@@ -445,7 +459,7 @@ int rows_per_block(int variant, int requested);
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
 hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st);
 hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st);
-int batch_blocks_per_cu(int W, int precision, int rows);
+int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
 
 
 int64_t energy_scratch_len();

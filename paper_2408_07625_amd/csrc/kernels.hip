@@ -47,18 +47,18 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
     if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
 }
 
-template <int W>
+template <int TK>
 __global__ __launch_bounds__(kBlock) void k_table_insert(const uint64_t* __restrict__ hash, int64_t n, void* slots,
                                                          Stash* __restrict__ stash, Table T,
                                                          uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    table_insert_one<W>(hash, i, slots, stash, T, err, static_cast<uint32_t>(kErrTable));
+    table_insert_one<TK>(hash, i, slots, stash, T, err, static_cast<uint32_t>(kErrTable));
 }
 
 // Duplicate check (every key must find itself) and the signature bitmap of
 // (popcount on even qubits, popcount on odd qubits) over U.
-template <int W>
+template <int W, int TK>
 __global__ __launch_bounds__(kBlock) void k_sample_verify(const uint64_t* __restrict__ keys,
                                                           const uint64_t* __restrict__ hash, int64_t n,
                                                           Table T, uint64_t* __restrict__ sig,
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_verify(const uint64_t* __rest
             pa += popc64(k[w] & kEven);
             pb += popc64(k[w] & kOdd);
         }
-        const int j = table_find<W>(T, keys, hash[i], k);
+        const int j = table_find<TK, W>(T, keys, hash[i], k);
         if (j != static_cast<int>(i)) atomicOr(err, static_cast<uint32_t>(kErrDup));
         atomicOr(&lsig[2 * pa + (pb >> 6)], 1ull << (pb & 63));
     }
@@ -580,22 +580,26 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_table_insert(int W, const uint64_t* hash, int64_t n, void* slots, Stash* stash, const Table& T,
-                               uint32_t* err, hipStream_t st) {
-    if (W == 1)
-        hipLaunchKernelGGL(k_table_insert<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
+hipError_t launch_table_insert(int table_kind, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
+                               const Table& T, uint32_t* err, hipStream_t st) {
+    const dim3 grid(blocks_for(n)), block(kBlock);
+    if (table_kind == kTabNarrow)
+        hipLaunchKernelGGL(k_table_insert<kTabNarrow>, grid, block, 0, st, hash, n, slots, stash, T, err);
+    else if (table_kind == kTabWide)
+        hipLaunchKernelGGL(k_table_insert<kTabWide>, grid, block, 0, st, hash, n, slots, stash, T, err);
     else
-        hipLaunchKernelGGL(k_table_insert<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, slots, stash, T, err);
+        hipLaunchKernelGGL(k_table_insert<kTabVerify>, grid, block, 0, st, hash, n, slots, stash, T, err);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_verify(int W, const SampleDev& S, uint64_t* sig, uint32_t* err, hipStream_t st) {
-    if (W == 1)
-        hipLaunchKernelGGL(k_sample_verify<1>, dim3(blocks_for(S.n)), dim3(kBlock), 0, st, S.keys, S.hash, S.n,
-                           S.table, sig, err);
+hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t* sig, uint32_t* err, hipStream_t st) {
+    const dim3 grid(blocks_for(S.n)), block(kBlock);
+    if (W == 2)
+        hipLaunchKernelGGL((k_sample_verify<2, kTabVerify>), grid, block, 0, st, S.keys, S.hash, S.n, S.table, sig, err);
+    else if (narrow)
+        hipLaunchKernelGGL((k_sample_verify<1, kTabNarrow>), grid, block, 0, st, S.keys, S.hash, S.n, S.table, sig, err);
     else
-        hipLaunchKernelGGL(k_sample_verify<2>, dim3(blocks_for(S.n)), dim3(kBlock), 0, st, S.keys, S.hash, S.n,
-                           S.table, sig, err);
+        hipLaunchKernelGGL((k_sample_verify<1, kTabWide>), grid, block, 0, st, S.keys, S.hash, S.n, S.table, sig, err);
     return hipGetLastError();
 }
 

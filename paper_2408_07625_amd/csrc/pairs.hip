@@ -131,8 +131,10 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
 // are discarded by the caller.
-template <int W, int SIG, int NR, class Sink>
+template <int W, int SIG, int NR, bool NW, class Sink>
 __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+    constexpr int TK = table_kind(W, NW);
+    using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.ktable;
     const int g0 = chunk * A.per_chunk;
@@ -154,24 +156,33 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         const int g = base + lane;
         const bool valid = g < g1;
         uint64_t xp[NR][W];
-        typename SlotT<W>::type v1[NR], v2[NR];
-        uint64_t hs[NR];
+        typename TabT<TK>::slot v1[NR], v2[NR];
+        HT hs[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             bool ok = valid;
             int pa = 0, n = 0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                xp[r][w] = R.x[r][w] ^ gxy[w];
+            if constexpr (NW) {
+                const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
+                xp[r][0] = x32;
                 if (SIG) {
-                    pa += popc64(xp[r][w] & kEven);
-                    n += popc64(xp[r][w]);
+                    pa = __popc(x32 & static_cast<uint32_t>(kEven));
+                    n = __popc(x32);
+                }
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    xp[r][w] = R.x[r][w] ^ gxy[w];
+                    if (SIG) {
+                        pa += popc64(xp[r][w] & kEven);
+                        n += popc64(xp[r][w]);
+                    }
                 }
             }
             if (SIG) ok = ok && pa == A.sig_pa && n == A.sig_n;
-            hs[r] = (R.hx[r] ^ T.salt) ^ gh;
-            v1[r] = ok ? load_slot<W>(T, slot1(T, hs[r])) : 0u;
-            v2[r] = ok ? load_slot<W>(T, slot2(T, hs[r])) : 0u;
+            hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
+            v1[r] = ok ? load_slot<TK>(T, slot1(T, hs[r])) : 0u;
+            v2[r] = ok ? load_slot<TK>(T, slot2(T, hs[r])) : 0u;
         }
         uint64_t nxy[W];
         int nrun = run;
@@ -188,7 +199,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int j = table_settle<W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash);
+            const int j = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash);
             sink.hit(r, j >= 0, g, j, run);
         }
         sink.flush();
@@ -200,8 +211,10 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
 }
 
 // LoopOverBatch: lanes over 64 samples x' of the chunk per step.
-template <int W, int NR, class Sink>
+template <int W, int NR, bool NW, class Sink>
 __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+    constexpr int TK = table_kind(W, NW);
+    using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.gtable;
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
@@ -215,24 +228,30 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
         const uint64_t hj = A.khash[jj];
         uint64_t m[NR][W];
-        typename SlotT<W>::type v1[NR], v2[NR];
-        uint64_t hs[NR];
+        typename TabT<TK>::slot v1[NR], v2[NR];
+        HT hs[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             int pc = 0;
+            if constexpr (NW) {
+                const uint32_t m32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]);
+                m[r][0] = m32;
+                pc = __popc(m32);
+            } else {
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                m[r][w] = R.x[r][w] ^ xj[w];
-                pc += popc64(m[r][w]);
+                for (int w = 0; w < W; ++w) {
+                    m[r][w] = R.x[r][w] ^ xj[w];
+                    pc += popc64(m[r][w]);
+                }
             }
             const bool ok = valid && pc <= A.maxpop;
-            hs[r] = (R.hx[r] ^ T.salt) ^ hj;
-            v1[r] = ok ? load_slot<W>(T, slot1(T, hs[r])) : 0u;
-            v2[r] = ok ? load_slot<W>(T, slot2(T, hs[r])) : 0u;
+            hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
+            v1[r] = ok ? load_slot<TK>(T, slot1(T, hs[r])) : 0u;
+            v2[r] = ok ? load_slot<TK>(T, slot2(T, hs[r])) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int g = table_settle<W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash);
+            const int g = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash);
             int run = 0;
             if (g >= 0) {
                 const GroupRec<W>& gr = groups[g];
@@ -247,7 +266,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
 // ---------------------------------------------------------------------------
 // Sinks: what happens to the pairs a wave finds.
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool ADJ, int NR>
+template <int W, int PREC, bool ADJ, int NR, bool NW>
 struct AccSink {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
@@ -292,7 +311,7 @@ struct AccSink {
 #pragma unroll
             for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
             typename P::H hr, hi;
-            melem<W>(terms, gr.begin, gr.mid, gr.end, static_cast<int>(threadIdx.x), kWave, ket, hr, hi);
+            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, static_cast<int>(threadIdx.x), kWave, ket, hr, hi);
             Acc v;
             P::madd(v, hr, hi, vec[ey]);
             add(r, v);
@@ -319,7 +338,7 @@ struct AccSink {
 #pragma unroll
             for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
             typename P::H hr, hi;
-            melem<W>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
+            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
             Acc v;
             P::madd(v, hr, hi, vec[e.y]);
             add(r, v);
@@ -380,14 +399,15 @@ struct FillSink {
 };
 
 // VARIANT: 0 TERMS without signature filter, 3 TERMS with it, 1 BATCH.
-template <int W, int VARIANT, int NR, class Sink>
+// NW: keys of at most 32 qubits (narrow table, 32-bit bit work).
+template <int W, int VARIANT, int NR, bool NW, class Sink>
 __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
     if constexpr (VARIANT == 0)
-        find_terms<W, 0, NR>(A, R, chunk, sink);
+        find_terms<W, 0, NR, NW>(A, R, chunk, sink);
     else if constexpr (VARIANT == 3)
-        find_terms<W, 1, NR>(A, R, chunk, sink);
+        find_terms<W, 1, NR, NW>(A, R, chunk, sink);
     else
-        find_batch<W, NR>(A, R, chunk, sink);
+        find_batch<W, NR, NW>(A, R, chunk, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,7 +415,7 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 //   forward: acc_x = sum_{x'} H_xx' vec_x'  (ket x', vec = a)
 //   adjoint: acc_y = sum_{x}  H_xy vec_x    (ket y,  vec = w / a)
 // ---------------------------------------------------------------------------
-template <int W, int VARIANT, int PREC, bool ADJ, int NR>
+template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW>
 __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                  void* __restrict__ partial) {
     using P = Prec<PREC>;
@@ -412,7 +432,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r * kWave + threadIdx.x] = Acc{};
     __syncthreads();
-    AccSink<W, PREC, ADJ, NR> sink;
+    AccSink<W, PREC, ADJ, NR, NW> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec);
@@ -420,7 +440,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
     sink.lq = lq;
     sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT, NR>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, NR, NW>(A, R, blockIdx.y, sink);
     sink.finish();
     // per-row totals: lane r adds the 64 lane columns of row r in order
     if (static_cast<int>(threadIdx.x) < R.n) {
@@ -430,7 +450,7 @@ __global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restr
     }
 }
 
-template <int W, int VARIANT>
+template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRows * W];
     read_stash_counts(A);
@@ -440,13 +460,13 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
-    find<W, VARIANT, kRows>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink);
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         if (static_cast<int>(threadIdx.x) == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
 }
 
-template <int W, int VARIANT>
+template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRows * W];
@@ -463,7 +483,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
-    find<W, VARIANT, kRows>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,7 +497,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 // problem's partial offset.  Every wave leaves the loop when the counter
 // passes the last item.
 // ---------------------------------------------------------------------------
-template <int W, int PREC, int NR>
+template <int W, int PREC, int NR, bool NW>
 __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void* __restrict__ vec_all,
                                                          void* __restrict__ partial_all) {
     using P = Prec<PREC>;
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r * kWave + lane] = Acc{};
         __syncthreads();
-        AccSink<W, PREC, false, NR> sink;
+        AccSink<W, PREC, false, NR, NW> sink;
         sink.groups = static_cast<const GroupRec<W>*>(A.groups);
         sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
         sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
@@ -543,11 +563,11 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         sink.rowkey = rowkey;
         sink.nrows = R.n;
         if (D.variant == 1)
-            find_batch<W, NR>(A, R, chunk, sink);
+            find_batch<W, NR, NW>(A, R, chunk, sink);
         else if (sig)
-            find_terms<W, 1, NR>(A, R, chunk, sink);
+            find_terms<W, 1, NR, NW>(A, R, chunk, sink);
         else
-            find_terms<W, 0, NR>(A, R, chunk, sink);
+            find_terms<W, 0, NR, NW>(A, R, chunk, sink);
         sink.finish();
         if (lane < R.n) {
             Acc s{};
@@ -637,7 +657,7 @@ __global__ __launch_bounds__(kTrieBlock) void k_fill_trie(PairArgs A, int chunks
 }
 
 // MatrixElement for given sample pairs (ket x_j).
-template <int W>
+template <int W, bool NW>
 __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, const int32_t* __restrict__ pi,
                                                        const int32_t* __restrict__ pj, double2* __restrict__ out,
                                                        uint32_t* __restrict__ err) {
@@ -655,46 +675,54 @@ __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, co
         xj[w] = A.keys[j * W + w];
         m[w] = A.keys[i * W + w] ^ xj[w];
     }
-    const int g = table_find<W>(A.gtable, A.gkeys, A.khash[i] ^ A.khash[j], m);
+    const int g = table_find<table_kind(W, NW), W>(A.gtable, A.gkeys, A.khash[i] ^ A.khash[j], m);
     double hr = 0.0, hi = 0.0;
     if (g >= 0) {
         const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
-        melem<W>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.mid, gr.end, 0, 1, xj, hr, hi);
+        melem<W, NW>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.mid, gr.end, 0, 1, xj, hr, hi);
     }
     out[t] = make_double2(hr, hi);
 }
 
 inline unsigned div_up(int64_t n, int64_t d) { return static_cast<unsigned>((n + d - 1) / d); }
 
-template <int W, int VARIANT, int PREC, bool ADJ>
+template <int W, int VARIANT, int PREC, bool ADJ, bool NW>
 hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
     if constexpr (VARIANT == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
     } else if (P.rows_per_block == 4) {
         dim3 grid(div_up(A.M, 4), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4>), grid, dim3(kWave), 0, st, A, vec, partial);
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW>), grid, dim3(kWave), 0, st, A, vec, partial);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows>), grid, dim3(kWave), 0, st, A, vec, partial);
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();
 }
 
-template <int W, int VARIANT, bool ADJ>
+template <int W, int VARIANT, bool ADJ, bool NW>
 hipError_t dispatch_prec(int precision, const PairArgs& A, const Plan& P, const void* vec, void* partial,
                          hipStream_t st) {
-    return precision == 0 ? launch_pairs_t<W, VARIANT, 0, ADJ>(A, P, vec, partial, st)
-                          : launch_pairs_t<W, VARIANT, 1, ADJ>(A, P, vec, partial, st);
+    return precision == 0 ? launch_pairs_t<W, VARIANT, 0, ADJ, NW>(A, P, vec, partial, st)
+                          : launch_pairs_t<W, VARIANT, 1, ADJ, NW>(A, P, vec, partial, st);
 }
 
-template <int W, bool ADJ>
+template <int W, bool ADJ, bool NW>
 hipError_t dispatch_variant(int variant, int precision, const PairArgs& A, const Plan& P, const void* vec,
                             void* partial, hipStream_t st) {
-    if (variant == 0 && P.sig_filter) return dispatch_prec<W, 3, ADJ>(precision, A, P, vec, partial, st);
-    if (variant == 0) return dispatch_prec<W, 0, ADJ>(precision, A, P, vec, partial, st);
-    if (variant == 1) return dispatch_prec<W, 1, ADJ>(precision, A, P, vec, partial, st);
-    return dispatch_prec<W, 2, ADJ>(precision, A, P, vec, partial, st);
+    if (variant == 0 && P.sig_filter) return dispatch_prec<W, 3, ADJ, NW>(precision, A, P, vec, partial, st);
+    if (variant == 0) return dispatch_prec<W, 0, ADJ, NW>(precision, A, P, vec, partial, st);
+    if (variant == 1) return dispatch_prec<W, 1, ADJ, NW>(precision, A, P, vec, partial, st);
+    return dispatch_prec<W, 2, ADJ, NW>(precision, A, P, vec, partial, st);
+}
+
+template <bool ADJ>
+hipError_t dispatch_width(const HamDev& H, int variant, int precision, const PairArgs& A, const Plan& P,
+                          const void* v, void* partial, hipStream_t st) {
+    if (H.W == 2) return dispatch_variant<2, ADJ, false>(variant, precision, A, P, v, partial, st);
+    if (H.narrow) return dispatch_variant<1, ADJ, true>(variant, precision, A, P, v, partial, st);
+    return dispatch_variant<1, ADJ, false>(variant, precision, A, P, v, partial, st);
 }
 
 }  // namespace
@@ -708,37 +736,30 @@ hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& 
                         const double2* vec, const float4* vecf, void* partial, hipStream_t st) {
     const PairArgs A = make_args(H, S, P);
     const void* v = precision == 0 ? static_cast<const void*>(vec) : static_cast<const void*>(vecf);
-    if (H.W == 1)
-        return adjoint ? dispatch_variant<1, true>(variant, precision, A, P, v, partial, st)
-                       : dispatch_variant<1, false>(variant, precision, A, P, v, partial, st);
-    return adjoint ? dispatch_variant<2, true>(variant, precision, A, P, v, partial, st)
-                   : dispatch_variant<2, false>(variant, precision, A, P, v, partial, st);
+    return adjoint ? dispatch_width<true>(H, variant, precision, A, P, v, partial, st)
+                   : dispatch_width<false>(H, variant, precision, A, P, v, partial, st);
 }
 
-template <int W, int PREC, int NR>
-static void batch_kernel_ptr(const void** f) {
-    *f = reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR>);
+template <int W, int PREC, int NR, bool NW>
+static const void* batch_kernel_ptr() {
+    return reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR, NW>);
 }
 
-static const void* batch_kernel(int W, int precision, int rows) {
-    const void* f = nullptr;
-    const int key = (W == 1 ? 0 : 4) + (precision == 0 ? 0 : 2) + (rows == 4 ? 0 : 1);
-    switch (key) {
-        case 0: batch_kernel_ptr<1, 0, 4>(&f); break;
-        case 1: batch_kernel_ptr<1, 0, 8>(&f); break;
-        case 2: batch_kernel_ptr<1, 1, 4>(&f); break;
-        case 3: batch_kernel_ptr<1, 1, 8>(&f); break;
-        case 4: batch_kernel_ptr<2, 0, 4>(&f); break;
-        case 5: batch_kernel_ptr<2, 0, 8>(&f); break;
-        case 6: batch_kernel_ptr<2, 1, 4>(&f); break;
-        default: batch_kernel_ptr<2, 1, 8>(&f); break;
-    }
-    return f;
+template <int W, bool NW>
+static const void* batch_kernel_w(int precision, int rows) {
+    if (precision == 0) return rows == 4 ? batch_kernel_ptr<W, 0, 4, NW>() : batch_kernel_ptr<W, 0, 8, NW>();
+    return rows == 4 ? batch_kernel_ptr<W, 1, 4, NW>() : batch_kernel_ptr<W, 1, 8, NW>();
 }
 
-int batch_blocks_per_cu(int W, int precision, int rows) {
+static const void* batch_kernel(int W, bool narrow, int precision, int rows) {
+    if (W == 2) return batch_kernel_w<2, false>(precision, rows);
+    return narrow ? batch_kernel_w<1, true>(precision, rows) : batch_kernel_w<1, false>(precision, rows);
+}
+
+int batch_blocks_per_cu(int W, bool narrow, int precision, int rows) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, precision, rows), kWave, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, narrow, precision, rows), kWave, 0) !=
+        hipSuccess)
         return 0;
     return n;
 }
@@ -747,11 +768,11 @@ hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int bl
     const void* vec = precision == 0 ? static_cast<const void*>(B.a) : static_cast<const void*>(B.af);
     void* part = B.partial;
     void* args[] = {const_cast<BatchDev*>(&B), &vec, &part};
-    return hipLaunchKernel(batch_kernel(B.W, precision, rows), dim3(static_cast<unsigned>(blocks)), dim3(kWave),
-                           args, 0, st);
+    return hipLaunchKernel(batch_kernel(B.W, B.narrow, precision, rows), dim3(static_cast<unsigned>(blocks)),
+                           dim3(kWave), args, 0, st);
 }
 
-template <int W>
+template <int W, bool NW>
 static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t* counts, hipStream_t st) {
     if (variant == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
@@ -759,16 +780,16 @@ static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
         if (variant == 0 && P.sig_filter)
-            hipLaunchKernelGGL((k_count<W, 3>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+            hipLaunchKernelGGL((k_count<W, 3, NW>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
         else if (variant == 0)
-            hipLaunchKernelGGL((k_count<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+            hipLaunchKernelGGL((k_count<W, 0, NW>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
         else
-            hipLaunchKernelGGL((k_count<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+            hipLaunchKernelGGL((k_count<W, 1, NW>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
     }
     return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool NW>
 static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbits, const int64_t* offsets,
                          uint64_t* pkey, uint32_t* pval, hipStream_t st) {
     if (variant == 2) {
@@ -777,11 +798,11 @@ static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbit
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
         if (variant == 0 && P.sig_filter)
-            hipLaunchKernelGGL((k_fill<W, 3>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+            hipLaunchKernelGGL((k_fill<W, 3, NW>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
         else if (variant == 0)
-            hipLaunchKernelGGL((k_fill<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+            hipLaunchKernelGGL((k_fill<W, 0, NW>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
         else
-            hipLaunchKernelGGL((k_fill<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+            hipLaunchKernelGGL((k_fill<W, 1, NW>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
     }
     return hipGetLastError();
 }
@@ -789,24 +810,29 @@ static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbit
 hipError_t launch_pairs_count(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int32_t* counts,
                               hipStream_t st) {
     const PairArgs A = make_args(H, S, P);
-    return H.W == 1 ? count_w<1>(variant, A, P, counts, st) : count_w<2>(variant, A, P, counts, st);
+    if (H.W == 2) return count_w<2, false>(variant, A, P, counts, st);
+    return H.narrow ? count_w<1, true>(variant, A, P, counts, st) : count_w<1, false>(variant, A, P, counts, st);
 }
 
 hipError_t launch_pairs_fill(int variant, const HamDev& H, const SampleDev& S, const Plan& P, int jbits,
                              const int64_t* offsets, uint64_t* pkey, uint32_t* pval, hipStream_t st) {
     const PairArgs A = make_args(H, S, P);
-    return H.W == 1 ? fill_w<1>(variant, A, P, jbits, offsets, pkey, pval, st)
-                    : fill_w<2>(variant, A, P, jbits, offsets, pkey, pval, st);
+    if (H.W == 2) return fill_w<2, false>(variant, A, P, jbits, offsets, pkey, pval, st);
+    return H.narrow ? fill_w<1, true>(variant, A, P, jbits, offsets, pkey, pval, st)
+                    : fill_w<1, false>(variant, A, P, jbits, offsets, pkey, pval, st);
 }
 
 hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pi, const int32_t* pj,
                                 double2* out, uint32_t* err, hipStream_t st) {
     Plan P;
     const PairArgs A = make_args(H, S, P);
-    if (H.W == 1)
-        hipLaunchKernelGGL(k_pair_elements<1>, dim3(div_up(n, 256)), dim3(256), 0, st, A, n, pi, pj, out, err);
+    const dim3 grid(div_up(n, 256)), block(256);
+    if (H.W == 2)
+        hipLaunchKernelGGL((k_pair_elements<2, false>), grid, block, 0, st, A, n, pi, pj, out, err);
+    else if (H.narrow)
+        hipLaunchKernelGGL((k_pair_elements<1, true>), grid, block, 0, st, A, n, pi, pj, out, err);
     else
-        hipLaunchKernelGGL(k_pair_elements<2>, dim3(div_up(n, 256)), dim3(256), 0, st, A, n, pi, pj, out, err);
+        hipLaunchKernelGGL((k_pair_elements<1, false>), grid, block, 0, st, A, n, pi, pj, out, err);
     return hipGetLastError();
 }
 
