@@ -71,7 +71,8 @@ enum eloc_status {
 enum eloc_variant {
     ELOC_TERMS = 0, /* loop over the unique XY set, look x ^ XY up in U (Alg. 2A)   */
     ELOC_BATCH = 1, /* loop over U, look x ^ x' up in the XY set (Alg. 2B)           */
-    ELOC_TRIE = 2   /* walk prefix trees of U and of the XY set together (Alg. 2C)   */
+    ELOC_TRIE = 2,  /* walk prefix trees of U and of the XY set together (Alg. 2C)   */
+    ELOC_AUTO = 3   /* ELOC_BATCH if |U| <= |unique XY set|, else ELOC_TERMS         */
 };
 
 /* Arithmetic of the ratio accumulation sum_x' H_xx' psi(x')/psi(x). */

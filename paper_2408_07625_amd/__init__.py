@@ -17,7 +17,7 @@ import torch  # loads the HIP runtime that libeloc.so then binds to
 _LIB_PATH = Path(__file__).resolve().parent / "libeloc.so"
 _lib = None
 
-VARIANTS = {"terms": 0, "batch": 1, "trie": 2}
+VARIANTS = {"terms": 0, "batch": 1, "trie": 2, "auto": 3}
 PRECISIONS = {"fp64": 0, "fp32c": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOMEM", -4: "ECAPACITY", -5: "ERANGE", -6: "EHIP",
           -7: "ESTATE", -8: "EAGAIN"}

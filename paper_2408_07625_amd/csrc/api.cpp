@@ -85,7 +85,15 @@ int hip_fail(eloc_ctx c, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
-int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH || v == ELOC_TRIE; }
+int valid_variant(int v) { return v == ELOC_TERMS || v == ELOC_BATCH || v == ELOC_TRIE || v == ELOC_AUTO; }
+
+// ELOC_AUTO: LoopOverBatch when U is no larger than the unique XY set (its
+// M^2 candidates, most rejected by a popcount test, are then fewer than
+// LoopOverTerms' M x |XY| lookups), else LoopOverTerms.
+int resolve_variant(const eloc_ctx c, int v) {
+    if (v != ELOC_AUTO) return v;
+    return c->S.n <= c->H.n_groups ? ELOC_BATCH : ELOC_TERMS;
+}
 
 // Launch geometry.  TERMS / BATCH: one wave per rows_per_block rows, the
 // inner loop (groups / samples) split into chunks of whole 64-lane steps so
@@ -490,6 +498,7 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
     int rc = check_ready(c);
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    variant = resolve_variant(c, variant);
     if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
     if (!logpsi_dev || !eloc_dev || !stats_dev) return fail(c, ELOC_EINVAL, "null pointer");
     const int64_t M = c->S.n;
@@ -529,6 +538,7 @@ int eloc_count_pairs(eloc_ctx c, int variant, int64_t* n_pairs_host) {
     int rc = check_ready(c);
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    variant = resolve_variant(c, variant);
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
     rc = prepare_variant(c, variant);
     if (rc) return rc;
@@ -541,6 +551,7 @@ int eloc_find_pairs(eloc_ctx c, int variant, int64_t capacity, int32_t* i_dev, i
     int rc = check_ready(c);
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    variant = resolve_variant(c, variant);
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
     rc = prepare_variant(c, variant);
     if (rc) return rc;
@@ -595,6 +606,7 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
     int rc = check_ready(c);
     if (rc) return rc;
     if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    variant = resolve_variant(c, variant);
     if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
     if (!logpsi_dev || !eloc_dev || !stats_dev || !grad_logpsi_dev) return fail(c, ELOC_EINVAL, "null pointer");
     const int64_t M = c->S.n;

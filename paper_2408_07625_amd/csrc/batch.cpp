@@ -139,9 +139,13 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
         const ProbInfo& I = b->info[static_cast<size_t>(k)];
         D.variant = (static_cast<double>(I.M) <= s.batch_ratio * static_cast<double>(I.G)) ? 1 : 0;
         const int64_t span = D.variant == 1 ? I.M : I.G;
+        // chunks of whole 64-lane steps, split as evenly as the single-problem
+        // plan splits them for the same chunk count
         const int64_t steps = (span + 63) / 64;
-        const int64_t want = (s.item_candidates + 64 * s.rows_per_wave - 1) / (64 * s.rows_per_wave);
-        const int64_t per_steps = std::max<int64_t>(1, std::min<int64_t>(steps, want));
+        const int64_t want = std::max<int64_t>(1, (s.item_candidates + 64 * s.rows_per_wave - 1) /
+                                                      (64 * s.rows_per_wave));
+        const int64_t nchunks = std::min<int64_t>(steps, (steps + want - 1) / want);
+        const int64_t per_steps = (steps + nchunks - 1) / nchunks;
         const int64_t per = per_steps * 64;
         D.per_chunk = static_cast<int32_t>(per);
         D.chunks = static_cast<int32_t>((span + per - 1) / per);
