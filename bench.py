@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", action="store_true", help="time only the headline variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-launch measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint measurement")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reads and writes it once), "
                          "the reference kernel for scaling hardware byte counters")
@@ -240,6 +241,8 @@ def main():
                                    "samples_per_s": M / cpu_s}
     if not args.no_batched:
         rec["batched"] = bench_batched(args)
+    if not args.no_adjoint:
+        rec["adjoint"] = bench_adjoint(args)
     if args.calibrate_mib:
         n = args.calibrate_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -250,6 +253,66 @@ def main():
         rec["calibration_copy_bytes"] = 2 * n * 8
     print(json.dumps(rec))
     eng.close()
+
+
+def bench_adjoint(args):
+    """Forward and adjoint (dE/dlog psi) on the 100-qubit workload (two-word
+    keys, 2^18 samples, occurrence counts), pairs recomputed by the adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    from synth import configs
+
+    t0 = time.perf_counter()
+    w = configs.wide()
+    eng = pe.Engine(0)
+    eng.set_hamiltonian(w.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
+    info = eng.info()
+    keys = torch.from_numpy(w.keys.view(np.int64)).cuda()
+    L = torch.from_numpy(w.logpsi).cuda()
+    Wt = torch.from_numpy(w.weights).cuda()
+    eng.set_samples(keys)
+    M = w.n_unique
+    out = torch.empty(M, dtype=torch.complex128, device="cuda")
+    stats = torch.empty(4, dtype=torch.float64, device="cuda")
+    grad = torch.empty(M, dtype=torch.complex128, device="cuda")
+    variant = "batch" if M <= info["n_groups"] else "terms"
+    print(f"# adjoint workload: {w.n_qubits} qubits, {M} samples, {info['n_terms']} terms, "
+          f"{info['n_groups']} groups, variant {variant} (set up in {time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    steps = max(2, args.steps // 5)
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        eng.check()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        eng.check()
+        return e0.elapsed_time(e1) / steps
+
+    res = {"workload": f"wide: {w.n_qubits} qubits (two-word keys), {w.n_electrons} electrons, {M} unique "
+                       f"determinants, {info['n_terms']} Pauli terms in {info['n_groups']} XY groups, "
+                       f"occurrence-count weights", "variant": variant, "steps": steps}
+    for prec in ("fp64", "fp32c"):
+        fwd = timed(lambda: eng.local_energy(L, Wt, variant, prec, out=out, stats=stats, check=False))
+        adj = timed(lambda: eng.adjoint(L, out, stats, 1.0 + 0.0j, Wt, variant, prec, out=grad, check=False))
+        res[prec] = {"forward_ms": fwd, "adjoint_ms": adj}
+        print(f"# adjoint {prec}: forward {fwd:.3f} ms, adjoint {adj:.3f} ms", file=sys.stderr, flush=True)
+    n_pairs = eng.count_pairs(variant)
+    res["coupled_pairs"] = n_pairs
+    for prec in ("fp64", "fp32c"):
+        res[prec]["pairs_per_s_forward_plus_adjoint"] = 2 * n_pairs / (
+            (res[prec]["forward_ms"] + res[prec]["adjoint_ms"]) * 1e-3)
+    eng.close()
+    return res
 
 
 def bench_batched(args):

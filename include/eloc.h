@@ -72,7 +72,8 @@ enum eloc_variant {
     ELOC_TERMS = 0, /* loop over the unique XY set, look x ^ XY up in U (Alg. 2A)   */
     ELOC_BATCH = 1, /* loop over U, look x ^ x' up in the XY set (Alg. 2B)           */
     ELOC_TRIE = 2,  /* walk prefix trees of U and of the XY set together (Alg. 2C)   */
-    ELOC_AUTO = 3   /* ELOC_BATCH if |U| <= |unique XY set|, else ELOC_TERMS         */
+    ELOC_AUTO = 3,  /* ELOC_BATCH if |U| <= |unique XY set|, else ELOC_TERMS         */
+    ELOC_STORED = 4 /* forward / adjoint only: the pair list kept by eloc_store_pairs */
 };
 
 /* Arithmetic of the ratio accumulation sum_x' H_xx' psi(x')/psi(x). */
@@ -158,12 +159,24 @@ int eloc_pair_elements(eloc_ctx ctx, int64_t n, const int32_t* i_dev, const int3
  * (H_xy = <x|H|y>, phase on the ket y) and grad_L_y = grad_e conj(dE/dL_y);
  * with |psi|^2 weights (weights_dev NULL) the real part gains
  * 2 w~_y Re(conj(grad_e) (E_loc(y) - E)).  eloc_dev and stats_dev are the
- * forward outputs for the same inputs.  Pairs are recomputed, never stored.
+ * forward outputs for the same inputs.  Pairs are found again by the
+ * variant's kernels, or read from the stored list (ELOC_STORED).
  * Errors as eloc_local_energy. */
 int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
                               const eloc_c64* logpsi_dev, const double* weights_dev,
                               const eloc_c64* eloc_dev, const double* stats_dev, eloc_c64 grad_e,
                               eloc_c64* grad_logpsi_dev);
+
+/* Store the coupled pairs of the current samples, found with `variant`, as
+ * a list by row of (column j, H_ij): afterwards eloc_local_energy and
+ * eloc_local_energy_adjoint with ELOC_STORED read it instead of finding the
+ * pairs again (one pass over about 20 bytes per pair), until the samples or
+ * the Hamiltonian change.  *n_pairs_host receives the pair count.  If the
+ * list (with the transient emission buffers: 32 bytes per pair, plus 8 per
+ * sample) needs more than budget_bytes of device memory, nothing is stored
+ * and ECAPACITY is returned: the caller keeps recomputing (any other
+ * variant).  Synchronising. */
+int eloc_store_pairs(eloc_ctx ctx, int variant, size_t budget_bytes, int64_t* n_pairs_host);
 
 /* Launch geometry of the pair kernels (autotuning, benchmarks).  Results do
  * not depend on these settings beyond the floating-point summation order of

@@ -17,7 +17,7 @@ import torch  # loads the HIP runtime that libeloc.so then binds to
 _LIB_PATH = Path(__file__).resolve().parent / "libeloc.so"
 _lib = None
 
-VARIANTS = {"terms": 0, "batch": 1, "trie": 2, "auto": 3}
+VARIANTS = {"terms": 0, "batch": 1, "trie": 2, "auto": 3, "stored": 4}
 PRECISIONS = {"fp64": 0, "fp32c": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOMEM", -4: "ECAPACITY", -5: "ERANGE", -6: "EHIP",
           -7: "ESTATE", -8: "EAGAIN"}
@@ -71,6 +71,7 @@ def library() -> ctypes.CDLL:
             "eloc_find_pairs": (i32, [P, i32, i64, P, P, P, ctypes.POINTER(i64)]),
             "eloc_pair_elements": (i32, [P, i64, P, P, P]),
             "eloc_local_energy_adjoint": (i32, [P, i32, i32, P, P, P, P, C64, P]),
+            "eloc_store_pairs": (i32, [P, i32, ctypes.c_size_t, ctypes.POINTER(i64)]),
             "eloc_set_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
             "eloc_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
             "eloc_profile_enable": (i32, [P, i32]),
@@ -103,7 +104,8 @@ def exported_symbols() -> list[str]:
     return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
                         "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples",
                         "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
-                        "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_set_tuning", "eloc_get_tuning",
+                        "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_store_pairs", "eloc_set_tuning",
+                        "eloc_get_tuning",
                         "eloc_profile_enable", "eloc_profile_read", "eloc_batch_create", "eloc_batch_destroy",
                         "eloc_batch_last_error", "eloc_batch_set_stream", "eloc_batch_run", "eloc_batch_set_graph",
                         "eloc_batch_check", "eloc_batch_pair_counts", "eloc_batch_problem_info",
@@ -254,6 +256,17 @@ class Engine:
         k = got.value
         return i[:k], j[:k], g[:k]
 
+    def store_pairs(self, variant="auto", budget_bytes: int | None = None) -> int:
+        """Keep the pair list of the current samples for variant "stored";
+        returns the pair count.  ElocError ECAPACITY if it needs more than
+        budget_bytes (default: half of the free device memory)."""
+        if budget_bytes is None:
+            budget_bytes = torch.cuda.mem_get_info(self.device)[0] // 2
+        n = ctypes.c_int64()
+        self._sync_stream()
+        self._call(self.lib.eloc_store_pairs(self.handle, _variant(variant), int(budget_bytes), ctypes.byref(n)))
+        return n.value
+
     def pair_elements(self, i: torch.Tensor, j: torch.Tensor) -> torch.Tensor:
         assert i.dtype == torch.int32 and j.dtype == torch.int32 and i.shape == j.shape
         i, j = i.contiguous(), j.contiguous()
@@ -283,12 +296,21 @@ class Engine:
 class LocalEnergy(torch.autograd.Function):
     """E = sum_x w~_x E_loc^var(x) as a differentiable function of log psi.
 
-    forward(logpsi, weights, engine, variant, precision) -> (E complex128
-    scalar, E_loc [M] (not differentiable), stats [4]).  Backward calls the
-    adjoint kernels; pairs are recomputed, never stored."""
+    forward(logpsi, weights, engine, variant, precision, store_budget) ->
+    (E complex128 scalar, E_loc [M] (not differentiable), stats [4]).
+    Backward calls the adjoint kernels.  With store_budget (bytes) the pair
+    list is stored when it fits and both passes read it; otherwise the
+    backward finds the pairs again."""
 
     @staticmethod
-    def forward(ctx, logpsi, weights, engine, variant="terms", precision="fp64"):
+    def forward(ctx, logpsi, weights, engine, variant="terms", precision="fp64", store_budget=None):
+        if store_budget is not None:
+            try:
+                engine.store_pairs(variant, store_budget)
+                variant = "stored"
+            except ElocError as e:
+                if e.status != "ECAPACITY":
+                    raise
         eloc, stats = engine.local_energy(logpsi, weights, variant, precision)
         ctx.engine, ctx.variant, ctx.precision = engine, variant, precision
         ctx.save_for_backward(logpsi, eloc, stats, *( [weights] if weights is not None else []))
@@ -304,11 +326,11 @@ class LocalEnergy(torch.autograd.Function):
         weights = saved[3] if ctx.has_w else None
         ge = complex(grad_E.item()) if grad_E is not None else 0j
         g = ctx.engine.adjoint(logpsi, eloc, stats, ge, weights, ctx.variant, ctx.precision)
-        return g, None, None, None, None
+        return g, None, None, None, None, None
 
 
-def local_energy(engine: Engine, logpsi, weights=None, variant="terms", precision="fp64"):
-    return LocalEnergy.apply(logpsi, weights, engine, variant, precision)
+def local_energy(engine: Engine, logpsi, weights=None, variant="terms", precision="fp64", store_budget=None):
+    return LocalEnergy.apply(logpsi, weights, engine, variant, precision, store_budget)
 
 
 class Batch:

@@ -49,6 +49,12 @@ struct eloc_ctx_s {
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
+    // stored pair list (CSR by row of (column, H_ij)), valid until the
+    // samples or the Hamiltonian change
+    DevBuf st_rowptr, st_col, st_h;
+    bool st_valid = false;
+    int64_t st_pairs = 0;
+
     int tune_chunks = 0;     // 0 = automatic
     int tune_sig = 1;
     int tune_rows = 8;
@@ -315,6 +321,38 @@ int amp_prep(eloc_ctx c, const eloc_c64* logpsi, bool fp32) {
     return ELOC_OK;
 }
 
+// The row sums of the forward (vec = a) or adjoint (vec = v) pass into
+// c->partial: the fused pair kernel for a variant, or one pass over the
+// stored pair list (one partial per row).
+int row_sums(eloc_ctx c, bool adjoint, int variant, int precision, const double2* vec, const float4* vecf, Plan* plan) {
+    const int64_t M = c->S.n;
+    const bool fp32 = precision == ELOC_FP32C;
+    const Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant);
+    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
+    const int pm = prof_begin(c, adjoint ? ELOC_STAGE_ADJOINT_PAIRS : ELOC_STAGE_PAIRS);
+    if (variant == ELOC_STORED) {
+        const void* v = fp32 ? static_cast<const void*>(vecf) : static_cast<const void*>(vec);
+        ELOC_HIP(c, launch_spmv(adjoint, precision, M, c->st_rowptr.as<int64_t>(), c->st_col.as<int32_t>(),
+                                c->st_h.as<double2>(), v, c->partial.p, c->stream));
+    } else {
+        ELOC_HIP(c, launch_pairs(adjoint, variant, precision, c->H, c->S, P, vec, vecf, c->partial.p, c->stream));
+    }
+    prof_end(c, pm);
+    *plan = P;
+    return ELOC_OK;
+}
+
+// Variant checks shared by the forward and adjoint entry points.
+int forward_variant(eloc_ctx c, int* variant) {
+    if (*variant == ELOC_STORED) {
+        if (!c->st_valid) return fail(c, ELOC_ESTATE, "no stored pair list for these samples (eloc_store_pairs)");
+        return ELOC_OK;
+    }
+    if (!valid_variant(*variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    *variant = resolve_variant(c, *variant);
+    return prepare_variant(c, *variant);
+}
+
 int count_into_offsets(eloc_ctx c, int variant, const Plan& P, int64_t* total) {
     const int64_t n = c->S.n * P.chunks;
     ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
@@ -411,6 +449,7 @@ int eloc_set_hamiltonian(eloc_ctx c, int n_qubits, int64_t n_terms, const double
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, ELOC_EHIP, "hipSetDevice");
     c->ham_set = false;
     c->samples_set = false;    // sample tables depend on the qubit count
+    c->st_valid = false;
     return W == 1 ? ingest<1>(c, n_qubits, n_terms, coeff, xy, yz) : ingest<2>(c, n_qubits, n_terms, coeff, xy, yz);
 }
 
@@ -489,6 +528,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
         }
     c->S = S;
     c->ut_valid = false;
+    c->st_valid = false;
     c->samples_set = true;
     return ELOC_OK;
 }
@@ -497,24 +537,19 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
                       const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
-    variant = resolve_variant(c, variant);
     if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
     if (!logpsi_dev || !eloc_dev || !stats_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    rc = forward_variant(c, &variant);
+    if (rc) return rc;
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
-    rc = prepare_variant(c, variant);
-    if (rc) return rc;
     ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     rc = amp_prep(c, logpsi_dev, fp32);
     if (rc) return rc;
-    const Plan P = make_plan(c, variant);
-    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
-    int pm = prof_begin(c, ELOC_STAGE_PAIRS);
-    ELOC_HIP(c, launch_pairs(false, variant, precision, c->H, c->S, P, c->a.as<double2>(), c->af.as<float4>(),
-                             c->partial.p, c->stream));
-    prof_end(c, pm);
-    pm = prof_begin(c, ELOC_STAGE_FINISH);
+    Plan P;
+    rc = row_sums(c, false, variant, precision, c->a.as<double2>(), c->af.as<float4>(), &P);
+    if (rc) return rc;
+    int pm = prof_begin(c, ELOC_STAGE_FINISH);
     ELOC_HIP(c, launch_finish(precision, M, P, c->partial.p, c->b.as<double2>(), c->bf.as<float4>(),
                               reinterpret_cast<double2*>(eloc_dev), c->stream));
     prof_end(c, pm);
@@ -605,14 +640,12 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
                               eloc_c64 grad_e, eloc_c64* grad_logpsi_dev) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
-    variant = resolve_variant(c, variant);
     if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
     if (!logpsi_dev || !eloc_dev || !stats_dev || !grad_logpsi_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    rc = forward_variant(c, &variant);
+    if (rc) return rc;
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
-    rc = prepare_variant(c, variant);
-    if (rc) return rc;
     ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     rc = amp_prep(c, logpsi_dev, fp32);
     if (rc) return rc;
@@ -620,18 +653,56 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
     ELOC_HIP(c, c->vf.ensure(sizeof(float4) * (fp32 ? M : 1)));
     ELOC_HIP(c, launch_adj_vec(c->a.as<double2>(), c->b.as<double2>(), weights_dev, M, fp32, c->v.as<double2>(),
                                c->vf.as<float4>(), c->stream));
-    const Plan P = make_plan(c, variant);
-    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
-    int pm = prof_begin(c, ELOC_STAGE_ADJOINT_PAIRS);
-    ELOC_HIP(c, launch_pairs(true, variant, precision, c->H, c->S, P, c->v.as<double2>(), c->vf.as<float4>(),
-                             c->partial.p, c->stream));
-    prof_end(c, pm);
-    pm = prof_begin(c, ELOC_STAGE_ADJOINT_FINISH);
+    Plan P;
+    rc = row_sums(c, true, variant, precision, c->v.as<double2>(), c->vf.as<float4>(), &P);
+    if (rc) return rc;
+    const int pm = prof_begin(c, ELOC_STAGE_ADJOINT_FINISH);
     ELOC_HIP(c, launch_adj_finish(precision, M, P, c->partial.p, c->a.as<double2>(), c->af.as<float4>(),
                                   reinterpret_cast<const double2*>(eloc_dev), weights_dev, stats_dev,
                                   c->shift.as<double>(), make_double2(grad_e.re, grad_e.im),
                                   reinterpret_cast<double2*>(grad_logpsi_dev), c->stream));
     prof_end(c, pm);
+    return ELOC_OK;
+}
+
+int eloc_store_pairs(eloc_ctx c, int variant, size_t budget_bytes, int64_t* n_pairs_host) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
+    if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown or unavailable variant");
+    variant = resolve_variant(c, variant);
+    rc = prepare_variant(c, variant);
+    if (rc) return rc;
+    c->st_valid = false;
+    const Plan P = make_plan(c, variant);
+    int64_t total = 0;
+    rc = count_into_offsets(c, variant, P, &total);
+    if (rc) return rc;
+    *n_pairs_host = total;
+    const int64_t M = c->S.n;
+    // kept: row pointers, columns, H; transient: the emitted (key, group) pairs
+    const double need = static_cast<double>(total) * (sizeof(int32_t) + sizeof(double2) + sizeof(uint64_t) +
+                                                      sizeof(uint32_t)) +
+                        static_cast<double>(M + 1) * sizeof(int64_t);
+    if (need > static_cast<double>(budget_bytes))
+        return fail(c, ELOC_ECAPACITY, "the pair list needs " + std::to_string(static_cast<long long>(need)) +
+                                           " bytes, more than the budget");
+    const int jbits = std::max(1, bits_for(static_cast<uint64_t>(M - 1)));
+    ELOC_HIP(c, c->pkey.ensure(sizeof(uint64_t) * std::max<int64_t>(total, 1)));
+    ELOC_HIP(c, c->pval.ensure(sizeof(uint32_t) * std::max<int64_t>(total, 1)));
+    ELOC_HIP(c, c->st_col.ensure(sizeof(int32_t) * std::max<int64_t>(total, 1)));
+    ELOC_HIP(c, c->st_h.ensure(sizeof(double2) * std::max<int64_t>(total, 1)));
+    ELOC_HIP(c, c->st_rowptr.ensure(sizeof(int64_t) * (M + 1)));
+    if (total > 0) {
+        ELOC_HIP(c, launch_pairs_fill(variant, c->H, c->S, P, jbits, c->offsets.as<int64_t>(), c->pkey.as<uint64_t>(),
+                                      c->pval.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_pairs_to_csr(c->H, c->S, total, c->pkey.as<uint64_t>(), c->pval.as<uint32_t>(), jbits,
+                                        c->st_col.as<int32_t>(), c->st_h.as<double2>(), c->stream));
+    }
+    ELOC_HIP(c, launch_rowptr(c->offsets.as<int64_t>(), M, P.chunks, c->st_rowptr.as<int64_t>(), c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    c->st_pairs = total;
+    c->st_valid = true;
     return ELOC_OK;
 }
 

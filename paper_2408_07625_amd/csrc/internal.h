@@ -440,6 +440,12 @@ hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n,
                                 const int32_t* i_idx, const int32_t* j_idx, double2* h_out,
                                 uint32_t* err, hipStream_t st);
 
+hipError_t launch_pairs_to_csr(const HamDev& H, const SampleDev& S, int64_t n, const uint64_t* pkey,
+                               const uint32_t* pval, int jbits, int32_t* col, double2* h, hipStream_t st);
+hipError_t launch_rowptr(const int64_t* offsets, int64_t M, int chunks, int64_t* rowptr, hipStream_t st);
+hipError_t launch_spmv(bool adjoint, int precision, int64_t M, const int64_t* rowptr, const int32_t* col,
+                       const double2* h, const void* vec, void* partial, hipStream_t st);
+
 struct SortScratch {
     uint64_t* key;
     uint32_t* val;

@@ -686,6 +686,62 @@ __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, co
 
 inline unsigned div_up(int64_t n, int64_t d) { return static_cast<unsigned>((n + d - 1) / d); }
 
+// ---------------------------------------------------------------------------
+// Stored pair lists.  k_pairs_to_csr turns the emitted pairs (row-major by
+// construction: each (row, chunk) writes a contiguous range) into a CSR of
+// (column j, H_ij with the ket x_j); k_spmv then sums a row with one wave,
+// lanes striding over its pairs and a fixed-order butterfly at the end:
+//   forward: acc_i = sum_p H_p vec[j_p]
+//   adjoint: acc_y = sum_p conj(H_p) vec[j_p]  (H_xy = conj(H_yx), H Hermitian)
+// ---------------------------------------------------------------------------
+template <int W, bool NW>
+__global__ __launch_bounds__(256) void k_pairs_to_csr(PairArgs A, int64_t n, const uint64_t* __restrict__ pkey,
+                                                      const uint32_t* __restrict__ pval, int jbits,
+                                                      int32_t* __restrict__ col, double2* __restrict__ h) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= n) return;
+    const int64_t j = static_cast<int64_t>(pkey[t] & ((1ull << jbits) - 1ull));
+    const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[pval[t]];
+    uint64_t xj[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) xj[w] = A.keys[j * W + w];
+    double hr, hi;
+    melem<W, NW>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.mid, gr.end, 0, 1, xj, hr, hi);
+    col[t] = static_cast<int32_t>(j);
+    h[t] = make_double2(hr, hi);
+}
+
+__global__ __launch_bounds__(256) void k_rowptr(const int64_t* __restrict__ offsets, int64_t M, int chunks,
+                                                int64_t* __restrict__ rowptr) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i <= M) rowptr[i] = offsets[i * chunks];
+}
+
+template <int PREC, bool ADJ>
+__global__ __launch_bounds__(kWave) void k_spmv(int64_t M, const int64_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col, const double2* __restrict__ h,
+                                                const void* __restrict__ vec, void* __restrict__ partial) {
+    using P = Prec<PREC>;
+    const int64_t i = blockIdx.x;
+    const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    typename P::Acc acc;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kWave) {
+        double2 hv = h[p];
+        if (ADJ) hv.y = -hv.y;
+        const int32_t j = col[p];
+        if constexpr (PREC == 0) {
+            mac(acc, hv.x, hv.y, static_cast<const double2*>(vec)[j]);
+        } else {
+            const float4 s = split_c(hv.x, hv.y);
+            mac(acc, F2{s.x, s.y}, F2{s.z, s.w}, static_cast<const float4*>(vec)[j]);
+        }
+    }
+    wave_sum(acc);
+    if (threadIdx.x == 0) store_acc(partial, i, acc);
+}
+
+
+
 template <int W, int VARIANT, int PREC, bool ADJ, bool NW>
 hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
     if constexpr (VARIANT == 2) {
@@ -820,6 +876,42 @@ hipError_t launch_pairs_fill(int variant, const HamDev& H, const SampleDev& S, c
     if (H.W == 2) return fill_w<2, false>(variant, A, P, jbits, offsets, pkey, pval, st);
     return H.narrow ? fill_w<1, true>(variant, A, P, jbits, offsets, pkey, pval, st)
                     : fill_w<1, false>(variant, A, P, jbits, offsets, pkey, pval, st);
+}
+
+hipError_t launch_pairs_to_csr(const HamDev& H, const SampleDev& S, int64_t n, const uint64_t* pkey,
+                               const uint32_t* pval, int jbits, int32_t* col, double2* h, hipStream_t st) {
+    Plan P;
+    const PairArgs A = make_args(H, S, P);
+    const dim3 grid(div_up(n, 256)), block(256);
+    if (H.W == 2)
+        hipLaunchKernelGGL((k_pairs_to_csr<2, false>), grid, block, 0, st, A, n, pkey, pval, jbits, col, h);
+    else if (H.narrow)
+        hipLaunchKernelGGL((k_pairs_to_csr<1, true>), grid, block, 0, st, A, n, pkey, pval, jbits, col, h);
+    else
+        hipLaunchKernelGGL((k_pairs_to_csr<1, false>), grid, block, 0, st, A, n, pkey, pval, jbits, col, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowptr(const int64_t* offsets, int64_t M, int chunks, int64_t* rowptr, hipStream_t st) {
+    hipLaunchKernelGGL(k_rowptr, dim3(div_up(M + 1, 256)), dim3(256), 0, st, offsets, M, chunks, rowptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(bool adjoint, int precision, int64_t M, const int64_t* rowptr, const int32_t* col,
+                       const double2* h, const void* vec, void* partial, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>(M)), block(kWave);
+    if (precision == 0) {
+        if (adjoint)
+            hipLaunchKernelGGL((k_spmv<0, true>), grid, block, 0, st, M, rowptr, col, h, vec, partial);
+        else
+            hipLaunchKernelGGL((k_spmv<0, false>), grid, block, 0, st, M, rowptr, col, h, vec, partial);
+    } else {
+        if (adjoint)
+            hipLaunchKernelGGL((k_spmv<1, true>), grid, block, 0, st, M, rowptr, col, h, vec, partial);
+        else
+            hipLaunchKernelGGL((k_spmv<1, false>), grid, block, 0, st, M, rowptr, col, h, vec, partial);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pi, const int32_t* pj,

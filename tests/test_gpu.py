@@ -316,3 +316,72 @@ def test_adjoint_small(eng, small_workload, use_counts, precision):
     ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, 1.0, weights=weights, energy_value=E)
     tol = TOL64 if precision == "fp64" else TOL32
     assert np.abs(L.grad.cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("variant", ["terms", "batch", "trie", "auto"])
+@pytest.mark.parametrize("use_counts", [False, True])
+def test_stored_pairs(eng, small_workload, variant, use_counts):
+    """Forward and adjoint read from the stored pair list: same results as the
+    oracle, and the stored list has exactly the oracle's pairs."""
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    weights = np.random.default_rng(2).integers(1, 30, size=w.n_unique).astype(float) if use_counts else None
+    n = eng.store_pairs(variant, 1 << 30)
+    assert n == oracle_pairs(w.ham, w.keys)[0].size
+    ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi)
+    E, var, _ = oracle.energy(ref_e, w.logpsi, weights)
+    L = dev(w.logpsi)
+    Wt = None if weights is None else dev(weights)
+    for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+        e, st = eng.local_energy(L, Wt, variant="stored", precision=prec)
+        assert np.abs(e.cpu().numpy() - ref_e).max() <= tol
+        s = st.cpu().numpy()
+        assert abs(s[0] - E.real) <= tol and abs(s[2] - var) <= tol * max(1.0, var)
+        for ge in (1.0, 0.3 - 0.4j):
+            ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, ge, weights=weights, energy_value=E)
+            g = eng.adjoint(L, e, st, ge, Wt, variant="stored", precision=prec).cpu().numpy()
+            assert np.abs(g - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+def test_stored_pairs_budget_and_lifetime(eng, small_workload):
+    import paper_2408_07625_amd as pe
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    L = dev(w.logpsi)
+    with pytest.raises(pe.ElocError) as ex:
+        eng.store_pairs("terms", 1024)
+    assert ex.value.status == "ECAPACITY"
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(L, None, variant="stored")
+    assert ex.value.status == "ESTATE"
+    eng.store_pairs("terms", 1 << 30)
+    eng.local_energy(L, None, variant="stored")
+    eng.set_samples(keys_dev(w.keys))          # new samples invalidate the list
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(L, None, variant="stored")
+    assert ex.value.status == "ESTATE"
+    # through autograd: stored when it fits, recomputed when it does not
+    ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi)
+    E, _, _ = oracle.energy(ref_e, w.logpsi, None)
+    ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, 1.0, energy_value=E)
+    for budget in (1 << 30, 1024):
+        Lg = dev(w.logpsi).requires_grad_(True)
+        E_t, _, _ = pe.local_energy(eng, Lg, None, "terms", "fp64", store_budget=budget)
+        E_t.real.backward()
+        assert np.abs(Lg.grad.cpu().numpy() - ref).max() <= TOL64 * max(1.0, np.abs(ref).max())
+
+
+def test_stored_pairs_wide_sampled(eng):
+    """Two-word keys with occurrence counts: stored forward + adjoint on the
+    100-qubit workload, sampled rows against the oracle."""
+    w = configs.wide()
+    load(eng, w.ham, w.keys)
+    n = eng.store_pairs("auto", 1 << 36)
+    assert n > 0
+    L, Wt = dev(w.logpsi), dev(w.weights)
+    rows = [(0, 64), ((1 << 18) - 40, 1 << 18)]
+    ref = np.concatenate([oracle.local_energy(w.ham, w.keys, w.logpsi, rows=r) for r in rows])
+    sel = np.concatenate([np.arange(a, b) for a, b in rows])
+    for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+        e, st = eng.local_energy(L, Wt, variant="stored", precision=prec)
+        assert np.abs(e.cpu().numpy()[sel] - ref).max() <= tol, prec
