@@ -145,6 +145,31 @@ __device__ __forceinline__ typename TabT<TK>::slot load_slot(const Table& T, uin
     return static_cast<const typename TabT<TK>::slot*>(T.slots)[s];
 }
 
+// Slot loads through a bounds-checked raw buffer resource: an offset past the
+// end of the slot array (kNoSlot) returns 0 without touching memory, so a
+// filtered-out candidate needs no branch around its loads.  Dword 3 of the
+// resource is the raw 32-bit format word of the gfx9 family.
+constexpr uint32_t kNoSlot = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;
+
+template <int TK>
+struct SlotReader {
+    using ST = typename TabT<TK>::slot;
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ explicit SlotReader(const Table& T)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(T.slots), static_cast<short>(0),
+                                               static_cast<int>((T.mask + 1u) * sizeof(ST)), kRawBufferWord3)) {}
+    __device__ __forceinline__ ST load(uint32_t slot, bool ok) const {
+        const uint32_t off = ok ? slot * static_cast<uint32_t>(sizeof(ST)) : kNoSlot;
+        if constexpr (sizeof(ST) == 4) {
+            return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        } else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+            return (static_cast<uint64_t>(v[1]) << 32) | v[0];
+        }
+    }
+};
+
 // Second half of a lookup of a key with salted hash hs, given its two slot
 // values; `nstash` is the stash count (wave-uniform).  Index of the key in
 // `keys` (two-word format only), or -1.

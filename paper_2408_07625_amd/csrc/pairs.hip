@@ -137,6 +137,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.ktable;
+    const SlotReader<TK> slots(T);
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     const int lane = static_cast<int>(threadIdx.x);
@@ -179,10 +180,10 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
                     }
                 }
             }
-            if (SIG) ok = ok && pa == A.sig_pa && n == A.sig_n;
+            if (SIG) ok = ok & (pa == A.sig_pa) & (n == A.sig_n);
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
-            v1[r] = ok ? load_slot<TK>(T, slot1(T, hs[r])) : 0u;
-            v2[r] = ok ? load_slot<TK>(T, slot2(T, hs[r])) : 0u;
+            v1[r] = slots.load(slot1(T, hs[r]), ok);
+            v2[r] = slots.load(slot2(T, hs[r]), ok);
         }
         uint64_t nxy[W];
         int nrun = run;
@@ -217,6 +218,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
     using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.gtable;
+    const SlotReader<TK> slots(T);
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
     const int64_t j1 = min(A.M, j0 + A.per_chunk);
     for (int64_t base = j0; base < j1; base += kWave) {
@@ -244,10 +246,10 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
                     pc += popc64(m[r][w]);
                 }
             }
-            const bool ok = valid && pc <= A.maxpop;
+            const bool ok = valid & (pc <= A.maxpop);
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
-            v1[r] = ok ? load_slot<TK>(T, slot1(T, hs[r])) : 0u;
-            v2[r] = ok ? load_slot<TK>(T, slot2(T, hs[r])) : 0u;
+            v1[r] = slots.load(slot1(T, hs[r]), ok);
+            v2[r] = slots.load(slot2(T, hs[r]), ok);
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
