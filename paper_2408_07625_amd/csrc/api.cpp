@@ -33,12 +33,12 @@ struct eloc_ctx_s {
     bool ham_set = false;
     HamDev H;
     DevBuf groups, terms, terms_f, ghash, gkeys, gslots, gstash;
-    DevBuf xyt_keys, xyt_gid, xyt_nodes;
+    DevBuf xyt_keys, xyt_gid, xyt_nodes, xyt_nkeys;
 
     bool samples_set = false;
     SampleDev S;
     DevBuf keys, khash, kslots, kstash, sig;
-    DevBuf ut_keys, ut_perm, ut_nodes;
+    DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
     bool ut_valid = false;
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
 
@@ -190,9 +190,11 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, c->xyt_keys.ensure(sizeof(uint64_t) * G * W));
     ELOC_HIP(c, c->xyt_gid.ensure(sizeof(int32_t) * G));
     ELOC_HIP(c, c->xyt_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, xy_chunks * (xy_chunk - 1))));
+    ELOC_HIP(c, c->xyt_nkeys.ensure(sizeof(uint64_t) * W * std::max<int64_t>(1, xy_chunks * (xy_chunk - 1))));
     ELOC_HIP(c, hipMemcpy(c->xyt_keys.p, xsorted.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->xyt_gid.p, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice));
-    ELOC_HIP(c, launch_trie_build(W, c->xyt_keys.as<uint64_t>(), G, xy_chunk, c->xyt_nodes.as<TNode>(), c->stream));
+    ELOC_HIP(c, launch_trie_build(W, c->xyt_keys.as<uint64_t>(), G, xy_chunk, c->xyt_nodes.as<TNode>(),
+                                  c->xyt_nkeys.as<uint64_t>(), c->stream));
     ELOC_HIP(c, c->groups.ensure(sizeof(GroupRec<W>) * G));
     ELOC_HIP(c, c->terms.ensure(sizeof(TermRec<W>) * n_terms));
     ELOC_HIP(c, c->terms_f.ensure(sizeof(TermRecF<W>) * n_terms));
@@ -228,6 +230,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
     H.xyt.gid = c->xyt_gid.as<int32_t>();
     H.xyt.nodes = c->xyt_nodes.as<TNode>();
+    H.xyt.nkeys = c->xyt_nkeys.as<uint64_t>();
     H.xyt.chunk = static_cast<int>(xy_chunk);
     H.xyt.chunks = static_cast<int>(xy_chunks);
     c->H = H;
@@ -278,6 +281,7 @@ int ensure_utrie(eloc_ctx c) {
     ELOC_HIP(c, c->ut_keys.ensure(sizeof(uint64_t) * M * W));
     ELOC_HIP(c, c->ut_perm.ensure(sizeof(int32_t) * M));
     ELOC_HIP(c, c->ut_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, M - 1)));
+    ELOC_HIP(c, c->ut_nkeys.ensure(sizeof(uint64_t) * W * std::max<int64_t>(1, M - 1)));
     ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * M));
     ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * M));
     ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * M));
@@ -291,11 +295,13 @@ int ensure_utrie(eloc_ctx c) {
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
     ELOC_HIP(c, launch_sort_keys(W, c->H.n_qubits, c->keys.as<uint64_t>(), M, ss, c->ut_keys.as<uint64_t>(),
                                  c->ut_perm.as<int32_t>(), c->stream));
-    ELOC_HIP(c, launch_trie_build(W, c->ut_keys.as<uint64_t>(), M, M, c->ut_nodes.as<TNode>(), c->stream));
+    ELOC_HIP(c, launch_trie_build(W, c->ut_keys.as<uint64_t>(), M, M, c->ut_nodes.as<TNode>(),
+                                  c->ut_nkeys.as<uint64_t>(), c->stream));
     prof_end(c, pm);
     c->S.ut.keys = c->ut_keys.as<uint64_t>();
     c->S.ut.perm = c->ut_perm.as<int32_t>();
     c->S.ut.nodes = c->ut_nodes.as<TNode>();
+    c->S.ut.nkeys = c->ut_nkeys.as<uint64_t>();
     c->ut_valid = true;
     return ELOC_OK;
 }
@@ -408,8 +414,8 @@ void eloc_destroy(eloc_ctx c) {
                       &c->keys, &c->khash, &c->kslots, &c->sig, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
-                      &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes,
-                      &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2};
+                      &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
+                      &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->ut_nkeys, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2};
     for (DevBuf* b : bufs) b->release();
     for (auto& m : c->marks) {
         c->ev_pool.push_back(m.a);

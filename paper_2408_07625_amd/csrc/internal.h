@@ -273,6 +273,7 @@ struct XYTrieDev {
     const uint64_t* keys = nullptr;   // [G][W] sorted
     const int32_t* gid = nullptr;     // group id of each sorted mask
     const TNode* nodes = nullptr;
+    const uint64_t* nkeys = nullptr;  // representative key of each node
     int chunk = 0;
     int chunks = 0;
 };
@@ -281,6 +282,7 @@ struct UTrieDev {
     const uint64_t* keys = nullptr;   // [M][W] sorted
     const int32_t* perm = nullptr;    // sample index of each sorted key
     const TNode* nodes = nullptr;     // [M - 1]
+    const uint64_t* nkeys = nullptr;  // [M - 1][W] representative key of each node
 };
 
 struct HamDev {
@@ -483,7 +485,7 @@ struct SortScratch {
 hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, const SortScratch& S,
                             uint64_t* sorted, int32_t* perm, hipStream_t st);
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
-                             hipStream_t st);
+                             uint64_t* nkeys, hipStream_t st);
 int rows_per_block(int variant, int requested);
 
 // Batched pipeline (batch.hip; the persistent pair kernel in pairs.hip).

@@ -553,7 +553,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_keys(const uint64_t* __restri
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_trie_build(const uint64_t* __restrict__ K, int64_t n_total, int64_t per,
-                                                       int64_t segs, TNode* __restrict__ nodes) {
+                                                       int64_t segs, TNode* __restrict__ nodes,
+                                                       uint64_t* __restrict__ nkeys) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t s = t / (per - 1);
     const int64_t i = t % (per - 1);
@@ -561,7 +562,11 @@ __global__ __launch_bounds__(kBlock) void k_trie_build(const uint64_t* __restric
     const int64_t base = s * per;
     const int64_t n = min(per, n_total - base);
     if (i >= n - 1) return;
-    nodes[s * (per - 1) + i] = trie_node<W>(K + base * W, n, i);
+    const TNode nd = trie_node<W>(K + base * W, n, i);
+    const int64_t o = s * (per - 1) + i;
+    nodes[o] = nd;
+#pragma unroll
+    for (int w = 0; w < W; ++w) nkeys[o * W + w] = K[(base + nd.rep) * W + w];
 }
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
@@ -706,16 +711,16 @@ hipError_t launch_split_pairs(const uint64_t* keys, const uint32_t* vals, int64_
 
 
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
-                             hipStream_t st) {
+                             uint64_t* nkeys, hipStream_t st) {
     if (per < 2 || n_total < 2) return hipSuccess;
     const int64_t segs = (n_total + per - 1) / per;
     const int64_t threads = segs * (per - 1);
     if (W == 1)
         hipLaunchKernelGGL(k_trie_build<1>, dim3(blocks_for(threads)), dim3(kBlock), 0, st, keys, n_total, per, segs,
-                           nodes);
+                           nodes, nkeys);
     else
         hipLaunchKernelGGL(k_trie_build<2>, dim3(blocks_for(threads)), dim3(kBlock), 0, st, keys, n_total, per, segs,
-                           nodes);
+                           nodes, nkeys);
     return hipGetLastError();
 }
 

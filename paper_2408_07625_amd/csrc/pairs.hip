@@ -58,9 +58,11 @@ struct PairArgs {
     const uint64_t* u_keys;
     const int32_t* u_perm;
     const TNode* u_nodes;
+    const uint64_t* u_nkeys;
     const uint64_t* xy_keys;
     const int32_t* xy_gid;
     const TNode* xy_nodes;
+    const uint64_t* xy_nkeys;
     int xy_chunk;
 };
 
@@ -84,9 +86,11 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.u_keys = S.ut.keys;
     a.u_perm = S.ut.perm;
     a.u_nodes = S.ut.nodes;
+    a.u_nkeys = S.ut.nkeys;
     a.xy_keys = H.xyt.keys;
     a.xy_gid = H.xyt.gid;
     a.xy_nodes = H.xyt.nodes;
+    a.xy_nkeys = H.xyt.nkeys;
     a.xy_chunk = H.xyt.chunk;
     return a;
 }
@@ -589,10 +593,12 @@ template <int W>
 __device__ __forceinline__ void trie_views(const PairArgs& A, int chunk, TrieView& U, TrieView& V, int64_t& vbase) {
     U.keys = A.u_keys;
     U.nodes = A.u_nodes;
+    U.nkeys = A.u_nkeys;
     U.n = A.M;
     vbase = static_cast<int64_t>(chunk) * A.xy_chunk;
     V.keys = A.xy_keys + vbase * W;
     V.nodes = A.xy_nodes + static_cast<int64_t>(chunk) * (A.xy_chunk - 1);
+    V.nkeys = A.xy_nkeys + static_cast<int64_t>(chunk) * (A.xy_chunk - 1) * W;
     V.n = min(static_cast<int64_t>(A.xy_chunk), static_cast<int64_t>(A.n_groups) - vbase);
 }
 

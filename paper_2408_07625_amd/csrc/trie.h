@@ -101,11 +101,13 @@ __host__ __device__ inline bool trie_agree(const uint64_t* a, const uint64_t* b,
     return ok;
 }
 
-// One tree: sorted keys K[n][W], internal nodes N[n-1], root 0 (or leaf ~0
-// when n == 1).
+// One tree: sorted keys K[n][W], internal nodes N[n-1] with the key of each
+// node's representative leaf beside them (nkeys[n-1][W], so that a node and
+// its key are loaded together), root 0 (or leaf ~0 when n == 1).
 struct TrieView {
     const uint64_t* keys;
     const TNode* nodes;
+    const uint64_t* nkeys;
     int64_t n;
 };
 
@@ -127,8 +129,8 @@ __host__ __device__ inline void trie_walk(const uint64_t* x, const TrieView& U, 
         bool next = false;
         const TNode nu = u >= 0 ? U.nodes[u] : TNode{0, 0, ~u, -1};
         const TNode nv = v >= 0 ? V.nodes[v] : TNode{0, 0, ~v, -1};
-        const uint64_t* ku = U.keys + static_cast<int64_t>(nu.rep) * W;
-        const uint64_t* kv = V.keys + static_cast<int64_t>(nv.rep) * W;
+        const uint64_t* ku = u >= 0 ? U.nkeys + static_cast<int64_t>(u) * W : U.keys + static_cast<int64_t>(~u) * W;
+        const uint64_t* kv = v >= 0 ? V.nkeys + static_cast<int64_t>(v) * W : V.keys + static_cast<int64_t>(~v) * W;
         const int b = nu.bit > nv.bit ? nu.bit : nv.bit;
         if (trie_agree<W>(x, ku, kv, b + 1, d)) {
             if (b < 0) {
