@@ -37,7 +37,7 @@ struct eloc_ctx_s {
 
     bool samples_set = false;
     SampleDev S;
-    DevBuf keys, khash, kslots, kstash, sig;
+    DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad;
     DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
     bool ut_valid = false;
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
@@ -46,6 +46,7 @@ struct eloc_ctx_s {
     DevBuf partial, energy_scratch, err_run, err_prep;
     uint32_t* err_host = nullptr;
     uint64_t* sig_host = nullptr;    // pinned copy of the signature bitmap
+    unsigned long long* rad_host = nullptr;   // pinned: reference key [2], max distance
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
@@ -60,6 +61,8 @@ struct eloc_ctx_s {
     int tune_rows = 8;
     bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
     int sig_pa = 0, sig_n = 0;
+    uint64_t rad_ref[2] = {0, 0};
+    int rad_max = 128;       // radius of U around rad_ref (128: filter off)
     uint64_t salt_state = 0x5EED2408ull;
 
     // stage profiling: HIP events around each stage, read (and reset) by
@@ -109,9 +112,16 @@ Plan make_plan(const eloc_ctx c, int variant) {
     Plan P;
     const int64_t M = c->S.n;
     P.rows_per_block = rows_per_block(variant, c->tune_rows);
-    P.sig_filter = c->tune_sig != 0 && c->sig_one;
+    // the exact prefilters of LoopOverTerms: U's single popcount signature,
+    // and U's radius around its majority key when that is under half the qubits
+    const bool rad_on = 2 * c->rad_max < c->H.n_qubits;
+    P.sig_filter = c->tune_sig != 0 && (c->sig_one || rad_on);
     P.sig_pa = c->sig_pa;
     P.sig_n = c->sig_n;
+    P.sig_all = !c->sig_one;
+    P.rad_ref[0] = c->rad_ref[0];
+    P.rad_ref[1] = c->rad_ref[1];
+    P.rad_max = rad_on ? c->rad_max : 128;
     if (variant == ELOC_TRIE) {
         P.chunks = c->H.xyt.chunks;
         P.per_chunk = c->H.xyt.chunk;
@@ -397,6 +407,8 @@ int eloc_create(eloc_ctx* out, int device, void* hip_stream) {
         hipMemset(c->err_run.p, 0, sizeof(uint32_t)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->sig_host), sizeof(uint64_t) * kSigWords, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->rad_host), sizeof(unsigned long long) * 3, hipHostMallocDefault) !=
             hipSuccess) {
         eloc_destroy(c);
         return ELOC_EHIP;
@@ -411,7 +423,7 @@ void eloc_destroy(eloc_ctx c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->R_dev, &c->groups, &c->terms, &c->terms_f, &c->ghash, &c->gkeys, &c->gslots,
-                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
+                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->bitcounts, &c->rad, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
                       &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
@@ -424,6 +436,7 @@ void eloc_destroy(eloc_ctx c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->err_host) (void)hipHostFree(c->err_host);
     if (c->sig_host) (void)hipHostFree(c->sig_host);
+    if (c->rad_host) (void)hipHostFree(c->rad_host);
     delete c;
 }
 
@@ -482,12 +495,19 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     ELOC_HIP(c, c->kslots.ensure(slot_bytes(tk) * cap));
     ELOC_HIP(c, c->kstash.ensure(sizeof(Stash)));
     ELOC_HIP(c, c->sig.ensure(sizeof(uint64_t) * kSigWords));
+    ELOC_HIP(c, c->bitcounts.ensure(sizeof(uint32_t) * 64 * W));
+    ELOC_HIP(c, c->rad.ensure(sizeof(unsigned long long) * 3));
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
     ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
                                c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->bitcounts.p, 0, sizeof(uint32_t) * 64 * W, c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->rad.p, 0, sizeof(unsigned long long) * 3, c->stream));
     ELOC_HIP(c, launch_sample_hash(W, c->keys.as<uint64_t>(), n_unique, c->R_dev.as<uint64_t>(), c->H.n_qubits,
-                                   c->khash.as<uint64_t>(), c->err_prep.as<uint32_t>(), c->stream));
+                                   c->khash.as<uint64_t>(), c->bitcounts.as<uint32_t>(), c->err_prep.as<uint32_t>(),
+                                   c->stream));
+    ELOC_HIP(c, launch_sample_radius(W, c->keys.as<uint64_t>(), n_unique, c->bitcounts.as<uint32_t>(),
+                                     c->rad.as<unsigned long long>(), c->stream));
     SampleDev S;
     S.n = n_unique;
     S.keys = c->keys.as<uint64_t>();
@@ -509,6 +529,8 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
                                          c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->err_host, c->err_prep.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->sig_host, c->sig.p, sizeof(uint64_t) * kSigWords, hipMemcpyDeviceToHost,
+                                   c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(c->rad_host, c->rad.p, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost,
                                    c->stream));
         ELOC_HIP(c, hipStreamSynchronize(c->stream));
         bits = *c->err_host;
@@ -532,6 +554,9 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
             c->sig_pa = pa;
             c->sig_n = pa + pb;
         }
+    c->rad_ref[0] = c->rad_host[0];
+    c->rad_ref[1] = W == 2 ? c->rad_host[1] : 0ull;
+    c->rad_max = static_cast<int>(c->rad_host[2]);
     c->S = S;
     c->ut_valid = false;
     c->st_valid = false;

@@ -56,7 +56,7 @@ struct eloc_batch_s {
 
     DevBuf R_dev, groups, terms, terms_f, ghash, gkeys, gslots, gstash;
     DevBuf probs, pid, tiles_dev, sched, keys, khash, kslots, kstash;
-    DevBuf err_dev, sigmin, sigmax, shift, scal, part, pairs, work, a, b, af, bf, partial;
+    DevBuf err_dev, sigmin, sigmax, bitcounts, rad, shift, scal, part, pairs, work, a, b, af, bf, partial;
     uint32_t* err_host = nullptr;
 
     eloc_batch_schedule schedule{};
@@ -112,6 +112,8 @@ BatchDev dev_view(const eloc_batch b) {
     B.err = b->err_dev.as<uint32_t>();
     B.sigmin = b->sigmin.as<uint32_t>();
     B.sigmax = b->sigmax.as<uint32_t>();
+    B.bitcounts = b->bitcounts.as<uint32_t>();
+    B.rad = b->rad.as<unsigned long long>();
     B.shift = b->shift.as<double>();
     B.scal = b->scal.as<double>();
     B.part = b->part.as<double>();
@@ -512,6 +514,8 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
     BATCH_HIP(b, b->khash.ensure(sizeof(uint64_t) * S));
     BATCH_HIP(b, b->sigmin.ensure(sizeof(uint32_t) * n));
     BATCH_HIP(b, b->sigmax.ensure(sizeof(uint32_t) * n));
+    BATCH_HIP(b, b->bitcounts.ensure(sizeof(uint32_t) * 128 * n));
+    BATCH_HIP(b, b->rad.ensure(sizeof(unsigned long long) * 3 * n));
     BATCH_HIP(b, b->shift.ensure(sizeof(double) * n));
     BATCH_HIP(b, b->scal.ensure(sizeof(double) * 3 * n));
     BATCH_HIP(b, b->part.ensure(sizeof(double) * 3 * nt));
@@ -539,7 +543,7 @@ void eloc_batch_destroy(eloc_batch b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     DevBuf* bufs[] = {&b->R_dev, &b->groups, &b->terms, &b->terms_f, &b->ghash, &b->gkeys, &b->gslots, &b->gstash,
                       &b->probs, &b->pid, &b->tiles_dev, &b->sched, &b->keys, &b->khash, &b->kslots, &b->kstash,
-                      &b->err_dev, &b->sigmin, &b->sigmax, &b->shift, &b->scal, &b->part, &b->pairs, &b->work,
+                      &b->err_dev, &b->sigmin, &b->sigmax, &b->bitcounts, &b->rad, &b->shift, &b->scal, &b->part, &b->pairs, &b->work,
                       &b->a, &b->b, &b->af, &b->bf, &b->partial};
     for (DevBuf* d : bufs) d->release();
     if (b->err_host) (void)hipHostFree(b->err_host);

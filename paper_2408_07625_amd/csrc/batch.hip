@@ -27,6 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_bt_clear(BatchDev B) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     for (int64_t i = t0; i < B.n_slot_words; i += stride) B.slots[i] = 0u;
+    for (int64_t i = t0; i < static_cast<int64_t>(B.n) * 128; i += stride) B.bitcounts[i] = 0u;
+    for (int64_t i = t0; i < static_cast<int64_t>(B.n) * 3; i += stride) B.rad[i] = 0ull;
     if (t0 < B.n) {
         B.stash[t0].count = 0u;
         B.err[t0] = 0u;
@@ -78,6 +80,23 @@ __global__ __launch_bounds__(kBlock) void k_bt_hash(BatchDev B) {
     const int k0 = __builtin_amdgcn_readfirstlane(k);
     const uint64_t all = __ballot(1);
     const bool one = __ballot(valid && k == k0) == all && __ballot(valid) == all;
+    // per-qubit counts of set bits: lane q adds the wave's count of qubit q
+    const int lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint64_t v = valid ? B.keys[i * W + w] : 0ull;
+        if (one) {
+            uint32_t mine = 0u;
+            for (int q = 0; q < 64; ++q) {
+                const uint32_t c = static_cast<uint32_t>(__popcll(__ballot((v >> q) & 1ull)));
+                if (lane == q) mine = c;
+            }
+            if (mine) atomicAdd(B.bitcounts + static_cast<int64_t>(k0) * 128 + 64 * w + lane, mine);
+        } else if (valid) {
+            for (uint64_t u = v; u; u &= u - 1ull)
+                atomicAdd(B.bitcounts + static_cast<int64_t>(k) * 128 + 64 * w + (__ffsll(static_cast<unsigned long long>(u)) - 1), 1u);
+        }
+    }
     if (one) {
         uint32_t mn = code, mx = code;
 #pragma unroll
@@ -92,6 +111,42 @@ __global__ __launch_bounds__(kBlock) void k_bt_hash(BatchDev B) {
     } else if (valid) {
         atomicMin(B.sigmin + k, code);
         atomicMax(B.sigmax + k, code);
+    }
+}
+
+// one thread per problem: majority key of U_k (radius filter reference)
+__global__ __launch_bounds__(kBlock) void k_bt_radius_ref(BatchDev B) {
+    const int k = static_cast<int>(blockIdx.x) * kBlock + threadIdx.x;
+    if (k >= B.n) return;
+    const int64_t M = B.probs[k].M;
+    for (int w = 0; w < 2; ++w) {
+        uint64_t c = 0;
+        if (w < B.W)
+            for (int q = 0; q < 64; ++q)
+                if (2 * static_cast<int64_t>(B.bitcounts[static_cast<int64_t>(k) * 128 + 64 * w + q]) > M) c |= 1ull << q;
+        B.rad[3 * k + w] = c;
+    }
+}
+
+// max distance of U_k's keys from that key
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_bt_radius_max(BatchDev B) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const bool valid = i < B.S;
+    const int k = valid ? B.pid[i] : 0;
+    int d = 0;
+    if (valid) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) d += popc64(B.keys[i * W + w] ^ B.rad[3 * k + w]);
+    }
+    const int k0 = __builtin_amdgcn_readfirstlane(k);
+    const uint64_t all = __ballot(1);
+    if (__ballot(valid && k == k0) == all && __ballot(valid) == all) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) d = max(d, __shfl_xor(d, m, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(B.rad + 3 * k0 + 2, static_cast<unsigned long long>(d));
+    } else if (valid) {
+        atomicMax(B.rad + 3 * k + 2, static_cast<unsigned long long>(d));
     }
 }
 
@@ -306,16 +361,21 @@ hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st) {
     const dim3 grid(blocks_for(B.S)), block(kBlock);
     if (B.W == 2) {
         hipLaunchKernelGGL(k_bt_hash<2>, grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_radius_ref, dim3(blocks_for(B.n)), block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_radius_max<2>, grid, block, 0, st, B);
         hipLaunchKernelGGL(k_bt_insert<kTabVerify>, grid, block, 0, st, B);
         hipLaunchKernelGGL((k_bt_verify<2, kTabVerify>), grid, block, 0, st, B);
-    } else if (B.narrow) {
-        hipLaunchKernelGGL(k_bt_hash<1>, grid, block, 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert<kTabNarrow>, grid, block, 0, st, B);
-        hipLaunchKernelGGL((k_bt_verify<1, kTabNarrow>), grid, block, 0, st, B);
     } else {
         hipLaunchKernelGGL(k_bt_hash<1>, grid, block, 0, st, B);
-        hipLaunchKernelGGL(k_bt_insert<kTabWide>, grid, block, 0, st, B);
-        hipLaunchKernelGGL((k_bt_verify<1, kTabWide>), grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_radius_ref, dim3(blocks_for(B.n)), block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_radius_max<1>, grid, block, 0, st, B);
+        if (B.narrow) {
+            hipLaunchKernelGGL(k_bt_insert<kTabNarrow>, grid, block, 0, st, B);
+            hipLaunchKernelGGL((k_bt_verify<1, kTabNarrow>), grid, block, 0, st, B);
+        } else {
+            hipLaunchKernelGGL(k_bt_insert<kTabWide>, grid, block, 0, st, B);
+            hipLaunchKernelGGL((k_bt_verify<1, kTabWide>), grid, block, 0, st, B);
+        }
     }
     hipLaunchKernelGGL(k_bt_minmax, dim3(static_cast<unsigned>(B.n_tiles)), dim3(kBlock), 0, st, B);
     hipLaunchKernelGGL(k_bt_shift, dim3(blocks_for(B.n)), dim3(kBlock), 0, st, B, fp32 ? 1 : 0);

@@ -322,9 +322,13 @@ struct AmpDev {
 struct Plan {
     int chunks = 1;            // group (or sample) chunks per row
     int per_chunk = 0;         // groups (or samples) per chunk
-    bool sig_filter = true;    // U has one (even, odd) popcount signature and the filter is on
+    bool sig_filter = true;    // exact LoopOverTerms prefilters on: U's single (even, total)
+                               // popcount signature and / or its radius
     int sig_pa = 0;            // that signature: popcount on even qubits
     int sig_n = 0;             //                 total popcount
+    bool sig_all = false;      // no single signature: the signature test passes everything
+    uint64_t rad_ref[kMaxWords] = {0, 0};   // radius filter: reference key and
+    int rad_max = 128;                      // max distance of U from it (128: off)
     int rows_per_block = 1;    // rows owned by one workgroup
 };
 
@@ -412,6 +416,8 @@ struct BatchDev {
     uint32_t* err;             // [n] error bits
     uint32_t* sigmin;          // [n] min / max of (even popcount << 8 | popcount) over U_k
     uint32_t* sigmax;
+    uint32_t* bitcounts;       // [n][128] per-qubit counts of set bits over U_k
+    unsigned long long* rad;   // [n][3] majority key of U_k (2 words), max distance from it
     double* shift;             // [n] max Re L
     double* scal;              // [n][3] E re, E im, sum w
     double* part;              // [n_tiles][3] reduction partials
@@ -428,7 +434,11 @@ struct BatchDev {
 // Launchers (kernels.hip).  All enqueue on `st` and return hipError_t.
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R,
-                              int n_qubits, uint64_t* hash, uint32_t* err, hipStream_t st);
+                              int n_qubits, uint64_t* hash, uint32_t* counts, uint32_t* err, hipStream_t st);
+// rad[0..W-1] = per-qubit majority key of U (from the counts), rad[2] = max
+// distance of U's keys from it (rad[2] must start at 0).
+hipError_t launch_sample_radius(int W, const uint64_t* keys, int64_t n, const uint32_t* counts,
+                                unsigned long long* rad, hipStream_t st);
 hipError_t launch_table_insert(int table_kind, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
                                const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t* sig, uint32_t* err,

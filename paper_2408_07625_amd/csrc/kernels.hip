@@ -22,29 +22,65 @@ constexpr int kBlock = 256;
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restrict__ keys, int64_t n,
                                                         const uint64_t* __restrict__ R, int n_qubits,
-                                                        uint64_t* __restrict__ hash,
+                                                        uint64_t* __restrict__ hash, uint32_t* __restrict__ counts,
                                                         uint32_t* __restrict__ err) {
+    __shared__ uint32_t lc[64 * W];   // per-qubit counts of set bits in this block
+    for (int t = threadIdx.x; t < 64 * W; t += kBlock) lc[t] = 0u;
+    __syncthreads();
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint64_t h = 0;
-    bool bad = false;
+    if (i < n) {
+        uint64_t h = 0;
+        bool bad = false;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        uint64_t v = keys[i * W + w];
-        const int valid = n_qubits - 64 * w;
-        if (valid < 64) {
-            const uint64_t allowed = valid <= 0 ? 0ull : ((1ull << valid) - 1ull);
-            bad = bad || (v & ~allowed) != 0ull;
-            v &= allowed;
+        for (int w = 0; w < W; ++w) {
+            uint64_t v = keys[i * W + w];
+            const int valid = n_qubits - 64 * w;
+            if (valid < 64) {
+                const uint64_t allowed = valid <= 0 ? 0ull : ((1ull << valid) - 1ull);
+                bad = bad || (v & ~allowed) != 0ull;
+                v &= allowed;
+            }
+            while (v) {
+                const int q = __ffsll(static_cast<unsigned long long>(v)) - 1;
+                h ^= R[64 * w + q];
+                atomicAdd(&lc[64 * w + q], 1u);
+                v &= v - 1ull;
+            }
         }
-        while (v) {
-            const int q = __ffsll(static_cast<unsigned long long>(v)) - 1;
-            h ^= R[64 * w + q];
-            v &= v - 1ull;
-        }
+        hash[i] = h;
+        if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
     }
-    hash[i] = h;
-    if (bad) atomicOr(err, static_cast<uint32_t>(kErrBits));
+    __syncthreads();
+    for (int t = threadIdx.x; t < 64 * W; t += kBlock)
+        if (lc[t]) atomicAdd(counts + t, lc[t]);
+}
+
+// Radius filter of LoopOverTerms: reference key c = per-qubit majority of U
+// (rad[0..W-1]), then rad[2] = max over U of |x ^ c|.  A candidate farther
+// than that from c is not in U.
+template <int W>
+__global__ void k_radius_ref(const uint32_t* __restrict__ counts, int64_t n, unsigned long long* __restrict__ rad) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int w = 0; w < W; ++w) {
+        uint64_t c = 0;
+        for (int q = 0; q < 64; ++q)
+            if (2 * static_cast<int64_t>(counts[64 * w + q]) > n) c |= 1ull << q;
+        rad[w] = c;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_radius_max(const uint64_t* __restrict__ keys, int64_t n,
+                                                       unsigned long long* __restrict__ rad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    int d = 0;
+    if (i < n) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) d += popc64(keys[i * W + w] ^ rad[w]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) d = max(d, __shfl_xor(d, m, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(rad + 2, static_cast<unsigned long long>(d));
 }
 
 template <int TK>
@@ -577,11 +613,25 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint64_t* R, int n_qubits,
-                              uint64_t* hash, uint32_t* err, hipStream_t st) {
+                              uint64_t* hash, uint32_t* counts, uint32_t* err, hipStream_t st) {
     if (W == 1)
-        hipLaunchKernelGGL(k_sample_hash<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, R, n_qubits, hash, err);
+        hipLaunchKernelGGL(k_sample_hash<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, R, n_qubits, hash,
+                           counts, err);
     else
-        hipLaunchKernelGGL(k_sample_hash<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, R, n_qubits, hash, err);
+        hipLaunchKernelGGL(k_sample_hash<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, R, n_qubits, hash,
+                           counts, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_radius(int W, const uint64_t* keys, int64_t n, const uint32_t* counts,
+                                unsigned long long* rad, hipStream_t st) {
+    if (W == 1) {
+        hipLaunchKernelGGL(k_radius_ref<1>, dim3(1), dim3(64), 0, st, counts, n, rad);
+        hipLaunchKernelGGL(k_radius_max<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, rad);
+    } else {
+        hipLaunchKernelGGL(k_radius_ref<2>, dim3(1), dim3(64), 0, st, counts, n, rad);
+        hipLaunchKernelGGL(k_radius_max<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, rad);
+    }
     return hipGetLastError();
 }
 

@@ -50,6 +50,9 @@ struct PairArgs {
     Table ktable;
     int sig_pa;
     int sig_n;
+    bool sig_all;
+    int rad_max;
+    uint64_t rad_ref[kMaxWords];
     int kstash;      // stash counts, read at kernel start
     int gstash;
     int64_t M;
@@ -81,6 +84,10 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.ktable = S.table;
     a.sig_pa = P.sig_pa;
     a.sig_n = P.sig_n;
+    a.sig_all = P.sig_all;
+    a.rad_max = P.rad_max;
+    a.rad_ref[0] = P.rad_ref[0];
+    a.rad_ref[1] = P.rad_ref[1];
     a.M = S.n;
     a.per_chunk = P.per_chunk;
     a.u_keys = S.ut.keys;
@@ -166,13 +173,14 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             bool ok = valid;
-            int pa = 0, n = 0;
+            int pa = 0, n = 0, d = 0;
             if constexpr (NW) {
                 const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
                 xp[r][0] = x32;
                 if (SIG) {
                     pa = __popc(x32 & static_cast<uint32_t>(kEven));
                     n = __popc(x32);
+                    d = __popc(x32 ^ static_cast<uint32_t>(A.rad_ref[0]));
                 }
             } else {
 #pragma unroll
@@ -181,10 +189,13 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
                     if (SIG) {
                         pa += popc64(xp[r][w] & kEven);
                         n += popc64(xp[r][w]);
+                        d += popc64(xp[r][w] ^ A.rad_ref[w]);
                     }
                 }
             }
-            if (SIG) ok = ok & (pa == A.sig_pa) & (n == A.sig_n);
+            // exact prefilters: U's single popcount signature (unless
+            // sig_all) and U's radius around its majority key
+            if (SIG) ok = ok & (A.sig_all | ((pa == A.sig_pa) & (n == A.sig_n))) & (d <= A.rad_max);
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
             v2[r] = slots.load(slot2(T, hs[r]), ok);
@@ -547,9 +558,14 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         A.M = D.M;
         A.per_chunk = D.per_chunk;
         const uint32_t smin = B.sigmin[k], smax = B.sigmax[k];
-        const bool sig = smin == smax;
         A.sig_pa = static_cast<int>(smin >> 8);
         A.sig_n = static_cast<int>(smin & 255u);
+        A.sig_all = smin != smax;
+        A.rad_ref[0] = B.rad[3 * k];
+        A.rad_ref[1] = B.rad[3 * k + 1];
+        const int rmax = static_cast<int>(B.rad[3 * k + 2]);
+        A.rad_max = 2 * rmax < D.n_qubits ? rmax : 128;
+        const bool sig = !A.sig_all || A.rad_max < 128;
         read_stash_counts(A);
         const int64_t u = t - D.item0;
         const int64_t tile = u / D.chunks;
