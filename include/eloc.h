@@ -182,12 +182,16 @@ int eloc_store_pairs(eloc_ctx ctx, int variant, size_t budget_bytes, int64_t* n_
  * not depend on these settings beyond the floating-point summation order of
  * the chunk partial sums. */
 typedef struct {
-    int chunks;        /* split of the loop over the unique XY set (TERMS) or over
-                          U (BATCH) of every row; 0 = automatic                  */
-    int sig_filter;    /* 1: skip TERMS candidates whose (even-qubit, total)
-                          popcounts differ from U's when U has a single such
-                          signature (exact); 0: off                             */
-    int rows_per_wave; /* rows one wave owns: 4 or 8 (0 = 8)                    */
+    int chunks;          /* split of the loop over the unique XY set (TERMS) or
+                            over U (BATCH) of every row; 0 = automatic           */
+    int sig_filter;      /* 1: exact TERMS prefilters (U's single (even-qubit,
+                            total) popcount signature, U's radius around its
+                            majority key); 0: off                               */
+    int rows_per_wave;   /* rows one wave owns: 4 or 8 (0 = automatic)          */
+    int bloom;           /* 1: TERMS probes first test U's Bloom filter, staged
+                            in LDS, when U is small enough to have one; 0: off  */
+    int waves_per_block; /* waves sharing a workgroup (and its Bloom filter):
+                            1 or 4 (0 = automatic)                              */
 } eloc_tuning;
 int eloc_set_tuning(eloc_ctx ctx, const eloc_tuning* tuning);
 int eloc_get_tuning(eloc_ctx ctx, eloc_tuning* tuning);

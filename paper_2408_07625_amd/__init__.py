@@ -35,7 +35,8 @@ class C64(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int)]
+    _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
+                ("bloom", ctypes.c_int), ("waves_per_block", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -188,14 +189,16 @@ class Engine:
         self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
         self.n_unique = keys.shape[0]
 
-    def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 8):
-        t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave))
+    def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = True,
+                   waves_per_block: int = 0):
+        t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave), 1 if bloom else 0, int(waves_per_block))
         self._call(self.lib.eloc_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         self._call(self.lib.eloc_get_tuning(self.handle, ctypes.byref(t)))
-        return {"chunks": t.chunks, "sig_filter": bool(t.sig_filter), "rows_per_wave": t.rows_per_wave}
+        return {"chunks": t.chunks, "sig_filter": bool(t.sig_filter), "rows_per_wave": t.rows_per_wave,
+                "bloom": bool(t.bloom), "waves_per_block": t.waves_per_block}
 
     STAGES = ("samples", "amplitudes", "pairs", "finish", "energy", "adjoint_pairs", "adjoint_finish")
 

@@ -37,7 +37,8 @@ struct eloc_ctx_s {
 
     bool samples_set = false;
     SampleDev S;
-    DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad;
+    DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad, bloom;
+    uint32_t bloom_words = 0;   // Bloom filter of U (0: none)
     DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
     bool ut_valid = false;
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
@@ -58,7 +59,9 @@ struct eloc_ctx_s {
 
     int tune_chunks = 0;     // 0 = automatic
     int tune_sig = 1;
-    int tune_rows = 8;
+    int tune_rows = 0;       // 0 = automatic
+    int tune_bloom = 1;
+    int tune_waves = 0;      // 0 = automatic
     bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
     int sig_pa = 0, sig_n = 0;
     uint64_t rad_ref[2] = {0, 0};
@@ -111,7 +114,14 @@ int resolve_variant(const eloc_ctx c, int v) {
 Plan make_plan(const eloc_ctx c, int variant) {
     Plan P;
     const int64_t M = c->S.n;
-    P.rows_per_block = rows_per_block(variant, c->tune_rows);
+    // LoopOverTerms with the prefilters reads U's Bloom filter from LDS when
+    // U has one: 4 waves of 4 rows share it; else one wave of 8 rows
+    // (the shared filter needs 4-row waves to keep the workgroup's LDS under 64 KB)
+    const bool bloom = variant == ELOC_TERMS && c->tune_bloom != 0 && c->bloom_words > 0 && c->tune_rows != 8 &&
+                       c->tune_waves != 1;
+    const int rows = c->tune_rows ? c->tune_rows : (bloom ? 4 : 8);
+    P.rows_per_block = rows_per_block(variant, rows);
+    P.waves_per_block = bloom ? 4 : 1;
     // the exact prefilters of LoopOverTerms: U's single popcount signature,
     // and U's radius around its majority key when that is under half the qubits
     const bool rad_on = 2 * c->rad_max < c->H.n_qubits;
@@ -122,12 +132,14 @@ Plan make_plan(const eloc_ctx c, int variant) {
     P.rad_ref[0] = c->rad_ref[0];
     P.rad_ref[1] = c->rad_ref[1];
     P.rad_max = rad_on ? c->rad_max : 128;
+    P.bloom_words = (bloom && P.sig_filter) ? c->bloom_words : 0;
+    P.bloom = c->bloom.as<uint32_t>();
     if (variant == ELOC_TRIE) {
         P.chunks = c->H.xyt.chunks;
         P.per_chunk = c->H.xyt.chunk;
         return P;
     }
-    const int64_t waves = (M + P.rows_per_block - 1) / P.rows_per_block;
+    const int64_t waves = (M + P.rows_per_block - 1) / P.rows_per_block;   // row tiles
     const int64_t target = 16384;
     const int64_t span = (variant == ELOC_TERMS) ? c->H.n_groups : M;
     const int64_t steps = (span + 63) / 64;
@@ -423,7 +435,7 @@ void eloc_destroy(eloc_ctx c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->R_dev, &c->groups, &c->terms, &c->terms_f, &c->ghash, &c->gkeys, &c->gslots,
-                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->bitcounts, &c->rad, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
+                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->bitcounts, &c->rad, &c->bloom, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
                       &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
@@ -508,6 +520,18 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
                                    c->stream));
     ELOC_HIP(c, launch_sample_radius(W, c->keys.as<uint64_t>(), n_unique, c->bitcounts.as<uint32_t>(),
                                      c->rad.as<unsigned long long>(), c->stream));
+    // Bloom filter of U: about 4 bits per key, at most 32 KB (it is staged in
+    // LDS); none for batches too large for it to reject much
+    c->bloom_words = n_unique <= (int64_t(1) << 17)
+                         ? static_cast<uint32_t>(std::min<uint64_t>(kBloomMaxWords,
+                                                                    std::max<uint64_t>(256, pow2_at_least(n_unique / 8))))
+                         : 0u;
+    if (c->bloom_words) {
+        ELOC_HIP(c, c->bloom.ensure(sizeof(uint32_t) * c->bloom_words));
+        ELOC_HIP(c, hipMemsetAsync(c->bloom.p, 0, sizeof(uint32_t) * c->bloom_words, c->stream));
+        ELOC_HIP(c, launch_bloom_build(c->khash.as<uint64_t>(), n_unique, c->bloom.as<uint32_t>(), c->bloom_words,
+                                       c->stream));
+    }
     SampleDev S;
     S.n = n_unique;
     S.keys = c->keys.as<uint64_t>();
@@ -738,11 +762,14 @@ int eloc_store_pairs(eloc_ctx c, int variant, size_t budget_bytes, int64_t* n_pa
 }
 
 int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
-    if (!c || !t || t->chunks < 0 || (t->rows_per_wave != 0 && t->rows_per_wave != 4 && t->rows_per_wave != 8))
+    if (!c || !t || t->chunks < 0 || (t->rows_per_wave != 0 && t->rows_per_wave != 4 && t->rows_per_wave != 8) ||
+        (t->waves_per_block != 0 && t->waves_per_block != 1 && t->waves_per_block != 4))
         return c ? fail(c, ELOC_EINVAL, "bad tuning") : ELOC_EINVAL;
     c->tune_chunks = t->chunks;
     c->tune_sig = t->sig_filter;
-    c->tune_rows = t->rows_per_wave == 0 ? 8 : t->rows_per_wave;
+    c->tune_rows = t->rows_per_wave;
+    c->tune_bloom = t->bloom;
+    c->tune_waves = t->waves_per_block;
     return ELOC_OK;
 }
 
@@ -751,6 +778,8 @@ int eloc_get_tuning(eloc_ctx c, eloc_tuning* t) {
     t->chunks = c->tune_chunks;
     t->sig_filter = c->tune_sig;
     t->rows_per_wave = c->tune_rows;
+    t->bloom = c->tune_bloom;
+    t->waves_per_block = c->tune_waves;
     return ELOC_OK;
 }
 

@@ -17,6 +17,17 @@ constexpr uint64_t kOdd = 0xAAAAAAAAAAAAAAAAull;
 
 __device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }
 
+// Lane of the thread in its wave, and a wave-scope barrier: LDS written by a
+// lane is visible to the other lanes of its wave afterwards (the wave runs
+// in lockstep; this orders the memory operations around it).  Used where a
+// workgroup holds several independent waves.
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63u); }
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exact prefilter of LoopOverTerms: a candidate x' can be in U only if its
 // (popcount on even qubits, popcount on odd qubits) occurs in U.
 template <int W>
@@ -227,7 +238,7 @@ __device__ __forceinline__ void wave_sum(AccF& a) {
         o.im.s = __shfl_xor(a.im.s, m, 64);
         o.im.c = __shfl_xor(a.im.c, m, 64);
         // add in a lane-independent order so both partners get the same bits
-        const bool low = (threadIdx.x & m) == 0;
+        const bool low = (lane_id() & m) == 0;
         AccF first = low ? a : o;
         const AccF second = low ? o : a;
         acc_plus(first, second);

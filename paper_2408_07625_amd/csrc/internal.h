@@ -261,6 +261,16 @@ __device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ ha
     }
 }
 
+// Blocked Bloom filter of U (LoopOverTerms): a key with linear hash h sets
+// two bits of one 32-bit word, all chosen from hf = the high half of h, so
+// the test of a candidate x ^ XY needs hf(x) ^ hf(XY) and one word.
+constexpr uint32_t kBloomMaxWords = 8192;   // 32 KB of LDS
+
+__host__ __device__ __forceinline__ uint32_t bloom_word(uint32_t hf, uint32_t fmask) { return (hf >> 10) & fmask; }
+__host__ __device__ __forceinline__ uint32_t bloom_bits(uint32_t hf) {
+    return (1u << (hf & 31u)) | (1u << ((hf >> 5) & 31u));
+}
+
 // ---------------------------------------------------------------------------
 // Device state handed to kernels.
 // ---------------------------------------------------------------------------
@@ -329,7 +339,10 @@ struct Plan {
     bool sig_all = false;      // no single signature: the signature test passes everything
     uint64_t rad_ref[kMaxWords] = {0, 0};   // radius filter: reference key and
     int rad_max = 128;                      // max distance of U from it (128: off)
-    int rows_per_block = 1;    // rows owned by one workgroup
+    int rows_per_block = 1;    // rows owned by one wave (TERMS, BATCH) or workgroup (TRIE)
+    int waves_per_block = 1;   // waves of a TERMS / BATCH workgroup
+    const uint32_t* bloom = nullptr;   // U's Bloom filter (LoopOverTerms), staged in LDS
+    uint32_t bloom_words = 0;          // its size in words, a power of two (0: not used)
 };
 
 // Error bits latched in a device word, read by eloc_check / synchronising calls.
@@ -439,6 +452,7 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
 // distance of U's keys from it (rad[2] must start at 0).
 hipError_t launch_sample_radius(int W, const uint64_t* keys, int64_t n, const uint32_t* counts,
                                 unsigned long long* rad, hipStream_t st);
+hipError_t launch_bloom_build(const uint64_t* hash, int64_t n, uint32_t* filt, uint32_t words, hipStream_t st);
 hipError_t launch_table_insert(int table_kind, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
                                const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t* sig, uint32_t* err,

@@ -55,6 +55,16 @@ __global__ __launch_bounds__(kBlock) void k_sample_hash(const uint64_t* __restri
         if (lc[t]) atomicAdd(counts + t, lc[t]);
 }
 
+// Blocked Bloom filter of U for the LoopOverTerms probes: each key sets two
+// bits of one 32-bit word, both chosen from the high half of its linear hash.
+__global__ __launch_bounds__(kBlock) void k_bloom_build(const uint64_t* __restrict__ hash, int64_t n,
+                                                        uint32_t* __restrict__ filt, uint32_t fmask) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t hf = static_cast<uint32_t>(hash[i] >> 32);
+    atomicOr(filt + bloom_word(hf, fmask), bloom_bits(hf));
+}
+
 // Radius filter of LoopOverTerms: reference key c = per-qubit majority of U
 // (rad[0..W-1]), then rad[2] = max over U of |x ^ c|.  A candidate farther
 // than that from c is not in U.
@@ -620,6 +630,11 @@ hipError_t launch_sample_hash(int W, const uint64_t* keys, int64_t n, const uint
     else
         hipLaunchKernelGGL(k_sample_hash<2>, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, n, R, n_qubits, hash,
                            counts, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_bloom_build(const uint64_t* hash, int64_t n, uint32_t* filt, uint32_t words, hipStream_t st) {
+    hipLaunchKernelGGL(k_bloom_build, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, filt, words - 1u);
     return hipGetLastError();
 }
 

@@ -53,6 +53,9 @@ struct PairArgs {
     bool sig_all;
     int rad_max;
     uint64_t rad_ref[kMaxWords];
+    const uint32_t* bloom;   // U's Bloom filter (global); staged in LDS by the kernel
+    uint32_t bloom_words;
+    uint32_t bloom_mask;
     int kstash;      // stash counts, read at kernel start
     int gstash;
     int64_t M;
@@ -88,6 +91,9 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.rad_max = P.rad_max;
     a.rad_ref[0] = P.rad_ref[0];
     a.rad_ref[1] = P.rad_ref[1];
+    a.bloom = P.bloom;
+    a.bloom_words = P.bloom_words;
+    a.bloom_mask = P.bloom_words ? P.bloom_words - 1u : 0u;
     a.M = S.n;
     a.per_chunk = P.per_chunk;
     a.u_keys = S.ut.keys;
@@ -132,9 +138,9 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
         for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
         R.hx[r] = A.khash[row];
     }
-    if (threadIdx.x < NR * W) {
-        const int64_t row = min(R.row0 + threadIdx.x / W, A.M - 1);
-        rowkey[threadIdx.x] = A.keys[row * W + threadIdx.x % W];
+    if (lane_id() < NR * W) {
+        const int64_t row = min(R.row0 + lane_id() / W, A.M - 1);
+        rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
     }
 }
 
@@ -142,8 +148,9 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
 // are discarded by the caller.
-template <int W, int SIG, int NR, bool NW, class Sink>
-__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+template <int W, int SIG, int NR, bool NW, bool BL, class Sink>
+__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
+                                           const uint32_t* lfilt) {
     constexpr int TK = table_kind(W, NW);
     using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
@@ -151,7 +158,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     const SlotReader<TK> slots(T);
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
-    const int lane = static_cast<int>(threadIdx.x);
+    const int lane = lane_id();
     // the step's group fields live in plain registers (mask words, run
     // length, hash); the next step's are requested after this step's probes
     uint64_t gxy[W];
@@ -196,6 +203,11 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             // exact prefilters: U's single popcount signature (unless
             // sig_all) and U's radius around its majority key
             if (SIG) ok = ok & (A.sig_all | ((pa == A.sig_pa) & (n == A.sig_n))) & (d <= A.rad_max);
+            if constexpr (BL) {   // U's Bloom filter, in LDS
+                const uint32_t hf = static_cast<uint32_t>(R.hx[r] >> 32) ^ static_cast<uint32_t>(gh >> 32);
+                const uint32_t bits = bloom_bits(hf);
+                ok = ok & ((lfilt[bloom_word(hf, A.bloom_mask)] & bits) == bits);
+            }
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
             v2[r] = slots.load(slot2(T, hs[r]), ok);
@@ -237,7 +249,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
     const int64_t j1 = min(A.M, j0 + A.per_chunk);
     for (int64_t base = j0; base < j1; base += kWave) {
-        const int64_t j = base + threadIdx.x;
+        const int64_t j = base + lane_id();
         const bool valid = j < j1;
         const int64_t jj = valid ? j : j0;
         uint64_t xj[W];
@@ -311,7 +323,7 @@ struct AccSink {
     }
 
     __device__ __forceinline__ void add(int r, const Acc& v) {
-        Acc& a = acc[r * kWave + threadIdx.x];
+        Acc& a = acc[r * kWave + lane_id()];
         Acc t = a;
         acc_plus(t, v);
         a = t;
@@ -328,7 +340,7 @@ struct AccSink {
 #pragma unroll
             for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
             typename P::H hr, hi;
-            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, static_cast<int>(threadIdx.x), kWave, ket, hr, hi);
+            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, lane_id(), kWave, ket, hr, hi);
             Acc v;
             P::madd(v, hr, hi, vec[ey]);
             add(r, v);
@@ -338,12 +350,12 @@ struct AccSink {
     // entries [o, o + n) of the queue, one pair per lane; runs longer than
     // kLongRun are set aside and done by the whole wave
     __device__ __forceinline__ void drain(int o, int n) {
-        const bool mine = static_cast<int>(threadIdx.x) < n;
+        const bool mine = lane_id() < n;
         uint2 e = make_uint2(0u, 0u);
         GroupRec<W> gr{};
         bool lng = false;
         if (mine) {
-            e = q[o + threadIdx.x];
+            e = q[o + lane_id()];
             gr = groups[e.x >> 4];
             lng = gr.end - gr.begin > kLongRun;
         }
@@ -361,32 +373,32 @@ struct AccSink {
             add(r, v);
         }
         if (ml) {
-            __syncthreads();
+            wave_sync();
             drain_long(__popcll(ml));
-            __syncthreads();
+            wave_sync();
         }
     }
 
     __device__ __forceinline__ void flush() {
         if (qn >= kWave) {
-            __syncthreads();
+            wave_sync();
             int o = 0;
             for (; qn - o >= kWave; o += kWave) drain(o, kWave);
-            __syncthreads();
+            wave_sync();
             const int rest = qn - o;
             uint2 t = make_uint2(0u, 0u);
-            if (static_cast<int>(threadIdx.x) < rest) t = q[o + threadIdx.x];
-            __syncthreads();
-            if (static_cast<int>(threadIdx.x) < rest) q[threadIdx.x] = t;
+            if (lane_id() < rest) t = q[o + lane_id()];
+            wave_sync();
+            if (lane_id() < rest) q[lane_id()] = t;
             qn = rest;
         }
     }
 
     __device__ __forceinline__ void finish() {
-        __syncthreads();
+        wave_sync();
         if (qn) drain(0, qn);
         qn = 0;
-        __syncthreads();
+        wave_sync();
     }
 };
 
@@ -417,12 +429,14 @@ struct FillSink {
 
 // VARIANT: 0 TERMS without signature filter, 3 TERMS with it, 1 BATCH.
 // NW: keys of at most 32 qubits (narrow table, 32-bit bit work).
-template <int W, int VARIANT, int NR, bool NW, class Sink>
-__device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+// BL: the prefiltered LoopOverTerms also tests U's Bloom filter in LDS.
+template <int W, int VARIANT, int NR, bool NW, bool BL = false, class Sink>
+__device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
+                                     const uint32_t* lfilt = nullptr) {
     if constexpr (VARIANT == 0)
-        find_terms<W, 0, NR, NW>(A, R, chunk, sink);
+        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, lfilt);
     else if constexpr (VARIANT == 3)
-        find_terms<W, 1, NR, NW>(A, R, chunk, sink);
+        find_terms<W, 1, NR, NW, BL>(A, R, chunk, sink, lfilt);
     else
         find_batch<W, NR, NW>(A, R, chunk, sink);
 }
@@ -432,38 +446,51 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 //   forward: acc_x = sum_{x'} H_xx' vec_x'  (ket x', vec = a)
 //   adjoint: acc_y = sum_{x}  H_xy vec_x    (ket y,  vec = w / a)
 // ---------------------------------------------------------------------------
-template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW>
-__global__ __launch_bounds__(kWave) void k_pairs(PairArgs A, const void* __restrict__ vec,
-                                                 void* __restrict__ partial) {
+// WPB waves per workgroup, each owning its own row tile (tile = blockIdx.x *
+// WPB + wave); with WPB > 1 the waves share U's Bloom filter, staged in LDS
+// (dynamic shared memory) once per workgroup.
+template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
+                                                       void* __restrict__ partial) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
-    __shared__ uint64_t rowkey[NR * W];
-    __shared__ uint2 q[kWave + NR * kWave];
-    __shared__ uint2 lq[kWave];
+    constexpr bool BL = WPB > 1;
+    __shared__ uint64_t rowkey_s[WPB][NR * W];
+    __shared__ uint2 q_s[WPB][kWave + NR * kWave];
+    __shared__ uint2 lq_s[WPB][kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
-    __shared__ double2 acc_raw[NR * kWave];
-    Acc* acc = reinterpret_cast<Acc*>(acc_raw);
+    __shared__ double2 acc_s[WPB][NR * kWave];
+    extern __shared__ uint32_t lfilt[];
+    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    if constexpr (BL) {
+        for (uint32_t t = threadIdx.x; t < A.bloom_words; t += kWave * WPB) lfilt[t] = A.bloom[t];
+        __syncthreads();
+    }
+    const int64_t tile = static_cast<int64_t>(blockIdx.x) * WPB + wave;
+    if (tile * NR >= A.M) return;   // no block-wide barrier follows
+    uint64_t* rowkey = rowkey_s[wave];
+    Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
     read_stash_counts(A);
     Rows<W, NR> R;
-    load_rows<W, NR>(A, R, rowkey, blockIdx.x);
+    load_rows<W, NR>(A, R, rowkey, tile);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r * kWave + threadIdx.x] = Acc{};
-    __syncthreads();
+    for (int r = 0; r < NR; ++r) acc[r * kWave + lane_id()] = Acc{};
+    wave_sync();
     AccSink<W, PREC, ADJ, NR, NW> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec);
-    sink.q = q;
-    sink.lq = lq;
+    sink.q = q_s[wave];
+    sink.lq = lq_s[wave];
     sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT, NR, NW>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, NR, NW, BL>(A, R, blockIdx.y, sink, lfilt);
     sink.finish();
     // per-row totals: lane r adds the 64 lane columns of row r in order
-    if (static_cast<int>(threadIdx.x) < R.n) {
+    if (lane_id() < R.n) {
         Acc t{};
-        for (int l = 0; l < kWave; ++l) acc_plus(t, acc[threadIdx.x * kWave + l]);
-        store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + R.row0 + threadIdx.x, t);
+        for (int l = 0; l < kWave; ++l) acc_plus(t, acc[lane_id() * kWave + l]);
+        store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + R.row0 + lane_id(), t);
     }
 }
 
@@ -473,14 +500,14 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
     read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
-    __syncthreads();
+    wave_sync();
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
     find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink);
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
-        if (static_cast<int>(threadIdx.x) == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
+        if (lane_id() == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
 }
 
 template <int W, int VARIANT, bool NW>
@@ -490,7 +517,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
     read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
-    __syncthreads();
+    wave_sync();
     FillSink sink;
     sink.row0 = R.row0;
     sink.n = R.n;
@@ -525,7 +552,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kWave];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
-    const int lane = static_cast<int>(threadIdx.x);
+    const int lane = lane_id();
     constexpr int kSlices = kMaxBatch / kWave;
     int64_t istart[kSlices];
 #pragma unroll
@@ -574,7 +601,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         load_rows<W, NR>(A, R, rowkey, tile);
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r * kWave + lane] = Acc{};
-        __syncthreads();
+        wave_sync();
         AccSink<W, PREC, false, NR, NW> sink;
         sink.groups = static_cast<const GroupRec<W>*>(A.groups);
         sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
@@ -587,9 +614,9 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         if (D.variant == 1)
             find_batch<W, NR, NW>(A, R, chunk, sink);
         else if (sig)
-            find_terms<W, 1, NR, NW>(A, R, chunk, sink);
+            find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr);
         else
-            find_terms<W, 0, NR, NW>(A, R, chunk, sink);
+            find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr);
         sink.finish();
         if (lane < R.n) {
             Acc s{};
@@ -598,7 +625,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
             store_acc(part, static_cast<int64_t>(chunk) * D.M + R.row0 + lane, s);
         }
         if (lane == 0) atomicAdd(B.pairs + k, static_cast<unsigned long long>(sink.hits));
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -771,12 +798,24 @@ hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, voi
     if constexpr (VARIANT == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+    } else if (VARIANT == 3 && P.bloom_words > 0 && P.waves_per_block == 4) {
+        constexpr int kW = 4;
+        const size_t lds = sizeof(uint32_t) * P.bloom_words;
+        if (P.rows_per_block == 4) {
+            dim3 grid(div_up(div_up(A.M, 4), kW), static_cast<unsigned>(P.chunks));
+            hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW, kW>), grid, dim3(kWave * kW), lds, st, A, vec,
+                               partial);
+        } else {
+            dim3 grid(div_up(div_up(A.M, kRows), kW), static_cast<unsigned>(P.chunks));
+            hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, kW>), grid, dim3(kWave * kW), lds, st, A,
+                               vec, partial);
+        }
     } else if (P.rows_per_block == 4) {
         dim3 grid(div_up(A.M, 4), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW>), grid, dim3(kWave), 0, st, A, vec, partial);
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW>), grid, dim3(kWave), 0, st, A, vec, partial);
+        hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();
 }
