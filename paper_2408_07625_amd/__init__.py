@@ -189,7 +189,7 @@ class Engine:
         self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
         self.n_unique = keys.shape[0]
 
-    def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = True,
+    def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = False,
                    waves_per_block: int = 0):
         t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave), 1 if bloom else 0, int(waves_per_block))
         self._call(self.lib.eloc_set_tuning(self.handle, ctypes.byref(t)))

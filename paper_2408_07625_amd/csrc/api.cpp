@@ -60,7 +60,7 @@ struct eloc_ctx_s {
     int tune_chunks = 0;     // 0 = automatic
     int tune_sig = 1;
     int tune_rows = 0;       // 0 = automatic
-    int tune_bloom = 1;
+    int tune_bloom = 0;      // the LDS Bloom filter is slower on MI355X (occupancy); opt-in
     int tune_waves = 0;      // 0 = automatic
     bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
     int sig_pa = 0, sig_n = 0;
