@@ -385,3 +385,21 @@ def test_stored_pairs_wide_sampled(eng):
     for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
         e, st = eng.local_energy(L, Wt, variant="stored", precision=prec)
         assert np.abs(e.cpu().numpy()[sel] - ref).max() <= tol, prec
+
+
+def test_bloom_filter_opt_in(eng, medium_workload):
+    """The opt-in LDS Bloom filter of U (shared by four-wave workgroups) is an
+    exact prefilter: same pairs and energies as without it."""
+    w = medium_workload
+    load(eng, w.ham, w.keys)
+    L = dev(w.logpsi)
+    rows = (31000, 31400)
+    ref = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=rows)
+    try:
+        eng.set_tuning(0, True, 4, True, 4)
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, _ = eng.local_energy(L, None, variant="terms", precision=prec)
+            assert np.abs(e.cpu().numpy()[rows[0]:rows[1]] - ref).max() <= tol
+        assert eng.count_pairs("terms") == 34420502
+    finally:
+        eng.set_tuning()
