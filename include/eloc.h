@@ -115,6 +115,12 @@ int eloc_hamiltonian_info(eloc_ctx ctx, int64_t* n_groups, int64_t* n_terms, int
  * >= 2^24, bits >= N), EDUP (a key repeats), ESTATE (no Hamiltonian). */
 int eloc_set_samples(eloc_ctx ctx, int64_t n_unique, const uint64_t* keys_dev);
 
+/* Geometry of U's membership table (two-choice cuckoo hashing with a stash):
+ * HOST outputs, each optional (NULL skips it): n_unique, table_slots (slot
+ * count, a power of two of at least 4 n_unique), table_stash (keys held in
+ * the stash, 0..32).  Errors: ESTATE (no samples set). */
+int eloc_samples_info(eloc_ctx ctx, int64_t* n_unique, int64_t* table_slots, int* table_stash);
+
 /* Forward pass.  DEVICE inputs logpsi_dev[n_unique] (complex log psi) and
  * weights_dev[n_unique] or NULL; DEVICE outputs eloc_dev[n_unique] and
  * stats_dev[4].  weights NULL: w = |psi|^2 renormalised over U

@@ -66,6 +66,7 @@ def library() -> ctypes.CDLL:
             "eloc_set_hamiltonian": (i32, [P, i32, i64, P, P, P]),
             "eloc_hamiltonian_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "eloc_set_samples": (i32, [P, i64, P]),
+            "eloc_samples_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "eloc_local_energy": (i32, [P, i32, i32, P, P, P, P]),
             "eloc_check": (i32, [P]),
             "eloc_count_pairs": (i32, [P, i32, ctypes.POINTER(i64)]),
@@ -103,7 +104,7 @@ def exported_symbols() -> list[str]:
     """Names the header declares that the loaded library exports."""
     lib = library()
     return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
-                        "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples",
+                        "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples", "eloc_samples_info",
                         "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
                         "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_store_pairs", "eloc_set_tuning",
                         "eloc_get_tuning",
@@ -188,6 +189,12 @@ class Engine:
         self._sync_stream()
         self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
         self.n_unique = keys.shape[0]
+
+    def samples_info(self) -> dict:
+        """Size of U and of its membership table (slots, keys in the stash)."""
+        n, slots, stash = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        self._call(self.lib.eloc_samples_info(self.handle, ctypes.byref(n), ctypes.byref(slots), ctypes.byref(stash)))
+        return {"n_unique": n.value, "table_slots": slots.value, "table_stash": stash.value}
 
     def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = False,
                    waves_per_block: int = 0):

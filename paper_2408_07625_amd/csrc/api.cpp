@@ -66,6 +66,8 @@ struct eloc_ctx_s {
     int sig_pa = 0, sig_n = 0;
     uint64_t rad_ref[2] = {0, 0};
     int rad_max = 128;       // radius of U around rad_ref (128: filter off)
+    int kstash_used = 0;     // keys of U held in the membership table's stash
+    uint64_t kslots_n = 0;   // slots of U's membership table
     uint64_t salt_state = 0x5EED2408ull;
 
     // stage profiling: HIP events around each stage, read (and reset) by
@@ -493,6 +495,15 @@ int eloc_hamiltonian_info(eloc_ctx c, int64_t* n_groups, int64_t* n_terms, int* 
     return ELOC_OK;
 }
 
+int eloc_samples_info(eloc_ctx c, int64_t* n_unique, int64_t* table_slots, int* table_stash) {
+    if (!c) return ELOC_EINVAL;
+    if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
+    if (n_unique) *n_unique = c->S.n;
+    if (table_slots) *table_slots = static_cast<int64_t>(c->kslots_n);
+    if (table_stash) *table_stash = c->kstash_used;
+    return ELOC_OK;
+}
+
 int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     if (!c) return ELOC_EINVAL;
     if (!c->ham_set) return fail(c, ELOC_ESTATE, "set the Hamiltonian first");
@@ -556,6 +567,8 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
                                    c->stream));
         ELOC_HIP(c, hipMemcpyAsync(c->rad_host, c->rad.p, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost,
                                    c->stream));
+        // the stash count is the first word of the stash
+        ELOC_HIP(c, hipMemcpyAsync(c->err_host + 1, c->kstash.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
         ELOC_HIP(c, hipStreamSynchronize(c->stream));
         bits = *c->err_host;
         // a key that did not settle also fails its own lookup (duplicate
@@ -581,6 +594,8 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     c->rad_ref[0] = c->rad_host[0];
     c->rad_ref[1] = W == 2 ? c->rad_host[1] : 0ull;
     c->rad_max = static_cast<int>(c->rad_host[2]);
+    c->kstash_used = static_cast<int>(c->err_host[1]);
+    c->kslots_n = cap;
     c->S = S;
     c->ut_valid = false;
     c->st_valid = false;

@@ -172,11 +172,14 @@ struct SlotReader {
 
 // Second half of a lookup of a key with salted hash hs, given its two slot
 // values; `nstash` is the stash count (wave-uniform).  Index of the key in
-// `keys` (two-word format only), or -1.
+// `keys` (two-word format only), or -1.  A candidate that was filtered out
+// (ok false: its slots read as empty) must not match the stash either, since
+// the padded lanes past a chunk's end repeat a real candidate.
 template <int TK, int W>
 __device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __restrict__ keys,
                                             typename TabT<TK>::slot v1, typename TabT<TK>::slot v2,
-                                            typename TabT<TK>::hash hs, const uint64_t* key, int nstash) {
+                                            typename TabT<TK>::hash hs, const uint64_t* key, int nstash,
+                                            bool ok = true) {
     using ST = typename TabT<TK>::slot;
     int j = -1;
     if constexpr (TK != kTabVerify) {
@@ -184,7 +187,7 @@ __device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __re
         if ((v1 >> T.ibits) == t) j = static_cast<int>(v1 & T.imask) - 1;
         if ((v2 >> T.ibits) == (t | 1u)) j = static_cast<int>(v2 & T.imask) - 1;
         for (int k = 0; k < nstash && k < kStash; ++k)
-            if (T.stash->hs[k] == static_cast<uint64_t>(hs)) j = static_cast<int>(T.stash->idx[k]);
+            if (ok && T.stash->hs[k] == static_cast<uint64_t>(hs)) j = static_cast<int>(T.stash->idx[k]);
     } else {
         const uint32_t fp = fingerprint(T, hs);
         if ((v1 >> T.ibits) == fp) {
@@ -196,7 +199,7 @@ __device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __re
             if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;
         }
         for (int k = 0; k < nstash && k < kStash; ++k) {
-            if (j < 0 && T.stash->hs[k] == hs) {
+            if (ok && j < 0 && T.stash->hs[k] == hs) {
                 const int js = static_cast<int>(T.stash->idx[k]);
                 if (keys_equal<W>(keys + static_cast<size_t>(js) * W, key)) j = js;
             }

@@ -177,6 +177,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         uint64_t xp[NR][W];
         typename TabT<TK>::slot v1[NR], v2[NR];
         HT hs[NR];
+        bool okr[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             bool ok = valid;
@@ -211,6 +212,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
             v2[r] = slots.load(slot2(T, hs[r]), ok);
+            okr[r] = ok;
         }
         uint64_t nxy[W];
         int nrun = run;
@@ -227,7 +229,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int j = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash);
+            const int j = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
             sink.hit(r, j >= 0, g, j, run);
         }
         sink.flush();
@@ -259,6 +261,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         uint64_t m[NR][W];
         typename TabT<TK>::slot v1[NR], v2[NR];
         HT hs[NR];
+        bool okr[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             int pc = 0;
@@ -277,10 +280,11 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
             v2[r] = slots.load(slot2(T, hs[r]), ok);
+            okr[r] = ok;
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int g = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash);
+            const int g = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash, okr[r]);
             int run = 0;
             if (g >= 0) {
                 const GroupRec<W>& gr = groups[g];
