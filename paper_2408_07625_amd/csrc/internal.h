@@ -170,8 +170,23 @@ struct SlotReader {
     }
 };
 
+// Whether a lookup must read the key's second slot, given its first: an
+// insertion always claims the key's first slot before anything else, and a
+// slot is never emptied again, so an empty first slot proves the key absent
+// from both slots, and a first slot that holds the key settles the lookup.
+// (Two-word keys: a fingerprint match at the first slot counts as settling;
+// table_settle reads the second slot itself if the key compare then fails.)
+template <int TK>
+__device__ __forceinline__ bool need_slot2(const Table& T, typename TabT<TK>::slot v1, typename TabT<TK>::hash hs) {
+    using ST = typename TabT<TK>::slot;
+    if constexpr (TK != kTabVerify)
+        return v1 != 0 && (v1 >> T.ibits) != static_cast<ST>((hs >> T.capbits) << 1);
+    else
+        return v1 != 0u && (v1 >> T.ibits) != fingerprint(T, hs);
+}
+
 // Second half of a lookup of a key with salted hash hs, given its two slot
-// values; `nstash` is the stash count (wave-uniform).  Index of the key in
+// values (the second may be left 0 where need_slot2 is false); `nstash` is the stash count (wave-uniform).  Index of the key in
 // `keys` (two-word format only), or -1.  A candidate that was filtered out
 // (ok false: its slots read as empty) must not match the stash either, since
 // the padded lanes past a chunk's end repeat a real candidate.
@@ -194,6 +209,7 @@ __device__ __forceinline__ int table_settle(const Table& T, const uint64_t* __re
             const int j1 = static_cast<int>(v1 & T.imask) - 1;
             if (keys_equal<W>(keys + static_cast<size_t>(j1) * W, key)) j = j1;
         }
+        if (j < 0 && (v1 >> T.ibits) == fp) v2 = load_slot<TK>(T, slot2(T, hs));   // rare: fingerprint clash
         if (j < 0 && (v2 >> T.ibits) == fp) {
             const int j2 = static_cast<int>(v2 & T.imask) - 1;
             if (keys_equal<W>(keys + static_cast<size_t>(j2) * W, key)) j = j2;

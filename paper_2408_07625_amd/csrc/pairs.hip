@@ -211,9 +211,11 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             }
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
-            v2[r] = slots.load(slot2(T, hs[r]), ok);
             okr[r] = ok;
         }
+        // second slots only where the first leaves the lookup open
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
         uint64_t nxy[W];
         int nrun = run;
         uint64_t ngh = gh;
@@ -279,9 +281,10 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
             const bool ok = valid & (pc <= A.maxpop);
             hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
             v1[r] = slots.load(slot1(T, hs[r]), ok);
-            v2[r] = slots.load(slot2(T, hs[r]), ok);
             okr[r] = ok;
         }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int g = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash, okr[r]);
