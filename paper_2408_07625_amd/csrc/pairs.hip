@@ -160,7 +160,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     const int lane = lane_id();
     // the step's group fields live in plain registers (mask words, run
-    // length, hash); the next step's are requested after this step's probes
+    // length, hash)
     uint64_t gxy[W];
     int run;
     uint64_t gh;
@@ -174,6 +174,20 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     for (int base = g0; base < g1; base += kWave) {
         const int g = base + lane;
         const bool valid = g < g1;
+        // the next step's group fields, requested before this step's probes
+        // so that they arrive with them (clamped: no branch, whose join would
+        // make the compiler wait for them at once)
+        uint64_t nxy[W];
+        int nrun;
+        uint64_t ngh;
+        {
+            const int ng = min(base + kWave + lane, g1 - 1);
+            const GroupRec<W>& gr = groups[ng];
+#pragma unroll
+            for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
+            nrun = gr.end - gr.begin;
+            ngh = A.ghash[ng];
+        }
         uint64_t xp[NR][W];
         typename TabT<TK>::slot v1[NR], v2[NR];
         HT hs[NR];
@@ -216,25 +230,12 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         // second slots only where the first leaves the lookup open
 #pragma unroll
         for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
-        uint64_t nxy[W];
-        int nrun = run;
-        uint64_t ngh = gh;
-#pragma unroll
-        for (int w = 0; w < W; ++w) nxy[w] = gxy[w];
-        if (base + kWave < g1) {
-            const int ng = min(base + kWave + lane, g1 - 1);
-            const GroupRec<W>& gr = groups[ng];
-#pragma unroll
-            for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
-            nrun = gr.end - gr.begin;
-            ngh = A.ghash[ng];
-        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int j = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
             sink.hit(r, j >= 0, g, j, run);
+            sink.flush();   // the queue never holds more than two waves of hits
         }
-        sink.flush();
 #pragma unroll
         for (int w = 0; w < W; ++w) gxy[w] = nxy[w];
         run = nrun;
@@ -294,8 +295,8 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
                 run = gr.end - gr.begin;
             }
             sink.hit(r, g >= 0, g, static_cast<int>(j), run);
+            sink.flush();
         }
-        sink.flush();
     }
 }
 
@@ -312,7 +313,7 @@ struct AccSink {
     const GroupRec<W>* groups;
     const Term* terms;
     const Vec* vec;
-    uint2* q;               // LDS hit queue [kWave + NR * kWave]
+    uint2* q;               // LDS hit queue [2 * kWave] (flushed after each row's hits)
     uint2* lq;              // LDS long runs met while draining [kWave]
     Acc* acc;               // LDS accumulators [NR][kWave]; lane l owns column l
     const uint64_t* rowkey; // LDS row keys [NR][W]
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     using Acc = typename P::Acc;
     constexpr bool BL = WPB > 1;
     __shared__ uint64_t rowkey_s[WPB][NR * W];
-    __shared__ uint2 q_s[WPB][kWave + NR * kWave];
+    __shared__ uint2 q_s[WPB][2 * kWave];
     __shared__ uint2 lq_s[WPB][kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_s[WPB][NR * kWave];
@@ -554,7 +555,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     __shared__ uint64_t rowkey[NR * W];
-    __shared__ uint2 q[kWave + NR * kWave];
+    __shared__ uint2 q[2 * kWave];
     __shared__ uint2 lq[kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kWave];
