@@ -151,9 +151,33 @@ __device__ __forceinline__ double term_f64(const TermRec<W>& tr, const uint64_t*
     return ket_parity<W, NW>(tr.yz, ket) ? -tr.h : tr.h;
 }
 
+// One lane's sum over terms [b, e) in order, reading four records per
+// round so that their loads overlap; records past e are clamped reads whose
+// value is replaced by an exact zero (the sum does not change).
+template <int W, bool NW>
+__device__ __forceinline__ double run_sum(const TermRec<W>* __restrict__ terms, int b, int e, const uint64_t* ket) {
+    double h = 0.0;
+    for (int t = b; t < e; t += 4) {
+        TermRec<W> tr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tr[u] = terms[min(t + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double v = term_f64<W, NW>(tr[u], ket);
+            h += (t + u < e) ? v : 0.0;
+        }
+    }
+    return h;
+}
+
 template <int W, bool NW = false>
 __device__ __forceinline__ void melem(const TermRec<W>* __restrict__ terms, int b, int m, int e, int off, int step,
                                       const uint64_t* ket, double& hr, double& hi) {
+    if (step == 1 && off == 0) {
+        hr = run_sum<W, NW>(terms, b, m, ket);
+        hi = run_sum<W, NW>(terms, m, e, ket);
+        return;
+    }
     hr = 0.0;
     hi = 0.0;
     for (int t = b + off; t < m; t += step) hr += term_f64<W, NW>(terms[t], ket);
@@ -167,9 +191,32 @@ __device__ __forceinline__ void term_f32(const TermRecF<W>& tr, const uint64_t* 
     vl = odd ? -tr.h_lo : tr.h_lo;
 }
 
+template <int W, bool NW>
+__device__ __forceinline__ F2 run_sum(const TermRecF<W>* __restrict__ terms, int b, int e, const uint64_t* ket) {
+    F2 h{0.f, 0.f};
+    for (int t = b; t < e; t += 4) {
+        TermRecF<W> tr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tr[u] = terms[min(t + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            float vh, vl;
+            term_f32<W, NW>(tr[u], ket, vh, vl);
+            const bool in = t + u < e;
+            acc_add(h, in ? vh : 0.f, in ? vl : 0.f);
+        }
+    }
+    return h;
+}
+
 template <int W, bool NW = false>
 __device__ __forceinline__ void melem(const TermRecF<W>* __restrict__ terms, int b, int m, int e, int off, int step,
                                       const uint64_t* ket, F2& hr, F2& hi) {
+    if (step == 1 && off == 0) {
+        hr = run_sum<W, NW>(terms, b, m, ket);
+        hi = run_sum<W, NW>(terms, m, e, ket);
+        return;
+    }
     hr = F2{0.f, 0.f};
     hi = F2{0.f, 0.f};
     float vh, vl;
