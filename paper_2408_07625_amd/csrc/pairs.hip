@@ -10,9 +10,10 @@
 // are compacted into an LDS queue with ballot + mbcnt.  Short term runs are
 // evaluated 64 pairs at a time, one pair per lane; runs longer than kLongRun
 // (the diagonal group, single excitations) are evaluated by the whole wave,
-// 64 terms per step.  Each lane keeps one accumulator per row in registers;
-// the per-row totals are formed at the end by a fixed-order butterfly over
-// the lanes, so results are bitwise reproducible without atomics.
+// 64 terms per step.  Accumulators live in LDS, kAccCols columns per row:
+// lane l adds into column l % kAccCols, the lower half of the wave before the
+// upper half, and at the end lane r adds row r's columns in order, so results
+// are bitwise reproducible without atomics.
 //
 // LoopOverTrie (Alg. 2C, trees of Alg. 3): one lane per row walks the
 // radix tree of U together with the radix tree of one chunk of the XY set
@@ -303,6 +304,8 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
 // ---------------------------------------------------------------------------
 // Sinks: what happens to the pairs a wave finds.
 // ---------------------------------------------------------------------------
+constexpr int kAccCols = 32;   // accumulator columns per row
+
 template <int W, int PREC, bool ADJ, int NR, bool NW>
 struct AccSink {
     using P = Prec<PREC>;
@@ -315,7 +318,7 @@ struct AccSink {
     const Vec* vec;
     uint2* q;               // LDS hit queue [2 * kWave] (flushed after each row's hits)
     uint2* lq;              // LDS long runs met while draining [kWave]
-    Acc* acc;               // LDS accumulators [NR][kWave]; lane l owns column l
+    Acc* acc;               // LDS accumulators [NR][kAccCols]: lane l adds into column l % kAccCols
     const uint64_t* rowkey; // LDS row keys [NR][W]
     int qn = 0;
     int nrows = 0;          // rows inside U (the rest are clamped copies)
@@ -330,11 +333,22 @@ struct AccSink {
         if (r < nrows) hits += __popcll(m);
     }
 
-    __device__ __forceinline__ void add(int r, const Acc& v) {
-        Acc& a = acc[r * kWave + lane_id()];
-        Acc t = a;
-        acc_plus(t, v);
-        a = t;
+    // called by the whole wave; lanes 0-31 add first, then lanes 32-63 (the
+    // two halves share the columns, so the order of the adds is fixed)
+    __device__ __forceinline__ void add(int r, const Acc& v, bool on) {
+        Acc* a = acc + r * kAccCols + (lane_id() & (kAccCols - 1));
+        if (on && lane_id() < kAccCols) {
+            Acc t = *a;
+            acc_plus(t, v);
+            *a = t;
+        }
+        wave_sync();
+        if (on && lane_id() >= kAccCols) {
+            Acc t = *a;
+            acc_plus(t, v);
+            *a = t;
+        }
+        wave_sync();
     }
 
     // the whole wave on each long run, 64 terms per step
@@ -351,7 +365,7 @@ struct AccSink {
             melem<W, NW>(terms, gr.begin, gr.mid, gr.end, lane_id(), kWave, ket, hr, hi);
             Acc v;
             P::madd(v, hr, hi, vec[ey]);
-            add(r, v);
+            add(r, v, true);
         }
     }
 
@@ -369,17 +383,17 @@ struct AccSink {
         }
         const uint64_t ml = __ballot(mine && lng);
         if (mine && lng) lq[lanes_below(ml)] = e;
+        const int r = static_cast<int>(e.x & 15u);
+        Acc v{};
         if (mine && !lng) {
-            const int r = static_cast<int>(e.x & 15u);
             uint64_t ket[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
             typename P::H hr, hi;
             melem<W, NW>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
-            Acc v;
             P::madd(v, hr, hi, vec[e.y]);
-            add(r, v);
         }
+        add(r, v, mine && !lng);
         if (ml) {
             wave_sync();
             drain_long(__popcll(ml));
@@ -458,7 +472,7 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 // WPB + wave); with WPB > 1 the waves share U's Bloom filter, staged in LDS
 // (dynamic shared memory) once per workgroup.
 template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
+__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                        void* __restrict__ partial) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
@@ -467,7 +481,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     __shared__ uint2 q_s[WPB][2 * kWave];
     __shared__ uint2 lq_s[WPB][kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
-    __shared__ double2 acc_s[WPB][NR * kWave];
+    __shared__ double2 acc_s[WPB][NR * kAccCols];
     extern __shared__ uint32_t lfilt[];
     const int wave = static_cast<int>(threadIdx.x) / kWave;
     if constexpr (BL) {
@@ -481,8 +495,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     read_stash_counts(A);
     Rows<W, NR> R;
     load_rows<W, NR>(A, R, rowkey, tile);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r * kWave + lane_id()] = Acc{};
+    for (int i = lane_id(); i < NR * kAccCols; i += kWave) acc[i] = Acc{};
     wave_sync();
     AccSink<W, PREC, ADJ, NR, NW> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
@@ -494,10 +507,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     sink.rowkey = rowkey;
     find<W, VARIANT, NR, NW, BL>(A, R, blockIdx.y, sink, lfilt);
     sink.finish();
-    // per-row totals: lane r adds the 64 lane columns of row r in order
+    // per-row totals: lane r adds the columns of row r in order
     if (lane_id() < R.n) {
         Acc t{};
-        for (int l = 0; l < kWave; ++l) acc_plus(t, acc[lane_id() * kWave + l]);
+        for (int l = 0; l < kAccCols; ++l) acc_plus(t, acc[lane_id() * kAccCols + l]);
         store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + R.row0 + lane_id(), t);
     }
 }
@@ -558,7 +571,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     __shared__ uint2 q[2 * kWave];
     __shared__ uint2 lq[kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
-    __shared__ double2 acc_raw[NR * kWave];
+    __shared__ double2 acc_raw[NR * kAccCols];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
     const int lane = lane_id();
     constexpr int kSlices = kMaxBatch / kWave;
@@ -607,8 +620,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         const int chunk = static_cast<int>(u - tile * D.chunks);
         Rows<W, NR> R;
         load_rows<W, NR>(A, R, rowkey, tile);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r * kWave + lane] = Acc{};
+        for (int i = lane; i < NR * kAccCols; i += kWave) acc[i] = Acc{};
         wave_sync();
         AccSink<W, PREC, false, NR, NW> sink;
         sink.groups = static_cast<const GroupRec<W>*>(A.groups);
@@ -628,7 +640,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         sink.finish();
         if (lane < R.n) {
             Acc s{};
-            for (int l = 0; l < kWave; ++l) acc_plus(s, acc[lane * kWave + l]);
+            for (int l = 0; l < kAccCols; ++l) acc_plus(s, acc[lane * kAccCols + l]);
             auto* part = static_cast<double2*>(partial_all) + D.pbase;
             store_acc(part, static_cast<int64_t>(chunk) * D.M + R.row0 + lane, s);
         }
