@@ -114,17 +114,22 @@ __device__ __forceinline__ void mac(AccD& acc, double hr, double hi, double2 v) 
     acc.im = fma(hr, v.y, fma(hi, v.x, acc.im));
 }
 
+// The imaginary part of H is exactly zero for a group without odd-|Y| terms
+// (every term of a real Hamiltonian); its two products would add exact
+// zeros, so they are skipped.
 __device__ __forceinline__ void mac(AccF& acc, F2 hr, F2 hi, float4 v) {
     const F2 vr{v.x, v.y}, vi{v.z, v.w};
     float p, q;
     df_mul(hr, vr, p, q);
     acc_add(acc.re, p, q);
-    df_mul(hi, vi, p, q);
-    acc_add(acc.re, -p, -q);
     df_mul(hr, vi, p, q);
     acc_add(acc.im, p, q);
-    df_mul(hi, vr, p, q);
-    acc_add(acc.im, p, q);
+    if (hi.s != 0.f || hi.c != 0.f) {
+        df_mul(hi, vi, p, q);
+        acc_add(acc.re, -p, -q);
+        df_mul(hi, vr, p, q);
+        acc_add(acc.im, p, q);
+    }
 }
 
 // ---------------------------------------------------------------------------
