@@ -273,6 +273,69 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
     return *reinterpret_cast<double*>(&q);
 }
 
+__device__ __forceinline__ AccD shfl_xor_acc(const AccD& a, int m) {
+    AccD o;
+    o.re = shfl_xor_d(a.re, m);
+    o.im = shfl_xor_d(a.im, m);
+    return o;
+}
+__device__ __forceinline__ AccF shfl_xor_acc(const AccF& a, int m) {
+    AccF o;
+    o.re.s = __shfl_xor(a.re.s, m, 64);
+    o.re.c = __shfl_xor(a.re.c, m, 64);
+    o.im.s = __shfl_xor(a.im.s, m, 64);
+    o.im.c = __shfl_xor(a.im.c, m, 64);
+    return o;
+}
+
+// Value of lane k's v in every lane (k wave-uniform).
+template <class T>
+__device__ __forceinline__ T lane_value(const T& v, int k) {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    constexpr int n = sizeof(T) / 4;
+    int w[n];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readlane(w[i], k);
+    T o;
+    __builtin_memcpy(&o, w, sizeof(T));
+    return o;
+}
+
+// First strided term of a run [b, e) for this lane (b + lane), or an exact
+// zero past the run; the read is clamped into the run.
+template <int W, bool NW>
+__device__ __forceinline__ double strided_first(const TermRec<W>* __restrict__ terms, int b, int e, int lane,
+                                                const uint64_t* ket) {
+    const int t = b + lane;
+    const TermRec<W> tr = terms[min(t, max(e - 1, b))];
+    return t < e ? term_f64<W, NW>(tr, ket) : 0.0;
+}
+template <int W, bool NW>
+__device__ __forceinline__ F2 strided_first(const TermRecF<W>* __restrict__ terms, int b, int e, int lane,
+                                            const uint64_t* ket) {
+    const int t = b + lane;
+    const TermRecF<W> tr = terms[min(t, max(e - 1, b))];
+    float vh, vl;
+    term_f32<W, NW>(tr, ket, vh, vl);
+    return t < e ? F2{vh, vl} : F2{0.f, 0.f};
+}
+// The rest of the strided sum (runs longer than the wave).
+template <int W, bool NW>
+__device__ __forceinline__ void strided_rest(const TermRec<W>* __restrict__ terms, int b, int e, int lane,
+                                             const uint64_t* ket, double& h) {
+    for (int t = b + lane + 64; t < e; t += 64) h += term_f64<W, NW>(terms[t], ket);
+}
+template <int W, bool NW>
+__device__ __forceinline__ void strided_rest(const TermRecF<W>* __restrict__ terms, int b, int e, int lane,
+                                             const uint64_t* ket, F2& h) {
+    float vh, vl;
+    for (int t = b + lane + 64; t < e; t += 64) {
+        term_f32<W, NW>(terms[t], ket, vh, vl);
+        acc_add(h, vh, vl);
+    }
+}
+
 __device__ __forceinline__ void wave_sum(AccD& a) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {

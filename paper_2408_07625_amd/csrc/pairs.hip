@@ -351,21 +351,43 @@ struct AccSink {
         wave_sync();
     }
 
-    // the whole wave on each long run, 64 terms per step
+    // adds the wave's 64 partial sums of row r (wave-uniform): lane l + 32
+    // hands its value to lane l, which adds its own first; the same order as
+    // add() with every lane on
+    __device__ __forceinline__ void add_wave(int r, const Acc& v) {
+        const Acc o = shfl_xor_acc(v, kAccCols);
+        if (lane_id() < kAccCols) {
+            Acc* a = acc + r * kAccCols + lane_id();
+            Acc t = *a;
+            acc_plus(t, v);
+            acc_plus(t, o);
+            *a = t;
+        }
+        wave_sync();
+    }
+
+    // the long runs set aside in lq[0, n), each spread over the wave (64
+    // terms per step): lane k first reads entry k's group record, so that a
+    // run waits only for its own terms (its vector element is a scalar read
+    // beside them)
     __device__ __forceinline__ void drain_long(int n) {
+        const int lane = lane_id();
+        const uint2 le = lq[min(lane, n - 1)];
+        const GroupRec<W> lgr = groups[le.x >> 4];
         for (int k = 0; k < n; ++k) {
-            const uint32_t ex = __builtin_amdgcn_readfirstlane(lq[k].x);
-            const uint32_t ey = __builtin_amdgcn_readfirstlane(lq[k].y);
-            const int r = static_cast<int>(ex & 15u);
-            const GroupRec<W> gr = groups[ex >> 4];
+            const int r = static_cast<int>(__builtin_amdgcn_readlane(static_cast<int>(le.x), k) & 15);
+            const uint32_t jv = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(le.y), k));
+            const GroupRec<W> gr = lane_value(lgr, k);
             uint64_t ket[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
-            typename P::H hr, hi;
-            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, lane_id(), kWave, ket, hr, hi);
+            typename P::H hr = strided_first<W, NW>(terms, gr.begin, gr.mid, lane, ket);
+            typename P::H hi = strided_first<W, NW>(terms, gr.mid, gr.end, lane, ket);
+            strided_rest<W, NW>(terms, gr.begin, gr.mid, lane, ket, hr);
+            strided_rest<W, NW>(terms, gr.mid, gr.end, lane, ket, hi);
             Acc v;
-            P::madd(v, hr, hi, vec[ey]);
-            add(r, v, true);
+            P::madd(v, hr, hi, vec[jv]);
+            add_wave(r, v);
         }
     }
 
@@ -472,7 +494,7 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 // WPB + wave); with WPB > 1 the waves share U's Bloom filter, staged in LDS
 // (dynamic shared memory) once per workgroup.
 template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB>
-__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs(PairArgs A, const void* __restrict__ vec,
+__global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                        void* __restrict__ partial) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
