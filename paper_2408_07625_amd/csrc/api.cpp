@@ -225,7 +225,10 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, c->ghash.ensure(sizeof(uint64_t) * G));
     ELOC_HIP(c, c->gkeys.ensure(sizeof(uint64_t) * G * W));
     const uint64_t cap = table_capacity(G);
-    const int tk = table_kind(W, n_qubits <= 32);
+    // narrow keys (one 32-bit word) also carry a run's real and imaginary
+    // lengths in 16 bits each through the hit queue
+    const bool narrow = n_qubits <= 32 && hh.maxpart < kNarrowMaxPart;
+    const int tk = table_kind(W, narrow);
     ELOC_HIP(c, c->gslots.ensure(slot_bytes(tk) * cap));
     ELOC_HIP(c, hipMemcpy(c->groups.p, groups.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->terms.p, terms.data(), sizeof(TermRec<W>) * n_terms, hipMemcpyHostToDevice));
@@ -240,7 +243,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     HamDev H;
     H.n_qubits = n_qubits;
     H.W = W;
-    H.narrow = n_qubits <= 32;
+    H.narrow = narrow;
     H.n_terms = n_terms;
     H.n_groups = G;
     H.maxpop = maxpop;

@@ -261,6 +261,10 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
             }
         const std::string why = build_host_ham<W>(b->R, p.n_terms, p.coeff, xy.data(), yz.data(), hh[static_cast<size_t>(k)]);
         if (!why.empty()) return bfail(b, ELOC_EINVAL, "problem " + std::to_string(k) + ": " + why);
+        if (hh[static_cast<size_t>(k)].maxpart >= kNarrowMaxPart && b->narrow) {
+            b->narrow = false;   // the hit queue's narrow entries hold 16-bit run lengths
+            b->tk = table_kind(W, false);
+        }
     }
     int64_t nt = 0, ng = 0, gcap = 0, kc = 0;
     std::vector<int64_t> toff(static_cast<size_t>(n)), goff(static_cast<size_t>(n)), gcoff(static_cast<size_t>(n)),

@@ -73,6 +73,7 @@ struct HostHam {
     int64_t G = 0;
     int maxpop = 0;
     int diag = -1;
+    int64_t maxpart = 0;             // longest real or imaginary part of a group's run
     std::vector<GroupRec<W>> groups;
     std::vector<TermRec<W>> terms;
     std::vector<TermRecF<W>> terms_f;
@@ -140,6 +141,7 @@ std::string build_host_ham(const uint64_t* R, int64_t n_terms, const double* coe
     out.ghash.resize(static_cast<size_t>(G));
     out.gkeys.resize(static_cast<size_t>(G * W));
     out.maxpop = 0;
+    out.maxpart = 0;
     out.diag = -1;
     for (int64_t g = 0; g < G; ++g) {
         GroupRec<W> r;
@@ -159,6 +161,7 @@ std::string build_host_ham(const uint64_t* R, int64_t n_terms, const double* coe
         out.groups[static_cast<size_t>(g)] = r;
         out.ghash[static_cast<size_t>(g)] = h;
         out.maxpop = std::max(out.maxpop, pc);
+        out.maxpart = std::max<int64_t>(out.maxpart, std::max(r.mid - r.begin, r.end - r.mid));
         if (pc == 0) out.diag = static_cast<int>(g);
     }
     // masks sorted ascending (top word first) for the XY prefix trees

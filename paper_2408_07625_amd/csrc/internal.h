@@ -33,6 +33,10 @@ struct GroupRec {
     int32_t pad;
 };
 
+// Narrow keys (at most 32 qubits) also need every group's real and imaginary
+// parts shorter than this: the hit queue carries their lengths in 16 bits.
+constexpr int64_t kNarrowMaxPart = 65536;
+
 template <int W>
 struct TermRec {
     uint64_t yz[W];

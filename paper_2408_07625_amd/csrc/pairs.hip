@@ -145,6 +145,18 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
     }
 }
 
+// A group's term run as the hit queue carries it for narrow keys: first
+// term and the real / imaginary part lengths in 16 bits each.
+struct RunRef {
+    uint32_t begin;
+    uint32_t lens;
+};
+template <int W>
+__device__ __forceinline__ RunRef run_ref(const GroupRec<W>& gr) {
+    return RunRef{static_cast<uint32_t>(gr.begin),
+                  static_cast<uint32_t>(gr.mid - gr.begin) | (static_cast<uint32_t>(gr.end - gr.mid) << 16)};
+}
+
 // LoopOverTerms: lanes over 64 groups of the chunk per step.  With SIG the
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
@@ -160,16 +172,16 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     const int lane = lane_id();
-    // the step's group fields live in plain registers (mask words, run
-    // length, hash)
+    // the step's group fields live in plain registers (mask words, term
+    // run, hash)
     uint64_t gxy[W];
-    int run;
+    RunRef run;
     uint64_t gh;
     {
         const GroupRec<W>& gr = groups[min(g0 + lane, g1 - 1)];
 #pragma unroll
         for (int w = 0; w < W; ++w) gxy[w] = gr.xy[w];
-        run = gr.end - gr.begin;
+        run = run_ref(gr);
         gh = A.ghash[min(g0 + lane, g1 - 1)];
     }
     for (int base = g0; base < g1; base += kWave) {
@@ -179,14 +191,14 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         // so that they arrive with them (clamped: no branch, whose join would
         // make the compiler wait for them at once)
         uint64_t nxy[W];
-        int nrun;
+        RunRef nrun;
         uint64_t ngh;
         {
             const int ng = min(base + kWave + lane, g1 - 1);
             const GroupRec<W>& gr = groups[ng];
 #pragma unroll
             for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
-            nrun = gr.end - gr.begin;
+            nrun = run_ref(gr);
             ngh = A.ghash[ng];
         }
         uint64_t xp[NR][W];
@@ -231,10 +243,13 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         // second slots only where the first leaves the lookup open
 #pragma unroll
         for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
+        // all rows settled first: only the indices stay live through the drains
+        int jr[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) jr[r] = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int j = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
-            sink.hit(r, j >= 0, g, j, run);
+            sink.hit(r, jr[r] >= 0, g, jr[r], run, static_cast<uint32_t>(R.x[r][0] ^ gxy[0]));
             sink.flush();   // the queue never holds more than two waves of hits
         }
 #pragma unroll
@@ -287,15 +302,15 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
+        int gr_[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gr_[r] = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash, okr[r]);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int g = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash, okr[r]);
-            int run = 0;
-            if (g >= 0) {
-                const GroupRec<W>& gr = groups[g];
-                run = gr.end - gr.begin;
-            }
-            sink.hit(r, g >= 0, g, static_cast<int>(j), run);
+            const int g = gr_[r];
+            RunRef run{};
+            if (Sink::kCarry && g >= 0) run = run_ref(groups[g]);
+            sink.hit(r, g >= 0, g, static_cast<int>(j), run, static_cast<uint32_t>(xj[0]));
             sink.flush();
         }
     }
@@ -306,31 +321,80 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
 // ---------------------------------------------------------------------------
 constexpr int kAccCols = 32;   // accumulator columns per row
 
+// Hit queue entries.  Narrow keys: (j | r << 24, first term, real / imaginary
+// lengths, candidate x'), so that draining needs no group record; otherwise
+// (r | g << 4, j) and the group record is read when draining.
+template <bool NW>
+using QEntry = std::conditional_t<NW, uint4, uint2>;
+
 template <int W, int PREC, bool ADJ, int NR, bool NW>
 struct AccSink {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     using Vec = typename P::Vec;
     using Term = typename P::template Term<W>;
+    using QE = QEntry<NW>;
+    static constexpr bool kCarry = NW;
 
     const GroupRec<W>* groups;
     const Term* terms;
     const Vec* vec;
-    uint2* q;               // LDS hit queue [2 * kWave] (flushed after each row's hits)
-    uint2* lq;              // LDS long runs met while draining [kWave]
+    QE* q;                  // LDS hit queue [2 * kWave] (flushed after each row's hits)
+    QE* lq;                 // LDS long runs met while draining [kWave]
     Acc* acc;               // LDS accumulators [NR][kAccCols]: lane l adds into column l % kAccCols
     const uint64_t* rowkey; // LDS row keys [NR][W]
     int qn = 0;
     int nrows = 0;          // rows inside U (the rest are clamped copies)
     int64_t hits = 0;       // coupled pairs of those rows
 
-    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
+    // a pair as the drain needs it
+    struct Pair {
+        int r;
+        uint32_t j;
+        int b, m, e;             // term run: real part [b, m), imaginary part [m, e)
+        uint64_t ket[W];
+    };
+
+    __device__ __forceinline__ void hit(int r, bool h, int g, int j, RunRef run, uint32_t xp) {
         const uint64_t m = __ballot(h);
-        if (h)
-            q[qn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
-                                                static_cast<uint32_t>(j));
+        if (h) {
+            if constexpr (NW)
+                q[qn + lanes_below(m)] = make_uint4(static_cast<uint32_t>(j) | (static_cast<uint32_t>(r) << 24),
+                                                    run.begin, run.lens, xp);
+            else
+                q[qn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(r) | (static_cast<uint32_t>(g) << 4),
+                                                    static_cast<uint32_t>(j));
+        }
         qn += __popcll(m);
         if (r < nrows) hits += __popcll(m);
+    }
+
+    __device__ __forceinline__ int entry_row(const QE& e) const {
+        if constexpr (NW)
+            return static_cast<int>(e.x >> 24);
+        else
+            return static_cast<int>(e.x & 15u);
+    }
+
+    // decodes entry e (narrow: from the entry alone; else with group record gr)
+    __device__ __forceinline__ Pair decode(const QE& e, const GroupRec<W>& gr) const {
+        Pair p;
+        p.r = entry_row(e);
+        if constexpr (NW) {
+            p.j = e.x & 0xFFFFFFu;
+            p.b = static_cast<int>(e.y);
+            p.m = p.b + static_cast<int>(e.z & 0xFFFFu);
+            p.e = p.m + static_cast<int>(e.z >> 16);
+            p.ket[0] = ADJ ? rowkey[p.r] : static_cast<uint64_t>(e.w);
+        } else {
+            p.j = e.y;
+            p.b = gr.begin;
+            p.m = gr.mid;
+            p.e = gr.end;
+#pragma unroll
+            for (int w = 0; w < W; ++w) p.ket[w] = rowkey[p.r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
+        }
+        return p;
     }
 
     // called by the whole wave; lanes 0-31 add first, then lanes 32-63 (the
@@ -367,27 +431,23 @@ struct AccSink {
     }
 
     // the long runs set aside in lq[0, n), each spread over the wave (64
-    // terms per step): lane k first reads entry k's group record, so that a
-    // run waits only for its own terms (its vector element is a scalar read
-    // beside them)
+    // terms per step): lane k first holds entry k (and, for wide keys, its
+    // group record), so that a run waits only for its own terms (its vector
+    // element is a scalar read beside them)
     __device__ __forceinline__ void drain_long(int n) {
         const int lane = lane_id();
-        const uint2 le = lq[min(lane, n - 1)];
-        const GroupRec<W> lgr = groups[le.x >> 4];
+        const QE le = lq[min(lane, n - 1)];
+        GroupRec<W> lgr{};
+        if constexpr (!NW) lgr = groups[le.x >> 4];
         for (int k = 0; k < n; ++k) {
-            const int r = static_cast<int>(__builtin_amdgcn_readlane(static_cast<int>(le.x), k) & 15);
-            const uint32_t jv = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(le.y), k));
-            const GroupRec<W> gr = lane_value(lgr, k);
-            uint64_t ket[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
-            typename P::H hr = strided_first<W, NW>(terms, gr.begin, gr.mid, lane, ket);
-            typename P::H hi = strided_first<W, NW>(terms, gr.mid, gr.end, lane, ket);
-            strided_rest<W, NW>(terms, gr.begin, gr.mid, lane, ket, hr);
-            strided_rest<W, NW>(terms, gr.mid, gr.end, lane, ket, hi);
+            const Pair p = decode(lane_value(le, k), lane_value(lgr, k));
+            typename P::H hr = strided_first<W, NW>(terms, p.b, p.m, lane, p.ket);
+            typename P::H hi = strided_first<W, NW>(terms, p.m, p.e, lane, p.ket);
+            strided_rest<W, NW>(terms, p.b, p.m, lane, p.ket, hr);
+            strided_rest<W, NW>(terms, p.m, p.e, lane, p.ket, hi);
             Acc v;
-            P::madd(v, hr, hi, vec[jv]);
-            add_wave(r, v);
+            P::madd(v, hr, hi, vec[p.j]);
+            add_wave(p.r, v);
         }
     }
 
@@ -395,27 +455,23 @@ struct AccSink {
     // kLongRun are set aside and done by the whole wave
     __device__ __forceinline__ void drain(int o, int n) {
         const bool mine = lane_id() < n;
-        uint2 e = make_uint2(0u, 0u);
+        QE e{};
         GroupRec<W> gr{};
-        bool lng = false;
         if (mine) {
             e = q[o + lane_id()];
-            gr = groups[e.x >> 4];
-            lng = gr.end - gr.begin > kLongRun;
+            if constexpr (!NW) gr = groups[e.x >> 4];
         }
-        const uint64_t ml = __ballot(mine && lng);
-        if (mine && lng) lq[lanes_below(ml)] = e;
-        const int r = static_cast<int>(e.x & 15u);
+        const Pair p = decode(e, gr);
+        const bool lng = mine && p.e - p.b > kLongRun;
+        const uint64_t ml = __ballot(lng);
+        if (lng) lq[lanes_below(ml)] = e;
         Acc v{};
         if (mine && !lng) {
-            uint64_t ket[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) ket[w] = rowkey[r * W + w] ^ (ADJ ? 0ull : gr.xy[w]);
             typename P::H hr, hi;
-            melem<W, NW>(terms, gr.begin, gr.mid, gr.end, 0, 1, ket, hr, hi);
-            P::madd(v, hr, hi, vec[e.y]);
+            melem<W, NW>(terms, p.b, p.m, p.e, 0, 1, p.ket, hr, hi);
+            P::madd(v, hr, hi, vec[p.j]);
         }
-        add(r, v, mine && !lng);
+        add(p.r, v, mine && !lng);
         if (ml) {
             wave_sync();
             drain_long(__popcll(ml));
@@ -430,7 +486,7 @@ struct AccSink {
             for (; qn - o >= kWave; o += kWave) drain(o, kWave);
             wave_sync();
             const int rest = qn - o;
-            uint2 t = make_uint2(0u, 0u);
+            QE t{};
             if (lane_id() < rest) t = q[o + lane_id()];
             wave_sync();
             if (lane_id() < rest) q[lane_id()] = t;
@@ -447,19 +503,23 @@ struct AccSink {
 };
 
 struct CountSink {
+    static constexpr bool kCarry = false;
     int cnt[kRows];
-    __device__ __forceinline__ void hit(int r, bool h, int, int, int) { cnt[r] += __popcll(__ballot(h)); }
+    __device__ __forceinline__ void hit(int r, bool h, int, int, RunRef, uint32_t) {
+        cnt[r] += __popcll(__ballot(h));
+    }
     __device__ __forceinline__ void flush() {}
 };
 
 struct FillSink {
+    static constexpr bool kCarry = false;
     int64_t pos[kRows];
     int64_t row0;
     int n;          // rows of this wave inside U; the rest are clamped copies
     int jbits;
     uint64_t* pkey;
     uint32_t* pval;
-    __device__ __forceinline__ void hit(int r, bool h, int g, int j, int) {
+    __device__ __forceinline__ void hit(int r, bool h, int g, int j, RunRef, uint32_t) {
         const uint64_t m = __ballot(h);
         if (h && r < n) {
             const int64_t p = pos[r] + lanes_below(m);
@@ -500,8 +560,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     using Acc = typename P::Acc;
     constexpr bool BL = WPB > 1;
     __shared__ uint64_t rowkey_s[WPB][NR * W];
-    __shared__ uint2 q_s[WPB][2 * kWave];
-    __shared__ uint2 lq_s[WPB][kWave];
+    __shared__ QEntry<NW> q_s[WPB][2 * kWave];
+    __shared__ QEntry<NW> lq_s[WPB][kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_s[WPB][NR * kAccCols];
     extern __shared__ uint32_t lfilt[];
@@ -590,8 +650,8 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     __shared__ uint64_t rowkey[NR * W];
-    __shared__ uint2 q[2 * kWave];
-    __shared__ uint2 lq[kWave];
+    __shared__ QEntry<NW> q[2 * kWave];
+    __shared__ QEntry<NW> lq[kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kAccCols];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
