@@ -161,9 +161,14 @@ __device__ __forceinline__ RunRef run_ref(const GroupRec<W>& gr) {
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
 // are discarded by the caller.
+// Compaction buffer entries of LoopOverTerms (exact tables): the salted
+// hash of a candidate that passed the prefilters and its (row, lane).
+template <bool NW>
+using CEntry = std::conditional_t<NW, uint2, uint4>;
+
 template <int W, int SIG, int NR, bool NW, bool BL, class Sink>
 __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
-                                           const uint32_t* lfilt) {
+                                           const uint32_t* lfilt, CEntry<NW>* cb, const uint64_t* rowkey) {
     constexpr int TK = table_kind(W, NW);
     using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
@@ -201,17 +206,15 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             nrun = run_ref(gr);
             ngh = A.ghash[ng];
         }
-        uint64_t xp[NR][W];
-        typename TabT<TK>::slot v1[NR], v2[NR];
-        HT hs[NR];
-        bool okr[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            bool ok = valid;
+        // the exact prefilters of candidate x ^ XY for row r: U's single
+        // popcount signature (unless sig_all), U's radius around its majority
+        // key, U's Bloom filter (BL); returns the salted hash
+        auto filter = [&](int r, uint64_t (&xpr)[W], bool& ok) -> HT {
+            ok = valid;
             int pa = 0, n = 0, d = 0;
             if constexpr (NW) {
                 const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
-                xp[r][0] = x32;
+                xpr[0] = x32;
                 if (SIG) {
                     pa = __popc(x32 & static_cast<uint32_t>(kEven));
                     n = __popc(x32);
@@ -220,37 +223,106 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             } else {
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    xp[r][w] = R.x[r][w] ^ gxy[w];
+                    xpr[w] = R.x[r][w] ^ gxy[w];
                     if (SIG) {
-                        pa += popc64(xp[r][w] & kEven);
-                        n += popc64(xp[r][w]);
-                        d += popc64(xp[r][w] ^ A.rad_ref[w]);
+                        pa += popc64(xpr[w] & kEven);
+                        n += popc64(xpr[w]);
+                        d += popc64(xpr[w] ^ A.rad_ref[w]);
                     }
                 }
             }
-            // exact prefilters: U's single popcount signature (unless
-            // sig_all) and U's radius around its majority key
             if (SIG) ok = ok & (A.sig_all | ((pa == A.sig_pa) & (n == A.sig_n))) & (d <= A.rad_max);
-            if constexpr (BL) {   // U's Bloom filter, in LDS
+            if constexpr (BL) {
                 const uint32_t hf = static_cast<uint32_t>(R.hx[r] >> 32) ^ static_cast<uint32_t>(gh >> 32);
                 const uint32_t bits = bloom_bits(hf);
                 ok = ok & ((lfilt[bloom_word(hf, A.bloom_mask)] & bits) == bits);
             }
-            hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
-            v1[r] = slots.load(slot1(T, hs[r]), ok);
-            okr[r] = ok;
-        }
-        // second slots only where the first leaves the lookup open
+            return static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
+        };
+        if constexpr (TK != kTabVerify) {
+            // exact tables: the candidates that pass are compacted into dense
+            // lanes (LDS, ballot + mbcnt), and only those are probed, 64 at a
+            // time; a probe's group fields come from its source lane
+            auto probe_round = [&](int n) {
+                const bool on = lane < n;
+                const CEntry<NW> e = cb[on ? lane : 0];
+                HT h;
+                uint32_t meta;
+                if constexpr (NW) {
+                    h = e.x;
+                    meta = e.y;
+                } else {
+                    h = (static_cast<uint64_t>(e.y) << 32) | e.x;
+                    meta = e.z;
+                }
+                const int r = static_cast<int>(meta & 7u);
+                const int src = static_cast<int>(meta >> 3);
+                const auto s1 = slots.load(slot1(T, h), on);
+                const auto s2 = slots.load(slot2(T, h), need_slot2<TK>(T, s1, h));
+                const int jj = table_settle<TK, W>(T, A.keys, s1, s2, h, nullptr, A.kstash, on);
+                const RunRef rr{static_cast<uint32_t>(__shfl(static_cast<int>(run.begin), src, kWave)),
+                                static_cast<uint32_t>(__shfl(static_cast<int>(run.lens), src, kWave))};
+                const uint32_t gx = static_cast<uint32_t>(__shfl(static_cast<int>(gxy[0]), src, kWave));
+                sink.hit(r, on && jj >= 0, base + src, jj, rr, static_cast<uint32_t>(rowkey[r * W]) ^ gx);
+                sink.flush();   // the queue never holds more than two waves of hits
+            };
+            int cn = 0;   // entries in cb (wave-uniform)
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
-        // all rows settled first: only the indices stay live through the drains
-        int jr[NR];
+            for (int r = 0; r < NR; ++r) {
+                uint64_t xpr[W];
+                bool ok;
+                const HT h = filter(r, xpr, ok);
+                const uint64_t m = __ballot(ok);
+                if (ok) {
+                    const uint32_t meta = static_cast<uint32_t>(r) | (static_cast<uint32_t>(lane) << 3);
+                    if constexpr (NW)
+                        cb[cn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(h), meta);
+                    else
+                        cb[cn + lanes_below(m)] = make_uint4(static_cast<uint32_t>(h),
+                                                             static_cast<uint32_t>(static_cast<uint64_t>(h) >> 32),
+                                                             meta, 0u);
+                }
+                cn += __popcll(m);
+                if (cn >= kWave) {
+                    wave_sync();
+                    probe_round(kWave);
+                    const int rest = cn - kWave;
+                    CEntry<NW> t{};
+                    if (lane < rest) t = cb[kWave + lane];
+                    wave_sync();
+                    if (lane < rest) cb[lane] = t;
+                    wave_sync();
+                    cn = rest;
+                }
+            }
+            if (cn > 0) {
+                wave_sync();
+                probe_round(cn);
+                wave_sync();
+            }
+        } else {
+            uint64_t xp[NR][W];
+            typename TabT<TK>::slot v1[NR], v2[NR];
+            HT hs[NR];
+            bool okr[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) jr[r] = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
+            for (int r = 0; r < NR; ++r) {
+                hs[r] = filter(r, xp[r], okr[r]);
+                v1[r] = slots.load(slot1(T, hs[r]), okr[r]);
+            }
+            // second slots only where the first leaves the lookup open
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            sink.hit(r, jr[r] >= 0, g, jr[r], run, static_cast<uint32_t>(R.x[r][0] ^ gxy[0]));
-            sink.flush();   // the queue never holds more than two waves of hits
+            for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
+            // all rows settled first: only the indices stay live through the drains
+            int jr[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                jr[r] = table_settle<TK, W>(T, A.keys, v1[r], v2[r], hs[r], xp[r], A.kstash, okr[r]);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                sink.hit(r, jr[r] >= 0, g, jr[r], run, static_cast<uint32_t>(R.x[r][0] ^ gxy[0]));
+                sink.flush();   // the queue never holds more than two waves of hits
+            }
         }
 #pragma unroll
         for (int w = 0; w < W; ++w) gxy[w] = nxy[w];
@@ -340,7 +412,6 @@ struct AccSink {
     const Term* terms;
     const Vec* vec;
     QE* q;                  // LDS hit queue [2 * kWave] (flushed after each row's hits)
-    QE* lq;                 // LDS long runs met while draining [kWave]
     Acc* acc;               // LDS accumulators [NR][kAccCols]: lane l adds into column l % kAccCols
     const uint64_t* rowkey; // LDS row keys [NR][W]
     int qn = 0;
@@ -366,7 +437,7 @@ struct AccSink {
                                                     static_cast<uint32_t>(j));
         }
         qn += __popcll(m);
-        if (r < nrows) hits += __popcll(m);
+        hits += __popcll(__ballot(h && r < nrows));
     }
 
     __device__ __forceinline__ int entry_row(const QE& e) const {
@@ -434,7 +505,7 @@ struct AccSink {
     // terms per step): lane k first holds entry k (and, for wide keys, its
     // group record), so that a run waits only for its own terms (its vector
     // element is a scalar read beside them)
-    __device__ __forceinline__ void drain_long(int n) {
+    __device__ __forceinline__ void drain_long(const QE* lq, int n) {
         const int lane = lane_id();
         const QE le = lq[min(lane, n - 1)];
         GroupRec<W> lgr{};
@@ -452,7 +523,8 @@ struct AccSink {
     }
 
     // entries [o, o + n) of the queue, one pair per lane; runs longer than
-    // kLongRun are set aside and done by the whole wave
+    // kLongRun are set aside (over the entries just read, q + o) and done by
+    // the whole wave
     __device__ __forceinline__ void drain(int o, int n) {
         const bool mine = lane_id() < n;
         QE e{};
@@ -464,6 +536,7 @@ struct AccSink {
         const Pair p = decode(e, gr);
         const bool lng = mine && p.e - p.b > kLongRun;
         const uint64_t ml = __ballot(lng);
+        QE* lq = q + o;
         if (lng) lq[lanes_below(ml)] = e;
         Acc v{};
         if (mine && !lng) {
@@ -474,7 +547,7 @@ struct AccSink {
         add(p.r, v, mine && !lng);
         if (ml) {
             wave_sync();
-            drain_long(__popcll(ml));
+            drain_long(lq, __popcll(ml));
             wave_sync();
         }
     }
@@ -505,8 +578,10 @@ struct AccSink {
 struct CountSink {
     static constexpr bool kCarry = false;
     int cnt[kRows];
+    // r may differ between lanes
     __device__ __forceinline__ void hit(int r, bool h, int, int, RunRef, uint32_t) {
-        cnt[r] += __popcll(__ballot(h));
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) cnt[k] += __popcll(__ballot(h && r == k));
     }
     __device__ __forceinline__ void flush() {}
 };
@@ -519,14 +594,18 @@ struct FillSink {
     int jbits;
     uint64_t* pkey;
     uint32_t* pval;
+    // r may differ between lanes
     __device__ __forceinline__ void hit(int r, bool h, int g, int j, RunRef, uint32_t) {
-        const uint64_t m = __ballot(h);
-        if (h && r < n) {
-            const int64_t p = pos[r] + lanes_below(m);
-            pkey[p] = (static_cast<uint64_t>(row0 + r) << jbits) | static_cast<uint64_t>(j);
-            pval[p] = static_cast<uint32_t>(g);
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const uint64_t m = __ballot(h && r == k);
+            if (h && r == k && k < n) {
+                const int64_t p = pos[k] + lanes_below(m);
+                pkey[p] = (static_cast<uint64_t>(row0 + k) << jbits) | static_cast<uint64_t>(j);
+                pval[p] = static_cast<uint32_t>(g);
+            }
+            pos[k] += __popcll(m);
         }
-        pos[r] += __popcll(m);
     }
     __device__ __forceinline__ void flush() {}
 };
@@ -536,11 +615,11 @@ struct FillSink {
 // BL: the prefiltered LoopOverTerms also tests U's Bloom filter in LDS.
 template <int W, int VARIANT, int NR, bool NW, bool BL = false, class Sink>
 __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
-                                     const uint32_t* lfilt = nullptr) {
+                                     CEntry<NW>* cb, const uint64_t* rowkey, const uint32_t* lfilt = nullptr) {
     if constexpr (VARIANT == 0)
-        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, lfilt);
+        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, lfilt, cb, rowkey);
     else if constexpr (VARIANT == 3)
-        find_terms<W, 1, NR, NW, BL>(A, R, chunk, sink, lfilt);
+        find_terms<W, 1, NR, NW, BL>(A, R, chunk, sink, lfilt, cb, rowkey);
     else
         find_batch<W, NR, NW>(A, R, chunk, sink);
 }
@@ -561,7 +640,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     constexpr bool BL = WPB > 1;
     __shared__ uint64_t rowkey_s[WPB][NR * W];
     __shared__ QEntry<NW> q_s[WPB][2 * kWave];
-    __shared__ QEntry<NW> lq_s[WPB][kWave];
+    __shared__ CEntry<NW> cb_s[WPB][2 * kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_s[WPB][NR * kAccCols];
     extern __shared__ uint32_t lfilt[];
@@ -584,10 +663,9 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec);
     sink.q = q_s[wave];
-    sink.lq = lq_s[wave];
     sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT, NR, NW, BL>(A, R, blockIdx.y, sink, lfilt);
+    find<W, VARIANT, NR, NW, BL>(A, R, blockIdx.y, sink, cb_s[wave], rowkey, lfilt);
     sink.finish();
     // per-row totals: lane r adds the columns of row r in order
     if (lane_id() < R.n) {
@@ -600,6 +678,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
 template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRows * W];
+    __shared__ CEntry<NW> cb[2 * kWave];
     read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
@@ -607,7 +686,7 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
-    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         if (lane_id() == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
@@ -617,6 +696,7 @@ template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRows * W];
+    __shared__ CEntry<NW> cb[2 * kWave];
     read_stash_counts(A);
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
@@ -630,7 +710,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
         sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
-    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink);
+    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,7 +731,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     using Acc = typename P::Acc;
     __shared__ uint64_t rowkey[NR * W];
     __shared__ QEntry<NW> q[2 * kWave];
-    __shared__ QEntry<NW> lq[kWave];
+    __shared__ CEntry<NW> cb[2 * kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kAccCols];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
@@ -709,16 +789,15 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
         sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
         sink.q = q;
-        sink.lq = lq;
         sink.acc = acc;
         sink.rowkey = rowkey;
         sink.nrows = R.n;
         if (D.variant == 1)
             find_batch<W, NR, NW>(A, R, chunk, sink);
         else if (sig)
-            find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr);
+            find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
         else
-            find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr);
+            find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
         sink.finish();
         if (lane < R.n) {
             Acc s{};
