@@ -302,16 +302,30 @@ __device__ __forceinline__ T lane_value(const T& v, int k) {
     return o;
 }
 
-// First strided term of a run [b, e) for this lane (b + lane), or an exact
-// zero past the run; the read is clamped into the run.
-template <int W, bool NW>
+// Value of lane k's v in this lane (k per lane).
+template <class T>
+__device__ __forceinline__ T lane_shfl(const T& v, int k) {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    constexpr int n = sizeof(T) / 4;
+    int w[n];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < n; ++i) w[i] = __shfl(w[i], k, 64);
+    T o;
+    __builtin_memcpy(&o, w, sizeof(T));
+    return o;
+}
+
+// First strided term of a run [b, e) for this lane (b + lane, stride S), or
+// an exact zero past the run; the read is clamped into the run.
+template <int W, bool NW, int S = 64>
 __device__ __forceinline__ double strided_first(const TermRec<W>* __restrict__ terms, int b, int e, int lane,
                                                 const uint64_t* ket) {
     const int t = b + lane;
     const TermRec<W> tr = terms[min(t, max(e - 1, b))];
     return t < e ? term_f64<W, NW>(tr, ket) : 0.0;
 }
-template <int W, bool NW>
+template <int W, bool NW, int S = 64>
 __device__ __forceinline__ F2 strided_first(const TermRecF<W>* __restrict__ terms, int b, int e, int lane,
                                             const uint64_t* ket) {
     const int t = b + lane;
@@ -320,17 +334,17 @@ __device__ __forceinline__ F2 strided_first(const TermRecF<W>* __restrict__ term
     term_f32<W, NW>(tr, ket, vh, vl);
     return t < e ? F2{vh, vl} : F2{0.f, 0.f};
 }
-// The rest of the strided sum (runs longer than the wave).
-template <int W, bool NW>
+// The rest of the strided sum (runs longer than the stride).
+template <int W, bool NW, int S = 64>
 __device__ __forceinline__ void strided_rest(const TermRec<W>* __restrict__ terms, int b, int e, int lane,
                                              const uint64_t* ket, double& h) {
-    for (int t = b + lane + 64; t < e; t += 64) h += term_f64<W, NW>(terms[t], ket);
+    for (int t = b + lane + S; t < e; t += S) h += term_f64<W, NW>(terms[t], ket);
 }
-template <int W, bool NW>
+template <int W, bool NW, int S = 64>
 __device__ __forceinline__ void strided_rest(const TermRecF<W>* __restrict__ terms, int b, int e, int lane,
                                              const uint64_t* ket, F2& h) {
     float vh, vl;
-    for (int t = b + lane + 64; t < e; t += 64) {
+    for (int t = b + lane + S; t < e; t += S) {
         term_f32<W, NW>(terms[t], ket, vh, vl);
         acc_add(h, vh, vl);
     }

@@ -486,39 +486,27 @@ struct AccSink {
         wave_sync();
     }
 
-    // adds the wave's 64 partial sums of row r (wave-uniform): lane l + 32
-    // hands its value to lane l, which adds its own first; the same order as
-    // add() with every lane on
-    __device__ __forceinline__ void add_wave(int r, const Acc& v) {
-        const Acc o = shfl_xor_acc(v, kAccCols);
-        if (lane_id() < kAccCols) {
-            Acc* a = acc + r * kAccCols + lane_id();
-            Acc t = *a;
-            acc_plus(t, v);
-            acc_plus(t, o);
-            *a = t;
-        }
-        wave_sync();
-    }
-
-    // the long runs set aside in lq[0, n), each spread over the wave (64
-    // terms per step): lane k first holds entry k (and, for wide keys, its
-    // group record), so that a run waits only for its own terms (its vector
-    // element is a scalar read beside them)
+    // the long runs set aside in lq[0, n), two at a time, each spread over
+    // half of the wave (32 terms per step): lane k first holds entry k (and,
+    // for wide keys, its group record); a half-wave takes its entry from that
+    // lane, so that a run waits only for its own terms
     __device__ __forceinline__ void drain_long(const QE* lq, int n) {
         const int lane = lane_id();
+        const int half = lane >> 5, sub = lane & 31;
         const QE le = lq[min(lane, n - 1)];
         GroupRec<W> lgr{};
         if constexpr (!NW) lgr = groups[le.x >> 4];
-        for (int k = 0; k < n; ++k) {
-            const Pair p = decode(lane_value(le, k), lane_value(lgr, k));
-            typename P::H hr = strided_first<W, NW>(terms, p.b, p.m, lane, p.ket);
-            typename P::H hi = strided_first<W, NW>(terms, p.m, p.e, lane, p.ket);
-            strided_rest<W, NW>(terms, p.b, p.m, lane, p.ket, hr);
-            strided_rest<W, NW>(terms, p.m, p.e, lane, p.ket, hi);
-            Acc v;
-            P::madd(v, hr, hi, vec[p.j]);
-            add_wave(p.r, v);
+        for (int k = 0; k < n; k += 2) {
+            const bool on = k + half < n;
+            const int src = min(k + half, n - 1);
+            const Pair p = decode(lane_shfl(le, src), lane_shfl(lgr, src));
+            typename P::H hr = strided_first<W, NW, 32>(terms, p.b, p.m, sub, p.ket);
+            typename P::H hi = strided_first<W, NW, 32>(terms, p.m, p.e, sub, p.ket);
+            strided_rest<W, NW, 32>(terms, p.b, p.m, sub, p.ket, hr);
+            strided_rest<W, NW, 32>(terms, p.m, p.e, sub, p.ket, hi);
+            Acc v{};
+            if (on) P::madd(v, hr, hi, vec[p.j]);
+            add(p.r, v, on);
         }
     }
 
