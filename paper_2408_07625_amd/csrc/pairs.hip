@@ -486,24 +486,26 @@ struct AccSink {
         wave_sync();
     }
 
-    // the long runs set aside in lq[0, n), two at a time, each spread over
-    // half of the wave (32 terms per step): lane k first holds entry k (and,
-    // for wide keys, its group record); a half-wave takes its entry from that
-    // lane, so that a run waits only for its own terms
+    // the long runs set aside in lq[0, n), kLongPer at a time, each spread
+    // over kWave / kLongPer lanes: lane k first holds entry k (and, for wide
+    // keys, its group record); a lane group takes its entry from that lane,
+    // so that a run waits only for its own terms
+    static constexpr int kLongPer = 2;
+    static constexpr int kLongLanes = kWave / kLongPer;
     __device__ __forceinline__ void drain_long(const QE* lq, int n) {
         const int lane = lane_id();
-        const int half = lane >> 5, sub = lane & 31;
+        const int part = lane / kLongLanes, sub = lane % kLongLanes;
         const QE le = lq[min(lane, n - 1)];
         GroupRec<W> lgr{};
         if constexpr (!NW) lgr = groups[le.x >> 4];
-        for (int k = 0; k < n; k += 2) {
-            const bool on = k + half < n;
-            const int src = min(k + half, n - 1);
+        for (int k = 0; k < n; k += kLongPer) {
+            const bool on = k + part < n;
+            const int src = min(k + part, n - 1);
             const Pair p = decode(lane_shfl(le, src), lane_shfl(lgr, src));
-            typename P::H hr = strided_first<W, NW, 32>(terms, p.b, p.m, sub, p.ket);
-            typename P::H hi = strided_first<W, NW, 32>(terms, p.m, p.e, sub, p.ket);
-            strided_rest<W, NW, 32>(terms, p.b, p.m, sub, p.ket, hr);
-            strided_rest<W, NW, 32>(terms, p.m, p.e, sub, p.ket, hi);
+            typename P::H hr = strided_first<W, NW, kLongLanes>(terms, p.b, p.m, sub, p.ket);
+            typename P::H hi = strided_first<W, NW, kLongLanes>(terms, p.m, p.e, sub, p.ket);
+            strided_rest<W, NW, kLongLanes>(terms, p.b, p.m, sub, p.ket, hr);
+            strided_rest<W, NW, kLongLanes>(terms, p.m, p.e, sub, p.ket, hi);
             Acc v{};
             if (on) P::madd(v, hr, hi, vec[p.j]);
             add(p.r, v, on);
