@@ -331,60 +331,99 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     }
 }
 
-// LoopOverBatch: lanes over 64 samples x' of the chunk per step.
+// LoopOverBatch: lanes over 64 samples x' of the chunk per step.  A pair
+// (x, x') can be coupled only if popcount(x ^ x') is at most the largest XY
+// popcount; the few that pass (under 1% at the workloads measured) are
+// compacted into an LDS buffer (ballot + mbcnt) across steps and looked up in
+// the XY table 64 at a time.
 template <int W, int NR, bool NW, class Sink>
-__device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink) {
+__device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
+                                           CEntry<NW>* cb, const uint64_t* rowkey) {
     constexpr int TK = table_kind(W, NW);
     using HT = typename TabT<TK>::hash;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const Table& T = A.gtable;
     const SlotReader<TK> slots(T);
+    const int lane = lane_id();
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
     const int64_t j1 = min(A.M, j0 + A.per_chunk);
+    // entries [0, n) of cb: (salted hash of x ^ x', row | sample << 3)
+    auto probe_round = [&](int n) {
+        const bool on = lane < n;
+        const CEntry<NW> e = cb[on ? lane : 0];
+        HT h;
+        uint32_t meta;
+        if constexpr (NW) {
+            h = e.x;
+            meta = e.y;
+        } else {
+            h = (static_cast<uint64_t>(e.y) << 32) | e.x;
+            meta = e.z;
+        }
+        const int r = static_cast<int>(meta & 7u);
+        const int j = static_cast<int>(meta >> 3);
+        uint64_t xj[W], m[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            xj[w] = A.keys[static_cast<int64_t>(j) * W + w];
+            m[w] = rowkey[r * W + w] ^ xj[w];
+        }
+        const auto s1 = slots.load(slot1(T, h), on);
+        const auto s2 = slots.load(slot2(T, h), need_slot2<TK>(T, s1, h));
+        const int g = table_settle<TK, W>(T, A.gkeys, s1, s2, h, m, A.gstash, on);
+        RunRef run{};
+        if (Sink::kCarry && g >= 0) run = run_ref(groups[g]);
+        sink.hit(r, on && g >= 0, g, j, run, static_cast<uint32_t>(xj[0]));
+        sink.flush();   // the queue never holds more than two waves of hits
+    };
+    int cn = 0;   // entries in cb (wave-uniform)
     for (int64_t base = j0; base < j1; base += kWave) {
-        const int64_t j = base + lane_id();
+        const int64_t j = base + lane;
         const bool valid = j < j1;
         const int64_t jj = valid ? j : j0;
         uint64_t xj[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
         const uint64_t hj = A.khash[jj];
-        uint64_t m[NR][W];
-        typename TabT<TK>::slot v1[NR], v2[NR];
-        HT hs[NR];
-        bool okr[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             int pc = 0;
             if constexpr (NW) {
-                const uint32_t m32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]);
-                m[r][0] = m32;
-                pc = __popc(m32);
+                pc = __popc(static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]));
             } else {
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    m[r][w] = R.x[r][w] ^ xj[w];
-                    pc += popc64(m[r][w]);
-                }
+                for (int w = 0; w < W; ++w) pc += popc64(R.x[r][w] ^ xj[w]);
             }
             const bool ok = valid & (pc <= A.maxpop);
-            hs[r] = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
-            v1[r] = slots.load(slot1(T, hs[r]), ok);
-            okr[r] = ok;
+            const uint64_t mk = __ballot(ok);
+            if (ok) {
+                const HT h = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
+                const uint32_t meta = static_cast<uint32_t>(r) | (static_cast<uint32_t>(j) << 3);
+                if constexpr (NW)
+                    cb[cn + lanes_below(mk)] = make_uint2(static_cast<uint32_t>(h), meta);
+                else
+                    cb[cn + lanes_below(mk)] = make_uint4(static_cast<uint32_t>(h),
+                                                          static_cast<uint32_t>(static_cast<uint64_t>(h) >> 32),
+                                                          meta, 0u);
+            }
+            cn += __popcll(mk);
+            if (cn >= kWave) {
+                wave_sync();
+                probe_round(kWave);
+                const int rest = cn - kWave;
+                CEntry<NW> t{};
+                if (lane < rest) t = cb[kWave + lane];
+                wave_sync();
+                if (lane < rest) cb[lane] = t;
+                wave_sync();
+                cn = rest;
+            }
         }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) v2[r] = slots.load(slot2(T, hs[r]), need_slot2<TK>(T, v1[r], hs[r]));
-        int gr_[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) gr_[r] = table_settle<TK, W>(T, A.gkeys, v1[r], v2[r], hs[r], m[r], A.gstash, okr[r]);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int g = gr_[r];
-            RunRef run{};
-            if (Sink::kCarry && g >= 0) run = run_ref(groups[g]);
-            sink.hit(r, g >= 0, g, static_cast<int>(j), run, static_cast<uint32_t>(xj[0]));
-            sink.flush();
-        }
+    }
+    if (cn > 0) {
+        wave_sync();
+        probe_round(cn);
+        wave_sync();
     }
 }
 
@@ -611,7 +650,7 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
     else if constexpr (VARIANT == 3)
         find_terms<W, 1, NR, NW, BL>(A, R, chunk, sink, lfilt, cb, rowkey);
     else
-        find_batch<W, NR, NW>(A, R, chunk, sink);
+        find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,7 +822,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         sink.rowkey = rowkey;
         sink.nrows = R.n;
         if (D.variant == 1)
-            find_batch<W, NR, NW>(A, R, chunk, sink);
+            find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
         else if (sig)
             find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
         else
