@@ -335,7 +335,8 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
 // (x, x') can be coupled only if popcount(x ^ x') is at most the largest XY
 // popcount; the few that pass (under 1% at the workloads measured) are
 // compacted into an LDS buffer (ballot + mbcnt) across steps and looked up in
-// the XY table 64 at a time.
+// the XY table 64 at a time.  Only the keys are streamed; the hashes are read
+// for the pairs that pass.
 template <int W, int NR, bool NW, class Sink>
 __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
                                            CEntry<NW>* cb, const uint64_t* rowkey) {
@@ -347,21 +348,14 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
     const int lane = lane_id();
     const int64_t j0 = static_cast<int64_t>(chunk) * A.per_chunk;
     const int64_t j1 = min(A.M, j0 + A.per_chunk);
-    // entries [0, n) of cb: (salted hash of x ^ x', row | sample << 3)
+    // entries [0, n) of cb: row | sample << 3 in the first word
     auto probe_round = [&](int n) {
         const bool on = lane < n;
-        const CEntry<NW> e = cb[on ? lane : 0];
-        HT h;
-        uint32_t meta;
-        if constexpr (NW) {
-            h = e.x;
-            meta = e.y;
-        } else {
-            h = (static_cast<uint64_t>(e.y) << 32) | e.x;
-            meta = e.z;
-        }
+        const uint32_t meta = cb[on ? lane : 0].x;
         const int r = static_cast<int>(meta & 7u);
         const int j = static_cast<int>(meta >> 3);
+        const int64_t row = min(R.row0 + r, A.M - 1);
+        const HT h = static_cast<HT>((A.khash[row] ^ T.salt) ^ A.khash[j]);
         uint64_t xj[W], m[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -384,27 +378,26 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         uint64_t xj[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
-        const uint64_t hj = A.khash[jj];
+        int pc[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            int pc = 0;
             if constexpr (NW) {
-                pc = __popc(static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]));
+                pc[r] = __popc(static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]));
             } else {
+                pc[r] = 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) pc += popc64(R.x[r][w] ^ xj[w]);
+                for (int w = 0; w < W; ++w) pc[r] += popc64(R.x[r][w] ^ xj[w]);
             }
-            const bool ok = valid & (pc <= A.maxpop);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const bool ok = valid & (pc[r] <= A.maxpop);
             const uint64_t mk = __ballot(ok);
             if (ok) {
-                const HT h = static_cast<HT>((R.hx[r] ^ T.salt) ^ hj);
                 const uint32_t meta = static_cast<uint32_t>(r) | (static_cast<uint32_t>(j) << 3);
-                if constexpr (NW)
-                    cb[cn + lanes_below(mk)] = make_uint2(static_cast<uint32_t>(h), meta);
-                else
-                    cb[cn + lanes_below(mk)] = make_uint4(static_cast<uint32_t>(h),
-                                                          static_cast<uint32_t>(static_cast<uint64_t>(h) >> 32),
-                                                          meta, 0u);
+                CEntry<NW> ce{};
+                ce.x = meta;
+                cb[cn + lanes_below(mk)] = ce;
             }
             cn += __popcll(mk);
             if (cn >= kWave) {
