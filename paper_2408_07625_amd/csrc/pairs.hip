@@ -848,18 +848,42 @@ __device__ __forceinline__ void trie_views(const PairArgs& A, int chunk, TrieVie
     V.n = min(static_cast<int64_t>(A.xy_chunk), static_cast<int64_t>(A.n_groups) - vbase);
 }
 
-template <int W, int PREC, bool ADJ>
+// Bytes of LDS that hold one XY chunk tree (nodes, node keys, keys).
+template <int W>
+__host__ __device__ inline size_t trie_chunk_bytes(int64_t chunk) {
+    const int64_t nn = chunk > 1 ? chunk - 1 : 0;
+    return static_cast<size_t>(nn) * sizeof(TNode) + static_cast<size_t>(nn + chunk) * W * sizeof(uint64_t);
+}
+constexpr size_t kTrieLdsMax = 48 * 1024;
+
+// STAGE: the workgroup first copies its XY chunk tree into LDS (when it fits
+// in kTrieLdsMax), so that the XY side of every walk step is an LDS read.
+template <int W, int PREC, bool ADJ, bool STAGE>
 __global__ __launch_bounds__(kTrieBlock) void k_pairs_trie(PairArgs A, const void* __restrict__ vec,
                                                            void* __restrict__ partial) {
     using P = Prec<PREC>;
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
-    if (row >= A.M) return;
-    uint64_t x[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
+    extern __shared__ uint64_t tsm[];
     TrieView U, V;
     int64_t vbase;
     trie_views<W>(A, blockIdx.y, U, V, vbase);
+    if constexpr (STAGE) {
+        const int64_t nn = V.n > 1 ? V.n - 1 : 0;
+        TNode* ln = reinterpret_cast<TNode*>(tsm);
+        uint64_t* lnk = reinterpret_cast<uint64_t*>(ln + nn);
+        uint64_t* lk = lnk + nn * W;
+        for (int64_t t = threadIdx.x; t < nn; t += kTrieBlock) ln[t] = V.nodes[t];
+        for (int64_t t = threadIdx.x; t < nn * W; t += kTrieBlock) lnk[t] = V.nkeys[t];
+        for (int64_t t = threadIdx.x; t < V.n * W; t += kTrieBlock) lk[t] = V.keys[t];
+        __syncthreads();
+        V.nodes = ln;
+        V.nkeys = lnk;
+        V.keys = lk;
+    }
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
+    if (row >= A.M) return;   // no barrier follows
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const auto* __restrict__ terms =
         static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
@@ -1000,7 +1024,11 @@ template <int W, int VARIANT, int PREC, bool ADJ, bool NW>
 hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
     if constexpr (VARIANT == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
-        hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+        const size_t lds = trie_chunk_bytes<W>(A.xy_chunk);
+        if (lds <= kTrieLdsMax)
+            hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, true>), grid, dim3(kTrieBlock), lds, st, A, vec, partial);
+        else
+            hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, false>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
     } else if (VARIANT == 3 && P.bloom_words > 0 && P.waves_per_block == 4) {
         constexpr int kW = 4;
         const size_t lds = sizeof(uint32_t) * P.bloom_words;
