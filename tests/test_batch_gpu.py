@@ -203,6 +203,35 @@ def test_weights_and_errors(pe, small_batch):
     b.run("fp64")
 
 
+def long_part_problem():
+    """20 qubits, a diagonal group of 70 000 Z strings (longer than the narrow
+    hit queue's 16-bit run lengths) plus random off-diagonal terms."""
+    rng = np.random.default_rng(12)
+    N = 20
+    off = jw.random_pauli(N, 200, rng, max_flip=4)
+    xy = np.concatenate([np.zeros(70000, np.uint64), off.xy[:, 0]])[:, None]
+    yz = np.concatenate([rng.choice(1 << N, size=70000, replace=False).astype(np.uint64), off.yz[:, 0]])[:, None]
+    ham = jw.PauliHamiltonian(N, np.concatenate([rng.normal(size=70000) * 1e-3, off.coeff]), xy, yz)
+    keys = rng.choice(1 << N, size=300, replace=False).astype(np.uint64)[:, None]
+    lp = rng.normal(size=300) * 0.2 + 1j * rng.uniform(0, 6.28, size=300)
+    return configs.Workload("long_part20", 0, ham, keys, lp, None)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32c", TOL32)])
+def test_long_group_part_in_batch(pe, small_batch, reference, precision, tol):
+    """A narrow batch with one problem whose group part is too long for the
+    narrow hit queue runs in the wide key format, and still matches."""
+    ws = [w for w in small_batch if w.n_qubits <= 32] + [long_part_problem()]
+    ref = [r for w, r in zip(small_batch, reference) if w.n_qubits <= 32]
+    w = ws[-1]
+    e, npairs = oracle.local_energy(w.ham, w.keys, w.logpsi, with_pairs=True)
+    E, var, tot = oracle.energy(e, w.logpsi, None)
+    ref.append((e, int(npairs.sum()), E, var, tot))
+    b = pe.Batch([as_problem(w) for w in ws])
+    b.run(precision)
+    check_against(b, ws, ref, tol)
+
+
 def test_tune_and_cache(pe, small_batch, reference, tmp_path):
     b = pe.Batch([as_problem(w) for w in small_batch])
     cache = tmp_path / "schedule.txt"

@@ -226,6 +226,32 @@ def test_random_pauli_odd_y(eng):
     np.testing.assert_allclose(h, oracle.matrix_elements(ham, keys[i], keys[j]), atol=1e-12)
 
 
+def test_long_group_part_uses_wide_format(eng):
+    """A diagonal group of 70 000 Z strings on 20 qubits: its real part is too
+    long for the 16-bit run lengths of the narrow hit queue, so the engine
+    takes the wide key format; results still match the oracle."""
+    rng = np.random.default_rng(11)
+    N = 20
+    yz_diag = rng.choice(1 << N, size=70000, replace=False).astype(np.uint64)
+    off = jw.random_pauli(N, 200, rng, max_flip=4)
+    xy = np.concatenate([np.zeros(70000, np.uint64), off.xy[:, 0]])[:, None]
+    yz = np.concatenate([yz_diag, off.yz[:, 0]])[:, None]
+    coeff = np.concatenate([rng.normal(size=70000) * 1e-3, off.coeff])
+    ham = jw.PauliHamiltonian(N, coeff, xy, yz)
+    keys = rng.choice(1 << N, size=300, replace=False).astype(np.uint64)[:, None]
+    lp = rng.normal(size=300) * 0.2 + 1j * rng.uniform(0, 6.28, size=300)
+    load(eng, ham, keys)
+    ref = oracle.local_energy(ham, keys, lp)
+    for variant in ("terms", "batch", "trie"):
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, _ = eng.local_energy(dev(lp), variant=variant, precision=prec)
+            assert np.abs(e.cpu().numpy() - ref).max() <= tol, (variant, prec)
+    ref_p = oracle_pairs(ham, keys)
+    for variant in ("terms", "batch", "trie"):
+        for a, b in zip(gpu_pairs(eng, variant), ref_p):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_deterministic(eng, small_workload):
     w = small_workload
     load(eng, w.ham, w.keys)
