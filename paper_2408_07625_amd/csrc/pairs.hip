@@ -879,11 +879,14 @@ __global__ __launch_bounds__(kTrieBlock) void k_pairs_trie(PairArgs A, const voi
         V.nkeys = lnk;
         V.keys = lk;
     }
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
-    if (row >= A.M) return;   // no barrier follows
+    // lanes take the rows in sorted key order: neighbouring lanes then walk
+    // similar paths (less divergence, shared cache lines)
+    const int64_t srow = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
+    if (srow >= A.M) return;   // no barrier follows
+    const int64_t row = A.u_perm[srow];
     uint64_t x[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
+    for (int w = 0; w < W; ++w) x[w] = A.u_keys[srow * W + w];
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const auto* __restrict__ terms =
         static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
