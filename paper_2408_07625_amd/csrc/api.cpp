@@ -208,8 +208,12 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     const std::vector<int32_t>& order = hh.order;
     const std::vector<uint64_t>& xsorted = hh.xsorted;
     const int maxpop = hh.maxpop, diag = hh.diag;
-    const int64_t xy_chunks_target = 16;
-    const int64_t xy_chunk = std::max<int64_t>(2, (G + xy_chunks_target - 1) / xy_chunks_target);
+    // LoopOverTrie walks U against one XY chunk tree per workgroup column:
+    // about 128 chunks of at least 64 masks (measured at the medium workload:
+    // 16 chunks 24 ms, 32: 19, 64: 16, 128 and 256: 14)
+    const int64_t xy_chunks_target = 128;
+    const int64_t xy_chunk = std::max<int64_t>(
+        2, std::max<int64_t>(std::min<int64_t>(G, 64), (G + xy_chunks_target - 1) / xy_chunks_target));
     const int64_t xy_chunks = (G + xy_chunk - 1) / xy_chunk;
     ELOC_HIP(c, c->xyt_keys.ensure(sizeof(uint64_t) * G * W));
     ELOC_HIP(c, c->xyt_gid.ensure(sizeof(int32_t) * G));
