@@ -43,8 +43,7 @@ struct eloc_batch_s {
     std::string err;
     int n = 0;
     int W = 1;
-    bool narrow = true;   // every problem has at most 32 qubits
-    int tk = kTabNarrow;  // membership-table format
+    int64_t kslot_bytes = 0;   // bytes of all key tables (each problem in its own format)
     int n_cu = 0;
     int64_t S = 0;
     uint64_t salt_state = 0xBA7C4ED5ull;
@@ -94,7 +93,6 @@ BatchDev dev_view(const eloc_batch b) {
     B.probs = b->probs.as<BatchProb>();
     B.n = b->n;
     B.W = b->W;
-    B.narrow = b->narrow;
     B.pid = b->pid.as<int32_t>();
     B.S = b->S;
     B.tiles = b->tiles_dev.as<RTile>();
@@ -105,9 +103,7 @@ BatchDev dev_view(const eloc_batch b) {
     B.keys = b->keys.as<uint64_t>();
     B.khash = b->khash.as<uint64_t>();
     B.slots = b->kslots.as<uint32_t>();
-    int64_t ns = 0;
-    for (uint64_t c : b->kcap) ns += static_cast<int64_t>(c);
-    B.n_slot_words = ns * static_cast<int64_t>(slot_bytes(b->tk) / sizeof(uint32_t));
+    B.n_slot_words = b->kslot_bytes / static_cast<int64_t>(sizeof(uint32_t));
     B.stash = b->kstash.as<Stash>();
     B.err = b->err_dev.as<uint32_t>();
     B.sigmin = b->sigmin.as<uint32_t>();
@@ -184,7 +180,7 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
 
 int launch_blocks(eloc_batch b, int precision) {
     int per_cu = b->schedule.blocks_per_cu;
-    const int fit = batch_blocks_per_cu(b->W, b->narrow, precision, b->schedule.rows_per_wave);
+    const int fit = batch_blocks_per_cu(b->W, precision, b->schedule.rows_per_wave);
     if (per_cu <= 0 || (fit > 0 && per_cu > fit)) per_cu = fit > 0 ? fit : 1;
     return std::max(1, per_cu * b->n_cu);
 }
@@ -229,14 +225,14 @@ int run(eloc_batch b, int precision) {
 
 // Group membership tables (LoopOverBatch), built once; a new salt is drawn if
 // an insertion does not settle.
-int build_group_table(eloc_batch b, const uint64_t* hash, int64_t n, void* slots, Stash* stash, uint64_t cap,
-                      Table* out) {
+int build_group_table(eloc_batch b, int tk, const uint64_t* hash, int64_t n, void* slots, Stash* stash,
+                      uint64_t cap, Table* out) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         Table T = make_table(slots, stash, cap, n, splitmix64(b->salt_state));
-        BATCH_HIP(b, hipMemset(slots, 0, slot_bytes(b->tk) * cap));
+        BATCH_HIP(b, hipMemset(slots, 0, slot_bytes(tk) * cap));
         BATCH_HIP(b, hipMemset(stash, 0, sizeof(Stash)));
         BATCH_HIP(b, hipMemset(b->err_dev.p, 0, sizeof(uint32_t)));
-        BATCH_HIP(b, launch_table_insert(b->tk, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
+        BATCH_HIP(b, launch_table_insert(tk, hash, n, slots, stash, T, b->err_dev.as<uint32_t>(), nullptr));
         BATCH_HIP(b, hipMemcpy(b->err_host, b->err_dev.p, sizeof(uint32_t), hipMemcpyDeviceToHost));
         if (!(b->err_host[0] & kErrTable)) {
             *out = T;
@@ -261,10 +257,14 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
             }
         const std::string why = build_host_ham<W>(b->R, p.n_terms, p.coeff, xy.data(), yz.data(), hh[static_cast<size_t>(k)]);
         if (!why.empty()) return bfail(b, ELOC_EINVAL, "problem " + std::to_string(k) + ": " + why);
-        if (hh[static_cast<size_t>(k)].maxpart >= kNarrowMaxPart && b->narrow) {
-            b->narrow = false;   // the hit queue's narrow entries hold 16-bit run lengths
-            b->tk = table_kind(W, false);
-        }
+    }
+    // each problem's table format: narrow for one-word batches of problems of
+    // at most 32 qubits whose group parts fit the narrow hit queue's 16 bits
+    std::vector<int> tk(static_cast<size_t>(n));
+    for (int k = 0; k < n; ++k) {
+        const bool nar = W == 1 && probs[k].n_qubits <= 32 && hh[static_cast<size_t>(k)].maxpart < kNarrowMaxPart;
+        tk[static_cast<size_t>(k)] = table_kind(W, nar);
+        b->desc[static_cast<size_t>(k)].narrow = nar ? 1 : 0;
     }
     int64_t nt = 0, ng = 0, gcap = 0, kc = 0;
     std::vector<int64_t> toff(static_cast<size_t>(n)), goff(static_cast<size_t>(n)), gcoff(static_cast<size_t>(n)),
@@ -275,23 +275,25 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         const HostHam<W>& h = hh[static_cast<size_t>(k)];
         toff[static_cast<size_t>(k)] = nt;
         goff[static_cast<size_t>(k)] = ng;
-        gcoff[static_cast<size_t>(k)] = gcap;
+        gcoff[static_cast<size_t>(k)] = gcap;   // bytes
         kcoff[static_cast<size_t>(k)] = kc;
         nt += h.n_terms;
         ng += h.G;
+        const int64_t sb = static_cast<int64_t>(slot_bytes(tk[static_cast<size_t>(k)]));
         gc[static_cast<size_t>(k)] = table_capacity(h.G);
-        gcap += static_cast<int64_t>(gc[static_cast<size_t>(k)]);
+        gcap += sb * static_cast<int64_t>(gc[static_cast<size_t>(k)]);
         b->kcap[static_cast<size_t>(k)] = table_capacity(probs[k].n_unique);
-        kc += static_cast<int64_t>(b->kcap[static_cast<size_t>(k)]);
+        kc += sb * static_cast<int64_t>(b->kcap[static_cast<size_t>(k)]);
     }
     BATCH_HIP(b, b->groups.ensure(sizeof(GroupRec<W>) * ng));
     BATCH_HIP(b, b->ghash.ensure(sizeof(uint64_t) * ng));
     BATCH_HIP(b, b->gkeys.ensure(sizeof(uint64_t) * ng * W));
     BATCH_HIP(b, b->terms.ensure(sizeof(TermRec<W>) * nt));
     BATCH_HIP(b, b->terms_f.ensure(sizeof(TermRecF<W>) * nt));
-    BATCH_HIP(b, b->gslots.ensure(slot_bytes(b->tk) * gcap));
+    BATCH_HIP(b, b->gslots.ensure(static_cast<size_t>(gcap)));
     BATCH_HIP(b, b->gstash.ensure(sizeof(Stash) * n));
-    BATCH_HIP(b, b->kslots.ensure(slot_bytes(b->tk) * kc));
+    BATCH_HIP(b, b->kslots.ensure(static_cast<size_t>(kc)));
+    b->kslot_bytes = kc;
     BATCH_HIP(b, b->kstash.ensure(sizeof(Stash) * n));
     auto* groups = b->groups.as<GroupRec<W>>();
     auto* terms = b->terms.as<TermRec<W>>();
@@ -314,9 +316,10 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         D.terms = terms + to;
         D.terms_f = terms_f + to;
         D.gkeys = b->gkeys.as<uint64_t>() + go * W;
-        void* gs = b->gslots.as<char>() + slot_bytes(b->tk) * static_cast<size_t>(gcoff[static_cast<size_t>(k)]);
+        void* gs = b->gslots.as<char>() + static_cast<size_t>(gcoff[static_cast<size_t>(k)]);
         Stash* gst = b->gstash.as<Stash>() + k;
-        const int rc = build_group_table(b, D.ghash, h.G, gs, gst, gc[static_cast<size_t>(k)], &D.gtable);
+        const int rc =
+            build_group_table(b, tk[static_cast<size_t>(k)], D.ghash, h.G, gs, gst, gc[static_cast<size_t>(k)], &D.gtable);
         if (rc) return rc;
         D.n_groups = static_cast<int32_t>(h.G);
         D.maxpop = h.maxpop;
@@ -324,7 +327,7 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
         I.n_terms = h.n_terms;
         I.G = h.G;
         I.maxpop = h.maxpop;
-        D.kslots = b->kslots.as<char>() + slot_bytes(b->tk) * static_cast<size_t>(kcoff[static_cast<size_t>(k)]);
+        D.kslots = b->kslots.as<char>() + static_cast<size_t>(kcoff[static_cast<size_t>(k)]);
         D.kstash = b->kstash.as<Stash>() + k;
         D.ktable = make_table(D.kslots, D.kstash, b->kcap[static_cast<size_t>(k)], I.M, splitmix64(b->salt_state));
     }
@@ -473,7 +476,6 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
             if (!std::isfinite(p.coeff[l])) return bfail(b, ELOC_EINVAL, pre + "non-finite coefficient");
         }
         W = std::max(W, wk);
-        b->narrow = b->narrow && p.n_qubits <= 32;
         ProbInfo& I = b->info[static_cast<size_t>(k)];
         I.n_qubits = p.n_qubits;
         I.M = p.n_unique;
@@ -490,7 +492,6 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
         S += p.n_unique;
     }
     b->W = W;
-    b->tk = table_kind(W, b->narrow);
     b->S = S;
     // reduction tiles and the sample -> problem map
     std::vector<int32_t> pid(static_cast<size_t>(S));
@@ -661,7 +662,7 @@ int eloc_batch_tune(eloc_batch b, int precision, const char* cache_path, int* fr
         if (t.batch_ratio != best.batch_ratio) rc = trial(t);
     }
     {
-        const int fit = batch_blocks_per_cu(b->W, b->narrow, precision, best.rows_per_wave);
+        const int fit = batch_blocks_per_cu(b->W, precision, best.rows_per_wave);
         for (int bpc : {fit / 2, fit}) {
             if (rc || bpc < 1) continue;
             eloc_batch_schedule t = best;

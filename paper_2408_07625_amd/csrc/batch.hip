@@ -160,6 +160,31 @@ __global__ __launch_bounds__(kBlock) void k_bt_insert(BatchDev B) {
                         static_cast<uint32_t>(kErrTable));
 }
 
+// one-word keys: each problem's key table in its own format (narrow or wide)
+__global__ __launch_bounds__(kBlock) void k_bt_insert1(BatchDev B) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= B.S) return;
+    const int k = B.pid[i];
+    const BatchProb& P = B.probs[k];
+    if (P.narrow)
+        table_insert_one<kTabNarrow>(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
+                                     static_cast<uint32_t>(kErrTable));
+    else
+        table_insert_one<kTabWide>(B.khash + P.s0, i - P.s0, P.kslots, P.kstash, P.ktable, B.err + k,
+                                   static_cast<uint32_t>(kErrTable));
+}
+
+__global__ __launch_bounds__(kBlock) void k_bt_verify1(BatchDev B) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= B.S) return;
+    const int k = B.pid[i];
+    const BatchProb& P = B.probs[k];
+    const uint64_t key[1] = {B.keys[i]};
+    const int j = P.narrow ? table_find<kTabNarrow, 1>(P.ktable, B.keys + P.s0, B.khash[i], key)
+                           : table_find<kTabWide, 1>(P.ktable, B.keys + P.s0, B.khash[i], key);
+    if (j != static_cast<int>(i - P.s0)) atomicOr(B.err + k, static_cast<uint32_t>(kErrDup));
+}
+
 // every key must find itself (U unique)
 template <int W, int TK>
 __global__ __launch_bounds__(kBlock) void k_bt_verify(BatchDev B) {
@@ -369,13 +394,8 @@ hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st) {
         hipLaunchKernelGGL(k_bt_hash<1>, grid, block, 0, st, B);
         hipLaunchKernelGGL(k_bt_radius_ref, dim3(blocks_for(B.n)), block, 0, st, B);
         hipLaunchKernelGGL(k_bt_radius_max<1>, grid, block, 0, st, B);
-        if (B.narrow) {
-            hipLaunchKernelGGL(k_bt_insert<kTabNarrow>, grid, block, 0, st, B);
-            hipLaunchKernelGGL((k_bt_verify<1, kTabNarrow>), grid, block, 0, st, B);
-        } else {
-            hipLaunchKernelGGL(k_bt_insert<kTabWide>, grid, block, 0, st, B);
-            hipLaunchKernelGGL((k_bt_verify<1, kTabWide>), grid, block, 0, st, B);
-        }
+        hipLaunchKernelGGL(k_bt_insert1, grid, block, 0, st, B);
+        hipLaunchKernelGGL(k_bt_verify1, grid, block, 0, st, B);
     }
     hipLaunchKernelGGL(k_bt_minmax, dim3(static_cast<unsigned>(B.n_tiles)), dim3(kBlock), 0, st, B);
     hipLaunchKernelGGL(k_bt_shift, dim3(blocks_for(B.n)), dim3(kBlock), 0, st, B, fp32 ? 1 : 0);

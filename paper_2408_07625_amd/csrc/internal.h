@@ -418,7 +418,7 @@ struct BatchProb {
     // caller buffers (device)
     const uint64_t* keys_in;   // [M][w_in]
     int32_t w_in;
-    int32_t pad;
+    int32_t narrow;            // one-word narrow tables and hit queue (at most 32 qubits, short runs)
     const double2* logpsi;
     const double* weights;     // null: |psi|^2 weights
     double2* eloc;
@@ -436,7 +436,6 @@ struct BatchDev {
     const BatchProb* probs;
     int n;
     int W;
-    bool narrow;               // every problem has at most 32 qubits
     const int32_t* pid;        // [S] problem of every global sample
     int64_t S;
     const RTile* tiles;
@@ -539,7 +538,7 @@ int rows_per_block(int variant, int requested);
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
 hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st);
 hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st);
-int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
+int batch_blocks_per_cu(int W, int precision, int rows);
 
 
 int64_t energy_scratch_len();

@@ -746,14 +746,42 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 // problem's partial offset.  Every wave leaves the loop when the counter
 // passes the last item.
 // ---------------------------------------------------------------------------
+// One work item of the batched kernel: the forward row kernel over a row
+// tile and chunk of problem D, with the problem's own tables, variant and
+// signature filter (NW: the problem's narrow format).  Returns the coupled
+// pairs of the tile's rows inside U.
 template <int W, int PREC, int NR, bool NW>
+__device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, NR>& R, const BatchProb& D, int chunk,
+                                              bool sig, const void* vec_all, typename Prec<PREC>::Acc* acc,
+                                              uint4* qraw, uint4* cbraw, const uint64_t* rowkey) {
+    using P = Prec<PREC>;
+    AccSink<W, PREC, false, NR, NW> sink;
+    sink.groups = static_cast<const GroupRec<W>*>(A.groups);
+    sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
+    sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
+    sink.q = reinterpret_cast<QEntry<NW>*>(qraw);
+    sink.acc = acc;
+    sink.rowkey = rowkey;
+    sink.nrows = R.n;
+    CEntry<NW>* cb = reinterpret_cast<CEntry<NW>*>(cbraw);
+    if (D.variant == 1)
+        find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
+    else if (sig)
+        find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
+    else
+        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
+    sink.finish();
+    return sink.hits;
+}
+
+template <int W, int PREC, int NR>
 __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void* __restrict__ vec_all,
                                                          void* __restrict__ partial_all) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     __shared__ uint64_t rowkey[NR * W];
-    __shared__ QEntry<NW> q[2 * kWave];
-    __shared__ CEntry<NW> cb[2 * kWave];
+    __shared__ uint4 q[2 * kWave];    // QEntry of either format
+    __shared__ uint4 cb[2 * kWave];   // CEntry of either format
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kAccCols];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
@@ -806,28 +834,22 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         load_rows<W, NR>(A, R, rowkey, tile);
         for (int i = lane; i < NR * kAccCols; i += kWave) acc[i] = Acc{};
         wave_sync();
-        AccSink<W, PREC, false, NR, NW> sink;
-        sink.groups = static_cast<const GroupRec<W>*>(A.groups);
-        sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
-        sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
-        sink.q = q;
-        sink.acc = acc;
-        sink.rowkey = rowkey;
-        sink.nrows = R.n;
-        if (D.variant == 1)
-            find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
-        else if (sig)
-            find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
-        else
-            find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
-        sink.finish();
+        int64_t hits;
+        if constexpr (W == 1) {
+            if (__builtin_amdgcn_readfirstlane(D.narrow))
+                hits = batch_item<W, PREC, NR, true>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
+            else
+                hits = batch_item<W, PREC, NR, false>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
+        } else {
+            hits = batch_item<W, PREC, NR, false>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
+        }
         if (lane < R.n) {
             Acc s{};
             for (int l = 0; l < kAccCols; ++l) acc_plus(s, acc[lane * kAccCols + l]);
             auto* part = static_cast<double2*>(partial_all) + D.pbase;
             store_acc(part, static_cast<int64_t>(chunk) * D.M + R.row0 + lane, s);
         }
-        if (lane == 0) atomicAdd(B.pairs + k, static_cast<unsigned long long>(sink.hits));
+        if (lane == 0) atomicAdd(B.pairs + k, static_cast<unsigned long long>(hits));
         wave_sync();
     }
 }
@@ -1093,25 +1115,24 @@ hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& 
                    : dispatch_width<false>(H, variant, precision, A, P, v, partial, st);
 }
 
-template <int W, int PREC, int NR, bool NW>
+template <int W, int PREC, int NR>
 static const void* batch_kernel_ptr() {
-    return reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR, NW>);
+    return reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR>);
 }
 
-template <int W, bool NW>
+template <int W>
 static const void* batch_kernel_w(int precision, int rows) {
-    if (precision == 0) return rows == 4 ? batch_kernel_ptr<W, 0, 4, NW>() : batch_kernel_ptr<W, 0, 8, NW>();
-    return rows == 4 ? batch_kernel_ptr<W, 1, 4, NW>() : batch_kernel_ptr<W, 1, 8, NW>();
+    if (precision == 0) return rows == 4 ? batch_kernel_ptr<W, 0, 4>() : batch_kernel_ptr<W, 0, 8>();
+    return rows == 4 ? batch_kernel_ptr<W, 1, 4>() : batch_kernel_ptr<W, 1, 8>();
 }
 
-static const void* batch_kernel(int W, bool narrow, int precision, int rows) {
-    if (W == 2) return batch_kernel_w<2, false>(precision, rows);
-    return narrow ? batch_kernel_w<1, true>(precision, rows) : batch_kernel_w<1, false>(precision, rows);
+static const void* batch_kernel(int W, int precision, int rows) {
+    return W == 2 ? batch_kernel_w<2>(precision, rows) : batch_kernel_w<1>(precision, rows);
 }
 
-int batch_blocks_per_cu(int W, bool narrow, int precision, int rows) {
+int batch_blocks_per_cu(int W, int precision, int rows) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, narrow, precision, rows), kWave, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, precision, rows), kWave, 0) !=
         hipSuccess)
         return 0;
     return n;
@@ -1121,7 +1142,7 @@ hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int bl
     const void* vec = precision == 0 ? static_cast<const void*>(B.a) : static_cast<const void*>(B.af);
     void* part = B.partial;
     void* args[] = {const_cast<BatchDev*>(&B), &vec, &part};
-    return hipLaunchKernel(batch_kernel(B.W, B.narrow, precision, rows), dim3(static_cast<unsigned>(blocks)),
+    return hipLaunchKernel(batch_kernel(B.W, precision, rows), dim3(static_cast<unsigned>(blocks)),
                            dim3(kWave), args, 0, st);
 }
 
