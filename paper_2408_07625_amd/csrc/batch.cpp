@@ -60,6 +60,7 @@ struct eloc_batch_s {
 
     eloc_batch_schedule schedule{};
     int64_t total_items = 0;
+    int64_t narrow_items = 0;   // items of the narrow problems, scheduled first
     bool use_graph = true;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
@@ -99,6 +100,7 @@ BatchDev dev_view(const eloc_batch b) {
     B.n_tiles = static_cast<int>(b->tiles.size());
     B.sched = b->sched.as<int32_t>();
     B.total_items = b->total_items;
+    B.narrow_items = b->narrow_items;
     B.R = b->R_dev.as<uint64_t>();
     B.keys = b->keys.as<uint64_t>();
     B.khash = b->khash.as<uint64_t>();
@@ -156,11 +158,15 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
     if (s.order == 0)
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return cost[static_cast<size_t>(x)] > cost[static_cast<size_t>(y)]; });
-    int64_t item = 0;
+    // narrow problems first: their items run in the narrow kernel
+    std::stable_partition(order.begin(), order.end(),
+                          [&](int32_t k) { return b->desc[static_cast<size_t>(k)].narrow != 0; });
+    int64_t item = 0, narrow_items = 0;
     for (int32_t k : order) {
         BatchProb& D = b->desc[static_cast<size_t>(k)];
         D.item0 = item;
         item += D.items;
+        if (D.narrow) narrow_items = item;
     }
     if (item >= (int64_t(1) << 31)) return bfail(b, ELOC_EINVAL, "too many work items; raise item_candidates");
     int64_t pbase = 0;
@@ -173,14 +179,15 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
     BATCH_HIP(b, hipMemcpy(b->probs.p, b->desc.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice));
     BATCH_HIP(b, hipMemcpy(b->sched.p, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     b->total_items = item;
+    b->narrow_items = narrow_items;
     b->schedule = s;
     drop_graphs(b);
     return ELOC_OK;
 }
 
-int launch_blocks(eloc_batch b, int precision) {
+int launch_blocks(eloc_batch b, int precision, bool narrow) {
     int per_cu = b->schedule.blocks_per_cu;
-    const int fit = batch_blocks_per_cu(b->W, precision, b->schedule.rows_per_wave);
+    const int fit = batch_blocks_per_cu(b->W, narrow, precision, b->schedule.rows_per_wave);
     if (per_cu <= 0 || (fit > 0 && per_cu > fit)) per_cu = fit > 0 ? fit : 1;
     return std::max(1, per_cu * b->n_cu);
 }
@@ -188,7 +195,8 @@ int launch_blocks(eloc_batch b, int precision) {
 int enqueue(eloc_batch b, int precision, hipStream_t st) {
     const BatchDev B = dev_view(b);
     BATCH_HIP(b, launch_batch_prepare(B, precision == ELOC_FP32C, st));
-    BATCH_HIP(b, launch_batch_pairs(B, precision, b->schedule.rows_per_wave, launch_blocks(b, precision), st));
+    BATCH_HIP(b, launch_batch_pairs(B, precision, b->schedule.rows_per_wave, launch_blocks(b, precision, true),
+                                    launch_blocks(b, precision, false), st));
     BATCH_HIP(b, launch_batch_finish(B, precision, st));
     return ELOC_OK;
 }
@@ -525,7 +533,7 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
     BATCH_HIP(b, b->scal.ensure(sizeof(double) * 3 * n));
     BATCH_HIP(b, b->part.ensure(sizeof(double) * 3 * nt));
     BATCH_HIP(b, b->pairs.ensure(sizeof(unsigned long long) * n));
-    BATCH_HIP(b, b->work.ensure(sizeof(unsigned int)));
+    BATCH_HIP(b, b->work.ensure(2 * sizeof(unsigned int)));
     BATCH_HIP(b, b->a.ensure(sizeof(double2) * S));
     BATCH_HIP(b, b->b.ensure(sizeof(double2) * S));
     BATCH_HIP(b, b->af.ensure(sizeof(float4) * S));
@@ -662,7 +670,8 @@ int eloc_batch_tune(eloc_batch b, int precision, const char* cache_path, int* fr
         if (t.batch_ratio != best.batch_ratio) rc = trial(t);
     }
     {
-        const int fit = batch_blocks_per_cu(b->W, precision, best.rows_per_wave);
+        const int fit = batch_blocks_per_cu(b->W, b->narrow_items < b->total_items ? false : true, precision,
+                                            best.rows_per_wave);
         for (int bpc : {fit / 2, fit}) {
             if (rc || bpc < 1) continue;
             eloc_batch_schedule t = best;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_bt_clear(BatchDev B) {
         B.sigmax[t0] = 0u;
         B.pairs[t0] = 0ull;
     }
-    if (t0 == 0) *B.work = 0u;
+    if (t0 < 2) B.work[t0] = 0u;
 }
 
 // Copy of the caller keys (words beyond the problem's own are zero), linear

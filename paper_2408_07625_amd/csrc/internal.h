@@ -457,7 +457,8 @@ struct BatchDev {
     double* scal;              // [n][3] E re, E im, sum w
     double* part;              // [n_tiles][3] reduction partials
     unsigned long long* pairs; // [n] coupled pairs found
-    unsigned int* work;        // work-item counter
+    unsigned int* work;        // work-item counters [2]: narrow items, wide items
+    int64_t narrow_items;      // items [0, narrow_items) belong to narrow problems
     double2* a;
     double2* b;
     float4* af;
@@ -536,9 +537,10 @@ int rows_per_block(int variant, int requested);
 
 // Batched pipeline (batch.hip; the persistent pair kernel in pairs.hip).
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
-hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st);
+hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int narrow_blocks, int wide_blocks,
+                              hipStream_t st);
 hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st);
-int batch_blocks_per_cu(int W, int precision, int rows);
+int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
 
 
 int64_t energy_scratch_len();

@@ -752,36 +752,37 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 // pairs of the tile's rows inside U.
 template <int W, int PREC, int NR, bool NW>
 __device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, NR>& R, const BatchProb& D, int chunk,
-                                              bool sig, const void* vec_all, typename Prec<PREC>::Acc* acc,
-                                              uint4* qraw, uint4* cbraw, const uint64_t* rowkey) {
+                                              const void* vec_all, typename Prec<PREC>::Acc* acc,
+                                              QEntry<NW>* q, CEntry<NW>* cb, const uint64_t* rowkey) {
     using P = Prec<PREC>;
     AccSink<W, PREC, false, NR, NW> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
-    sink.q = reinterpret_cast<QEntry<NW>*>(qraw);
+    sink.q = q;
     sink.acc = acc;
     sink.rowkey = rowkey;
     sink.nrows = R.n;
-    CEntry<NW>* cb = reinterpret_cast<CEntry<NW>*>(cbraw);
+    // one LoopOverTerms body: without a usable prefilter the problem has
+    // sig_all set and rad_max 128, which every candidate passes
     if (D.variant == 1)
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
-    else if (sig)
-        find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
     else
-        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
+        find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
     sink.finish();
     return sink.hits;
 }
 
-template <int W, int PREC, int NR>
+// NW: the kernel takes the items of the narrow problems, [0, narrow_items),
+// from counter 0; else the rest from counter 1.
+template <int W, int PREC, int NR, bool NW>
 __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void* __restrict__ vec_all,
                                                          void* __restrict__ partial_all) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     __shared__ uint64_t rowkey[NR * W];
-    __shared__ uint4 q[2 * kWave];    // QEntry of either format
-    __shared__ uint4 cb[2 * kWave];   // CEntry of either format
+    __shared__ QEntry<NW> q[2 * kWave];
+    __shared__ CEntry<NW> cb[2 * kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_raw[NR * kAccCols];
     Acc* acc = reinterpret_cast<Acc*>(acc_raw);
@@ -793,11 +794,13 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         const int p = c * kWave + lane;
         istart[c] = p < B.n ? B.probs[B.sched[p]].item0 : INT64_MAX;
     }
+    const int64_t first = NW ? 0 : B.narrow_items;
+    const int64_t last = NW ? B.narrow_items : B.total_items;
     for (;;) {
         unsigned int t0 = 0u;
-        if (lane == 0) t0 = atomicAdd(B.work, 1u);
-        const int64_t t = static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(t0)));
-        if (t >= B.total_items) break;
+        if (lane == 0) t0 = atomicAdd(B.work + (NW ? 0 : 1), 1u);
+        const int64_t t = first + static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(t0)));
+        if (t >= last) break;
         int pos = -1;
 #pragma unroll
         for (int c = 0; c < kSlices; ++c) pos += __popcll(__ballot(istart[c] <= t));
@@ -825,7 +828,6 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         A.rad_ref[1] = B.rad[3 * k + 1];
         const int rmax = static_cast<int>(B.rad[3 * k + 2]);
         A.rad_max = 2 * rmax < D.n_qubits ? rmax : 128;
-        const bool sig = !A.sig_all || A.rad_max < 128;
         read_stash_counts(A);
         const int64_t u = t - D.item0;
         const int64_t tile = u / D.chunks;
@@ -834,15 +836,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         load_rows<W, NR>(A, R, rowkey, tile);
         for (int i = lane; i < NR * kAccCols; i += kWave) acc[i] = Acc{};
         wave_sync();
-        int64_t hits;
-        if constexpr (W == 1) {
-            if (__builtin_amdgcn_readfirstlane(D.narrow))
-                hits = batch_item<W, PREC, NR, true>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
-            else
-                hits = batch_item<W, PREC, NR, false>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
-        } else {
-            hits = batch_item<W, PREC, NR, false>(A, R, D, chunk, sig, vec_all, acc, q, cb, rowkey);
-        }
+        const int64_t hits = batch_item<W, PREC, NR, NW>(A, R, D, chunk, vec_all, acc, q, cb, rowkey);
         if (lane < R.n) {
             Acc s{};
             for (int l = 0; l < kAccCols; ++l) acc_plus(s, acc[lane * kAccCols + l]);
@@ -1115,35 +1109,45 @@ hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& 
                    : dispatch_width<false>(H, variant, precision, A, P, v, partial, st);
 }
 
-template <int W, int PREC, int NR>
+template <int W, int PREC, int NR, bool NW>
 static const void* batch_kernel_ptr() {
-    return reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR>);
+    return reinterpret_cast<const void*>(&k_pairs_batched<W, PREC, NR, NW>);
 }
 
-template <int W>
+template <int W, bool NW>
 static const void* batch_kernel_w(int precision, int rows) {
-    if (precision == 0) return rows == 4 ? batch_kernel_ptr<W, 0, 4>() : batch_kernel_ptr<W, 0, 8>();
-    return rows == 4 ? batch_kernel_ptr<W, 1, 4>() : batch_kernel_ptr<W, 1, 8>();
+    if (precision == 0) return rows == 4 ? batch_kernel_ptr<W, 0, 4, NW>() : batch_kernel_ptr<W, 0, 8, NW>();
+    return rows == 4 ? batch_kernel_ptr<W, 1, 4, NW>() : batch_kernel_ptr<W, 1, 8, NW>();
 }
 
-static const void* batch_kernel(int W, int precision, int rows) {
-    return W == 2 ? batch_kernel_w<2>(precision, rows) : batch_kernel_w<1>(precision, rows);
+static const void* batch_kernel(int W, bool narrow, int precision, int rows) {
+    if (W == 2) return batch_kernel_w<2, false>(precision, rows);
+    return narrow ? batch_kernel_w<1, true>(precision, rows) : batch_kernel_w<1, false>(precision, rows);
 }
 
-int batch_blocks_per_cu(int W, int precision, int rows) {
+int batch_blocks_per_cu(int W, bool narrow, int precision, int rows) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, precision, rows), kWave, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel(W, W == 1 && narrow, precision, rows), kWave,
+                                                     0) !=
         hipSuccess)
         return 0;
     return n;
 }
 
-hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int blocks, hipStream_t st) {
+hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int narrow_blocks, int wide_blocks,
+                              hipStream_t st) {
     const void* vec = precision == 0 ? static_cast<const void*>(B.a) : static_cast<const void*>(B.af);
     void* part = B.partial;
     void* args[] = {const_cast<BatchDev*>(&B), &vec, &part};
-    return hipLaunchKernel(batch_kernel(B.W, precision, rows), dim3(static_cast<unsigned>(blocks)),
-                           dim3(kWave), args, 0, st);
+    if (B.narrow_items > 0) {
+        const hipError_t e = hipLaunchKernel(batch_kernel(B.W, true, precision, rows),
+                                             dim3(static_cast<unsigned>(narrow_blocks)), dim3(kWave), args, 0, st);
+        if (e != hipSuccess) return e;
+    }
+    if (B.total_items > B.narrow_items)
+        return hipLaunchKernel(batch_kernel(B.W, false, precision, rows), dim3(static_cast<unsigned>(wide_blocks)),
+                               dim3(kWave), args, 0, st);
+    return hipSuccess;
 }
 
 template <int W, bool NW>
