@@ -146,6 +146,9 @@ Plan make_plan(const eloc_ctx c, int variant) {
     const int64_t span = (variant == ELOC_TERMS) ? c->H.n_groups : M;
     const int64_t steps = (span + 63) / 64;
     int64_t chunks = c->tune_chunks > 0 ? c->tune_chunks : (target + waves - 1) / waves;
+    // LoopOverBatch: a multiple of eight chunks, one set per XCD (the kernel
+    // maps workgroup id mod chunks to the chunk)
+    if (variant == ELOC_BATCH && c->tune_chunks <= 0) chunks = (std::max<int64_t>(chunks, 8) + 7) / 8 * 8;
     chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, steps));
     const int64_t per_steps = (steps + chunks - 1) / chunks;
     const int64_t per = per_steps * 64;

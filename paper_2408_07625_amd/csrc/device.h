@@ -273,35 +273,6 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
     return *reinterpret_cast<double*>(&q);
 }
 
-__device__ __forceinline__ AccD shfl_xor_acc(const AccD& a, int m) {
-    AccD o;
-    o.re = shfl_xor_d(a.re, m);
-    o.im = shfl_xor_d(a.im, m);
-    return o;
-}
-__device__ __forceinline__ AccF shfl_xor_acc(const AccF& a, int m) {
-    AccF o;
-    o.re.s = __shfl_xor(a.re.s, m, 64);
-    o.re.c = __shfl_xor(a.re.c, m, 64);
-    o.im.s = __shfl_xor(a.im.s, m, 64);
-    o.im.c = __shfl_xor(a.im.c, m, 64);
-    return o;
-}
-
-// Value of lane k's v in every lane (k wave-uniform).
-template <class T>
-__device__ __forceinline__ T lane_value(const T& v, int k) {
-    static_assert(sizeof(T) % 4 == 0, "32-bit words");
-    constexpr int n = sizeof(T) / 4;
-    int w[n];
-    __builtin_memcpy(w, &v, sizeof(T));
-#pragma unroll
-    for (int i = 0; i < n; ++i) w[i] = __builtin_amdgcn_readlane(w[i], k);
-    T o;
-    __builtin_memcpy(&o, w, sizeof(T));
-    return o;
-}
-
 // Value of lane k's v in this lane (k per lane).
 template <class T>
 __device__ __forceinline__ T lane_shfl(const T& v, int k) {

@@ -61,6 +61,7 @@ struct PairArgs {
     int gstash;
     int64_t M;
     int per_chunk;
+    int chunks;      // LoopOverBatch forward / adjoint: chunks of the 1-D grid
     // prefix trees
     const uint64_t* u_keys;
     const int32_t* u_perm;
@@ -97,6 +98,7 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.bloom_mask = P.bloom_words ? P.bloom_words - 1u : 0u;
     a.M = S.n;
     a.per_chunk = P.per_chunk;
+    a.chunks = P.chunks;
     a.u_keys = S.ut.keys;
     a.u_perm = S.ut.perm;
     a.u_nodes = S.ut.nodes;
@@ -653,7 +655,10 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 // ---------------------------------------------------------------------------
 // WPB waves per workgroup, each owning its own row tile (tile = blockIdx.x *
 // WPB + wave); with WPB > 1 the waves share U's Bloom filter, staged in LDS
-// (dynamic shared memory) once per workgroup.
+// (dynamic shared memory) once per workgroup.  LoopOverBatch runs on a 1-D
+// grid with chunk = workgroup id mod chunks: workgroups go to the eight XCDs
+// in turn, so with a multiple of eight chunks each XCD streams only its own
+// chunks of U through its L2.
 template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB>
 __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                        void* __restrict__ partial) {
@@ -671,7 +676,12 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
         for (uint32_t t = threadIdx.x; t < A.bloom_words; t += kWave * WPB) lfilt[t] = A.bloom[t];
         __syncthreads();
     }
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * WPB + wave;
+    int64_t tile = static_cast<int64_t>(blockIdx.x) * WPB + wave;
+    int chunk = static_cast<int>(blockIdx.y);
+    if constexpr (VARIANT == 1) {
+        chunk = static_cast<int>(blockIdx.x % static_cast<unsigned>(A.chunks));
+        tile = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(A.chunks));
+    }
     if (tile * NR >= A.M) return;   // no block-wide barrier follows
     uint64_t* rowkey = rowkey_s[wave];
     Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
@@ -687,13 +697,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     sink.q = q_s[wave];
     sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT, NR, NW, BL>(A, R, blockIdx.y, sink, cb_s[wave], rowkey, lfilt);
+    find<W, VARIANT, NR, NW, BL>(A, R, chunk, sink, cb_s[wave], rowkey, lfilt);
     sink.finish();
     // per-row totals: lane r adds the columns of row r in order
     if (lane_id() < R.n) {
         Acc t{};
         for (int l = 0; l < kAccCols; ++l) acc_plus(t, acc[lane_id() * kAccCols + l]);
-        store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + R.row0 + lane_id(), t);
+        store_acc(partial, static_cast<int64_t>(chunk) * A.M + R.row0 + lane_id(), t);
     }
 }
 
@@ -1062,9 +1072,11 @@ hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, voi
         }
     } else if (P.rows_per_block == 4) {
         dim3 grid(div_up(A.M, 4), static_cast<unsigned>(P.chunks));
+        if (VARIANT == 1) grid = dim3(div_up(A.M, 4) * static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
+        if (VARIANT == 1) grid = dim3(div_up(A.M, kRows) * static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();
