@@ -39,6 +39,7 @@ struct eloc_ctx_s {
     SampleDev S;
     DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad, bloom;
     uint32_t bloom_words = 0;   // Bloom filter of U (0: none)
+    bool bloom_built = false;   // built on first use by a kernel that reads it
     DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
     bool ut_valid = false;
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
@@ -302,6 +303,14 @@ int check_ready(eloc_ctx c) {
     if (!c) return ELOC_EINVAL;
     if (!c->ham_set) return fail(c, ELOC_ESTATE, "no Hamiltonian set");
     if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
+    // U's Bloom filter is built only when the tuning asks for it
+    if (c->tune_bloom && c->bloom_words && !c->bloom_built) {
+        ELOC_HIP(c, c->bloom.ensure(sizeof(uint32_t) * c->bloom_words));
+        ELOC_HIP(c, hipMemsetAsync(c->bloom.p, 0, sizeof(uint32_t) * c->bloom_words, c->stream));
+        ELOC_HIP(c, launch_bloom_build(c->khash.as<uint64_t>(), c->S.n, c->bloom.as<uint32_t>(), c->bloom_words,
+                                       c->stream));
+        c->bloom_built = true;
+    }
     return ELOC_OK;
 }
 
@@ -547,12 +556,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
                          ? static_cast<uint32_t>(std::min<uint64_t>(kBloomMaxWords,
                                                                     std::max<uint64_t>(256, pow2_at_least(n_unique / 8))))
                          : 0u;
-    if (c->bloom_words) {
-        ELOC_HIP(c, c->bloom.ensure(sizeof(uint32_t) * c->bloom_words));
-        ELOC_HIP(c, hipMemsetAsync(c->bloom.p, 0, sizeof(uint32_t) * c->bloom_words, c->stream));
-        ELOC_HIP(c, launch_bloom_build(c->khash.as<uint64_t>(), n_unique, c->bloom.as<uint32_t>(), c->bloom_words,
-                                       c->stream));
-    }
+    c->bloom_built = false;
     SampleDev S;
     S.n = n_unique;
     S.keys = c->keys.as<uint64_t>();
