@@ -52,6 +52,8 @@ def _load():
                                            P, P, P, P, P]
         _lib.oracle_matrix_elements.restype = ctypes.c_int
         _lib.oracle_matrix_elements.argtypes = [ctypes.c_int, i64, P, P, P, i64, P, P, P]
+        _lib.oracle_phase_exponents.restype = i64
+        _lib.oracle_phase_exponents.argtypes = [ctypes.c_int, i64, P, P, i64, P, P, P, P, i64]
         _lib.oracle_energy.restype = ctypes.c_int
         _lib.oracle_energy.argtypes = [i64, P, P, P, P]
         _lib.oracle_adjoint.restype = ctypes.c_int
@@ -149,6 +151,26 @@ def matrix_elements(ham, x, xprime):
     _check(lib.oracle_matrix_elements(ham.n_qubits, ham.n_terms, _p(c), _p(xy), _p(yz),
                                       x.shape[0], _p(x), _p(xp), _p(out)))
     return out
+
+
+def phase_exponents(ham, x, xprime):
+    """(offsets int64 [n + 1], k uint8 [offsets[n]]): for pair p the
+    exponent k of <x|P_l|x'> = i^k of every term l of the group of x ^ x',
+    in ascending caller index (Eq. pauli_melem); no terms if x ^ x' is not
+    an XY mask of H."""
+    lib = _load()
+    c, xy, yz = _ham_arrays(ham)
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    xp = np.ascontiguousarray(xprime, dtype=np.uint64)
+    n = x.shape[0]
+    off = np.empty(n + 1, dtype=np.int64)
+    total = lib.oracle_phase_exponents(ham.n_qubits, ham.n_terms, _p(xy), _p(yz), n, _p(x), _p(xp), _p(off),
+                                       None, 0)
+    if total < 0:
+        raise OracleError("bad Hamiltonian")
+    k = np.empty(max(total, 1), dtype=np.uint8)
+    lib.oracle_phase_exponents(ham.n_qubits, ham.n_terms, _p(xy), _p(yz), n, _p(x), _p(xp), _p(off), _p(k), total)
+    return off, k[:total]
 
 
 def energy(eloc, logpsi, weights=None):

@@ -344,6 +344,41 @@ int oracle_matrix_elements(int n_qubits, int64_t n_terms, const double* coeff, c
     return 0;
 }
 
+/* Phase exponents of Eq. pauli_melem for arbitrary pairs of keys: for pair
+ * p, with g the group of x ^ x' (none: no terms), offsets[p + 1] - offsets[p]
+ * = |P_g| and k[offsets[p] + t] = (|Y_l| + 2 |x' & YZ_l|) mod 4 for the t-th
+ * term l of P_g in ascending caller index, so <x|P_l|x'> = i^k.  offsets has
+ * n + 1 entries (offsets[0] = 0); k is written only while it fits in
+ * `capacity`.  Returns the total number of exponents, or < 0 on error. */
+int64_t oracle_phase_exponents(int n_qubits, int64_t n_terms, const uint64_t* xy, const uint64_t* yz,
+                               int64_t n, const uint64_t* x, const uint64_t* xprime,
+                               int64_t* offsets, uint8_t* k, int64_t capacity) {
+    ham_t H;
+    if (ham_build(&H, n_qubits, n_terms, NULL, xy, yz) != 0) return -1;
+    int W = H.W;
+    uint64_t d[MAXW] = {0, 0};
+    int64_t pos = 0;
+    offsets[0] = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        for (int w = 0; w < W; ++w) d[w] = x[p * W + w] ^ xprime[p * W + w];
+        int64_t g = ham_find_group(&H, d);
+        if (g >= 0) {
+            for (int64_t t = H.grp_begin[g]; t < H.grp_begin[g + 1]; ++t, ++pos) {
+                int64_t l = H.term_of[t];
+                int ny = 0, nxz = 0;
+                for (int w = 0; w < W; ++w) {
+                    ny += __builtin_popcountll(xy[l * W + w] & yz[l * W + w]);
+                    nxz += __builtin_popcountll(xprime[p * W + w] & yz[l * W + w]);
+                }
+                if (pos < capacity) k[pos] = (uint8_t)((ny + 2 * nxz) & 3);
+            }
+        }
+        offsets[p + 1] = pos;
+    }
+    ham_free(&H);
+    return pos;
+}
+
 /* Normalised weights: w_i / sum w (counts) or |psi_i|^2 / sum |psi|^2. */
 static double* normalised_weights(int64_t M, const double* logpsi, const double* weights, double* total) {
     double* wt = (double*)malloc(sizeof(double) * (size_t)M);

@@ -97,6 +97,35 @@ def test_dense_random_pauli(N, T, seed):
                                atol=1e-12)
 
 
+@pytest.mark.parametrize("N,T,seed,max_flip", [(3, 20, 10, None), (5, 60, 11, 2), (7, 90, 12, 2)])
+def test_phase_exponents_against_kron(N, T, seed, max_flip):
+    """Each exponent k the oracle gives for a term of a pair's group is that
+    term's own matrix element i^k, read from the Kronecker product of the
+    textbook 2x2 matrices (odd |Y| included); the terms come in ascending
+    caller index, and uncoupled pairs get none."""
+    rng = np.random.default_rng(seed)
+    ham = jw.random_pauli(N, T, rng, max_flip=max_flip)
+    D = 2 ** N
+    ii, jj = np.meshgrid(np.arange(D), np.arange(D), indexing="ij")
+    x = ii.ravel().astype(np.uint64)[:, None]
+    xp = jj.ravel().astype(np.uint64)[:, None]
+    off, k = oracle.phase_exponents(ham, x, xp)
+    mats = [pins.dense_pauli_kron(jw.PauliHamiltonian(N, np.ones(1), ham.xy[l:l + 1], ham.yz[l:l + 1]))
+            for l in range(T)]
+    xy = ham.xy[:, 0].astype(np.int64)
+    ipow = np.array([1, 1j, -1, -1j])
+    checked = 0
+    for p in range(D * D):
+        a, b = int(x[p, 0]), int(xp[p, 0])
+        terms = np.flatnonzero(xy == (a ^ b))
+        ks = k[off[p]:off[p + 1]]
+        assert ks.size == terms.size
+        for l, kk in zip(terms, ks):
+            assert mats[l][a, b] == ipow[kk], (p, l, kk)
+            checked += 1
+    assert checked == int(off[-1]) > 0
+
+
 def test_dense_builds_agree():
     ham = jw.random_pauli(5, 40, np.random.default_rng(9))
     np.testing.assert_allclose(pins.dense_pauli(ham), pins.dense_pauli_kron(ham), atol=1e-13)
