@@ -109,19 +109,31 @@ int eloc_set_hamiltonian(eloc_ctx ctx, int n_qubits, int64_t n_terms, const doub
 int eloc_hamiltonian_info(eloc_ctx ctx, int64_t* n_groups, int64_t* n_terms, int* n_qubits);
 
 /* Store the batch U of unique samples (the sampler's output, Sec.
- * "Sampling without replacement").  DEVICE keys_dev[n_unique][W] in any
- * order; sample index i below always means row i of this array.
- * Synchronising (validates the batch).  Errors: EINVAL (n_unique < 1 or
- * >= 2^24, bits >= N), EDUP (a key repeats), ESTATE (no Hamiltonian). */
+ * "Sampling without replacement"; U holds each sampled basis vector once,
+ * Eq. energy_estimator_via_unique).  DEVICE keys_dev[n_unique][W] in any
+ * order, copied; sample index i below always means row i of this array.
+ * Asynchronous: the copy, the membership table, the duplicate and bit
+ * checks and the prefilter parameters of U are all computed on the device.
+ * A key that repeats or has bits >= N is reported by the next synchronising
+ * call (eloc_check, eloc_count_pairs, eloc_find_pairs, eloc_store_pairs)
+ * as EDUP / EINVAL; until then the pair kernels do no work and the outputs
+ * of eloc_local_energy / adjoint are unspecified.  eloc_check returns
+ * EAGAIN (after rebuilding it) if U's membership table did not settle,
+ * which invalidates the calls made since.
+ * Errors (immediate): EINVAL (n_unique < 1 or >= 2^24, null keys),
+ * ESTATE (no Hamiltonian), ENOMEM, EHIP. */
 int eloc_set_samples(eloc_ctx ctx, int64_t n_unique, const uint64_t* keys_dev);
 
 /* Geometry of U's membership table (two-choice cuckoo hashing with a stash):
  * HOST outputs, each optional (NULL skips it): n_unique, table_slots (slot
  * count, a power of two of at least 4 n_unique), table_stash (keys held in
- * the stash, 0..32).  Errors: ESTATE (no samples set). */
+ * the stash, 0..32; reading it synchronises).  Errors: ESTATE (no samples
+ * set). */
 int eloc_samples_info(eloc_ctx ctx, int64_t* n_unique, int64_t* table_slots, int* table_stash);
 
-/* Forward pass.  DEVICE inputs logpsi_dev[n_unique] (complex log psi) and
+/* Forward pass (Eq. local_energy restricted to U: the sample-aware local
+ * energy; weighted energy of Eq. variational_energy or
+ * Eq. energy_estimator_via_unique).  DEVICE inputs logpsi_dev[n_unique] (complex log psi) and
  * weights_dev[n_unique] or NULL; DEVICE outputs eloc_dev[n_unique] and
  * stats_dev[4].  weights NULL: w = |psi|^2 renormalised over U
  * (Eq. variational_energy); else w >= 0 with sum w > 0, renormalised by
@@ -130,17 +142,24 @@ int eloc_samples_info(eloc_ctx ctx, int64_t* n_unique, int64_t* table_slots, int
  * Var = sum w~ |E_loc - E|^2.  Asynchronous: invalid weights or an FP32C
  * range failure are reported by the next synchronising call
  * (eloc_check) as EINVAL / ERANGE and the outputs are then unspecified.
- * ELOC_FP32C requires max Re L - min Re L <= 60.
+ * Re L must be finite with max Re L - min Re L <= 60 for ELOC_FP32C and
+ * <= 700 for ELOC_FP64 (exp(L - max Re L) and its inverse stay normal),
+ * else ERANGE (deferred).
  * Errors (immediate): EINVAL (variant/precision), ESTATE. */
 int eloc_local_energy(eloc_ctx ctx, int variant, int precision, const eloc_c64* logpsi_dev,
                       const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev);
 
-/* Wait for the context's stream and report a deferred device-side error of
- * the last eloc_local_energy / adjoint call (EINVAL, ERANGE).  Synchronising. */
+/* Wait for the context's stream and report a deferred device-side error:
+ * first of the current samples (EINVAL, EDUP, EAGAIN as in
+ * eloc_set_samples), then of the last eloc_local_energy / adjoint /
+ * pair_elements call (EINVAL, ERANGE, ECAPACITY).  Synchronising. */
 int eloc_check(eloc_ctx ctx);
 
-/* Number of coupled ordered pairs (x, x') in U x U, diagonal included.
- * Synchronising. */
+/* Number of coupled ordered pairs (x, x') in U x U, diagonal included:
+ * the size of the set that FindCoupledPairs returns (Sec. "Streamlined
+ * local energy calculations"; Alg. 2A, 2B and 2C give the same set), which
+ * is the number of terms in the sum of Eq. local_energy restricted to U.
+ * Synchronising; EDUP / EINVAL if the current samples are invalid. */
 int eloc_count_pairs(eloc_ctx ctx, int variant, int64_t* n_pairs_host);
 
 /* The coupled pairs themselves: DEVICE i_dev/j_dev/g_dev[capacity] receive
@@ -151,14 +170,30 @@ int eloc_count_pairs(eloc_ctx ctx, int variant, int64_t* n_pairs_host);
 int eloc_find_pairs(eloc_ctx ctx, int variant, int64_t capacity, int32_t* i_dev, int32_t* j_dev,
                     int32_t* g_dev, int64_t* n_pairs_host);
 
-/* MatrixElement (supplementary algorithm) for n given pairs of samples:
- * DEVICE i_dev/j_dev[n] sample indices, h_dev[n] receives H_{x_i x_j}
- * (0 when x_i ^ x_j is not an XY of H).  EINVAL if an index is outside U
- * (reported by eloc_check).  Asynchronous. */
+/* MatrixElement (supplementary algorithm; Eq. pauli_melem) for n given
+ * pairs of samples: DEVICE i_dev/j_dev[n] sample indices, h_dev[n]
+ * receives H_{x_i x_j} = sum over the terms l of the group of x_i ^ x_j of
+ * h_l i^(k_l), k_l = (|Y_l| + 2 |x_j & YZ_l|) mod 4 (phase on the ket
+ * x_j); 0 when x_i ^ x_j is not an XY mask of H.
+ * Optional phase exponents (both DEVICE, NULL skips them):
+ *   term_offsets_dev[n + 1] receives the exclusive prefix sum of the pairs'
+ *     term counts |P_{x_i ^ x_j}| (0 for an uncoupled pair), so that
+ *     term_offsets_dev[n] is the total;
+ *   k_dev[k_capacity] (needs term_offsets_dev) receives, for pair t at
+ *     [term_offsets[t], term_offsets[t + 1]), the exponent k_l in {0,1,2,3}
+ *     of every term l of the group in ascending caller index l (the term
+ *     set P_XY of Eq. xy_to_yz_set, in the caller's order).  If the total
+ *     exceeds k_capacity nothing is written to k_dev and eloc_check
+ *     reports ECAPACITY; call once with k_dev NULL to learn the total.
+ * EINVAL (deferred, eloc_check) if an index is outside U.  Asynchronous. */
 int eloc_pair_elements(eloc_ctx ctx, int64_t n, const int32_t* i_dev, const int32_t* j_dev,
-                       eloc_c64* h_dev);
+                       eloc_c64* h_dev, int64_t* term_offsets_dev, uint8_t* k_dev, int64_t k_capacity);
 
-/* Adjoint of the forward energy.  For a real loss with upstream
+/* Adjoint of the forward energy: the derivative of E with respect to the
+ * log-amplitudes, which the parameter gradient of Eq. grad_def is built from
+ * (the chain rule through log psi(x; theta) is the caller's).  The paper
+ * gives no adjoint; this is the derivative of Eq. local_energy restricted to
+ * U and of the weighted sum of Eq. variational_energy / counts.  For a real loss with upstream
  * grad_e = dLoss/dRe E + i dLoss/dIm E, writes DEVICE grad_logpsi_dev[n]
  * = dLoss/dRe L + i dLoss/dIm L.  With fixed weights E is holomorphic in L:
  *   dE/dL_y = sum_{x coupled to y} w~_x H_xy psi(y)/psi(x) - w~_y E_loc(y)

@@ -71,7 +71,7 @@ def library() -> ctypes.CDLL:
             "eloc_check": (i32, [P]),
             "eloc_count_pairs": (i32, [P, i32, ctypes.POINTER(i64)]),
             "eloc_find_pairs": (i32, [P, i32, i64, P, P, P, ctypes.POINTER(i64)]),
-            "eloc_pair_elements": (i32, [P, i64, P, P, P]),
+            "eloc_pair_elements": (i32, [P, i64, P, P, P, P, P, i64]),
             "eloc_local_energy_adjoint": (i32, [P, i32, i32, P, P, P, P, C64, P]),
             "eloc_store_pairs": (i32, [P, i32, ctypes.c_size_t, ctypes.POINTER(i64)]),
             "eloc_set_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
@@ -143,6 +143,10 @@ class Engine:
         self._call(self.lib.eloc_create(ctypes.byref(self.handle), device, ctypes.c_void_p(stream)))
         self.n_unique = 0
         self.n_qubits = 0
+        # bumped by every call that changes the Hamiltonian, the samples or the
+        # stored pair list: a backward pass refuses to run on other state than
+        # its forward pass saw
+        self.generation = 0
 
     def close(self):
         if self.handle:
@@ -173,6 +177,7 @@ class Engine:
         W = (n_qubits + 63) // 64
         assert xy.shape == (c.size, W) and yz.shape == (c.size, W)
         self._sync_stream()
+        self.generation += 1
         self._call(self.lib.eloc_set_hamiltonian(self.handle, n_qubits, c.size, _np_ptr(c), _np_ptr(xy),
                                                  _np_ptr(yz)))
         self.n_qubits = n_qubits
@@ -183,12 +188,21 @@ class Engine:
         self._call(self.lib.eloc_hamiltonian_info(self.handle, ctypes.byref(g), ctypes.byref(t), ctypes.byref(n)))
         return {"n_groups": g.value, "n_terms": t.value, "n_qubits": n.value}
 
-    def set_samples(self, keys: torch.Tensor):
-        """keys: int64/uint64 device tensor [M, W] (bit patterns)."""
-        assert keys.is_cuda and keys.dtype in (torch.int64, torch.uint64) and keys.is_contiguous()
+    def set_samples(self, keys: torch.Tensor, check: bool = True):
+        """keys: int64/uint64 device tensor [M, W] (bit patterns).  The
+        library prepares U asynchronously; with check (default) this waits
+        and raises EDUP / EINVAL for invalid samples, else they are reported
+        by the next check()."""
+        W = (self.n_qubits + 63) // 64
+        if not (keys.is_cuda and keys.dtype in (torch.int64, torch.uint64) and keys.is_contiguous()
+                and keys.dim() == 2 and keys.shape[1] == W):
+            raise ValueError(f"keys must be a contiguous int64 CUDA tensor [M, {W}]")
+        self.generation += 1
         self._sync_stream()
         self._call(self.lib.eloc_set_samples(self.handle, keys.shape[0], _ptr(keys)))
         self.n_unique = keys.shape[0]
+        if check:
+            self.check()
 
     def samples_info(self) -> dict:
         """Size of U and of its membership table (slots, keys in the stash)."""
@@ -273,31 +287,65 @@ class Engine:
         if budget_bytes is None:
             budget_bytes = torch.cuda.mem_get_info(self.device)[0] // 2
         n = ctypes.c_int64()
+        self.generation += 1
         self._sync_stream()
         self._call(self.lib.eloc_store_pairs(self.handle, _variant(variant), int(budget_bytes), ctypes.byref(n)))
         return n.value
 
-    def pair_elements(self, i: torch.Tensor, j: torch.Tensor) -> torch.Tensor:
-        assert i.dtype == torch.int32 and j.dtype == torch.int32 and i.shape == j.shape
+    def pair_elements(self, i: torch.Tensor, j: torch.Tensor, phases: bool = False):
+        """H_{x_i x_j} (complex128 [n]); with phases also (term_offsets int64
+        [n + 1], k uint8 [term_offsets[n]]): the exponent k of i^k of every
+        term of the pair's group, terms in ascending caller index."""
+        if not (i.dtype == torch.int32 and j.dtype == torch.int32 and i.shape == j.shape and i.dim() == 1
+                and i.is_cuda and j.is_cuda):
+            raise ValueError("i and j must be int32 CUDA tensors of one shape [n]")
         i, j = i.contiguous(), j.contiguous()
-        h = torch.empty(i.shape[0], dtype=torch.complex128, device=self.device)
+        n = i.shape[0]
+        h = torch.empty(n, dtype=torch.complex128, device=self.device)
         self._sync_stream()
-        self._call(self.lib.eloc_pair_elements(self.handle, i.shape[0], _ptr(i), _ptr(j), _ptr(h)))
+        if not phases:
+            self._call(self.lib.eloc_pair_elements(self.handle, n, _ptr(i), _ptr(j), _ptr(h), None, None, 0))
+            self.check()
+            return h
+        off = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        self._call(self.lib.eloc_pair_elements(self.handle, n, _ptr(i), _ptr(j), _ptr(h), _ptr(off), None, 0))
         self.check()
-        return h
+        total = int(off[n].item())
+        k = torch.empty(max(total, 1), dtype=torch.uint8, device=self.device)
+        self._call(self.lib.eloc_pair_elements(self.handle, n, _ptr(i), _ptr(j), _ptr(h), _ptr(off), _ptr(k),
+                                               total))
+        self.check()
+        return h, off, k[:total]
 
     # -- adjoint ------------------------------------------------------------
     def adjoint(self, logpsi, eloc, stats, grad_e: complex, weights=None, variant="terms", precision="fp64",
                 out=None, check=True):
+        """dLoss/dlog psi [M] (complex128) for upstream grad_e = dLoss/dRe E +
+        i dLoss/dIm E; eloc and stats are the forward outputs for the same
+        logpsi and weights."""
         M = self.n_unique
+
+        def need(t, name, dtype, shape):
+            if t is None or t.dtype != dtype or not t.is_cuda or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a {dtype} CUDA tensor of shape {shape}")
+            return t.contiguous()
+
+        logpsi = need(logpsi, "logpsi", torch.complex128, (M,))
+        eloc = need(eloc, "eloc", torch.complex128, (M,))
+        stats = need(stats, "stats", torch.float64, (4,))
+        if weights is not None:
+            weights = need(weights, "weights", torch.float64, (M,))
         if out is None:
             out = torch.empty(M, dtype=torch.complex128, device=self.device)
+        else:
+            need(out, "out", torch.complex128, (M,))
+            if not out.is_contiguous():
+                raise ValueError("out must be contiguous")
         ge = C64(float(np.real(grad_e)), float(np.imag(grad_e)))
         self._sync_stream()
         self._call(self.lib.eloc_local_energy_adjoint(self.handle, _variant(variant), _precision(precision),
-                                                      _ptr(logpsi.contiguous()),
-                                                      _ptr(None if weights is None else weights.contiguous()),
-                                                      _ptr(eloc), _ptr(stats), ge, _ptr(out)))
+                                                      _ptr(logpsi), _ptr(weights), _ptr(eloc), _ptr(stats), ge,
+                                                      _ptr(out)))
         if check:
             self.check()
         return out
@@ -323,6 +371,7 @@ class LocalEnergy(torch.autograd.Function):
                     raise
         eloc, stats = engine.local_energy(logpsi, weights, variant, precision)
         ctx.engine, ctx.variant, ctx.precision = engine, variant, precision
+        ctx.generation = engine.generation
         ctx.save_for_backward(logpsi, eloc, stats, *( [weights] if weights is not None else []))
         ctx.has_w = weights is not None
         E = torch.complex(stats[0], stats[1])
@@ -334,6 +383,9 @@ class LocalEnergy(torch.autograd.Function):
         saved = ctx.saved_tensors
         logpsi, eloc, stats = saved[:3]
         weights = saved[3] if ctx.has_w else None
+        if ctx.engine.generation != ctx.generation:
+            raise RuntimeError("the engine's Hamiltonian, samples or stored pairs changed between the forward "
+                               "and the backward pass of LocalEnergy")
         ge = complex(grad_E.item()) if grad_E is not None else 0j
         g = ctx.engine.adjoint(logpsi, eloc, stats, ge, weights, ctx.variant, ctx.precision)
         return g, None, None, None, None, None

@@ -36,15 +36,34 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> Path:
+    """Compile every source to an object file (in parallel), then link."""
+    obj_dir = PKG / "_build"
+    obj_dir.mkdir(exist_ok=True)
+    inc = [f"-I{ROOT / 'include'}", f"-I{CSRC}"]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    for src in SOURCES:
+        obj = obj_dir / (src.name + ".o")
+        cmd = [hipcc(), *compile_flags, *inc, "-c", str(src), "-o", str(obj)]
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                  text=True)))
+    logs, failed = [], False
+    for src, obj, p in procs:
+        out, _ = p.communicate()
+        logs.append(out)
+        failed = failed or p.returncode != 0
+    if failed:
+        sys.stderr.write("\n".join(logs))
+        raise RuntimeError("hipcc failed")
     tmp = LIB.with_name(LIB.name + ".tmp")
-    cmd = [hipcc(), *FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", *map(str, SOURCES), "-o", str(tmp)]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    res = subprocess.run([hipcc(), *FLAGS, *[str(o) for _, o, _ in procs], "-o", str(tmp)], capture_output=True,
+                         text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError("hipcc link failed")
     if verbose:
         noise = ("packed-fp32-ops", "is not a recognized feature")
-        for line in (res.stdout + res.stderr).splitlines():
+        for line in ("\n".join(logs) + res.stdout + res.stderr).splitlines():
             if line.strip() and not any(n in line for n in noise):
                 print(line)
     os.replace(tmp, LIB)

@@ -32,12 +32,13 @@ struct eloc_ctx_s {
 
     bool ham_set = false;
     HamDev H;
-    DevBuf groups, terms, terms_f, ghash, gkeys, gslots, gstash;
+    DevBuf groups, terms, terms_f, term_src, term_ny, ghash, gkeys, gslots, gstash;
+    DevBuf pe_cnt, pe_grp;   // pair_elements: term counts and groups of the pairs
     DevBuf xyt_keys, xyt_gid, xyt_nodes, xyt_nkeys;
 
     bool samples_set = false;
     SampleDev S;
-    DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad, bloom;
+    DevBuf keys, khash, kslots, kstash, sig, bitcounts, rad, sparams, bloom;
     uint32_t bloom_words = 0;   // Bloom filter of U (0: none)
     bool bloom_built = false;   // built on first use by a kernel that reads it
     DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
@@ -46,9 +47,7 @@ struct eloc_ctx_s {
 
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
     DevBuf partial, energy_scratch, err_run, err_prep;
-    uint32_t* err_host = nullptr;
-    uint64_t* sig_host = nullptr;    // pinned copy of the signature bitmap
-    unsigned long long* rad_host = nullptr;   // pinned: reference key [2], max distance
+    uint32_t* err_host = nullptr;    // pinned words for synchronous read-backs
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
@@ -63,11 +62,6 @@ struct eloc_ctx_s {
     int tune_rows = 0;       // 0 = automatic
     int tune_bloom = 0;      // the LDS Bloom filter is slower on MI355X (occupancy); opt-in
     int tune_waves = 0;      // 0 = automatic
-    bool sig_one = false;    // U has a single (even-qubit, total) popcount signature
-    int sig_pa = 0, sig_n = 0;
-    uint64_t rad_ref[2] = {0, 0};
-    int rad_max = 128;       // radius of U around rad_ref (128: filter off)
-    int kstash_used = 0;     // keys of U held in the membership table's stash
     uint64_t kslots_n = 0;   // slots of U's membership table
     uint64_t salt_state = 0x5EED2408ull;
 
@@ -125,16 +119,10 @@ Plan make_plan(const eloc_ctx c, int variant) {
     const int rows = c->tune_rows ? c->tune_rows : (bloom ? 4 : 8);
     P.rows_per_block = rows_per_block(variant, rows);
     P.waves_per_block = bloom ? 4 : 1;
-    // the exact prefilters of LoopOverTerms: U's single popcount signature,
-    // and U's radius around its majority key when that is under half the qubits
-    const bool rad_on = 2 * c->rad_max < c->H.n_qubits;
-    P.sig_filter = c->tune_sig != 0 && (c->sig_one || rad_on);
-    P.sig_pa = c->sig_pa;
-    P.sig_n = c->sig_n;
-    P.sig_all = !c->sig_one;
-    P.rad_ref[0] = c->rad_ref[0];
-    P.rad_ref[1] = c->rad_ref[1];
-    P.rad_max = rad_on ? c->rad_max : 128;
+    // the exact prefilters of LoopOverTerms (U's single popcount signature,
+    // U's radius around its majority key): the kernel reads their parameters
+    // from the device, and a prefilter that U does not allow passes everything
+    P.sig_filter = c->tune_sig != 0;
     P.bloom_words = (bloom && P.sig_filter) ? c->bloom_words : 0;
     P.bloom = c->bloom.as<uint32_t>();
     if (variant == ELOC_TRIE) {
@@ -160,6 +148,24 @@ Plan make_plan(const eloc_ctx c, int variant) {
     return P;
 }
 
+// One cuckoo table of U with a fresh salt, its verification (duplicates,
+// signature bitmap) and the prefilter parameters; asynchronous.
+int build_sample_table(eloc_ctx c) {
+    const int64_t n = c->S.n;
+    const int tk = table_kind(c->H.W, c->H.narrow);
+    c->S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), c->kslots_n, n, splitmix64(c->salt_state));
+    ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(tk) * c->kslots_n, c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(Stash), c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
+    ELOC_HIP(c, launch_table_insert(tk, c->khash.as<uint64_t>(), n, c->kslots.p, c->kstash.as<Stash>(), c->S.table,
+                                    c->err_prep.as<uint32_t>(), c->stream));
+    ELOC_HIP(c, launch_sample_verify(c->H.W, c->H.narrow, c->S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(),
+                                     c->stream));
+    ELOC_HIP(c, launch_sample_params(c->sig.as<uint64_t>(), c->rad.as<unsigned long long>(), c->H.n_qubits,
+                                     c->sparams.as<SampleParams>(), c->stream));
+    return ELOC_OK;
+}
+
 int read_err(eloc_ctx c, DevBuf& word) {
     hipError_t e = hipMemcpyAsync(c->err_host, word.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read error word");
@@ -169,13 +175,36 @@ int read_err(eloc_ctx c, DevBuf& word) {
 }
 
 int map_err(eloc_ctx c, uint32_t bits) {
+    if (bits & kErrBits) return fail(c, ELOC_EINVAL, "a sample key has bits set at or above n_qubits");
     if (bits & kErrDup) return fail(c, ELOC_EDUP, "duplicate keys in the sample batch");
     if (bits & kErrBits) return fail(c, ELOC_EINVAL, "a sample key has bits set at or above n_qubits");
     if (bits & kErrWeights) return fail(c, ELOC_EINVAL, "weights must be finite, >= 0, with a positive sum");
     if (bits & kErrRange)
-        return fail(c, ELOC_ERANGE, "log-amplitudes not finite, or Re log psi spread > 60 in the FP32 form");
+        return fail(c, ELOC_ERANGE, "log-amplitudes not finite, or Re log psi spread above 60 (FP32 form) or 700 (FP64 form)");
     if (bits & kErrIndex) return fail(c, ELOC_EINVAL, "pair index outside the sample batch");
+    if (bits & kErrCapacity) return fail(c, ELOC_ECAPACITY, "an output buffer of the last call was too small");
     return ELOC_OK;
+}
+
+// Synchronous verdict on the current samples (the errors eloc_set_samples
+// latched on the device).  A membership table whose cuckoo insertion did not
+// settle (which also fails the key's own lookup, so it reads as a duplicate)
+// is rebuilt here with new salts; *rebuilt tells the caller that work
+// enqueued before this call saw the broken table.
+int samples_verdict(eloc_ctx c, bool* rebuilt) {
+    if (rebuilt) *rebuilt = false;
+    int bits = read_err(c, c->err_prep);
+    if (bits < 0) return bits;
+    for (int attempt = 0; (bits & kErrTable) && !(bits & kErrBits); ++attempt) {
+        if (attempt == 8) return fail(c, ELOC_EHIP, "membership table could not be built");
+        ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+        const int rc = build_sample_table(c);
+        if (rc) return rc;
+        bits = read_err(c, c->err_prep);
+        if (bits < 0) return bits;
+        if (rebuilt) *rebuilt = true;
+    }
+    return map_err(c, static_cast<uint32_t>(bits));
 }
 
 // Fill a cuckoo table with keys 0..n-1 (hashes `hash`); a new salt is drawn
@@ -232,6 +261,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, c->groups.ensure(sizeof(GroupRec<W>) * G));
     ELOC_HIP(c, c->terms.ensure(sizeof(TermRec<W>) * n_terms));
     ELOC_HIP(c, c->terms_f.ensure(sizeof(TermRecF<W>) * n_terms));
+    ELOC_HIP(c, c->term_src.ensure(sizeof(int32_t) * n_terms));
+    ELOC_HIP(c, c->term_ny.ensure(sizeof(uint8_t) * n_terms));
     ELOC_HIP(c, c->ghash.ensure(sizeof(uint64_t) * G));
     ELOC_HIP(c, c->gkeys.ensure(sizeof(uint64_t) * G * W));
     const uint64_t cap = table_capacity(G);
@@ -243,6 +274,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->groups.p, groups.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->terms.p, terms.data(), sizeof(TermRec<W>) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->terms_f.p, terms_f.data(), sizeof(TermRecF<W>) * n_terms, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->term_src.p, hh.term_src.data(), sizeof(int32_t) * n_terms, hipMemcpyHostToDevice));
+    ELOC_HIP(c, hipMemcpy(c->term_ny.p, hh.term_ny.data(), sizeof(uint8_t) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
     ELOC_HIP(c, c->gstash.ensure(sizeof(Stash)));
@@ -261,6 +294,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.groups = c->groups.p;
     H.terms = c->terms.p;
     H.terms_f = c->terms_f.p;
+    H.term_src = c->term_src.as<int32_t>();
+    H.term_ny = c->term_ny.as<uint8_t>();
     H.group_hash = c->ghash.as<uint64_t>();
     H.group_keys = c->gkeys.as<uint64_t>();
     H.group_table = T;
@@ -405,6 +440,8 @@ int forward_variant(eloc_ctx c, int* variant) {
 }
 
 int count_into_offsets(eloc_ctx c, int variant, const Plan& P, int64_t* total) {
+    const int rc = samples_verdict(c, nullptr);   // synchronising anyway
+    if (rc) return rc;
     const int64_t n = c->S.n * P.chunks;
     ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
     ELOC_HIP(c, c->offsets.ensure(sizeof(int64_t) * (n + 1)));
@@ -440,11 +477,8 @@ int eloc_create(eloc_ctx* out, int device, void* hip_stream) {
         hipMemcpy(c->R_dev.p, c->R, sizeof(c->R), hipMemcpyHostToDevice) != hipSuccess ||
         c->err_run.ensure(sizeof(uint32_t)) != hipSuccess || c->err_prep.ensure(sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->err_run.p, 0, sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->sig_host), sizeof(uint64_t) * kSigWords, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->rad_host), sizeof(unsigned long long) * 3, hipHostMallocDefault) !=
-            hipSuccess) {
+        hipMemset(c->err_prep.p, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
         eloc_destroy(c);
         return ELOC_EHIP;
     }
@@ -457,8 +491,8 @@ void eloc_destroy(eloc_ctx c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&c->R_dev, &c->groups, &c->terms, &c->terms_f, &c->ghash, &c->gkeys, &c->gslots,
-                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->bitcounts, &c->rad, &c->bloom, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
+    DevBuf* bufs[] = {&c->R_dev, &c->groups, &c->terms, &c->terms_f, &c->term_src, &c->term_ny, &c->pe_cnt, &c->pe_grp, &c->ghash, &c->gkeys, &c->gslots,
+                      &c->keys, &c->khash, &c->kslots, &c->sig, &c->bitcounts, &c->rad, &c->sparams, &c->bloom, &c->a, &c->b, &c->af, &c->bf, &c->v, &c->vf,
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
                       &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
@@ -470,8 +504,6 @@ void eloc_destroy(eloc_ctx c) {
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->err_host) (void)hipHostFree(c->err_host);
-    if (c->sig_host) (void)hipHostFree(c->sig_host);
-    if (c->rad_host) (void)hipHostFree(c->rad_host);
     delete c;
 }
 
@@ -521,7 +553,12 @@ int eloc_samples_info(eloc_ctx c, int64_t* n_unique, int64_t* table_slots, int* 
     if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
     if (n_unique) *n_unique = c->S.n;
     if (table_slots) *table_slots = static_cast<int64_t>(c->kslots_n);
-    if (table_stash) *table_stash = c->kstash_used;
+    if (table_stash) {
+        // the stash count is the first word of the stash
+        const int bits = read_err(c, c->kstash);
+        if (bits < 0) return bits;
+        *table_stash = bits;
+    }
     return ELOC_OK;
 }
 
@@ -541,6 +578,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     ELOC_HIP(c, c->sig.ensure(sizeof(uint64_t) * kSigWords));
     ELOC_HIP(c, c->bitcounts.ensure(sizeof(uint32_t) * 64 * W));
     ELOC_HIP(c, c->rad.ensure(sizeof(unsigned long long) * 3));
+    ELOC_HIP(c, c->sparams.ensure(sizeof(SampleParams)));
     const int pm = prof_begin(c, ELOC_STAGE_SAMPLES);
     ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
                                c->stream));
@@ -564,55 +602,16 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     S.keys = c->keys.as<uint64_t>();
     S.hash = c->khash.as<uint64_t>();
     S.sig = c->sig.as<uint64_t>();
-    // table insert + verification, one read-back; a fresh salt only if a
-    // cuckoo insertion did not settle
-    uint32_t bits = 0;
-    for (int attempt = 0;; ++attempt) {
-        if (attempt == 8) return fail(c, ELOC_EHIP, "membership table could not be built");
-        S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), cap, n_unique,
-                             splitmix64(c->salt_state));
-        ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(tk) * cap, c->stream));
-        ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(Stash), c->stream));
-        ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
-        ELOC_HIP(c, launch_table_insert(tk, c->khash.as<uint64_t>(), n_unique, c->kslots.p, c->kstash.as<Stash>(),
-                                        S.table, c->err_prep.as<uint32_t>(), c->stream));
-        ELOC_HIP(c, launch_sample_verify(W, c->H.narrow, S, c->sig.as<uint64_t>(), c->err_prep.as<uint32_t>(),
-                                         c->stream));
-        ELOC_HIP(c, hipMemcpyAsync(c->err_host, c->err_prep.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-        ELOC_HIP(c, hipMemcpyAsync(c->sig_host, c->sig.p, sizeof(uint64_t) * kSigWords, hipMemcpyDeviceToHost,
-                                   c->stream));
-        ELOC_HIP(c, hipMemcpyAsync(c->rad_host, c->rad.p, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost,
-                                   c->stream));
-        // the stash count is the first word of the stash
-        ELOC_HIP(c, hipMemcpyAsync(c->err_host + 1, c->kstash.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-        ELOC_HIP(c, hipStreamSynchronize(c->stream));
-        bits = *c->err_host;
-        // a key that did not settle also fails its own lookup (duplicate
-        // flag): rebuild and verify again; bad bits are final
-        if (!(bits & kErrTable) || (bits & kErrBits)) break;
-        ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
-    }
-    prof_end(c, pm);
-    const int rc = map_err(c, bits);
-    if (rc != ELOC_OK) return rc;
-    // a single (even, odd) popcount signature over U enables the exact
-    // prefilter of LoopOverTerms
-    int nsig = 0;
-    for (int k = 0; k < kSigWords; ++k) nsig += __builtin_popcountll(c->sig_host[k]);
-    c->sig_one = nsig == 1;
-    for (int k = 0; c->sig_one && k < kSigWords; ++k)
-        if (c->sig_host[k]) {
-            const int pa = k / 2;
-            const int pb = (k % 2) * 64 + __builtin_ctzll(c->sig_host[k]);
-            c->sig_pa = pa;
-            c->sig_n = pa + pb;
-        }
-    c->rad_ref[0] = c->rad_host[0];
-    c->rad_ref[1] = W == 2 ? c->rad_host[1] : 0ull;
-    c->rad_max = static_cast<int>(c->rad_host[2]);
-    c->kstash_used = static_cast<int>(c->err_host[1]);
-    c->kslots_n = cap;
+    S.params = c->sparams.as<SampleParams>();
+    S.prep_err = c->err_prep.as<uint32_t>();
     c->S = S;
+    c->kslots_n = cap;
+    // table insert, verification and prefilter parameters, all on the
+    // device: errors (duplicates, bits >= N, a table that did not settle)
+    // stay latched in the preparation error word until a synchronising call
+    const int rc = build_sample_table(c);
+    if (rc) return rc;
+    prof_end(c, pm);
     c->ut_valid = false;
     c->st_valid = false;
     c->samples_set = true;
@@ -650,6 +649,13 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
 
 int eloc_check(eloc_ctx c) {
     if (!c) return ELOC_EINVAL;
+    if (c->samples_set) {
+        bool rebuilt = false;
+        const int rc = samples_verdict(c, &rebuilt);
+        if (rc) return rc;
+        if (rebuilt)
+            return fail(c, ELOC_EAGAIN, "U's membership table was rebuilt with a new salt; repeat the last call");
+    }
     const int bits = read_err(c, c->err_run);
     if (bits < 0) return bits;
     return map_err(c, static_cast<uint32_t>(bits));
@@ -709,15 +715,36 @@ int eloc_find_pairs(eloc_ctx c, int variant, int64_t capacity, int32_t* i_dev, i
     return ELOC_OK;
 }
 
-int eloc_pair_elements(eloc_ctx c, int64_t n, const int32_t* i_dev, const int32_t* j_dev, eloc_c64* h_dev) {
+int eloc_pair_elements(eloc_ctx c, int64_t n, const int32_t* i_dev, const int32_t* j_dev, eloc_c64* h_dev,
+                       int64_t* term_offsets_dev, uint8_t* k_dev, int64_t k_capacity) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (n < 0) return fail(c, ELOC_EINVAL, "negative count");
-    if (n == 0) return ELOC_OK;
-    if (!i_dev || !j_dev || !h_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, ELOC_EINVAL, "pair count must be in 0..2^31-1");
+    if (!h_dev || (k_dev && !term_offsets_dev) || (n > 0 && (!i_dev || !j_dev)))
+        return fail(c, ELOC_EINVAL, "null pointer");
+    if (k_capacity < 0) return fail(c, ELOC_EINVAL, "negative capacity");
     ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    if (n == 0) {
+        if (term_offsets_dev) ELOC_HIP(c, hipMemsetAsync(term_offsets_dev, 0, sizeof(int64_t), c->stream));
+        return ELOC_OK;
+    }
+    const bool phases = term_offsets_dev != nullptr;
+    if (phases) {
+        ELOC_HIP(c, c->pe_cnt.ensure(sizeof(int32_t) * n));
+        ELOC_HIP(c, c->pe_grp.ensure(sizeof(int32_t) * n));
+        ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(n)));
+    }
     ELOC_HIP(c, launch_pair_elements(c->H, c->S, n, i_dev, j_dev, reinterpret_cast<double2*>(h_dev),
-                                     c->err_run.as<uint32_t>(), c->stream));
+                                     phases ? c->pe_cnt.as<int32_t>() : nullptr,
+                                     phases ? c->pe_grp.as<int32_t>() : nullptr, c->err_run.as<uint32_t>(),
+                                     c->stream));
+    if (phases) {
+        ELOC_HIP(c, launch_scan_i32(c->pe_cnt.as<int32_t>(), n, term_offsets_dev, c->scan_scratch.as<int64_t>(),
+                                    c->stream));
+        if (k_dev)
+            ELOC_HIP(c, launch_pair_phases(c->H, c->S, n, j_dev, c->pe_grp.as<int32_t>(), term_offsets_dev, k_dev,
+                                           k_capacity, c->err_run.as<uint32_t>(), c->stream));
+    }
     return ELOC_OK;
 }
 
@@ -742,10 +769,11 @@ int eloc_local_energy_adjoint(eloc_ctx c, int variant, int precision, const eloc
     Plan P;
     rc = row_sums(c, true, variant, precision, c->v.as<double2>(), c->vf.as<float4>(), &P);
     if (rc) return rc;
+    ELOC_HIP(c, c->amp_scratch.ensure(sizeof(double) * amp_scratch_len()));
     const int pm = prof_begin(c, ELOC_STAGE_ADJOINT_FINISH);
     ELOC_HIP(c, launch_adj_finish(precision, M, P, c->partial.p, c->a.as<double2>(), c->af.as<float4>(),
                                   reinterpret_cast<const double2*>(eloc_dev), weights_dev, stats_dev,
-                                  c->shift.as<double>(), make_double2(grad_e.re, grad_e.im),
+                                  c->amp_scratch.as<double>(), make_double2(grad_e.re, grad_e.im),
                                   reinterpret_cast<double2*>(grad_logpsi_dev), c->stream));
     prof_end(c, pm);
     return ELOC_OK;

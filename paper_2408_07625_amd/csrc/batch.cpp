@@ -355,7 +355,7 @@ int map_bits(eloc_batch b, int k, uint32_t bits) {
     if (bits & kErrDup) return bfail(b, ELOC_EDUP, p + "duplicate keys in the sample batch");
     if (bits & kErrWeights) return bfail(b, ELOC_EINVAL, p + "weights must be finite, >= 0, with a positive sum");
     if (bits & kErrRange)
-        return bfail(b, ELOC_ERANGE, p + "log-amplitudes not finite, or Re log psi spread > 60 in the FP32 form");
+        return bfail(b, ELOC_ERANGE, p + "log-amplitudes not finite, or Re log psi spread above 60 (FP32 form) or 700 (FP64 form)");
     return ELOC_OK;
 }
 

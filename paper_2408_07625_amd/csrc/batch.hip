@@ -237,7 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_bt_shift(BatchDev B, int fp32) {
         mn = fmin(mn, B.part[3 * t + 1]);
     }
     B.shift[k] = mx;
-    if ((fp32 && !(mx - mn <= 60.0)) || !isfinite(mx) || !isfinite(mn))
+    // exp(L - c) and exp(c - L) finite and normal: spread <= 60 (FP32 form), 700 (FP64)
+    if (!(mx - mn <= (fp32 ? 60.0 : 700.0)) || !isfinite(mx) || !isfinite(mn))
         atomicOr(B.err + k, static_cast<uint32_t>(kErrRange));
 }
 

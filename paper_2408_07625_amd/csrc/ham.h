@@ -77,6 +77,8 @@ struct HostHam {
     std::vector<GroupRec<W>> groups;
     std::vector<TermRec<W>> terms;
     std::vector<TermRecF<W>> terms_f;
+    std::vector<int32_t> term_src;   // caller index of every stored term
+    std::vector<uint8_t> term_ny;    // its |Y| mod 4
     std::vector<uint64_t> ghash;     // lin(XY_g)
     std::vector<uint64_t> gkeys;     // XY_g [G][W]
     std::vector<int32_t> order;      // group ids sorted by XY (top word first)
@@ -120,6 +122,8 @@ std::string build_host_ham(const uint64_t* R, int64_t n_terms, const double* coe
     out.G = G;
     out.terms.resize(static_cast<size_t>(n_terms));
     out.terms_f.resize(static_cast<size_t>(n_terms));
+    out.term_src.resize(static_cast<size_t>(n_terms));
+    out.term_ny.resize(static_cast<size_t>(n_terms));
     for (int64_t l = 0; l < n_terms; ++l) {   // caller order kept inside each part
         const size_t g = static_cast<size_t>(gid[l]);
         const int k = ny[static_cast<size_t>(l)];
@@ -136,6 +140,8 @@ std::string build_host_ham(const uint64_t* R, int64_t n_terms, const double* coe
         tf.h_lo = static_cast<float>(h - static_cast<double>(tf.h_hi));
         out.terms[static_cast<size_t>(p)] = t;
         out.terms_f[static_cast<size_t>(p)] = tf;
+        out.term_src[static_cast<size_t>(p)] = static_cast<int32_t>(l);
+        out.term_ny[static_cast<size_t>(p)] = static_cast<uint8_t>(k & 3);
     }
     out.groups.resize(static_cast<size_t>(G));
     out.ghash.resize(static_cast<size_t>(G));

@@ -329,14 +329,33 @@ struct HamDev {
     const void* groups = nullptr;     // GroupRec<W>[G]
     const void* terms = nullptr;      // TermRec<W>[T]
     const void* terms_f = nullptr;    // TermRecF<W>[T]
+    const int32_t* term_src = nullptr;     // caller index of every stored term [T]
+    const uint8_t* term_ny = nullptr;      // its |Y| mod 4 [T]
     const uint64_t* group_hash = nullptr;  // lin(XY_g) [G]
     const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
     Table group_table{};               // XY -> group id
     XYTrieDev xyt{};
 };
 
+// Prefilter parameters of U for LoopOverTerms, derived on the device by
+// eloc_set_samples and read by the pair kernels at their start (so that
+// preparing U needs no host round trip): U's single (even-qubit, total)
+// popcount signature, or sig_all = 1 when U has several; U's per-qubit
+// majority key and its largest distance from it, or rad_max = 128 (off)
+// when that radius is not under half the qubits.
+struct SampleParams {
+    int32_t sig_pa;
+    int32_t sig_n;
+    int32_t sig_all;
+    int32_t rad_max;
+    uint64_t rad_ref[kMaxWords];
+};
+
 struct SampleDev {
     int64_t n = 0;
+    const SampleParams* params = nullptr;   // device
+    const uint32_t* prep_err = nullptr;     // device error word of the preparation: the
+                                            // pair kernels do nothing while it is non-zero
     const uint64_t* keys = nullptr;    // [M][W] caller order
     const uint64_t* hash = nullptr;    // lin(x_i) [M]
     Table table{};
@@ -376,6 +395,7 @@ enum ErrBits : uint32_t {
     kErrRange = 8u,
     kErrIndex = 16u,
     kErrTable = 32u,   // cuckoo insertion did not settle; rebuild with another salt
+    kErrCapacity = 64u,   // a caller buffer of an asynchronous call was too small
 };
 
 // ---------------------------------------------------------------------------
@@ -480,6 +500,9 @@ hipError_t launch_table_insert(int table_kind, const uint64_t* hash, int64_t n, 
                                const Table& T, uint32_t* err, hipStream_t st);
 hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t* sig, uint32_t* err,
                                 hipStream_t st);
+// SampleParams from the signature bitmap and the radius words (one thread).
+hipError_t launch_sample_params(const uint64_t* sig, const unsigned long long* rad, int n_qubits,
+                                SampleParams* out, hipStream_t st);
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b,
                            float4* af, float4* bf, double* shift, double* scratch, uint32_t* err,
                            hipStream_t st);
@@ -492,7 +515,7 @@ hipError_t launch_finish(int precision, int64_t n, const Plan& P, const void* pa
                          const double2* b, const float4* bf, double2* out, hipStream_t st);
 hipError_t launch_adj_finish(int precision, int64_t n, const Plan& P, const void* partial,
                              const double2* a, const float4* af, const double2* eloc,
-                             const double* weights, const double* stats, const double* shift,
+                             const double* weights, const double* stats, double* scratch,
                              double2 ge, double2* out, hipStream_t st);
 hipError_t launch_energy(const double2* eloc, const double2* logpsi, const double* weights,
                          const double* shift, int64_t n, double* stats, double* scratch,
@@ -510,9 +533,18 @@ hipError_t launch_radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* key
                                    hipStream_t st);
 hipError_t launch_split_pairs(const uint64_t* keys, const uint32_t* vals, int64_t n, int jbits,
                               int32_t* i_out, int32_t* j_out, int32_t* g_out, hipStream_t st);
+// h_out[t] = H_{x_i x_j} for the pair t = (i_idx[t], j_idx[t]); with cnt /
+// grp (both or neither) also the term count of the pair's group (0 if the
+// pair is not coupled) and the group id (-1).
 hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n,
                                 const int32_t* i_idx, const int32_t* j_idx, double2* h_out,
-                                uint32_t* err, hipStream_t st);
+                                int32_t* cnt, int32_t* grp, uint32_t* err, hipStream_t st);
+// Phase exponents k = (|Y_l| + 2 |x_j & YZ_l|) mod 4 of every term l of the
+// pair's group, ascending l, at k_out[offsets[t] ..]; nothing is written
+// and kErrCapacity is latched if offsets[n] > capacity.
+hipError_t launch_pair_phases(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* j_idx,
+                              const int32_t* grp, const int64_t* offsets, uint8_t* k_out, int64_t capacity,
+                              uint32_t* err, hipStream_t st);
 
 hipError_t launch_pairs_to_csr(const HamDev& H, const SampleDev& S, int64_t n, const uint64_t* pkey,
                                const uint32_t* pval, int jbits, int32_t* col, double2* h, hipStream_t st);

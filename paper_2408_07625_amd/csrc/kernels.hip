@@ -131,6 +131,35 @@ __global__ __launch_bounds__(kBlock) void k_sample_verify(const uint64_t* __rest
         if (lsig[t]) atomicOr(reinterpret_cast<unsigned long long*>(sig + t), lsig[t]);
 }
 
+// Prefilter parameters of U from the signature bitmap (a single set bit:
+// U's only (even, odd) popcount signature) and the radius words (majority
+// key, largest distance from it; used when under half the qubits).
+__global__ void k_sample_params(const uint64_t* __restrict__ sig, const unsigned long long* __restrict__ rad,
+                                int n_qubits, SampleParams* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int nsig = 0, first = -1;
+    for (int k = 0; k < kSigWords; ++k) {
+        const uint64_t v = sig[k];
+        if (v && first < 0) first = k;
+        nsig += popc64(v);
+    }
+    SampleParams p;
+    p.sig_all = nsig == 1 ? 0 : 1;
+    p.sig_pa = 0;
+    p.sig_n = 0;
+    if (nsig == 1) {
+        const int pa = first / 2;
+        const int pb = (first % 2) * 64 + (__ffsll(static_cast<unsigned long long>(sig[first])) - 1);
+        p.sig_pa = pa;
+        p.sig_n = pa + pb;
+    }
+    const int rmax = static_cast<int>(rad[2]);
+    p.rad_max = 2 * rmax < n_qubits ? rmax : 128;
+    p.rad_ref[0] = rad[0];
+    p.rad_ref[1] = n_qubits > 64 ? rad[1] : 0ull;
+    *out = p;
+}
+
 constexpr int kRedBlocks = 256;   // fixed partition of reductions over U
 
 __global__ __launch_bounds__(kBlock) void k_minmax_partial(const double2* __restrict__ L, int64_t n,
@@ -175,7 +204,9 @@ __global__ __launch_bounds__(kBlock) void k_amp_prep(const double2* __restrict__
         cmax = mx;
         if (blockIdx.x == 0) {
             *shift = mx;
-            if (!(mx - mn <= 60.0) && fp32) atomicOr(err, static_cast<uint32_t>(kErrRange));
+            // exp(L - c) and exp(c - L) stay finite and normal over the spread:
+            // 60 for the FP32 form, 700 for FP64 (exp overflows past 709.78)
+            if (!(mx - mn <= (fp32 ? 60.0 : 700.0))) atomicOr(err, static_cast<uint32_t>(kErrRange));
             if (!isfinite(mx) || !isfinite(mn)) atomicOr(err, static_cast<uint32_t>(kErrRange));
         }
     }
@@ -254,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_finish(const void* __restrict__ 
                                                        const double2* __restrict__ eloc,
                                                        const double* __restrict__ weights,
                                                        const double* __restrict__ stats,
-                                                       const double* __restrict__ shift, double2 ge,
+                                                       const double* __restrict__ atotal, double2 ge,
                                                        double2* __restrict__ out) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -283,17 +314,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_finish(const void* __restrict__ 
         sr = static_cast<double>(r.re.s) + static_cast<double>(r.re.c);
         si = static_cast<double>(r.im.s) + static_cast<double>(r.im.c);
     }
-    // raw weight of the row relative to the normaliser stats[3]
+    // raw weight of the row relative to the normaliser: the caller's
+    // weights over their sum stats[3], or |psi|^2 weights relative to
+    // exp(2c) (v = conj(a) carried |a|^2 / a) over the shifted total
+    // sum |a|^2, which stays finite for any offset of Re log psi
     double wrow;
     double inv_total;
     if (weights) {
         wrow = weights[i];
         inv_total = 1.0 / stats[3];
     } else {
-        // |psi|^2 weights are used relative to exp(2c): v = conj(a) carried |a|^2 / a.
         const double2 ai = a[i];
         wrow = ai.x * ai.x + ai.y * ai.y;
-        inv_total = exp(2.0 * shift[0]) / stats[3];
+        inv_total = 1.0 / atotal[0];
     }
     const double2 e = eloc[i];
     const double gr = (sr - wrow * e.x) * inv_total;
@@ -307,6 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_finish(const void* __restrict__ 
     }
     out[i] = make_double2(outr, outi);
 }
+
+// Sum of |a_i|^2 = |psi_i|^2 exp(-2c) over U in a fixed partition (the
+// |psi|^2 normaliser of the adjoint, relative to exp(2c)).
+__global__ __launch_bounds__(kBlock) void k_asum_partial(const double2* __restrict__ a, int64_t n,
+                                                         double* __restrict__ part);
+__global__ __launch_bounds__(kBlock) void k_asum_total(const double* __restrict__ part, double* __restrict__ total);
 
 // ---------------------------------------------------------------------------
 // Weighted energy and variance (FP64, fixed partition).
@@ -406,6 +445,27 @@ __global__ __launch_bounds__(kBlock) void k_energy_p3(const double* __restrict__
     for (int k = threadIdx.x; k < kRedBlocks; k += kBlock) v[0] += part[k];
     block_sum<1, kBlock>(v, lds);
     if (threadIdx.x == 0) stats[2] = v[0] / scal[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_asum_partial(const double2* __restrict__ a, int64_t n,
+                                                         double* __restrict__ part) {
+    __shared__ double lds[1][kBlock];
+    double v[1] = {0.0};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(kRedBlocks) * kBlock) {
+        const double2 ai = a[i];
+        v[0] += ai.x * ai.x + ai.y * ai.y;
+    }
+    block_sum<1, kBlock>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_asum_total(const double* __restrict__ part, double* __restrict__ total) {
+    __shared__ double lds[1][kBlock];
+    double v[1] = {0.0};
+    for (int k = threadIdx.x; k < kRedBlocks; k += kBlock) v[0] += part[k];
+    block_sum<1, kBlock>(v, lds);
+    if (threadIdx.x == 0) total[0] = v[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -673,6 +733,12 @@ hipError_t launch_sample_verify(int W, bool narrow, const SampleDev& S, uint64_t
     return hipGetLastError();
 }
 
+hipError_t launch_sample_params(const uint64_t* sig, const unsigned long long* rad, int n_qubits, SampleParams* out,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_params, dim3(1), dim3(64), 0, st, sig, rad, n_qubits, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_amp_prep(const double2* logpsi, int64_t n, bool fp32, double2* a, double2* b, float4* af,
                            float4* bf, double* shift, double* scratch, uint32_t* err, hipStream_t st) {
     hipLaunchKernelGGL(k_minmax_partial, dim3(kRedBlocks), dim3(kBlock), 0, st, logpsi, n, scratch);
@@ -700,13 +766,19 @@ hipError_t launch_finish(int precision, int64_t n, const Plan& P, const void* pa
 
 hipError_t launch_adj_finish(int precision, int64_t n, const Plan& P, const void* partial, const double2* a,
                              const float4* af, const double2* eloc, const double* weights, const double* stats,
-                             const double* shift, double2 ge, double2* out, hipStream_t st) {
+                             double* scratch, double2 ge, double2* out, hipStream_t st) {
+    // scratch: kRedBlocks partials, then the total of |a|^2
+    double* atotal = scratch + kRedBlocks;
+    if (!weights) {
+        hipLaunchKernelGGL(k_asum_partial, dim3(kRedBlocks), dim3(kBlock), 0, st, a, n, scratch);
+        hipLaunchKernelGGL(k_asum_total, dim3(1), dim3(kBlock), 0, st, scratch, atotal);
+    }
     if (precision == 0)
         hipLaunchKernelGGL(k_adj_finish<0>, dim3(blocks_for(n)), dim3(kBlock), 0, st, partial, P.chunks, n, a, af,
-                           eloc, weights, stats, shift, ge, out);
+                           eloc, weights, stats, atotal, ge, out);
     else
         hipLaunchKernelGGL(k_adj_finish<1>, dim3(blocks_for(n)), dim3(kBlock), 0, st, partial, P.chunks, n, a, af,
-                           eloc, weights, stats, shift, ge, out);
+                           eloc, weights, stats, atotal, ge, out);
     return hipGetLastError();
 }
 

@@ -49,6 +49,10 @@ struct PairArgs {
     const uint64_t* keys;
     const uint64_t* khash;
     Table ktable;
+    // prefilter parameters of U: read from `sp` at kernel start (single
+    // problem) or from the batch's per-problem arrays
+    const SampleParams* sp;
+    const uint32_t* prep_err;   // U's preparation error word (single problem; else null)
     int sig_pa;
     int sig_n;
     bool sig_all;
@@ -87,12 +91,14 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.keys = S.keys;
     a.khash = S.hash;
     a.ktable = S.table;
-    a.sig_pa = P.sig_pa;
-    a.sig_n = P.sig_n;
-    a.sig_all = P.sig_all;
-    a.rad_max = P.rad_max;
-    a.rad_ref[0] = P.rad_ref[0];
-    a.rad_ref[1] = P.rad_ref[1];
+    a.sp = S.params;
+    a.prep_err = S.prep_err;
+    a.sig_pa = 0;
+    a.sig_n = 0;
+    a.sig_all = true;
+    a.rad_max = 128;
+    a.rad_ref[0] = 0;
+    a.rad_ref[1] = 0;
     a.bloom = P.bloom;
     a.bloom_words = P.bloom_words;
     a.bloom_mask = P.bloom_words ? P.bloom_words - 1u : 0u;
@@ -128,6 +134,28 @@ struct Rows {
 __device__ __forceinline__ void read_stash_counts(PairArgs& A) {
     A.kstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.ktable.stash->count));
     A.gstash = static_cast<int>(__builtin_amdgcn_readfirstlane(A.gtable.stash->count));
+}
+
+// Kernel prologue of the single-problem pair kernels: false when U's
+// preparation latched an error (duplicate keys, bits >= N, a table that did
+// not settle), in which case the kernel does nothing and the outputs are
+// unspecified; else the prefilter parameters are loaded (wave-uniform).
+__device__ __forceinline__ bool read_sample_params(PairArgs& A) {
+    if (__builtin_amdgcn_readfirstlane(static_cast<int>(*A.prep_err)) != 0) return false;
+    const SampleParams& p = *A.sp;
+    A.sig_pa = __builtin_amdgcn_readfirstlane(p.sig_pa);
+    A.sig_n = __builtin_amdgcn_readfirstlane(p.sig_n);
+    A.sig_all = __builtin_amdgcn_readfirstlane(p.sig_all) != 0;
+    A.rad_max = __builtin_amdgcn_readfirstlane(p.rad_max);
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w) {
+        const uint64_t v = p.rad_ref[w];
+        A.rad_ref[w] = (static_cast<uint64_t>(static_cast<uint32_t>(
+                            __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)))) << 32) |
+                       static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+    }
+    read_stash_counts(A);
+    return true;
 }
 
 template <int W, int NR>
@@ -672,6 +700,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     __shared__ double2 acc_s[WPB][NR * kAccCols];
     extern __shared__ uint32_t lfilt[];
     const int wave = static_cast<int>(threadIdx.x) / kWave;
+    if (!read_sample_params(A)) return;   // the same for every thread of the block
     if constexpr (BL) {
         for (uint32_t t = threadIdx.x; t < A.bloom_words; t += kWave * WPB) lfilt[t] = A.bloom[t];
         __syncthreads();
@@ -685,7 +714,6 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     if (tile * NR >= A.M) return;   // no block-wide barrier follows
     uint64_t* rowkey = rowkey_s[wave];
     Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
-    read_stash_counts(A);
     Rows<W, NR> R;
     load_rows<W, NR>(A, R, rowkey, tile);
     for (int i = lane_id(); i < NR * kAccCols; i += kWave) acc[i] = Acc{};
@@ -711,8 +739,12 @@ template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRows * W];
     __shared__ CEntry<NW> cb[2 * kWave];
-    read_stash_counts(A);
     Rows<W, kRows> R;
+    if (!read_sample_params(A)) {   // no pairs while U is invalid
+        const int64_t row = static_cast<int64_t>(blockIdx.x) * kRows + lane_id();
+        if (lane_id() < kRows && row < A.M) counts[row * chunks + blockIdx.y] = 0;
+        return;
+    }
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
     wave_sync();
     CountSink sink;
@@ -729,7 +761,7 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRows * W];
     __shared__ CEntry<NW> cb[2 * kWave];
-    read_stash_counts(A);
+    if (!read_sample_params(A)) return;
     Rows<W, kRows> R;
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
     wave_sync();
@@ -889,6 +921,8 @@ __global__ __launch_bounds__(kTrieBlock) void k_pairs_trie(PairArgs A, const voi
                                                            void* __restrict__ partial) {
     using P = Prec<PREC>;
     extern __shared__ uint64_t tsm[];
+    // no walk over an invalid U (the trees assume unique keys); uniform per block
+    if (__builtin_amdgcn_readfirstlane(static_cast<int>(*A.prep_err)) != 0) return;
     TrieView U, V;
     int64_t vbase;
     trie_views<W>(A, blockIdx.y, U, V, vbase);
@@ -932,6 +966,10 @@ template <int W>
 __global__ __launch_bounds__(kTrieBlock) void k_count_trie(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
     if (row >= A.M) return;
+    if (*A.prep_err != 0u) {   // no pairs while U is invalid
+        counts[row * chunks + blockIdx.y] = 0;
+        return;
+    }
     uint64_t x[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
@@ -948,7 +986,7 @@ __global__ __launch_bounds__(kTrieBlock) void k_fill_trie(PairArgs A, int chunks
                                                           const int64_t* __restrict__ offsets,
                                                           uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     const int64_t row = static_cast<int64_t>(blockIdx.x) * kTrieBlock + threadIdx.x;
-    if (row >= A.M) return;
+    if (row >= A.M || *A.prep_err != 0u) return;
     uint64_t x[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = A.keys[row * W + w];
@@ -963,10 +1001,12 @@ __global__ __launch_bounds__(kTrieBlock) void k_fill_trie(PairArgs A, int chunks
     });
 }
 
-// MatrixElement for given sample pairs (ket x_j).
+// MatrixElement for given sample pairs (ket x_j); with cnt / grp also the
+// pair's group and its term count.
 template <int W, bool NW>
 __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, const int32_t* __restrict__ pi,
                                                        const int32_t* __restrict__ pj, double2* __restrict__ out,
+                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ grp,
                                                        uint32_t* __restrict__ err) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (t >= n) return;
@@ -974,6 +1014,10 @@ __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, co
     if (i < 0 || j < 0 || i >= A.M || j >= A.M) {
         atomicOr(err, static_cast<uint32_t>(kErrIndex));
         out[t] = make_double2(0.0, 0.0);
+        if (cnt) {
+            cnt[t] = 0;
+            grp[t] = -1;
+        }
         return;
     }
     uint64_t xj[W], m[W];
@@ -984,11 +1028,56 @@ __global__ __launch_bounds__(256) void k_pair_elements(PairArgs A, int64_t n, co
     }
     const int g = table_find<table_kind(W, NW), W>(A.gtable, A.gkeys, A.khash[i] ^ A.khash[j], m);
     double hr = 0.0, hi = 0.0;
+    int32_t nt = 0;
     if (g >= 0) {
         const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
         melem<W, NW>(static_cast<const TermRec<W>*>(A.terms), gr.begin, gr.mid, gr.end, 0, 1, xj, hr, hi);
+        nt = gr.end - gr.begin;
     }
     out[t] = make_double2(hr, hi);
+    if (cnt) {
+        cnt[t] = nt;
+        grp[t] = g;
+    }
+}
+
+// Per-term phase exponents of pair t (ket x_j): the group's terms are
+// stored as two runs, even |Y| then odd |Y|, each in caller order; they are
+// merged back into caller order by their caller index.
+template <int W>
+__global__ __launch_bounds__(256) void k_pair_phases(PairArgs A, int64_t n, const int32_t* __restrict__ pj,
+                                                     const int32_t* __restrict__ grp,
+                                                     const int64_t* __restrict__ offsets, uint8_t* __restrict__ kout,
+                                                     int64_t capacity, const int32_t* __restrict__ src,
+                                                     const uint8_t* __restrict__ ny, uint32_t* __restrict__ err) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= n) return;
+    if (offsets[n] > capacity) {
+        if (t == 0) atomicOr(err, static_cast<uint32_t>(kErrCapacity));
+        return;
+    }
+    const int g = grp[t];
+    if (g < 0) return;
+    const int64_t j = pj[t];
+    uint64_t xj[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) xj[w] = A.keys[j * W + w];
+    const GroupRec<W> gr = static_cast<const GroupRec<W>*>(A.groups)[g];
+    const TermRec<W>* __restrict__ terms = static_cast<const TermRec<W>*>(A.terms);
+    int a = gr.begin, b = gr.mid;
+    int64_t o = offsets[t];
+    while (a < gr.mid || b < gr.end) {
+        const bool take_a = b >= gr.end || (a < gr.mid && src[a] < src[b]);
+        const int p = take_a ? a : b;
+        int pc = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) pc += popc64(xj[w] & terms[p].yz[w]);
+        kout[o++] = static_cast<uint8_t>((ny[p] + 2 * pc) & 3);
+        if (take_a)
+            ++a;
+        else
+            ++b;
+    }
 }
 
 inline unsigned div_up(int64_t n, int64_t d) { return static_cast<unsigned>((n + d - 1) / d); }
@@ -1249,16 +1338,31 @@ hipError_t launch_spmv(bool adjoint, int precision, int64_t M, const int64_t* ro
 }
 
 hipError_t launch_pair_elements(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pi, const int32_t* pj,
-                                double2* out, uint32_t* err, hipStream_t st) {
+                                double2* out, int32_t* cnt, int32_t* grp, uint32_t* err, hipStream_t st) {
     Plan P;
     const PairArgs A = make_args(H, S, P);
     const dim3 grid(div_up(n, 256)), block(256);
     if (H.W == 2)
-        hipLaunchKernelGGL((k_pair_elements<2, false>), grid, block, 0, st, A, n, pi, pj, out, err);
+        hipLaunchKernelGGL((k_pair_elements<2, false>), grid, block, 0, st, A, n, pi, pj, out, cnt, grp, err);
     else if (H.narrow)
-        hipLaunchKernelGGL((k_pair_elements<1, true>), grid, block, 0, st, A, n, pi, pj, out, err);
+        hipLaunchKernelGGL((k_pair_elements<1, true>), grid, block, 0, st, A, n, pi, pj, out, cnt, grp, err);
     else
-        hipLaunchKernelGGL((k_pair_elements<1, false>), grid, block, 0, st, A, n, pi, pj, out, err);
+        hipLaunchKernelGGL((k_pair_elements<1, false>), grid, block, 0, st, A, n, pi, pj, out, cnt, grp, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_phases(const HamDev& H, const SampleDev& S, int64_t n, const int32_t* pj, const int32_t* grp,
+                              const int64_t* offsets, uint8_t* kout, int64_t capacity, uint32_t* err,
+                              hipStream_t st) {
+    Plan P;
+    const PairArgs A = make_args(H, S, P);
+    const dim3 grid(div_up(n, 256)), block(256);
+    if (H.W == 2)
+        hipLaunchKernelGGL(k_pair_phases<2>, grid, block, 0, st, A, n, pj, grp, offsets, kout, capacity, H.term_src,
+                           H.term_ny, err);
+    else
+        hipLaunchKernelGGL(k_pair_phases<1>, grid, block, 0, st, A, n, pj, grp, offsets, kout, capacity, H.term_src,
+                           H.term_ny, err);
     return hipGetLastError();
 }
 

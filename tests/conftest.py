@@ -33,3 +33,15 @@ def small_workload():
 def medium_workload():
     from synth import configs
     return cached("medium", configs.medium)
+
+
+@pytest.fixture(scope="session")
+def large_workload():
+    from synth import configs
+    return cached("large", configs.large)
+
+
+@pytest.fixture(scope="session")
+def wide_workload():
+    from synth import configs
+    return cached("wide", configs.wide)

@@ -146,30 +146,108 @@ def test_medium_workload(eng, medium_workload):
     assert eng.count_pairs("terms") == int(npairs.sum())
 
 
-def test_large_workload_sampled(eng):
-    w = configs.large()
-    check_workload(eng, w, variants=("terms",), rows=[(0, 300), (524288, 524600), ((1 << 20) - 211, 1 << 20)],
-                   pairs=False)
+# ----------------------------------------------------------------------------
+# 52 qubits, 2^20 samples: every variant against the oracle's stored results
+# (tests/golden/make_large_golden.py): E_loc, pair count and pair digest of
+# 12 800 sampled rows, E and Var over all rows, the total pair count.
+GOLDEN = Path(__file__).resolve().parent / "golden"
 
 
-def test_wide_workload_sampled(eng):
-    """100 qubits, two words per key, occurrence-count weights."""
-    w = configs.wide()
-    rows = [(0, 100), ((1 << 18) - 77, 1 << 18)]
-    check_workload(eng, w, variants=("terms",), rows=rows, pairs=False)
+@pytest.fixture(scope="module")
+def large_golden(large_workload):
+    import hashlib
+    path = GOLDEN / "large_oracle.npz"
+    if not path.exists():
+        pytest.fail(f"{path} missing: run tests/golden/make_large_golden.py")
+    g = dict(np.load(path, allow_pickle=False))
+    w = large_workload
+    h = hashlib.sha256()
+    for a in (w.ham.coeff, w.ham.xy, w.ham.yz, w.keys, w.logpsi):
+        h.update(np.ascontiguousarray(a).tobytes())
+    assert np.frombuffer(h.digest(), dtype=np.uint8).tobytes() == g["fingerprint"].tobytes(), \
+        "the generated 52-qubit inputs differ from those the golden file was made from"
+    return g
+
+
+def gpu_row_digests(eng, variant, rows):
+    """(count, digest) of the sampled rows from the engine's canonical pair
+    list (sorted by row, so each contiguous block of rows is one slice)."""
+    from digest import row_digests
+    i, j, g = eng.find_pairs(variant)
+    cnt, dig = [], []
+    starts = np.flatnonzero(np.diff(rows, prepend=-2) != 1)
+    ends = np.append(starts[1:], rows.size)
+    for s0, s1 in zip(starts, ends):
+        a, b = int(rows[s0]), int(rows[s1 - 1]) + 1
+        lo, hi = torch.searchsorted(i, torch.tensor([a, b], dtype=torch.int32, device=i.device)).tolist()
+        c, d = row_digests(i[lo:hi].cpu().numpy(), j[lo:hi].cpu().numpy(), g[lo:hi].cpu().numpy(),
+                           rows[s0:s1])
+        cnt.append(c)
+        dig.append(d)
+    del i, j, g
+    return np.concatenate(cnt), np.concatenate(dig)
+
+
+@pytest.mark.parametrize("variant", ["terms", "batch", "trie"])
+def test_large_workload_golden(eng, large_workload, large_golden, variant):
+    w, gold = large_workload, large_golden
+    load(eng, w.ham, w.keys)
+    rows = gold["rows"]
+    L = dev(w.logpsi)
+    E_ref = gold["stats"][0] + 1j * gold["stats"][1]
+    var_ref = gold["stats"][2]
+    for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+        e, st = eng.local_energy(L, None, variant=variant, precision=prec)
+        err = np.abs(e.cpu().numpy()[rows] - gold["eloc"]).max()
+        s = st.cpu().numpy()
+        print(f"large {variant} {prec}: max |dE_loc| = {err:.3e}, |dE| = {abs(s[0] + 1j * s[1] - E_ref):.3e}, "
+              f"|dVar| = {abs(s[2] - var_ref):.3e}", flush=True)
+        assert err <= tol
+        assert abs(s[0] - E_ref.real) <= tol and abs(s[1] - E_ref.imag) <= tol
+        assert abs(s[2] - var_ref) <= tol * max(1.0, var_ref)
+        np.testing.assert_allclose(s[3], gold["stats"][3], rtol=1e-12)
+    assert eng.count_pairs(variant) == int(gold["total_pairs"])
+    cnt, dig = gpu_row_digests(eng, variant, rows)
+    np.testing.assert_array_equal(cnt, gold["count"])
+    np.testing.assert_array_equal(dig, gold["digest"])
+
+
+# ----------------------------------------------------------------------------
+WIDE_ROWS = [(0, 100), ((1 << 18) - 77, 1 << 18)]
+
+
+@pytest.mark.parametrize("variant", ["terms", "batch"])
+def test_wide_workload_sampled(eng, wide_workload, variant):
+    """100 qubits, two words per key, occurrence-count weights: forward and
+    adjoint (the pairs found again by the variant's kernels) on sampled rows."""
+    w = wide_workload
+    check_workload(eng, w, variants=(variant,), rows=WIDE_ROWS, pairs=False)
     L = dev(w.logpsi)
     Wt = dev(w.weights)
-    e, st = eng.local_energy(L, Wt, variant="terms", precision="fp64")
+    e, st = eng.local_energy(L, Wt, variant=variant, precision="fp64")
     E = complex(st[0].item(), st[1].item())
     for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
-        g = eng.adjoint(L, e, st, 1.0 + 0.5j, Wt, precision=prec).cpu().numpy()
-        for a, b in rows:
+        g = eng.adjoint(L, e, st, 1.0 + 0.5j, Wt, variant=variant, precision=prec).cpu().numpy()
+        for a, b in WIDE_ROWS:
             ref_e = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=(a, b))
             ref = oracle.adjoint(w.ham, w.keys, w.logpsi, ref_e, 1.0 + 0.5j, weights=w.weights,
                                  energy_value=E, rows=(a, b))
             err = np.abs(g[a:b] - ref).max()
-            print(f"wide adjoint {prec}: max |dG| = {err:.3e} (max |G| {np.abs(ref).max():.3e})")
+            print(f"wide {variant} adjoint {prec}: max |dG| = {err:.3e} (max |G| {np.abs(ref).max():.3e})")
             assert err <= tol * max(1.0, np.abs(ref).max())
+
+
+def test_wide_workload_pairs_sampled(eng, wide_workload):
+    """Two-word keys: LoopOverBatch's pair list equals the oracle's on the
+    sampled rows (row sets of the canonical list)."""
+    w = wide_workload
+    load(eng, w.ham, w.keys)
+    got = gpu_pairs(eng, "batch")
+    for a, b in WIDE_ROWS:
+        ref = oracle_pairs(w.ham, w.keys, rows=(a, b))
+        m = (got[0] >= a) & (got[0] < b)
+        for x, y in zip(got, ref):
+            np.testing.assert_array_equal(x[m], y)
 
 
 # ----------------------------------------------------------------------------
@@ -252,6 +330,46 @@ def test_long_group_part_uses_wide_format(eng):
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["toy", "odd_y", "small"])
+def test_phase_exponents(eng, small_workload, case):
+    """Per-(pair, term) phase exponents of MatrixElement, bit for bit against
+    the oracle's (themselves pinned by the dense Kronecker build), over the
+    engine's own pair list plus uncoupled pairs; H_ij within 1e-12."""
+    if case == "toy":
+        _, ham, keys, _ = _toy()
+    elif case == "odd_y":
+        rng = np.random.default_rng(17)
+        ham = jw.random_pauli(9, 400, rng, max_flip=3)
+        keys = rng.choice(512, size=300, replace=False).astype(np.uint64)[:, None]
+    else:
+        ham, keys = small_workload.ham, small_workload.keys
+    load(eng, ham, keys)
+    i, j, _ = gpu_pairs(eng, "terms")
+    rng = np.random.default_rng(5)
+    extra = rng.integers(0, keys.shape[0], size=(200, 2))     # mostly uncoupled
+    i = np.concatenate([i, extra[:, 0]])
+    j = np.concatenate([j, extra[:, 1]])
+    h, off, k = eng.pair_elements(dev(i, torch.int32), dev(j, torch.int32), phases=True)
+    ref_off, ref_k = oracle.phase_exponents(ham, keys[i], keys[j])
+    np.testing.assert_array_equal(off.cpu().numpy(), ref_off)
+    np.testing.assert_array_equal(k.cpu().numpy(), ref_k)
+    np.testing.assert_allclose(h.cpu().numpy(), oracle.matrix_elements(ham, keys[i], keys[j]), atol=1e-12)
+    # too small a buffer: ECAPACITY from the deferred check, nothing written
+    import paper_2408_07625_amd as pe
+    if ref_k.size > 1:
+        kk = torch.full((ref_k.size,), 7, dtype=torch.uint8, device="cuda")
+        offs = torch.empty(i.size + 1, dtype=torch.int64, device="cuda")
+        hh = torch.empty(i.size, dtype=torch.complex128, device="cuda")
+        rc = eng.lib.eloc_pair_elements(eng.handle, i.size, pe._ptr(dev(i, torch.int32)),
+                                        pe._ptr(dev(j, torch.int32)), pe._ptr(hh), pe._ptr(offs), pe._ptr(kk),
+                                        ref_k.size - 1)
+        assert rc == 0
+        with pytest.raises(pe.ElocError) as ex:
+            eng.check()
+        assert ex.value.status == "ECAPACITY"
+        assert bool((kk == 7).all())
+
+
 def test_deterministic(eng, small_workload):
     w = small_workload
     load(eng, w.ham, w.keys)
@@ -310,6 +428,16 @@ def test_errors(eng, small_workload):
     e, _ = eng.local_energy(dev(wide), precision="fp64")     # FP64 takes the wide spread
     ref = oracle.local_energy(w.ham, w.keys[:10], wide)
     assert np.abs(e.cpu().numpy() - ref).max() <= TOL64 * max(1.0, np.abs(ref).max())
+    # FP64 up to a spread of 700 (exp of it and of its negative stay normal), not beyond
+    wide = w.logpsi[:10].copy()
+    wide[4] = wide.real.max() - 690.0 + 1j * wide[4].imag
+    e, _ = eng.local_energy(dev(wide), precision="fp64")
+    ref = oracle.local_energy(w.ham, w.keys[:10], wide)
+    assert np.all(np.abs(e.cpu().numpy() - ref) <= TOL64 * np.maximum(1.0, np.abs(ref)))
+    wide[4] -= 20.0
+    with pytest.raises(pe.ElocError) as ex:
+        eng.local_energy(dev(wide), precision="fp64")
+    assert ex.value.status == "ERANGE"
     with pytest.raises(pe.ElocError) as ex:
         eng.pair_elements(dev(np.array([0, 11], dtype=np.int32)), dev(np.array([1, 1], dtype=np.int32)))
     assert ex.value.status == "EINVAL"
@@ -429,3 +557,73 @@ def test_bloom_filter_opt_in(eng, medium_workload):
         assert eng.count_pairs("terms") == 34420502
     finally:
         eng.set_tuning()
+
+
+# ----------------------------------------------------------------------------
+def test_deferred_sample_errors(eng, small_workload):
+    """eloc_set_samples is asynchronous: a duplicate key or a bit >= N is
+    reported by the next synchronising call, the pair kernels do no work on
+    the invalid batch meanwhile, and valid samples afterwards work again."""
+    import paper_2408_07625_amd as pe
+    w = small_workload
+    eng.set_hamiltonian(w.ham.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
+    dup = np.concatenate([w.keys[:50], w.keys[7:8]])
+    lp = dev(np.concatenate([w.logpsi[:50], w.logpsi[7:8]]))
+    eng.set_samples(keys_dev(dup), check=False)
+    for variant in ("terms", "batch", "trie"):
+        eng.local_energy(lp, variant=variant, check=False)
+    with pytest.raises(pe.ElocError) as ex:
+        eng.check()
+    assert ex.value.status == "EDUP"
+    with pytest.raises(pe.ElocError) as ex:
+        eng.count_pairs("terms")
+    assert ex.value.status == "EDUP"
+    bad = w.keys[:50].copy()
+    bad[9, 0] |= np.uint64(1 << 20)
+    eng.set_samples(keys_dev(bad), check=False)
+    with pytest.raises(pe.ElocError) as ex:
+        eng.find_pairs("trie")
+    assert ex.value.status == "EINVAL"
+    eng.set_samples(keys_dev(w.keys[:50]), check=False)
+    e, _ = eng.local_energy(dev(w.logpsi[:50]), variant="trie")
+    ref = oracle.local_energy(w.ham, w.keys[:50], w.logpsi[:50])
+    assert np.abs(e.cpu().numpy() - ref).max() <= TOL64
+
+
+@pytest.mark.parametrize("shift", [400.0, -400.0])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_adjoint_large_log_offset(eng, small_workload, shift, precision):
+    """|psi|^2 weights with every Re log psi offset by +-400 (|psi|^2 itself
+    over- or underflows): E and the gradient do not change."""
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    lp = w.logpsi + shift
+    ref_e = oracle.local_energy(w.ham, w.keys, lp)
+    E, _, _ = oracle.energy(ref_e, lp, None)
+    ref = oracle.adjoint(w.ham, w.keys, lp, ref_e, 0.3 - 0.4j, energy_value=E)
+    L = dev(lp)
+    e, st = eng.local_energy(L, None, precision=precision)
+    g = eng.adjoint(L, e, st, 0.3 - 0.4j, None, precision=precision).cpu().numpy()
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert np.all(np.isfinite(g))
+    assert np.abs(g - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+def test_backward_after_state_change_raises(eng, small_workload):
+    """A LocalEnergy backward refuses to run when the engine's samples or
+    Hamiltonian changed after its forward pass; bad adjoint inputs raise
+    before any kernel launch."""
+    import paper_2408_07625_amd as pe
+    w = small_workload
+    load(eng, w.ham, w.keys)
+    L = dev(w.logpsi).requires_grad_(True)
+    E, e, st = pe.local_energy(eng, L)
+    eng.set_samples(keys_dev(w.keys))
+    with pytest.raises(RuntimeError, match="changed between the forward"):
+        E.real.backward()
+    with pytest.raises(ValueError):
+        eng.adjoint(dev(w.logpsi[:10]), e, st, 1.0)
+    with pytest.raises(ValueError):
+        eng.adjoint(dev(w.logpsi), e, st[:3], 1.0)
+    with pytest.raises(ValueError):
+        eng.adjoint(dev(w.logpsi), e, st, 1.0, weights=dev(np.ones(5)))
