@@ -59,6 +59,14 @@ def _load():
         _lib.oracle_adjoint.restype = ctypes.c_int
         _lib.oracle_adjoint.argtypes = [ctypes.c_int, i64, P, P, P, i64, P, P, P, P, P,
                                         ctypes.c_double, ctypes.c_double, i64, i64, P]
+        _lib.oracle_find_misses.restype = i64
+        _lib.oracle_find_misses.argtypes = [ctypes.c_int, i64, P, P, P, i64, P, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64))]
+        _lib.oracle_free.argtypes = [P]
+        _lib.oracle_free.restype = None
+        _lib.oracle_local_energy_full.restype = ctypes.c_int
+        _lib.oracle_local_energy_full.argtypes = [ctypes.c_int, i64, P, P, P, i64, P, P, i64, P, P,
+                                                  ctypes.c_double, i64, i64, P]
     return _lib
 
 
@@ -203,4 +211,50 @@ def adjoint(ham, keys, logpsi, eloc_rows, grad_e, weights=None, energy_value=Non
     _check(lib.oracle_adjoint(ham.n_qubits, ham.n_terms, _p(c), _p(xy), _p(yz), keys.shape[0],
                               _p(keys), _p(lp), _p(w), _p(er), _p(en),
                               float(np.real(grad_e)), float(np.imag(grad_e)), a, b, _p(out)))
+    return out
+
+
+MISS_TOL = 1e-10   # H_xx' counts as non-zero when |H_xx'| > MISS_TOL * sum |h_l| of its group
+
+
+def find_misses(ham, keys, tol=MISS_TOL):
+    """The states outside U coupled to U by a non-zero matrix element (the
+    x' of Eq. local_energy that the sample-aware sum leaves out): uint64
+    [n, W], unique, sorted ascending as W-word integers."""
+    lib = _load()
+    c, xy, yz = _ham_arrays(ham)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    W = keys.shape[1]
+    ptr = ctypes.POINTER(ctypes.c_uint64)()
+    n = lib.oracle_find_misses(ham.n_qubits, ham.n_terms, _p(c), _p(xy), _p(yz), keys.shape[0], _p(keys),
+                               float(tol), ctypes.byref(ptr))
+    if n < 0:
+        if ptr:
+            lib.oracle_free(ptr)
+        _check(int(n))
+    try:
+        out = np.ctypeslib.as_array(ptr, shape=(max(int(n), 1) * W,))[: int(n) * W].copy().reshape(int(n), W)
+    finally:
+        lib.oracle_free(ptr)
+    return out
+
+
+def local_energy_full(ham, keys, logpsi, keys_v, logpsi_v, tol=MISS_TOL, rows=None):
+    """Conventional local energy (Eq. local_energy) for rows [a, b) of U,
+    amplitudes of U from logpsi and of the extra states V from logpsi_v."""
+    lib = _load()
+    c, xy, yz = _ham_arrays(ham)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    lp = np.ascontiguousarray(logpsi, dtype=np.complex128)
+    kv = np.ascontiguousarray(keys_v, dtype=np.uint64).reshape(-1, keys.shape[1])
+    lv = np.ascontiguousarray(logpsi_v, dtype=np.complex128)
+    assert lv.size == kv.shape[0]
+    a, b = (0, keys.shape[0]) if rows is None else rows
+    out = np.empty(b - a, dtype=np.complex128)
+    rc = lib.oracle_local_energy_full(ham.n_qubits, ham.n_terms, _p(c), _p(xy), _p(yz), keys.shape[0], _p(keys),
+                                      _p(lp), kv.shape[0], _p(kv) if kv.size else None, _p(lv) if lv.size else None,
+                                      float(tol), a, b, _p(out))
+    if rc == -3:
+        raise OracleError("a coupled state with a non-zero matrix element is in neither U nor V")
+    _check(rc)
     return out

@@ -466,3 +466,147 @@ int oracle_adjoint(int n_qubits, int64_t n_terms, const double* coeff, const uin
     ham_free(&H);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Conventional local energy (Eq. local_energy over all x', not only U)     */
+/* ---------------------------------------------------------------------- */
+
+/* sum of |h_l| over the terms of group g: the scale of "H_xx' != 0" */
+static double group_abs_sum(const ham_t* H, int64_t g) {
+    double s = 0.0;
+    for (int64_t t = H->grp_begin[g]; t < H->grp_begin[g + 1]; ++t) s += fabs(H->coeff[H->term_of[t]]);
+    return s;
+}
+
+/* |H_xx'| > tol * sum_{l in P_g} |h_l|: the reading of "H_xx' != 0" that
+ * treats strings cancelling in exact arithmetic (hopping strings between
+ * particle-number sectors) as zero */
+static int coupled_nonzero(const ham_t* H, int64_t g, const uint64_t* xprime, double tol) {
+    double complex h = matrix_element(H, g, xprime);
+    return cabs(h) > tol * group_abs_sum(H, g);
+}
+
+static int key_cmp_desc_words(const void* a, const void* b) {
+    const uint64_t* x = (const uint64_t*)a;
+    const uint64_t* y = (const uint64_t*)b;
+    for (int w = W_cmp - 1; w >= 0; --w) {
+        if (x[w] < y[w]) return -1;
+        if (x[w] > y[w]) return 1;
+    }
+    return 0;
+}
+
+void oracle_free(void* p) { free(p); }
+
+/* The states outside U that H couples to a sampled state: the x' of the sum
+ * of Eq. local_energy that the sample-aware form leaves out,
+ *   V = { x' not in U : x' = x ^ XY_g, x in U, |H_xx'| > tol sum_{l in P_g} |h_l| },
+ * each once, sorted ascending as W-word integers (most significant word
+ * first).  *out receives a malloc'ed [count][W] array (oracle_free).
+ * Returns the count, -1 bad input, -2 duplicate keys in U. */
+int64_t oracle_find_misses(int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
+                           const uint64_t* yz, int64_t n_unique, const uint64_t* keys, double tol,
+                           uint64_t** out) {
+    *out = NULL;
+    ham_t H;
+    if (ham_build(&H, n_qubits, n_terms, coeff, xy, yz) != 0) return -1;
+    table_t T;
+    int rc = table_build(&T, H.W, n_unique, keys);
+    if (rc != 0) { ham_free(&H); free(T.sorted); return rc; }
+    const int W = H.W;
+    int nthreads = omp_get_max_threads();
+    uint64_t** part = (uint64_t**)calloc((size_t)nthreads, sizeof(uint64_t*));
+    int64_t* plen = (int64_t*)calloc((size_t)nthreads, sizeof(int64_t));
+    int64_t* pcap = (int64_t*)calloc((size_t)nthreads, sizeof(int64_t));
+#pragma omp parallel
+    {
+        const int t = omp_get_thread_num();
+        uint64_t xp[MAXW] = {0, 0};
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n_unique; ++i) {
+            const uint64_t* x = keys + i * W;
+            for (int64_t g = 0; g < H.n_groups; ++g) {
+                for (int w = 0; w < W; ++w) xp[w] = x[w] ^ H.grp_xy[g * W + w];
+                if (table_find(&T, xp) >= 0) continue;          /* in U: a pair of E_loc^var */
+                if (!coupled_nonzero(&H, g, xp, tol)) continue;
+                if (plen[t] == pcap[t]) {
+                    pcap[t] = pcap[t] ? 2 * pcap[t] : 1024;
+                    part[t] = (uint64_t*)realloc(part[t], sizeof(uint64_t) * (size_t)(pcap[t] * W));
+                }
+                for (int w = 0; w < W; ++w) part[t][plen[t] * W + w] = xp[w];
+                ++plen[t];
+            }
+        }
+    }
+    int64_t total = 0;
+    for (int t = 0; t < nthreads; ++t) total += plen[t];
+    uint64_t* all = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)((total > 0 ? total : 1) * W));
+    int64_t pos = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (plen[t]) memcpy(all + pos * W, part[t], sizeof(uint64_t) * (size_t)(plen[t] * W));
+        pos += plen[t];
+        free(part[t]);
+    }
+    free(part);
+    free(plen);
+    free(pcap);
+    W_cmp = W;
+    qsort(all, (size_t)total, sizeof(uint64_t) * (size_t)W, key_cmp_desc_words);
+    int64_t n = 0;
+    for (int64_t a = 0; a < total; ++a) {
+        if (n > 0 && key_cmp_desc_words(all + a * W, all + (n - 1) * W) == 0) continue;
+        if (n != a) memmove(all + n * W, all + a * W, sizeof(uint64_t) * (size_t)W);
+        ++n;
+    }
+    *out = all;
+    free(T.sorted);
+    ham_free(&H);
+    return n;
+}
+
+/* Conventional local energy of Eq. local_energy for rows [row_begin,
+ * row_end) of U: E_loc(x) = sum over the XY groups g of H_{x x'} psi(x')/psi(x)
+ * with x' = x ^ XY_g, the amplitudes taken from U (logpsi) or from the extra
+ * states V (keys_v, logpsi_v; V disjoint from U).  A coupled x' found in
+ * neither contributes only when |H_xx'| > tol sum |h| (the reading of
+ * H_xx' != 0 above), and is then an error: its amplitude is missing.
+ * Returns 0, -1 bad input, -2 duplicate keys in U or V, -3 missing state. */
+int oracle_local_energy_full(int n_qubits, int64_t n_terms, const double* coeff, const uint64_t* xy,
+                             const uint64_t* yz, int64_t n_unique, const uint64_t* keys, const double* logpsi,
+                             int64_t n_v, const uint64_t* keys_v, const double* logpsi_v, double tol,
+                             int64_t row_begin, int64_t row_end, double* eloc_out) {
+    ham_t H;
+    if (ham_build(&H, n_qubits, n_terms, coeff, xy, yz) != 0) return -1;
+    const int W = H.W;
+    /* one ordered table of U followed by V: index < n_unique is a sample of U */
+    uint64_t* all = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)((n_unique + n_v) * W + 1));
+    memcpy(all, keys, sizeof(uint64_t) * (size_t)(n_unique * W));
+    if (n_v) memcpy(all + n_unique * W, keys_v, sizeof(uint64_t) * (size_t)(n_v * W));
+    table_t T;
+    int rc = table_build(&T, W, n_unique + n_v, all);
+    if (rc != 0) { ham_free(&H); free(T.sorted); free(all); return rc; }
+    int missing = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : missing)
+    for (int64_t i = row_begin; i < row_end; ++i) {
+        const uint64_t* x = keys + i * W;
+        double complex Li = load_c(logpsi, i);
+        double complex e = 0.0;
+        uint64_t xp[MAXW] = {0, 0};
+        for (int64_t g = 0; g < H.n_groups; ++g) {
+            for (int w = 0; w < W; ++w) xp[w] = x[w] ^ H.grp_xy[g * W + w];
+            int64_t j = table_find(&T, xp);
+            if (j < 0) {
+                if (coupled_nonzero(&H, g, xp, tol)) missing = 1;
+                continue;
+            }
+            double complex Lj = j < n_unique ? load_c(logpsi, j) : load_c(logpsi_v, j - n_unique);
+            e += matrix_element(&H, g, xp) * cexp(Lj - Li);
+        }
+        eloc_out[2 * (i - row_begin)] = creal(e);
+        eloc_out[2 * (i - row_begin) + 1] = cimag(e);
+    }
+    free(T.sorted);
+    free(all);
+    ham_free(&H);
+    return missing ? -3 : 0;
+}

@@ -343,3 +343,119 @@ def test_adjoint_matches_torch_autograd_dense():
             Eo, _, _ = oracle.energy(e, L, weights)
             g = oracle.adjoint(ham, keys, L, e, ge, weights=weights, energy_value=Eo)
             np.testing.assert_allclose(g, Lt.grad.numpy(), atol=1e-10)
+
+
+# ----------------------------------------------------------------------------
+# Conventional local energy (Eq. local_energy, the sum over every x'): the
+# states outside U with a non-zero matrix element, and E_loc over U and them.
+def _dense_misses(H, basis_idx, thresh=1e-9):
+    """x' not in U with |<x|H|x'>| > thresh for some x in U (dense H)."""
+    rows = np.abs(H[basis_idx, :]).max(axis=0) > thresh
+    rows[basis_idx] = False
+    return np.flatnonzero(rows)
+
+
+@pytest.mark.parametrize("N,T,seed", [(5, 40, 20), (7, 80, 21)])
+def test_full_local_energy_dense_random_pauli(N, T, seed):
+    """Against the dense matrix of textbook Pauli products: the miss set is
+    every state outside U that H reaches from U, and E_loc(x) = (H psi)(x) /
+    psi(x) over the whole space for a random psi."""
+    rng = np.random.default_rng(seed)
+    ham = jw.random_pauli(N, T, rng, max_flip=3)
+    H = pins.dense_pauli_kron(ham)
+    D = 2 ** N
+    M = 12
+    idx = rng.choice(D, size=M, replace=False)
+    keys = idx.astype(np.uint64)[:, None]
+    V = oracle.find_misses(ham, keys)
+    np.testing.assert_array_equal(V[:, 0].astype(np.int64), _dense_misses(H, idx))
+    L = rng.normal(scale=0.5, size=D) + 1j * rng.uniform(0, 2 * np.pi, size=D)
+    psi = np.exp(L)
+    vi = V[:, 0].astype(np.int64)
+    e = oracle.local_energy_full(ham, keys, L[idx], V, L[vi])
+    np.testing.assert_allclose(e, (H @ psi)[idx] / psi[idx], rtol=1e-10, atol=1e-10)
+
+
+def test_full_local_energy_jw_cancellation():
+    """Jordan-Wigner H of real integrals: strings coupling different
+    particle-number sectors cancel, so those x' are not misses even though
+    x ^ x' is an XY mask of H; the miss set equals the dense non-zeros."""
+    N = 8
+    rng = np.random.default_rng(30)
+    ham, h, g = jw.random_jw(N, rng)
+    H = pins.dense_pauli(ham)
+    sector = _sector(N, 2, 2)
+    others = np.setdiff1d(np.arange(2 ** N), sector)
+    idx = np.concatenate([rng.choice(sector, size=10, replace=False), rng.choice(others, size=6, replace=False)])
+    keys = idx.astype(np.uint64)[:, None]
+    V = oracle.find_misses(ham, keys)
+    np.testing.assert_array_equal(V[:, 0].astype(np.int64), _dense_misses(H, idx))
+    # some XOR partners of U exist that are not coupled (cancelled strings)
+    xy = {int(m) for m in ham.xy[:, 0]}
+    partners = {int(x) ^ m for x in idx for m in xy} - set(int(x) for x in idx)
+    assert len(partners) > V.shape[0]
+    L = rng.normal(scale=0.5, size=2 ** N) + 1j * rng.uniform(0, 2 * np.pi, size=2 ** N)
+    psi = np.exp(L)
+    e = oracle.local_energy_full(ham, keys, L[idx], V, L[V[:, 0].astype(np.int64)])
+    np.testing.assert_allclose(e, (H @ psi)[idx] / psi[idx], rtol=1e-10, atol=1e-10)
+    # without the misses' amplitudes the conventional sum is incomplete
+    with pytest.raises(oracle.OracleError):
+        oracle.local_energy_full(ham, keys, L[idx], V[:-1], L[V[:-1, 0].astype(np.int64)])
+
+
+@pytest.mark.parametrize("k", [0, 5])
+def test_full_local_energy_of_eigenvector_is_eigenvalue(k):
+    """For an eigenvector psi of H, E_loc(x) = lambda for every x, whatever
+    U is (no sector structure in a random Pauli Hamiltonian)."""
+    rng = np.random.default_rng(40 + k)
+    N = 6
+    ham = jw.random_pauli(N, 50, rng, max_flip=3)
+    H = pins.dense_pauli_kron(ham)
+    lam, vec = np.linalg.eigh(H)
+    psi = vec[:, k]
+    assert np.abs(psi).min() > 1e-8
+    L = np.log(psi.astype(complex))
+    idx = rng.choice(2 ** N, size=9, replace=False)
+    keys = idx.astype(np.uint64)[:, None]
+    V = oracle.find_misses(ham, keys)
+    e = oracle.local_energy_full(ham, keys, L[idx], V, L[V[:, 0].astype(np.int64)])
+    np.testing.assert_allclose(e, lam[k], atol=1e-9)
+
+
+def test_misses_two_words_brute_force():
+    """70 qubits (two words per key): the miss set equals a brute force over
+    U x Pauli strings whose matrix elements are products of textbook 2x2
+    entries, sorted as 128-bit integers (high word first)."""
+    rng = np.random.default_rng(50)
+    N, T, M = 70, 40, 25
+    ham = jw.random_pauli(N, T, rng, max_flip=2)
+    keys = np.unique(rng.integers(0, 2 ** 63, size=(M, 2), dtype=np.int64).astype(np.uint64), axis=0)
+    keys[:, 1] &= np.uint64((1 << (N - 64)) - 1)
+    keys = np.unique(keys, axis=0)
+    U = {(int(k[1]) << 64) | int(k[0]) for k in keys}
+    lets = [pins.letters(N, ham.xy[l], ham.yz[l]) for l in range(T)]
+
+    def entry(ls, x, xp):
+        v = 1.0 + 0j
+        for q in range(N):
+            v *= pins.PAULI[ls[q]][(x >> q) & 1, (xp >> q) & 1]
+            if v == 0:
+                return 0j
+        return v
+
+    masks = {}
+    for l in range(T):
+        m = (int(ham.xy[l, 1]) << 64) | int(ham.xy[l, 0])
+        masks.setdefault(m, []).append(l)
+    want = set()
+    for x in U:
+        for m, ls in masks.items():
+            xp = x ^ m
+            if xp in U:
+                continue
+            h = sum(ham.coeff[l] * entry(lets[l], x, xp) for l in ls)
+            if abs(h) > 1e-10 * sum(abs(ham.coeff[l]) for l in ls):
+                want.add(xp)
+    V = oracle.find_misses(ham, keys)
+    got = [(int(v[1]) << 64) | int(v[0]) for v in V]
+    assert got == sorted(want)
