@@ -36,8 +36,13 @@ def build(force: bool = True) -> Path:
 def _load():
     global _lib
     if _lib is None:
-        build(force=False)
-        _lib = ctypes.CDLL(str(_LIB))
+        # ORACLE_LIB: a separately built copy (the sanitizer test's build)
+        alt = os.environ.get("ORACLE_LIB")
+        if alt:
+            _lib = ctypes.CDLL(alt)
+        else:
+            build(force=False)
+            _lib = ctypes.CDLL(str(_LIB))
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         _lib.oracle_set_threads.argtypes = [ctypes.c_int]
