@@ -6,15 +6,17 @@ ratio accumulation (one fused kernel), the per-row combination and the
 weighted energy / variance reductions.  Hamiltonian ingest is done once,
 before timing, as the paper precomputes it.
 
-Workload: 28 qubits, 14 electrons, 65 536 unique determinants (HF plus
-rank <= 4 excitations), JW Hamiltonian from seeded random integrals; inputs
-are resident in device memory before timing starts.
+Headline workload (default): 52 qubits, 20 electrons, 2^20 unique
+determinants (HF plus rank <= 4 excitations), JW Hamiltonian from seeded
+random integrals (669 579 Pauli terms); inputs are resident in device memory
+before timing starts.  All three FindCoupledPairs variants are timed in both
+precisions, with the per-stage breakdown.
 
-Prints one JSON line.  value = coupled pairs/s of the compensated-FP32 form;
-the plain FP64 form is reported beside it.  The "batched" object times the
-64-problem batched launch (qubit counts 16..40, unique batches 10^3..10^5,
-one persistent launch replayed from a HIP graph, autotuned schedule)
-against the same problems run as 64 sequential single launches.
+Prints one JSON line.  value = coupled pairs/s of the compensated-FP32 form
+of the headline variant; the plain FP64 form is reported beside it.  Extra
+objects: "medium" (28 qubits, 65 536 samples), "batched" (64 problems in one
+persistent launch replayed from a HIP graph, against 64 sequential
+launches), "adjoint" (100 qubits, forward + dE/dlog psi).
 """
 from __future__ import annotations
 
@@ -29,7 +31,11 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 PROFILES = ROOT / "profiles"
+GOLDEN = ROOT / "tests" / "golden"
 PAIR_SOURCES = [ROOT / "paper_2408_07625_amd" / "csrc" / f for f in ("pairs.hip", "device.h", "internal.h")]
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock: one wave instruction per CU per clock
+PEAK_HBM = 8.0e12                  # bytes/s
 
 
 def pair_source_hash() -> str:
@@ -59,18 +65,34 @@ def measured_traffic(name: str):
         return None
 
 
-# Algorithmic lane-op counts per unit of work of the fused pair kernel (W
-# 64-bit words per key); see the design notes for the derivation.
-def ops_per_candidate(W):
-    return 2 * W + 3          # x ^ XY (2W), hash combine (2), slot index (1)
+# Algorithmic lane-operations per unit of work (W 64-bit words per key):
+#  LoopOverTerms candidate: x ^ XY (2W int32 ops) + one hash probe (~10);
+#  LoopOverBatch candidate: x ^ x' (2W), popcount (2W), compare + ballot (2);
+#  term evaluation: AND + popcount of ket & YZ, parity select, add (~12);
+#  coupled pair: one complex multiply-accumulate, 4 FP64 FMAs or about 30
+#  FP32 operations in the compensated form (TwoProduct x4 + TwoSum x2).
+#  LoopOverTrie node-pair visit: masked XOR of row, U and XY keys over the
+#  bit run (4W), branch-bit compare, child selection and push (~10).
+def ops_per_candidate(variant: str, W: int) -> int:
+    if variant == "terms":
+        return 2 * W + 10
+    if variant == "trie":
+        return 4 * W + 10
+    return 4 * W + 2
 
 
-def ops_per_term(W):
-    return 4 * W + 3          # AND + popcount of ket & YZ (4W), parity select (2), add (1)
+OPS_PER_TERM = 12
+OPS_PER_PAIR = {"fp64": 4, "fp32c": 30}
 
 
-OPS_PER_PAIR = 4              # complex multiply-accumulate: 4 FMAs
-PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes/clock x clock: 3.93e13 lane-ops/s
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def parse():
@@ -78,16 +100,84 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="medium")
-    ap.add_argument("--variant", default="terms")
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--variant", default="terms", help="headline FindCoupledPairs variant")
+    ap.add_argument("--other-steps", type=int, default=5, help="timed steps of the other variants (at most --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", action="store_true", help="time only the headline variant")
+    ap.add_argument("--no-medium", action="store_true", help="skip the 28-qubit object")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-launch measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint measurement")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the conventional local energy, SR and sampler measurements")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reads and writes it once), "
                          "the reference kernel for scaling hardware byte counters")
     return ap.parse_args()
+
+
+def group_sizes_by_id(ham):
+    """Terms per XY group, groups numbered in first-appearance order."""
+    import numpy as np
+    _, first, cnt = np.unique(ham.xy, axis=0, return_index=True, return_counts=True)
+    rank = np.empty(first.size, dtype=np.int64)
+    rank[np.argsort(first)] = np.arange(first.size)
+    sizes = np.zeros(first.size, dtype=np.int64)
+    sizes[rank] = cnt
+    return sizes
+
+
+def term_evaluations(eng, variant, sizes):
+    """Sum over the coupled pairs of their group's term count (on the GPU)."""
+    import torch
+    _, _, g = eng.find_pairs(variant)
+    sz = torch.from_numpy(sizes).cuda()
+    total = 0
+    step = 1 << 27
+    for a in range(0, g.numel(), step):
+        total += int(sz[g[a:a + step].long()].sum().item())
+    del g
+    torch.cuda.empty_cache()
+    return total
+
+
+def time_steps(eng, step, steps, warmup):
+    """W warm-up steps, then K timed steps between synchronisations, HIP
+    events on the engine's stream around each stage (eloc_profile_*)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    eng.check()
+    torch.cuda.synchronize()
+    eng.profile(True)
+    eng.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    eng.check()
+    prof = eng.profile_read()
+    eng.profile(False)
+    return e0.elapsed_time(e1) / steps, prof
+
+
+def roofline(variant, prec, W, M, n_terms, n_groups, cand, term_evals, n_pairs, kernel_s, traffic):
+    ops = cand * ops_per_candidate(variant, W) + term_evals * OPS_PER_TERM + n_pairs * OPS_PER_PAIR[prec]
+    # compulsory bytes of one launch: keys, amplitudes in, row sums out,
+    # the term and group records of the Hamiltonian
+    compulsory = M * (8 * W + 16 + 16) + n_terms * (8 * W + 8) + n_groups * (8 * W + 8)
+    achieved = ops / kernel_s
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+         "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+         "kernel": f"k_pairs {variant} {prec} (fused FindCoupledPairs + MatrixElement + accumulation)",
+         "kernel_ms": kernel_s * 1e3, "ops_per_launch": ops,
+         "hbm": {"compulsory_bytes": compulsory, "compulsory_frac": compulsory / kernel_s / PEAK_HBM,
+                 "counter_bytes": traffic,
+                 "counter_frac": None if traffic is None else traffic / kernel_s / PEAK_HBM}}
+    return r
 
 
 def main():
@@ -104,145 +194,123 @@ def main():
     import paper_2408_07625_amd as pe
     from synth import configs
 
+    t0 = time.perf_counter()
     w = configs.by_name(args.workload)
     M, N, W = w.n_unique, w.n_qubits, w.ham.n_words
     eng = pe.Engine(0)
     eng.set_hamiltonian(N, w.ham.coeff, w.ham.xy, w.ham.yz)
     info = eng.info()
+    G, NT = info["n_groups"], info["n_terms"]
     keys = torch.from_numpy(w.keys.view(np.int64)).cuda()
     L = torch.from_numpy(w.logpsi).cuda()
     Wt = None if w.weights is None else torch.from_numpy(w.weights).cuda()
     out = torch.empty(M, dtype=torch.complex128, device="cuda")
     stats = torch.empty(4, dtype=torch.float64, device="cuda")
-    print(f"# workload {w.name}: N={N} M={M} terms={info['n_terms']} groups={info['n_groups']}",
+    print(f"# workload {w.name}: N={N} M={M} terms={NT} groups={G} (set up in {time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
 
-    def step(prec):
-        eng.set_samples(keys, check=False)
-        eng.local_energy(L, Wt, args.variant, prec, out=out, stats=stats, check=False)
+    def make_step(variant, prec):
+        def step():
+            eng.set_samples(keys, check=False)
+            eng.local_energy(L, Wt, variant, prec, out=out, stats=stats, check=False)
+        return step
 
-    results = {}
-    for prec in ("fp64", "fp32c"):
-        for _ in range(args.warmup):
-            step(prec)
-        eng.check()
-        torch.cuda.synchronize()
-        eng.profile(True)
-        eng.profile_read()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record()
-        for _ in range(args.steps):
-            step(prec)
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        eng.check()
-        prof = eng.profile_read()
-        eng.profile(False)
-        ms = e0.elapsed_time(e1) / args.steps
-        results[prec] = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / args.steps, "stages": prof,
-                         "eloc": out.cpu().numpy().copy(), "stats": stats.cpu().numpy().copy()}
-        print(f"# {prec}: {ms:.3f} ms/step  stages(ms/launch): " +
-              ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]),
-              file=sys.stderr, flush=True)
+    order = [args.variant] + [v for v in ("terms", "batch", "trie") if v != args.variant and not args.only]
+    res = {}
+    for var in order:
+        steps = args.steps if var == args.variant else min(args.steps, args.other_steps)
+        warm = args.warmup if var == args.variant else min(args.warmup, 2)
+        for prec in ("fp64", "fp32c"):
+            ms, prof = time_steps(eng, make_step(var, prec), steps, warm)
+            res.setdefault(var, {})[prec] = {
+                "ms_per_step": ms, "steps": steps,
+                "stage_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+                "eloc": out.cpu().numpy().copy(), "stats": stats.cpu().numpy().copy()}
+            print(f"# {var} {prec}: {ms:.3f} ms/step  stages(ms/launch): " +
+                  ", ".join(f"{k}={v[0] / v[1]:.3f}" for k, v in prof.items() if v[1]),
+                  file=sys.stderr, flush=True)
 
-    # the other FindCoupledPairs variants, same workload and protocol
-    variants = {}
-    for var in ("terms", "batch", "trie"):
-        if var == args.variant or args.only:
+    # work counts (outside the timed regions)
+    sizes = group_sizes_by_id(w.ham)
+    n_pairs = eng.count_pairs(args.variant)
+    term_evals = term_evaluations(eng, args.variant, sizes)
+    counts = {}
+    for var in order:
+        counts[var] = {"coupled_pairs": eng.count_pairs(var),
+                       "candidates": M * G if var == "terms" else (M * M if var == "batch" else eng.trie_visits())}
+        assert counts[var]["coupled_pairs"] == n_pairs, (var, counts[var], n_pairs)
+    print(f"# {n_pairs} coupled pairs, {term_evals} term evaluations", file=sys.stderr, flush=True)
+
+    head = res[args.variant]["fp32c"]
+    fp64 = res[args.variant]["fp64"]
+    pairs_s = n_pairs / (head["ms_per_step"] * 1e-3)
+
+    traffic = measured_traffic(f"k_pairs_{w.name}_{args.variant}_fp32c_traffic.md")
+    rooflines = {}
+    for var in order:
+        if counts[var]["candidates"] is None:
             continue
         for prec in ("fp64", "fp32c"):
-            for _ in range(args.warmup):
-                eng.set_samples(keys, check=False)
-                eng.local_energy(L, Wt, var, prec, out=out, stats=stats, check=False)
-            eng.check()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.steps):
-                eng.set_samples(keys, check=False)
-                eng.local_energy(L, Wt, var, prec, out=out, stats=stats, check=False)
-            e1.record()
-            torch.cuda.synchronize()
-            eng.check()
-            variants.setdefault(var, {})[prec] = e0.elapsed_time(e1) / args.steps
-        print(f"# variant {var}: " + ", ".join(f"{p}={v:.3f} ms/step" for p, v in variants[var].items()),
-              file=sys.stderr, flush=True)
-
-    # work counts (outside the timed region)
-    n_pairs = eng.count_pairs(args.variant)
-    _, _, gids = eng.find_pairs(args.variant)
-    # terms per group, groups numbered in first-appearance order of their XY mask
-    _, first, inv, cnt = np.unique(w.ham.xy, axis=0, return_index=True, return_inverse=True,
-                                   return_counts=True)
-    rank = np.empty(first.size, dtype=np.int64)
-    rank[np.argsort(first)] = np.arange(first.size)
-    sizes = np.zeros(first.size, dtype=np.int64)
-    sizes[rank] = cnt
-    term_evals = int(sizes[gids.cpu().numpy()].sum())
-    candidates = M * info["n_groups"] if args.variant == "terms" else M * M
-
-    headline = results["fp32c"]
-    pairs_s = n_pairs / (headline["ms_per_step"] * 1e-3)
-    samples_s = M / (headline["ms_per_step"] * 1e-3)
-    fp64 = results["fp64"]
-
-    # roofline of the dominant kernel (fused pair kernel), ALU bound
-    pair_ms, pair_n = headline["stages"]["pairs"]
-    pair_avg_s = pair_ms / max(pair_n, 1) * 1e-3
-    ops = candidates * ops_per_candidate(W) + term_evals * ops_per_term(W) + n_pairs * OPS_PER_PAIR
-    achieved = ops / pair_avg_s
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-            "frac": achieved / PEAK_LANE_OPS,
-            "traffic": measured_traffic(f"k_pairs_{w.name}_{args.variant}_fp32c_traffic.md"),
-            "kernel": "k_pairs (fused FindCoupledPairs + MatrixElement + accumulation)",
-            "kernel_ms": pair_avg_s * 1e3,
-            "ops_per_launch": ops}
+            k_ms = res[var][prec]["stage_ms"]["pairs"]
+            rooflines[f"{var}_{prec}"] = roofline(var, prec, W, M, NT, G, counts[var]["candidates"], term_evals,
+                                                  n_pairs, k_ms * 1e-3,
+                                                  traffic if (var, prec) == (args.variant, "fp32c") else None)
+    roof = rooflines[f"{args.variant}_fp32c"]
 
     rec = {
         "metric": "coupled pairs/sec + E_loc^var samples/sec vs plain FP64 at |dE|<=1e-6 Ha",
         "value": pairs_s, "unit": "coupled pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": headline["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32c", "data": "synthetic",
         "config": {"workload": f"{w.name}: {N} qubits, {w.n_electrons} electrons, {M} unique determinants, "
-                               f"{info['n_terms']} Pauli terms in {info['n_groups']} XY groups",
+                               f"{NT} Pauli terms in {G} XY groups",
                    "variant": args.variant, "global_batch": M},
-        "samples_per_s": samples_s,
-        "coupled_pairs": n_pairs, "candidates": candidates, "term_evaluations": term_evals,
+        "samples_per_s": M / (head["ms_per_step"] * 1e-3),
+        "coupled_pairs": n_pairs, "candidates": counts[args.variant]["candidates"], "term_evaluations": term_evals,
         "fp64": {"pairs_per_s": n_pairs / (fp64["ms_per_step"] * 1e-3),
                  "samples_per_s": M / (fp64["ms_per_step"] * 1e-3), "ms_per_step": fp64["ms_per_step"]},
-        "fp32c_over_fp64": fp64["ms_per_step"] / headline["ms_per_step"],
-        "stage_ms": {p: {k: v[0] / max(v[1], 1) for k, v in results[p]["stages"].items() if v[1]}
-                     for p in results},
+        "fp32c_over_fp64": fp64["ms_per_step"] / head["ms_per_step"],
         "roofline": roof,
-        "other_variants_ms_per_step": variants,
+        "variants": {var: {prec: {"ms_per_step": res[var][prec]["ms_per_step"], "steps": res[var][prec]["steps"],
+                                  "pairs_per_s": n_pairs / (res[var][prec]["ms_per_step"] * 1e-3),
+                                  "stage_ms": res[var][prec]["stage_ms"],
+                                  "roofline_frac": rooflines.get(f"{var}_{prec}", {}).get("frac")}
+                           for prec in ("fp64", "fp32c")} | {"candidates": counts[var]["candidates"]}
+                     for var in order},
     }
 
+    # accuracy against the oracle's stored results for this workload
+    gold_path = GOLDEN / f"{w.name}_oracle.npz"
+    if gold_path.exists():
+        gold = dict(np.load(gold_path, allow_pickle=False))
+        rows = gold["rows"]
+        E_ref = gold["stats"][0] + 1j * gold["stats"][1]
+        rec["accuracy"] = {"reference": f"oracle results stored in tests/golden/{gold_path.name} "
+                                        f"({rows.size} sampled rows; E and Var over all rows)"}
+        for var in order:
+            for prec in ("fp64", "fp32c"):
+                r = res[var][prec]
+                rec["accuracy"][f"{var}_{prec}"] = {
+                    "max_abs_dE_loc": float(np.abs(r["eloc"][rows] - gold["eloc"]).max()),
+                    "abs_dE": float(abs(r["stats"][0] + 1j * r["stats"][1] - E_ref)),
+                    "abs_dVar": float(abs(r["stats"][2] - gold["stats"][2]))}
+        rec["energy"] = {"E": float(gold["stats"][0]), "Var": float(gold["stats"][2])}
+
     if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.perf_counter()
-        ref = oracle.local_energy(w.ham, w.keys, w.logpsi)
-        cpu_s = time.perf_counter() - t0
-        E_ref, var_ref, _ = oracle.energy(ref, w.logpsi, w.weights)
-        rec["accuracy"] = {
-            p: {"max_abs_dE_loc": float(np.abs(results[p]["eloc"] - ref).max()),
-                "abs_dE": float(abs(results[p]["stats"][0] + 1j * results[p]["stats"][1] - E_ref)),
-                "abs_dVar": float(abs(results[p]["stats"][2] - var_ref))} for p in results}
-        rec["energy"] = {"E": E_ref.real, "Var": var_ref}
-        if not args.no_cpu_baseline:
-            rec["cpu_baseline"] = {"value": n_pairs / cpu_s, "unit": "coupled pairs/s",
-                                   "cores": oracle.max_threads(), "kind": "oracle",
-                                   "sample": f"all {M} rows of the workload, one forward pass "
-                                             f"({cpu_s:.2f} s wall)",
-                                   "samples_per_s": M / cpu_s}
+        rec["cpu_baseline"] = cpu_baseline(w, res[args.variant])
+    if not args.no_medium and w.name != "medium":
+        eng.close()
+        eng = None
+        rec["medium"] = bench_medium(args)
     if not args.no_batched:
         rec["batched"] = bench_batched(args)
     if not args.no_adjoint:
         rec["adjoint"] = bench_adjoint(args)
+    if not args.no_next:
+        rec["full_local_energy"] = bench_full(args)
+        rec["sr"] = bench_sr(args)
+        rec["sampler"] = bench_sampler(args)
     if args.calibrate_mib:
         n = args.calibrate_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -252,7 +320,192 @@ def main():
         torch.cuda.synchronize()
         rec["calibration_copy_bytes"] = 2 * n * 8
     print(json.dumps(rec))
+    if eng is not None:
+        eng.close()
+
+
+def cpu_baseline(w, res_head):
+    """The oracle (plain C, FP64, OpenMP over rows) on a bounded sample of
+    rows of the same workload: all host threads, and one thread."""
+    import numpy as np
+
+    import oracle
+    M = w.n_unique
+    threads = oracle.max_threads()
+    # about 10 s of oracle work each at the 52-qubit workload
+    per_thread_rows = max(16, min(M // max(threads, 1), int(4096 * 16 / max(threads, 1)) // 16))
+    rows_all = (0, min(M, per_thread_rows * threads))
+    rows_one = (0, min(M, per_thread_rows))
+    t0 = time.perf_counter()
+    ref, npairs = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=rows_all, with_pairs=True)
+    t_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    _, npairs1 = oracle.local_energy(w.ham, w.keys, w.logpsi, rows=rows_one, with_pairs=True)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    a, b = rows_all
+    acc = {p: float(np.abs(res_head[p]["eloc"][a:b] - ref).max()) for p in ("fp64", "fp32c")}
+    return {"value": float(npairs.sum()) / t_all, "unit": "coupled pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows [{a}, {b}) of the workload ({b - a} of {M} samples, {int(npairs.sum())} coupled "
+                      f"pairs), one forward pass, {t_all:.2f} s wall on {threads} threads",
+            "samples_per_s": (b - a) / t_all,
+            "single_thread": {"value": float(npairs1.sum()) / t_one, "unit": "coupled pairs/s",
+                              "sample": f"rows [{rows_one[0]}, {rows_one[1]}), {t_one:.2f} s wall",
+                              "samples_per_s": (rows_one[1] - rows_one[0]) / t_one},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "gpu_vs_oracle_max_abs_dE_loc": acc}
+
+
+def bench_medium(args):
+    """28 qubits, 65 536 samples: LoopOverTerms, both precisions."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    from synth import configs
+
+    w = configs.medium()
+    M, N, W = w.n_unique, w.n_qubits, w.ham.n_words
+    eng = pe.Engine(0)
+    eng.set_hamiltonian(N, w.ham.coeff, w.ham.xy, w.ham.yz)
+    info = eng.info()
+    keys = torch.from_numpy(w.keys.view(np.int64)).cuda()
+    L = torch.from_numpy(w.logpsi).cuda()
+    out = torch.empty(M, dtype=torch.complex128, device="cuda")
+    stats = torch.empty(4, dtype=torch.float64, device="cuda")
+    r = {"workload": f"medium: {N} qubits, {w.n_electrons} electrons, {M} unique determinants, "
+                     f"{info['n_terms']} Pauli terms in {info['n_groups']} XY groups", "variant": "terms"}
+    for prec in ("fp64", "fp32c"):
+        def step():
+            eng.set_samples(keys, check=False)
+            eng.local_energy(L, None, "terms", prec, out=out, stats=stats, check=False)
+        ms, prof = time_steps(eng, step, args.steps, args.warmup)
+        r[prec] = {"ms_per_step": ms, "stage_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]}}
+    n_pairs = eng.count_pairs("terms")
+    te = term_evaluations(eng, "terms", group_sizes_by_id(w.ham))
+    r["coupled_pairs"] = n_pairs
+    for prec in ("fp64", "fp32c"):
+        r[prec]["pairs_per_s"] = n_pairs / (r[prec]["ms_per_step"] * 1e-3)
+        rf = roofline("terms", prec, W, M, info["n_terms"], info["n_groups"], M * info["n_groups"], te, n_pairs,
+                      r[prec]["stage_ms"]["pairs"] * 1e-3, None)
+        r[prec]["roofline_frac"] = rf["frac"]
+    print(f"# medium: fp64 {r['fp64']['ms_per_step']:.3f} ms, fp32c {r['fp32c']['ms_per_step']:.3f} ms",
+          file=sys.stderr, flush=True)
     eng.close()
+    return r
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_full(args):
+    """Conventional local energy (Eq. local_energy over every coupled x') on
+    the 28-qubit workload: the list of coupled states outside U, then E_loc
+    over U and them; their log-amplitudes are synthetic (the recipe's rank
+    law), as an ansatz would supply them."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    from synth import configs, samples
+
+    w = configs.medium()
+    eng = pe.Engine(0)
+    eng.set_hamiltonian(w.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
+    keys = torch.from_numpy(w.keys.view(np.int64)).cuda()
+    eng.set_samples(keys)
+    L = torch.from_numpy(w.logpsi).cuda()
+    steps = max(1, min(args.steps, args.other_steps))
+    t_find = _timed(lambda: eng.find_misses(), steps, 1)
+    V = eng.find_misses()
+    Vn = V.cpu().numpy().view(np.uint64)
+    rank = samples.excitation_rank(Vn, w.n_qubits, w.n_electrons)
+    rng = np.random.default_rng(11)
+    Lv = torch.from_numpy(samples.log_amplitudes(rank, rng)).cuda()
+    res = {"workload": f"medium: {w.n_qubits} qubits, {w.n_unique} samples; {V.shape[0]} coupled states outside U",
+           "extra_states": int(V.shape[0]), "find_ms": t_find}
+    for prec in ("fp64", "fp32c"):
+        res[prec] = {"ms": _timed(lambda: eng.local_energy_full(L, V, Lv, None, prec), steps, 1)}
+    e_full, st_full = eng.local_energy_full(L, V, Lv, None, "fp64")
+    e_var, st_var = eng.local_energy(L, None, "terms", "fp64")
+    res["E_full"] = float(st_full[0].item())
+    res["E_var"] = float(st_var[0].item())
+    print(f"# full local energy: {V.shape[0]} extra states, find {t_find:.2f} ms, "
+          f"E_loc {res['fp64']['ms']:.2f} / {res['fp32c']['ms']:.2f} ms", file=sys.stderr, flush=True)
+    eng.close()
+    return res
+
+
+def bench_sr(args):
+    """SR step at the paper's working point: N_SR = 100 samples, a parameter
+    vector of the size of its ansatz at 52 qubits (9 qudits of 6 qubits, two
+    perceptrons of width 64 each: 210 816 parameters), synthetic Jacobian."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    n_sr, n_p = 100, 210_816
+    rng = np.random.default_rng(12)
+    O_re = torch.from_numpy(rng.normal(size=(n_sr, n_p))).cuda()
+    O_im = torch.from_numpy(rng.normal(size=(n_sr, n_p))).cuda()
+    L = torch.from_numpy(rng.normal(size=n_sr) + 1j * rng.uniform(0, 6, n_sr)).cuda()
+    F = torch.from_numpy(rng.normal(size=n_p)).cuda()
+    M = 1 << 20
+    Lu = torch.from_numpy(rng.normal(size=M) + 1j * rng.uniform(0, 6, M)).cuda()
+    eng = pe.Engine(0)
+    out = torch.empty(n_p, dtype=torch.float64, device="cuda")
+    steps = max(2, min(args.steps, 10))
+    ms = _timed(lambda: eng.sr_solve(O_re, O_im, L, F, 1e-3, out=out, check=False), steps, 2)
+    eng.check()
+    sel = _timed(lambda: eng.sr_select(Lu, n_sr), steps, 2)
+    R = 2 * n_sr + 1
+    flops = R * R * n_p          # Gram of the centred rows (upper triangle: half of 2 R^2 N_p)
+    bytes_ = 2 * (2 * n_sr * n_p * 8) + 3 * n_p * 8   # the Jacobian read twice, F, mean, d
+    res = {"workload": f"N_SR = {n_sr}, {n_p} parameters, lambda = 1e-3; selection from 2^20 samples",
+           "solve_ms": ms, "select_ms": sel,
+           "gram_fp64_tflops_effective": flops / (ms * 1e-3) / 1e12,
+           "hbm_gb_s_effective": bytes_ / (ms * 1e-3) / 1e9}
+    print(f"# sr: solve {ms:.3f} ms, select {sel:.3f} ms", file=sys.stderr, flush=True)
+    eng.close()
+    return res
+
+
+def bench_sampler(args):
+    """ARGumbelTopK: 2^16 unique samples of 52 qubits (9 qudits of 6),
+    (10, 10) electrons, perceptrons of width 64 with random weights."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07625_amd as pe
+    N, D, K = 52, 6, 1 << 16
+    Q = (N + D - 1) // D
+    rng = np.random.default_rng(13)
+    wts = {"W1": rng.normal(scale=1.5 / np.sqrt(N), size=(Q, 64, N)), "b1": rng.normal(scale=0.1, size=(Q, 64)),
+           "W2": rng.normal(scale=1.5 / 8, size=(Q, 64, 64)), "b2": rng.normal(scale=0.1, size=(Q, 64)),
+           "W3": rng.normal(scale=1.5 / 8, size=(Q, 64, 64)), "b3": rng.normal(scale=0.5, size=(Q, 64))}
+    wts = {k: torch.from_numpy(v).cuda() for k, v in wts.items()}
+    eng = pe.Engine(0)
+    steps = max(2, min(args.steps, args.other_steps))
+    ms = _timed(lambda: eng.sample(N, D, wts, K, seed=5, n_up=10, n_down=10), steps, 1)
+    keys, logp, _ = eng.sample(N, D, wts, K, seed=5, n_up=10, n_down=10)
+    res = {"workload": f"{N} qubits, qudits of {D}, (10, 10) electrons, K = {K}", "ms": ms,
+           "samples": int(keys.shape[0]), "samples_per_s": keys.shape[0] / (ms * 1e-3)}
+    print(f"# sampler: {ms:.2f} ms for {keys.shape[0]} samples", file=sys.stderr, flush=True)
+    eng.close()
+    return res
 
 
 def bench_adjoint(args):
@@ -281,10 +534,10 @@ def bench_adjoint(args):
     print(f"# adjoint workload: {w.n_qubits} qubits, {M} samples, {info['n_terms']} terms, "
           f"{info['n_groups']} groups, variant {variant} (set up in {time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
-    steps = max(2, args.steps // 5)
+    steps = max(2, min(args.steps, args.other_steps))
 
     def timed(fn):
-        for _ in range(max(1, args.warmup)):
+        for _ in range(max(1, min(args.warmup, 2))):
             fn()
         eng.check()
         torch.cuda.synchronize()
@@ -360,17 +613,23 @@ def bench_batched(args):
         b.check()
         pairs = int(b.pair_counts().sum())
         b.set_graph(False)
+        b.profile(True)
+        b.profile_read()
         ms_eager = timed(lambda: b.run(prec, check=False), args.steps)
         b.check()
+        prof = b.profile_read()
+        b.profile(False)
         b.set_graph(True)
         out[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "samples_per_s": S / (ms * 1e-3),
-                     "eager_ms_per_step": ms_eager}
+                     "eager_ms_per_step": ms_eager,
+                     "eager_stage_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]}}
         out["coupled_pairs"] = pairs
-        print(f"# batched {prec}: graph {ms:.3f} ms, eager {ms_eager:.3f} ms, {pairs} pairs",
-              file=sys.stderr, flush=True)
+        print(f"# batched {prec}: graph {ms:.3f} ms, eager {ms_eager:.3f} ms, {pairs} pairs, stages "
+              + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items()), file=sys.stderr, flush=True)
     # the same problems one by one: one context each (Hamiltonian ingested
     # once), each step sets the samples and runs the forward pass
     engines = []
+    cand, te, pairs_k = 0, 0, 0
     for k, w in enumerate(ws):
         e = pe.Engine(0)
         e.set_hamiltonian(w.n_qubits, w.ham.coeff, w.ham.xy, w.ham.yz)
@@ -378,6 +637,14 @@ def bench_batched(args):
         engines.append((e, info["variant"], probs[k]["keys"], probs[k]["logpsi"],
                         torch.empty(w.n_unique, dtype=torch.complex128, device="cuda"),
                         torch.empty(4, dtype=torch.float64, device="cuda")))
+        # work counts of the batched pair kernel, per problem
+        e.set_samples(probs[k]["keys"])
+        Wk = w.ham.n_words
+        cand += w.n_unique * (info["n_groups"] * ops_per_candidate("terms", Wk) if info["variant"] == "terms"
+                              else w.n_unique * ops_per_candidate("batch", Wk))
+        te += term_evaluations(e, info["variant"], group_sizes_by_id(w.ham))
+        pairs_k += e.count_pairs(info["variant"])
+    assert pairs_k == out["coupled_pairs"], (pairs_k, out["coupled_pairs"])
 
     def sequential(prec):
         for e, var, keys, L, o, s in engines:
@@ -389,6 +656,13 @@ def bench_batched(args):
         out[prec]["sequential_ms_per_step"] = ms
         out[prec]["speedup_vs_sequential"] = ms / out[prec]["ms_per_step"]
         print(f"# sequential {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        ops = cand + te * OPS_PER_TERM + pairs_k * OPS_PER_PAIR[prec]
+        k_s = out[prec]["eager_stage_ms"]["pairs"] * 1e-3
+        out[prec]["roofline"] = {"bound": "alu", "achieved": ops / k_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                                 "unit": "Tlane-op/s", "frac": ops / k_s / PEAK_LANE_OPS,
+                                 "kernel": "k_pairs_batched (both key formats), eager launch",
+                                 "kernel_ms": k_s * 1e3, "ops_per_launch": ops}
+    out["term_evaluations"] = te
     out["fp32c_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
     for e, *_ in engines:
         e.close()

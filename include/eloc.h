@@ -152,7 +152,9 @@ int eloc_local_energy(eloc_ctx ctx, int variant, int precision, const eloc_c64* 
 /* Wait for the context's stream and report a deferred device-side error:
  * first of the current samples (EINVAL, EDUP, EAGAIN as in
  * eloc_set_samples), then of the last eloc_local_energy / adjoint /
- * pair_elements call (EINVAL, ERANGE, ECAPACITY).  Synchronising. */
+ * pair_elements call (EINVAL, ERANGE, ECAPACITY).  A run error is reported
+ * once (this call clears it), and eloc_set_samples clears it too.
+ * Synchronising. */
 int eloc_check(eloc_ctx ctx);
 
 /* Number of coupled ordered pairs (x, x') in U x U, diagonal included:
@@ -208,6 +210,107 @@ int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
                               const eloc_c64* eloc_dev, const double* stats_dev, eloc_c64 grad_e,
                               eloc_c64* grad_logpsi_dev);
 
+/* The conventional local energy (Eq. local_energy summed over every x',
+ * the estimator that Sec. "Streamlined local energy calculations" replaces
+ * by the sample-aware sum over U) needs the amplitudes of the states outside
+ * U that H couples to U.  eloc_find_misses lists them: every
+ * x' = x ^ XY_g (x in U, XY_g a mask of H) that is not in U and whose
+ * matrix element is non-zero, read as |H_xx'| > tol * sum_{l in P_g} |h_l|
+ * (FP64; strings that cancel exactly, such as hopping strings between
+ * particle-number sectors, give no state; tol >= 0, 1e-10 is a good value).
+ * DEVICE keys_dev[capacity][W] receives them once each, sorted ascending as
+ * W-word integers (word W-1 most significant); *n_misses_host receives
+ * their count, ECAPACITY (nothing written) if it exceeds capacity (call with
+ * capacity 0 to learn it).  Synchronising; EDUP / EINVAL for invalid
+ * samples, ECAPACITY beyond 2^31 states before deduplication. */
+int eloc_find_misses(eloc_ctx ctx, double tol, int64_t capacity, uint64_t* keys_dev, int64_t* n_misses_host);
+
+/* Conventional local energy of Eq. local_energy for every sample of U:
+ * E_loc(x) = sum_{x'} H_xx' psi(x')/psi(x) over U and the extra states V,
+ * DEVICE extra_keys_dev[n_extra][W] with extra_logpsi_dev[n_extra] (the
+ * list of eloc_find_misses in any order, with the ansatz's log-amplitudes;
+ * V must not meet U or repeat a key: EDUP).  A coupled state in neither U
+ * nor V is skipped, so V must hold every state with a non-zero matrix
+ * element.  DEVICE outputs eloc_dev[n_unique] and stats_dev[4] as in
+ * eloc_local_energy (weights over U only).  LoopOverTerms over U's rows
+ * with membership in U and V; |U| + n_extra < 2^24.  Synchronising; the
+ * deferred errors of eloc_local_energy are returned directly. */
+int eloc_local_energy_full(eloc_ctx ctx, int precision, const eloc_c64* logpsi_dev, const double* weights_dev,
+                           int64_t n_extra, const uint64_t* extra_keys_dev, const eloc_c64* extra_logpsi_dev,
+                           eloc_c64* eloc_dev, double* stats_dev);
+
+/* Stochastic reconfiguration over the highest-probability samples
+ * (Sec. "ANQS-tailored stochastic reconfiguration": the quantum geometric
+ * tensor of Eq. qgt_definition is estimated only over the N_SR unique
+ * samples of highest probability, with their probabilities renormalised
+ * over that set).
+ *
+ * eloc_sr_select: DEVICE idx_dev[n_sr] receives the indices of the n_sr
+ * entries of logpsi_dev[n] with the largest Re log psi (largest |psi|),
+ * in descending order, ties to the lower index.  Works on any log-amplitude
+ * array (no Hamiltonian or samples needed); uses the context's sort scratch.
+ * Asynchronous.  Errors: EINVAL (1 <= n_sr <= n < 2^31). */
+int eloc_sr_select(eloc_ctx ctx, int64_t n, const eloc_c64* logpsi_dev, int n_sr, int32_t* idx_dev);
+
+/* eloc_sr_solve: the SR-transformed gradient d = (Re S + lambda I)^{-1} F for
+ * real parameters theta.  DEVICE inputs: o_re_dev / o_im_dev [n_sr][n_params]
+ * row-major, the real and imaginary parts of O_xp = d log psi(x) / d theta_p
+ * (d log|psi| and d phase) of the set's samples; logpsi_set_dev[n_sr] their
+ * log-amplitudes (weights w_x = |psi_x|^2 / sum over the set); grad_dev
+ * [n_params] the energy gradient F (Eq. grad_def); lambda > 0 the diagonal
+ * shift.  S_pq = sum_x w_x conj(O_xp - Obar_p)(O_xq - Obar_q), Obar = sum_x
+ * w_x O_x.  DEVICE output d_dev[n_params].  The solve runs through the
+ * 2 n_sr x 2 n_sr Gram matrix of the centred, weighted rows (no n_params^2
+ * matrix is formed).  1 <= n_sr <= 256.  Asynchronous; a shifted matrix
+ * that is not positive definite in FP64 is reported by eloc_check as
+ * ERANGE.  Scratch: about 8 (2 n_params + 512 (2 n_sr + 16)^2) bytes. */
+int eloc_sr_solve(eloc_ctx ctx, int n_sr, int64_t n_params, const double* o_re_dev, const double* o_im_dev,
+                  const eloc_c64* logpsi_set_dev, const double* grad_dev, double lambda, double* d_dev);
+
+/* Autoregressive sampling without replacement (Methods, "Autoregressive
+ * sampling without replacement", Algorithm ARGumbelTopK): the producer of
+ * the unique batch U.  The ansatz is the paper's for the modulus (Methods,
+ * "Ansatz architecture", "Grouping qubits into qudits", "Global
+ * activation", "Local pruning strategy"): qudit k covers qubits
+ * [k D, k D + D_k) (D_k = D except for the last, which takes the rest); its
+ * conditional distribution given the earlier qubits comes from a
+ * perceptron with two hidden layers of width 64,
+ *   h1 = tanh(W1 x + b1),  h2 = tanh(W2 h1 + b2 + h1),  z = W3 h2 + b3,
+ * x_q = +1 / -1 for an earlier qubit set / clear and 0 for the others; z
+ * (the qudit's log|psi| per outcome c, bit t of c = qubit kD + t) is
+ * shifted by its mean, outcomes that can no longer reach n_up electrons on
+ * the even qubits and n_down on the odd ones get probability 0 (n_up < 0:
+ * no mask), and log p(c | x_<) = 2 z_c - log sum_allowed exp(2 z_c').
+ * The search keeps, qudit by qudit, the K prefixes with the largest
+ * conditioned perturbed log-probability; the Gumbel variable of a node
+ * (qudit, prefix, outcome) is -log(-log u) with u from the top 53 bits of
+ * the SplitMix64 output function chained over (seed + 0x9E3779B97F4A7C15
+ * (qudit + 1), prefix words, outcome).  Ties go to the earlier (prefix,
+ * outcome).  All DEVICE weights row-major: W1 [Q][64][N], b1 [Q][64],
+ * W2 [Q][64][64], b2 [Q][64], W3 [Q][2^D][64] (the last qudit uses the first
+ * 2^D_last rows), b3 [Q][2^D]. */
+typedef struct {
+    int n_qubits;        /* N, 1..128 */
+    int qudit;           /* D, 1..6 */
+    int hidden;          /* must be 64 */
+    int n_up, n_down;    /* electron targets on even / odd qubits, or -1 */
+    const double* W1;
+    const double* b1;
+    const double* W2;
+    const double* b2;
+    const double* W3;
+    const double* b3;
+} eloc_ar_model;
+
+/* DEVICE outputs keys_dev[k][W] (W = ceil(N / 64)), logp_dev[k] (log p(x)
+ * of each sample) and pert_dev[k] or NULL (the conditioned perturbed
+ * log-probability), in descending order of the latter; *n_out_host
+ * receives the number produced, min(k, number of allowed states).  The
+ * keys are unique by construction.  Synchronising (one host read per qudit).
+ * Errors: EINVAL (sizes, hidden != 64, 1 <= k < 2^24), ENOMEM, EHIP. */
+int eloc_sample(eloc_ctx ctx, const eloc_ar_model* model, int64_t k, uint64_t seed, uint64_t* keys_dev,
+                double* logp_dev, double* pert_dev, int64_t* n_out_host);
+
 /* Store the coupled pairs of the current samples, found with `variant`, as
  * a list by row of (column j, H_ij): afterwards eloc_local_energy and
  * eloc_local_energy_adjoint with ELOC_STORED read it instead of finding the
@@ -218,6 +321,13 @@ int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
  * and ECAPACITY is returned: the caller keeps recomputing (any other
  * variant).  Synchronising. */
 int eloc_store_pairs(eloc_ctx ctx, int variant, size_t budget_bytes, int64_t* n_pairs_host);
+
+/* Work count of LoopOverTrie (Alg. 2C): the number of (U tree node, XY tree
+ * node) pairs its walk visits over all rows of the current samples and all
+ * XY chunk trees - the unit of work of this variant, as the candidates
+ * |U| |XY| are for LoopOverTerms and |U|^2 for LoopOverBatch.
+ * Synchronising. */
+int eloc_trie_visits(eloc_ctx ctx, int64_t* visits_host);
 
 /* Launch geometry of the pair kernels (autotuning, benchmarks).  Results do
  * not depend on these settings beyond the floating-point summation order of
@@ -326,6 +436,16 @@ int eloc_batch_run(eloc_batch batch, int precision);
 /* 1: replay the captured graph (default); 0: launch the same kernels one by
  * one on the stream (for comparison). */
 int eloc_batch_set_graph(eloc_batch batch, int on);
+
+/* Stage timing of the batched pipeline with HIP events on the batch's
+ * stream (for roofline figures): while enabled, every eloc_batch_run with
+ * the graph off records events around its three stages - per-sample
+ * preparation, the persistent pair kernels, row sums and reductions.
+ * eloc_batch_profile_read writes HOST ms_total[3] and count[3] (totals since
+ * the last read) and resets them; synchronising.  Graph replays are not
+ * timed. */
+int eloc_batch_profile_enable(eloc_batch batch, int on);
+int eloc_batch_profile_read(eloc_batch batch, double* ms_total, int64_t* count);
 
 /* Wait for the stream and report the first problem (*bad_problem, -1 if
  * none) whose last run failed: EINVAL, EDUP, ERANGE as in the

@@ -21,6 +21,7 @@ VARIANTS = {"terms": 0, "batch": 1, "trie": 2, "auto": 3, "stored": 4}
 PRECISIONS = {"fp64": 0, "fp32c": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOMEM", -4: "ECAPACITY", -5: "ERANGE", -6: "EHIP",
           -7: "ESTATE", -8: "EAGAIN"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 
 class ElocError(RuntimeError):
@@ -46,6 +47,12 @@ class Problem(ctypes.Structure):
                 ("eloc_dev", ctypes.c_void_p), ("stats_dev", ctypes.c_void_p)]
 
 
+class ArModel(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int), ("qudit", ctypes.c_int), ("hidden", ctypes.c_int),
+                ("n_up", ctypes.c_int), ("n_down", ctypes.c_int), ("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p),
+                ("W2", ctypes.c_void_p), ("b2", ctypes.c_void_p), ("W3", ctypes.c_void_p), ("b3", ctypes.c_void_p)]
+
+
 class Schedule(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
                 ("item_candidates", ctypes.c_int64), ("order", ctypes.c_int), ("batch_ratio", ctypes.c_double)]
@@ -68,6 +75,12 @@ def library() -> ctypes.CDLL:
             "eloc_set_samples": (i32, [P, i64, P]),
             "eloc_samples_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "eloc_local_energy": (i32, [P, i32, i32, P, P, P, P]),
+            "eloc_find_misses": (i32, [P, ctypes.c_double, i64, P, ctypes.POINTER(i64)]),
+            "eloc_local_energy_full": (i32, [P, i32, P, P, i64, P, P, P, P]),
+            "eloc_sr_select": (i32, [P, i64, P, i32, P]),
+            "eloc_sr_solve": (i32, [P, i32, i64, P, P, P, P, ctypes.c_double, P]),
+            "eloc_sample": (i32, [P, ctypes.POINTER(ArModel), i64, ctypes.c_uint64, P, P, P, ctypes.POINTER(i64)]),
+            "eloc_trie_visits": (i32, [P, ctypes.POINTER(i64)]),
             "eloc_check": (i32, [P]),
             "eloc_count_pairs": (i32, [P, i32, ctypes.POINTER(i64)]),
             "eloc_find_pairs": (i32, [P, i32, i64, P, P, P, ctypes.POINTER(i64)]),
@@ -91,6 +104,8 @@ def library() -> ctypes.CDLL:
             "eloc_batch_get_schedule": (i32, [P, ctypes.POINTER(Schedule)]),
             "eloc_batch_set_schedule": (i32, [P, ctypes.POINTER(Schedule)]),
             "eloc_batch_tune": (i32, [P, i32, ctypes.c_char_p, ctypes.POINTER(i32)]),
+            "eloc_batch_profile_enable": (i32, [P, i32]),
+            "eloc_batch_profile_read": (i32, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -105,13 +120,15 @@ def exported_symbols() -> list[str]:
     lib = library()
     return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
                         "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples", "eloc_samples_info",
-                        "eloc_local_energy", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
+                        "eloc_local_energy", "eloc_find_misses",
+                        "eloc_local_energy_full", "eloc_sr_select", "eloc_sr_solve", "eloc_sample", "eloc_trie_visits", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
                         "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_store_pairs", "eloc_set_tuning",
                         "eloc_get_tuning",
                         "eloc_profile_enable", "eloc_profile_read", "eloc_batch_create", "eloc_batch_destroy",
                         "eloc_batch_last_error", "eloc_batch_set_stream", "eloc_batch_run", "eloc_batch_set_graph",
                         "eloc_batch_check", "eloc_batch_pair_counts", "eloc_batch_problem_info",
-                        "eloc_batch_get_schedule", "eloc_batch_set_schedule", "eloc_batch_tune")
+                        "eloc_batch_get_schedule", "eloc_batch_set_schedule", "eloc_batch_tune",
+                        "eloc_batch_profile_enable", "eloc_batch_profile_read")
             if hasattr(lib, n)]
 
 
@@ -260,11 +277,119 @@ class Engine:
     def check(self):
         self._call(self.lib.eloc_check(self.handle))
 
+    # -- sampling without replacement ----------------------------------------
+    def sample(self, n_qubits: int, qudit: int, weights: dict, k: int, seed: int, n_up: int = -1,
+               n_down: int = -1):
+        """ARGumbelTopK over the per-qudit perceptron ansatz.  weights: float64
+        CUDA tensors W1 [Q,64,N], b1 [Q,64], W2 [Q,64,64], b2 [Q,64], W3
+        [Q,2^qudit,64], b3 [Q,2^qudit].  Returns (keys int64 [n, W], log p
+        float64 [n], perturbed log-probabilities float64 [n]), n <= k."""
+        Q = (n_qubits + qudit - 1) // qudit
+        shapes = {"W1": (Q, 64, n_qubits), "b1": (Q, 64), "W2": (Q, 64, 64), "b2": (Q, 64),
+                  "W3": (Q, 1 << qudit, 64), "b3": (Q, 1 << qudit)}
+        ws = {}
+        for name, shape in shapes.items():
+            t = weights[name]
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a float64 CUDA tensor of shape {shape}")
+            ws[name] = t.contiguous()
+        m = ArModel(int(n_qubits), int(qudit), 64, int(n_up), int(n_down), *(ws[n].data_ptr() for n in
+                                                                          ("W1", "b1", "W2", "b2", "W3", "b3")))
+        W = (n_qubits + 63) // 64
+        keys = torch.empty((k, W), dtype=torch.int64, device=self.device)
+        logp = torch.empty(k, dtype=torch.float64, device=self.device)
+        pert = torch.empty(k, dtype=torch.float64, device=self.device)
+        n = ctypes.c_int64()
+        self._sync_stream()
+        self._call(self.lib.eloc_sample(self.handle, ctypes.byref(m), int(k), ctypes.c_uint64(seed & ((1 << 64) - 1)),
+                                        _ptr(keys), _ptr(logp), _ptr(pert), ctypes.byref(n)))
+        return keys[: n.value], logp[: n.value], pert[: n.value]
+
+    # -- stochastic reconfiguration ------------------------------------------
+    def sr_select(self, logpsi: torch.Tensor, n_sr: int) -> torch.Tensor:
+        """Indices (int32 [n_sr]) of the n_sr largest Re log psi, descending."""
+        if logpsi.dtype != torch.complex128 or not logpsi.is_cuda or logpsi.dim() != 1:
+            raise ValueError("logpsi must be a complex128 CUDA vector")
+        logpsi = logpsi.contiguous()
+        out = torch.empty(n_sr, dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        self._call(self.lib.eloc_sr_select(self.handle, logpsi.shape[0], _ptr(logpsi), int(n_sr), _ptr(out)))
+        return out
+
+    def sr_solve(self, o_re: torch.Tensor, o_im: torch.Tensor, logpsi_set: torch.Tensor, grad: torch.Tensor,
+                 lam: float, out: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+        """(Re S + lam I)^{-1} grad with S estimated over the set (float64 [n_params])."""
+        n_sr, n_p = o_re.shape
+        for t, name in ((o_re, "o_re"), (o_im, "o_im")):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != (n_sr, n_p):
+                raise ValueError(f"{name} must be a float64 CUDA tensor [n_sr, n_params]")
+        if logpsi_set.dtype != torch.complex128 or not logpsi_set.is_cuda or logpsi_set.shape != (n_sr,):
+            raise ValueError("logpsi_set must be a complex128 CUDA tensor [n_sr]")
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.shape != (n_p,):
+            raise ValueError("grad must be a float64 CUDA tensor [n_params]")
+        o_re, o_im, logpsi_set, grad = o_re.contiguous(), o_im.contiguous(), logpsi_set.contiguous(), grad.contiguous()
+        if out is None:
+            out = torch.empty(n_p, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        self._call(self.lib.eloc_sr_solve(self.handle, n_sr, n_p, _ptr(o_re), _ptr(o_im), _ptr(logpsi_set),
+                                          _ptr(grad), float(lam), _ptr(out)))
+        if check:
+            self.check()
+        return out
+
+    # -- conventional local energy -------------------------------------------
+    def find_misses(self, tol: float = 1e-10) -> torch.Tensor:
+        """States outside U coupled to U by a non-zero matrix element: int64
+        device tensor [n, W] (bit patterns), sorted, each once."""
+        n = ctypes.c_int64()
+        self._sync_stream()
+        rc = self.lib.eloc_find_misses(self.handle, float(tol), 0, None, ctypes.byref(n))
+        if rc != STATUS_CODE["ECAPACITY"]:   # the count comes back with ECAPACITY unless it is 0
+            self._call(rc)
+        W = (self.n_qubits + 63) // 64
+        out = torch.empty((max(n.value, 1), W), dtype=torch.int64, device=self.device)
+        self._call(self.lib.eloc_find_misses(self.handle, float(tol), n.value, _ptr(out), ctypes.byref(n)))
+        return out[: n.value]
+
+    def local_energy_full(self, logpsi: torch.Tensor, extra_keys: torch.Tensor, extra_logpsi: torch.Tensor,
+                          weights: torch.Tensor | None = None, precision="fp64"):
+        """Conventional local energy of every sample (Eq. local_energy): (E_loc
+        complex128 [M], stats float64 [4]) from U's and the extra states'
+        log-amplitudes."""
+        M = self.n_unique
+        W = (self.n_qubits + 63) // 64
+        if logpsi.dtype != torch.complex128 or not logpsi.is_cuda or logpsi.shape != (M,):
+            raise ValueError("logpsi must be a complex128 CUDA tensor with one entry per sample")
+        n = extra_keys.shape[0]
+        if not (extra_keys.is_cuda and extra_keys.dtype in (torch.int64, torch.uint64) and extra_keys.dim() == 2
+                and extra_keys.shape[1] == W):
+            raise ValueError(f"extra_keys must be an int64 CUDA tensor [n, {W}]")
+        if extra_logpsi.dtype != torch.complex128 or not extra_logpsi.is_cuda or extra_logpsi.shape != (n,):
+            raise ValueError("extra_logpsi must be a complex128 CUDA tensor [n]")
+        if weights is not None and (weights.dtype != torch.float64 or not weights.is_cuda or weights.shape != (M,)):
+            raise ValueError("weights must be a float64 CUDA tensor with one entry per sample")
+        logpsi, extra_keys, extra_logpsi = logpsi.contiguous(), extra_keys.contiguous(), extra_logpsi.contiguous()
+        weights = None if weights is None else weights.contiguous()
+        out = torch.empty(M, dtype=torch.complex128, device=self.device)
+        stats = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        self._call(self.lib.eloc_local_energy_full(self.handle, _precision(precision), _ptr(logpsi), _ptr(weights),
+                                                   n, _ptr(extra_keys) if n else None,
+                                                   _ptr(extra_logpsi) if n else None, _ptr(out), _ptr(stats)))
+        return out, stats
+
     # -- pairs --------------------------------------------------------------
     def count_pairs(self, variant="terms") -> int:
         n = ctypes.c_int64()
         self._sync_stream()
         self._call(self.lib.eloc_count_pairs(self.handle, _variant(variant), ctypes.byref(n)))
+        return n.value
+
+    def trie_visits(self) -> int:
+        """Node pairs LoopOverTrie's walk visits for the current samples."""
+        n = ctypes.c_int64()
+        self._sync_stream()
+        self._call(self.lib.eloc_trie_visits(self.handle, ctypes.byref(n)))
         return n.value
 
     def find_pairs(self, variant="terms"):
@@ -480,6 +605,18 @@ class Batch:
 
     def set_graph(self, on: bool):
         self._call(self.lib.eloc_batch_set_graph(self.handle, 1 if on else 0))
+
+    def profile(self, on: bool):
+        """Stage timing of eager runs (set_graph(False)) with HIP events."""
+        self._call(self.lib.eloc_batch_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, runs)} since the last read, stages prepare,
+        pairs, finish; synchronising."""
+        ms = np.zeros(3, dtype=np.float64)
+        n = np.zeros(3, dtype=np.int64)
+        self._call(self.lib.eloc_batch_profile_read(self.handle, _np_ptr(ms), _np_ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(("prepare", "pairs", "finish"))}
 
     def pair_counts(self) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.int64)

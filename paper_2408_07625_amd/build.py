@@ -14,7 +14,9 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libeloc.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "pairs.hip", CSRC / "batch.hip", CSRC / "api.cpp", CSRC / "batch.cpp"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "pairs.hip", CSRC / "batch.hip", CSRC / "misses.hip", CSRC / "sr.hip", CSRC / "sampler.hip",
+           CSRC / "api.cpp",
+           CSRC / "batch.cpp"]
 HEADERS = [CSRC / "internal.h", CSRC / "device.h", CSRC / "trie.h", CSRC / "ham.h", CSRC / "host.h",
            ROOT / "include" / "eloc.h"]
 
@@ -35,20 +37,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile every source to an object file (in parallel), then link."""
+def build(verbose: bool = False, incremental: bool = False) -> Path:
+    """Compile every source to an object file (in parallel), then link.
+    incremental: keep object files newer than their source and every header."""
     obj_dir = PKG / "_build"
     obj_dir.mkdir(exist_ok=True)
     inc = [f"-I{ROOT / 'include'}", f"-I{CSRC}"]
     compile_flags = [f for f in FLAGS if f != "-shared"]
     procs = []
+    newest_header = max(h.stat().st_mtime for h in HEADERS)
     for src in SOURCES:
         obj = obj_dir / (src.name + ".o")
+        if incremental and obj.exists() and obj.stat().st_mtime > max(src.stat().st_mtime, newest_header):
+            procs.append((src, obj, None))
+            continue
         cmd = [hipcc(), *compile_flags, *inc, "-c", str(src), "-o", str(obj)]
         procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
                                                   text=True)))
     logs, failed = [], False
     for src, obj, p in procs:
+        if p is None:
+            continue
         out, _ = p.communicate()
         logs.append(out)
         failed = failed or p.returncode != 0
@@ -78,4 +87,4 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -51,6 +51,16 @@ struct eloc_ctx_s {
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
+    // conventional local energy: the extra states' list (raw, sorted, run
+    // flags and positions) and the set X = U followed by the extra states
+    DevBuf m_raw, m_sorted, m_perm, m_flags, m_pos;
+    DevBuf x_keys, x_hash, x_slots, x_stash, x_sig, x_bitcounts, x_rad, x_params, x_err, x_logpsi;
+    DevBuf x_a, x_b, x_af, x_bf, x_shift;
+    // stochastic reconfiguration scratch
+    DevBuf sr_w, sr_mean, sr_part, sr_T, sr_L, sr_y;
+    // sampler: two prefix beams, the candidates of a level, the allowed count
+    DevBuf ar_keys[2], ar_l[2], ar_T[2], ar_cl, ar_cT, ar_ck, ar_ci, ar_ck2, ar_ci2, ar_cnt;
+
     // stored pair list (CSR by row of (column, H_ij)), valid until the
     // samples or the Hamiltonian change
     DevBuf st_rowptr, st_col, st_h;
@@ -108,9 +118,9 @@ int resolve_variant(const eloc_ctx c, int v) {
 // inner loop (groups / samples) split into chunks of whole 64-lane steps so
 // that the grid has about `target` waves.  TRIE: one lane per row, one chunk
 // per XY tree.
-Plan make_plan(const eloc_ctx c, int variant) {
+Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1) {
     Plan P;
-    const int64_t M = c->S.n;
+    const int64_t M = n_rows >= 0 ? n_rows : c->S.n;
     // LoopOverTerms with the prefilters reads U's Bloom filter from LDS when
     // U has one: 4 waves of 4 rows share it; else one wave of 8 rows
     // (the shared filter needs 4-row waves to keep the workgroup's LDS under 64 KB)
@@ -496,7 +506,13 @@ void eloc_destroy(eloc_ctx c) {
                       &c->shift, &c->amp_scratch, &c->partial, &c->energy_scratch, &c->err_run, &c->err_prep,
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
                       &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
-                      &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->ut_nkeys, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2};
+                      &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->ut_nkeys, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2,
+                      &c->m_raw, &c->m_sorted, &c->m_perm, &c->m_flags, &c->m_pos, &c->x_keys, &c->x_hash, &c->x_slots,
+                      &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
+                      &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->st_rowptr, &c->st_col, &c->st_h,
+                      &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
+                      &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
+                      &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt};
     for (DevBuf* b : bufs) b->release();
     for (auto& m : c->marks) {
         c->ev_pool.push_back(m.a);
@@ -583,6 +599,8 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     ELOC_HIP(c, hipMemcpyAsync(c->keys.p, keys_dev, sizeof(uint64_t) * n_unique * W, hipMemcpyDeviceToDevice,
                                c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->err_prep.p, 0, sizeof(uint32_t), c->stream));
+    // errors of calls on the previous samples are not carried over
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->bitcounts.p, 0, sizeof(uint32_t) * 64 * W, c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->rad.p, 0, sizeof(unsigned long long) * 3, c->stream));
     ELOC_HIP(c, launch_sample_hash(W, c->keys.as<uint64_t>(), n_unique, c->R_dev.as<uint64_t>(), c->H.n_qubits,
@@ -647,6 +665,309 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
     return ELOC_OK;
 }
 
+int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_dev, int64_t* n_misses_host) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!n_misses_host) return fail(c, ELOC_EINVAL, "null pointer");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, ELOC_EINVAL, "tol must be finite and >= 0");
+    if (capacity < 0) return fail(c, ELOC_EINVAL, "negative capacity");
+    rc = samples_verdict(c, nullptr);
+    if (rc) return rc;
+    const int64_t M = c->S.n;
+    const int W = c->H.W;
+    const Plan P = make_plan(c, ELOC_TERMS);
+    const int64_t n = M * P.chunks;
+    ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
+    ELOC_HIP(c, c->offsets.ensure(sizeof(int64_t) * (n + 1)));
+    ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(n)));
+    ELOC_HIP(c, launch_misses(c->H, c->S, P.chunks, P.per_chunk, tol, false, c->counts.as<int32_t>(), nullptr,
+                              nullptr, c->stream));
+    ELOC_HIP(c, launch_scan_i32(c->counts.as<int32_t>(), n, c->offsets.as<int64_t>(), c->scan_scratch.as<int64_t>(),
+                                c->stream));
+    int64_t total = 0;
+    ELOC_HIP(c, hipMemcpyAsync(&total, c->offsets.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    if (total >= (int64_t(1) << 31))
+        return fail(c, ELOC_ECAPACITY, "more than 2^31 coupled states outside U before deduplication");
+    int64_t uniq = 0;
+    if (total > 0) {
+        ELOC_HIP(c, c->m_raw.ensure(sizeof(uint64_t) * total * W));
+        ELOC_HIP(c, launch_misses(c->H, c->S, P.chunks, P.per_chunk, tol, true, nullptr, c->offsets.as<int64_t>(),
+                                  c->m_raw.as<uint64_t>(), c->stream));
+        // sort (W-word keys, most significant word last) and keep the first of every run
+        const int64_t tiles = radix_tiles(total);
+        ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * total));
+        ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * total));
+        ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * total));
+        ELOC_HIP(c, c->s_val2.ensure(sizeof(uint32_t) * total));
+        ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+        ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+        ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+        ELOC_HIP(c, c->m_sorted.ensure(sizeof(uint64_t) * total * W));
+        ELOC_HIP(c, c->m_perm.ensure(sizeof(int32_t) * total));
+        ELOC_HIP(c, c->m_flags.ensure(sizeof(int32_t) * total));
+        ELOC_HIP(c, c->m_pos.ensure(sizeof(int64_t) * (total + 1)));
+        ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(total)));
+        SortScratch ss{c->s_key.as<uint64_t>(), c->s_val.as<uint32_t>(), c->s_key2.as<uint64_t>(),
+                       c->s_val2.as<uint32_t>(), c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(),
+                       c->hist_scratch.as<int64_t>()};
+        ELOC_HIP(c, launch_sort_keys(W, c->H.n_qubits, c->m_raw.as<uint64_t>(), total, ss, c->m_sorted.as<uint64_t>(),
+                                     c->m_perm.as<int32_t>(), c->stream));
+        ELOC_HIP(c, launch_unique_flags(W, c->m_sorted.as<uint64_t>(), total, c->m_flags.as<int32_t>(), c->stream));
+        ELOC_HIP(c, launch_scan_i32(c->m_flags.as<int32_t>(), total, c->m_pos.as<int64_t>(),
+                                    c->scan_scratch.as<int64_t>(), c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(&uniq, c->m_pos.as<int64_t>() + total, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   c->stream));
+        ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    *n_misses_host = uniq;
+    if (uniq > capacity) return fail(c, ELOC_ECAPACITY, "capacity too small for the coupled states outside U");
+    if (uniq > 0) {
+        if (!keys_dev) return fail(c, ELOC_EINVAL, "null pointer");
+        ELOC_HIP(c, launch_unique_scatter(W, c->m_sorted.as<uint64_t>(), total, c->m_flags.as<int32_t>(),
+                                          c->m_pos.as<int64_t>(), keys_dev, c->stream));
+    }
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    return ELOC_OK;
+}
+
+int eloc_local_energy_full(eloc_ctx c, int precision, const eloc_c64* logpsi_dev, const double* weights_dev,
+                           int64_t n_extra, const uint64_t* extra_keys_dev, const eloc_c64* extra_logpsi_dev,
+                           eloc_c64* eloc_dev, double* stats_dev) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
+    if (!logpsi_dev || !eloc_dev || !stats_dev || n_extra < 0 || (n_extra > 0 && (!extra_keys_dev || !extra_logpsi_dev)))
+        return fail(c, ELOC_EINVAL, "null pointer or negative count");
+    rc = samples_verdict(c, nullptr);
+    if (rc) return rc;
+    const int64_t M = c->S.n;
+    const int64_t X = M + n_extra;
+    if (X >= (int64_t(1) << 24)) return fail(c, ELOC_EINVAL, "U and the extra states must number under 2^24");
+    const int W = c->H.W;
+    const bool fp32 = precision == ELOC_FP32C;
+    const int tk = table_kind(W, c->H.narrow);
+    const uint64_t cap = table_capacity(X);
+    ELOC_HIP(c, c->x_keys.ensure(sizeof(uint64_t) * X * W));
+    ELOC_HIP(c, c->x_hash.ensure(sizeof(uint64_t) * X));
+    ELOC_HIP(c, c->x_slots.ensure(slot_bytes(tk) * cap));
+    ELOC_HIP(c, c->x_stash.ensure(sizeof(Stash)));
+    ELOC_HIP(c, c->x_sig.ensure(sizeof(uint64_t) * kSigWords));
+    ELOC_HIP(c, c->x_bitcounts.ensure(sizeof(uint32_t) * 64 * W));
+    ELOC_HIP(c, c->x_rad.ensure(sizeof(unsigned long long) * 3));
+    ELOC_HIP(c, c->x_params.ensure(sizeof(SampleParams)));
+    ELOC_HIP(c, c->x_err.ensure(sizeof(uint32_t)));
+    ELOC_HIP(c, c->x_logpsi.ensure(sizeof(double2) * X));
+    // X = U's keys and log-amplitudes, then the extra states'
+    ELOC_HIP(c, hipMemcpyAsync(c->x_keys.p, c->keys.p, sizeof(uint64_t) * M * W, hipMemcpyDeviceToDevice, c->stream));
+    ELOC_HIP(c, hipMemcpyAsync(c->x_logpsi.p, logpsi_dev, sizeof(double2) * M, hipMemcpyDeviceToDevice, c->stream));
+    if (n_extra > 0) {
+        ELOC_HIP(c, hipMemcpyAsync(c->x_keys.as<uint64_t>() + M * W, extra_keys_dev, sizeof(uint64_t) * n_extra * W,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(c->x_logpsi.as<double2>() + M, extra_logpsi_dev, sizeof(double2) * n_extra,
+                                   hipMemcpyDeviceToDevice, c->stream));
+    }
+    ELOC_HIP(c, hipMemsetAsync(c->x_err.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->x_bitcounts.p, 0, sizeof(uint32_t) * 64 * W, c->stream));
+    ELOC_HIP(c, hipMemsetAsync(c->x_rad.p, 0, sizeof(unsigned long long) * 3, c->stream));
+    ELOC_HIP(c, launch_sample_hash(W, c->x_keys.as<uint64_t>(), X, c->R_dev.as<uint64_t>(), c->H.n_qubits,
+                                   c->x_hash.as<uint64_t>(), c->x_bitcounts.as<uint32_t>(), c->x_err.as<uint32_t>(),
+                                   c->stream));
+    ELOC_HIP(c, launch_sample_radius(W, c->x_keys.as<uint64_t>(), X, c->x_bitcounts.as<uint32_t>(),
+                                     c->x_rad.as<unsigned long long>(), c->stream));
+    SampleDev S;
+    S.n = X;
+    S.rows = M;
+    S.keys = c->x_keys.as<uint64_t>();
+    S.hash = c->x_hash.as<uint64_t>();
+    S.sig = c->x_sig.as<uint64_t>();
+    S.params = c->x_params.as<SampleParams>();
+    S.prep_err = c->x_err.as<uint32_t>();
+    // membership table of X (a new salt if an insertion does not settle),
+    // duplicate and bit checks, prefilter parameters; verdict before use
+    uint32_t bits = kErrTable;
+    for (int attempt = 0; attempt < 8 && (bits & kErrTable) && !(bits & kErrBits); ++attempt) {
+        S.table = make_table(c->x_slots.p, c->x_stash.as<Stash>(), cap, X, splitmix64(c->salt_state));
+        ELOC_HIP(c, hipMemsetAsync(c->x_slots.p, 0, slot_bytes(tk) * cap, c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->x_stash.p, 0, sizeof(Stash), c->stream));
+        ELOC_HIP(c, hipMemsetAsync(c->x_sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
+        if (attempt > 0) ELOC_HIP(c, hipMemsetAsync(c->x_err.p, 0, sizeof(uint32_t), c->stream));
+        ELOC_HIP(c, launch_table_insert(tk, c->x_hash.as<uint64_t>(), X, c->x_slots.p, c->x_stash.as<Stash>(), S.table,
+                                        c->x_err.as<uint32_t>(), c->stream));
+        ELOC_HIP(c, launch_sample_verify(W, c->H.narrow, S, c->x_sig.as<uint64_t>(), c->x_err.as<uint32_t>(),
+                                         c->stream));
+        ELOC_HIP(c, launch_sample_params(c->x_sig.as<uint64_t>(), c->x_rad.as<unsigned long long>(), c->H.n_qubits,
+                                         c->x_params.as<SampleParams>(), c->stream));
+        const int b = read_err(c, c->x_err);
+        if (b < 0) return b;
+        bits = static_cast<uint32_t>(b);
+    }
+    if (bits & kErrBits) return fail(c, ELOC_EINVAL, "an extra state has bits set at or above n_qubits");
+    if (bits & kErrTable) return fail(c, ELOC_EHIP, "membership table could not be built");
+    if (bits & kErrDup) return fail(c, ELOC_EDUP, "an extra state repeats or is in U");
+    // amplitudes over X, LoopOverTerms over U's rows, row combination
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, c->x_a.ensure(sizeof(double2) * X));
+    ELOC_HIP(c, c->x_b.ensure(sizeof(double2) * X));
+    ELOC_HIP(c, c->x_af.ensure(sizeof(float4) * (fp32 ? X : 1)));
+    ELOC_HIP(c, c->x_bf.ensure(sizeof(float4) * (fp32 ? X : 1)));
+    ELOC_HIP(c, c->x_shift.ensure(sizeof(double) * 2));
+    ELOC_HIP(c, c->amp_scratch.ensure(sizeof(double) * amp_scratch_len()));
+    ELOC_HIP(c, launch_amp_prep(c->x_logpsi.as<double2>(), X, fp32, c->x_a.as<double2>(), c->x_b.as<double2>(),
+                                c->x_af.as<float4>(), c->x_bf.as<float4>(), c->x_shift.as<double>(),
+                                c->amp_scratch.as<double>(), c->err_run.as<uint32_t>(), c->stream));
+    Plan P = make_plan(c, ELOC_TERMS, M);
+    P.bloom_words = 0;
+    ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
+    ELOC_HIP(c, launch_pairs(false, ELOC_TERMS, precision, c->H, S, P, c->x_a.as<double2>(), c->x_af.as<float4>(),
+                             c->partial.p, c->stream));
+    ELOC_HIP(c, launch_finish(precision, M, P, c->partial.p, c->x_b.as<double2>(), c->x_bf.as<float4>(),
+                              reinterpret_cast<double2*>(eloc_dev), c->stream));
+    // weighted energy over U (its own amplitude shift for the |psi|^2 weights)
+    rc = amp_prep(c, logpsi_dev, fp32);
+    if (rc) return rc;
+    ELOC_HIP(c, c->energy_scratch.ensure(sizeof(double) * energy_scratch_len()));
+    ELOC_HIP(c, launch_energy(reinterpret_cast<const double2*>(eloc_dev), reinterpret_cast<const double2*>(logpsi_dev),
+                              weights_dev, c->shift.as<double>(), M, stats_dev, c->energy_scratch.as<double>(),
+                              c->err_run.as<uint32_t>(), c->stream));
+    const int b = read_err(c, c->err_run);
+    if (b < 0) return b;
+    if (b) ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    return map_err(c, static_cast<uint32_t>(b));
+}
+
+int eloc_sr_select(eloc_ctx c, int64_t n, const eloc_c64* logpsi_dev, int n_sr, int32_t* idx_dev) {
+    if (!c) return ELOC_EINVAL;
+    if (n < 1 || n >= (int64_t(1) << 31) || n_sr < 1 || n_sr > n || !logpsi_dev || !idx_dev)
+        return fail(c, ELOC_EINVAL, "need 1 <= n_sr <= n < 2^31 and device pointers");
+    const int64_t tiles = radix_tiles(n);
+    ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * n));
+    ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * n));
+    ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * n));
+    ELOC_HIP(c, c->s_val2.ensure(sizeof(uint32_t) * n));
+    ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+    ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+    c->ut_valid = false;   // the sort scratch is shared with U's sorted copy
+    ELOC_HIP(c, launch_sr_select(reinterpret_cast<const double2*>(logpsi_dev), n, n_sr, c->s_key.as<uint64_t>(),
+                                 c->s_val.as<uint32_t>(), c->s_key2.as<uint64_t>(), c->s_val2.as<uint32_t>(),
+                                 c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(),
+                                 idx_dev, c->stream));
+    return ELOC_OK;
+}
+
+int eloc_sr_solve(eloc_ctx c, int n_sr, int64_t n_params, const double* o_re_dev, const double* o_im_dev,
+                  const eloc_c64* logpsi_set_dev, const double* grad_dev, double lambda, double* d_dev) {
+    if (!c) return ELOC_EINVAL;
+    if (n_sr < 1 || n_sr > 256 || n_params < 1 || !(lambda > 0.0) || !std::isfinite(lambda))
+        return fail(c, ELOC_EINVAL, "need 1 <= n_sr <= 256, n_params >= 1, finite lambda > 0");
+    if (!o_re_dev || !o_im_dev || !logpsi_set_dev || !grad_dev || !d_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    const int R = 2 * n_sr + 1;
+    const int64_t R16 = (R + 15) / 16 * 16;
+    const int64_t n = 2 * n_sr;
+    ELOC_HIP(c, c->sr_w.ensure(sizeof(double) * 2 * n_sr));
+    ELOC_HIP(c, c->sr_mean.ensure(sizeof(double) * 2 * n_params));
+    ELOC_HIP(c, c->sr_part.ensure(sizeof(double) * sr_partial_blocks(n_params) * R16 * R16));
+    ELOC_HIP(c, c->sr_T.ensure(sizeof(double) * R * R));
+    ELOC_HIP(c, c->sr_L.ensure(sizeof(double) * n * n));
+    ELOC_HIP(c, c->sr_y.ensure(sizeof(double) * n));
+    ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
+    ELOC_HIP(c, launch_sr_solve(n_sr, n_params, o_re_dev, o_im_dev, reinterpret_cast<const double2*>(logpsi_set_dev),
+                                grad_dev, lambda, c->sr_w.as<double>(), c->sr_mean.as<double>(), c->sr_part.as<double>(),
+                                c->sr_T.as<double>(), c->sr_L.as<double>(), c->sr_y.as<double>(), d_dev,
+                                c->err_run.as<uint32_t>(), c->stream));
+    return ELOC_OK;
+}
+
+int eloc_sample(eloc_ctx c, const eloc_ar_model* m, int64_t k, uint64_t seed, uint64_t* keys_dev, double* logp_dev,
+                double* pert_dev, int64_t* n_out_host) {
+    if (!c) return ELOC_EINVAL;
+    if (!m || !keys_dev || !logp_dev || !n_out_host) return fail(c, ELOC_EINVAL, "null pointer");
+    if (m->n_qubits < 1 || m->n_qubits > 128 || m->qudit < 1 || m->qudit > 6 || m->hidden != 64)
+        return fail(c, ELOC_EINVAL, "need 1 <= n_qubits <= 128, 1 <= qudit <= 6, hidden == 64");
+    if (k < 1 || k >= (int64_t(1) << 24)) return fail(c, ELOC_EINVAL, "need 1 <= k < 2^24");
+    if (!m->W1 || !m->b1 || !m->W2 || !m->b2 || !m->W3 || !m->b3) return fail(c, ELOC_EINVAL, "null weights");
+    *n_out_host = 0;
+    ArModelDev M{m->n_qubits, m->qudit, m->n_up, m->n_down, m->W1, m->b1, m->W2, m->b2, m->W3, m->b3};
+    if (M.n_up < 0 || M.n_down < 0) M.n_up = M.n_down = -1;
+    const int N = m->n_qubits, W = (N + 63) / 64, D = m->qudit;
+    const int Q = (N + D - 1) / D;
+    const int64_t maxc = k * (int64_t(1) << D);
+    for (int s = 0; s < 2; ++s) {
+        ELOC_HIP(c, c->ar_keys[s].ensure(sizeof(uint64_t) * W * k));
+        ELOC_HIP(c, c->ar_l[s].ensure(sizeof(double) * k));
+        ELOC_HIP(c, c->ar_T[s].ensure(sizeof(double) * k));
+    }
+    ELOC_HIP(c, c->ar_cl.ensure(sizeof(double) * maxc));
+    ELOC_HIP(c, c->ar_cT.ensure(sizeof(double) * maxc));
+    ELOC_HIP(c, c->ar_ck.ensure(sizeof(uint64_t) * maxc));
+    ELOC_HIP(c, c->ar_ci.ensure(sizeof(uint32_t) * maxc));
+    ELOC_HIP(c, c->ar_ck2.ensure(sizeof(uint64_t) * maxc));
+    ELOC_HIP(c, c->ar_ci2.ensure(sizeof(uint32_t) * maxc));
+    ELOC_HIP(c, c->ar_cnt.ensure(sizeof(unsigned long long)));
+    const int64_t tiles = radix_tiles(maxc);
+    ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+    ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+    ELOC_HIP(c, launch_ar_root(c->ar_keys[0].as<uint64_t>(), W, c->ar_l[0].as<double>(), c->ar_T[0].as<double>(),
+                               c->stream));
+    int cur = 0;
+    int64_t B = 1;
+    for (int level = 0; level < Q; ++level) {
+        const int Dk = std::min(D, N - level * D);
+        const int O = 1 << Dk;
+        const int64_t n = B * O;
+        ELOC_HIP(c, hipMemsetAsync(c->ar_cnt.p, 0, sizeof(unsigned long long), c->stream));
+        ELOC_HIP(c, launch_ar_level(M, level, B, seed, c->ar_keys[cur].as<uint64_t>(), c->ar_l[cur].as<double>(),
+                                    c->ar_T[cur].as<double>(), c->ar_cl.as<double>(), c->ar_cT.as<double>(),
+                                    c->ar_ck.as<uint64_t>(), c->ar_ci.as<uint32_t>(),
+                                    c->ar_cnt.as<unsigned long long>(), c->stream));
+        unsigned long long allowed = 0;
+        ELOC_HIP(c, hipMemcpyAsync(&allowed, c->ar_cnt.p, sizeof(allowed), hipMemcpyDeviceToHost, c->stream));
+        ELOC_HIP(c, hipStreamSynchronize(c->stream));
+        const int64_t Bn = std::min<int64_t>(k, static_cast<int64_t>(allowed));
+        if (Bn == 0) return ELOC_OK;   // no allowed state
+        int alt = 0;
+        ELOC_HIP(c, launch_radix_sort_pairs(c->ar_ck.as<uint64_t>(), c->ar_ci.as<uint32_t>(), c->ar_ck2.as<uint64_t>(),
+                                            c->ar_ci2.as<uint32_t>(), n, 64, c->hist.as<uint32_t>(),
+                                            c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(), &alt, c->stream));
+        const int nxt = cur ^ 1;
+        ELOC_HIP(c, launch_ar_gather(c->ar_keys[cur].as<uint64_t>(), alt ? c->ar_ci2.as<uint32_t>() : c->ar_ci.as<uint32_t>(),
+                                     Bn, O, W, level * D, c->ar_cl.as<double>(), c->ar_cT.as<double>(),
+                                     c->ar_keys[nxt].as<uint64_t>(), c->ar_l[nxt].as<double>(),
+                                     c->ar_T[nxt].as<double>(), c->stream));
+        cur = nxt;
+        B = Bn;
+    }
+    ELOC_HIP(c, hipMemcpyAsync(keys_dev, c->ar_keys[cur].p, sizeof(uint64_t) * W * B, hipMemcpyDeviceToDevice, c->stream));
+    ELOC_HIP(c, hipMemcpyAsync(logp_dev, c->ar_l[cur].p, sizeof(double) * B, hipMemcpyDeviceToDevice, c->stream));
+    if (pert_dev)
+        ELOC_HIP(c, hipMemcpyAsync(pert_dev, c->ar_T[cur].p, sizeof(double) * B, hipMemcpyDeviceToDevice, c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    *n_out_host = B;
+    return ELOC_OK;
+}
+
+int eloc_trie_visits(eloc_ctx c, int64_t* visits_host) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!visits_host) return fail(c, ELOC_EINVAL, "null pointer");
+    rc = samples_verdict(c, nullptr);
+    if (rc) return rc;
+    rc = ensure_utrie(c);
+    if (rc) return rc;
+    const Plan P = make_plan(c, ELOC_TRIE);
+    ELOC_HIP(c, c->ar_cnt.ensure(sizeof(unsigned long long)));
+    ELOC_HIP(c, hipMemsetAsync(c->ar_cnt.p, 0, sizeof(unsigned long long), c->stream));
+    ELOC_HIP(c, launch_trie_visits(c->H, c->S, P, c->ar_cnt.as<unsigned long long>(), c->stream));
+    unsigned long long v = 0;
+    ELOC_HIP(c, hipMemcpyAsync(&v, c->ar_cnt.p, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    ELOC_HIP(c, hipStreamSynchronize(c->stream));
+    *visits_host = static_cast<int64_t>(v);
+    return ELOC_OK;
+}
+
 int eloc_check(eloc_ctx c) {
     if (!c) return ELOC_EINVAL;
     if (c->samples_set) {
@@ -658,6 +979,8 @@ int eloc_check(eloc_ctx c) {
     }
     const int bits = read_err(c, c->err_run);
     if (bits < 0) return bits;
+    // a run error is reported once: the word is cleared for the calls after it
+    if (bits) ELOC_HIP(c, hipMemsetAsync(c->err_run.p, 0, sizeof(uint32_t), c->stream));
     return map_err(c, static_cast<uint32_t>(bits));
 }
 

@@ -63,6 +63,11 @@ struct eloc_batch_s {
     int64_t narrow_items = 0;   // items of the narrow problems, scheduled first
     bool use_graph = true;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    // stage timing of eager runs: events around prepare, pairs and finish
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;   // 4 per timed run
+    std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
@@ -192,12 +197,34 @@ int launch_blocks(eloc_batch b, int precision, bool narrow) {
     return std::max(1, per_cu * b->n_cu);
 }
 
-int enqueue(eloc_batch b, int precision, hipStream_t st) {
+hipEvent_t batch_event(eloc_batch b) {
+    if (!b->ev_pool.empty()) {
+        hipEvent_t e = b->ev_pool.back();
+        b->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// `timed`: eager run with profiling on; events before prepare, pairs,
+// finish and after finish
+int enqueue(eloc_batch b, int precision, hipStream_t st, bool timed = false) {
     const BatchDev B = dev_view(b);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (timed)
+        for (auto& e : ev)
+            if (!(e = batch_event(b))) return bfail(b, ELOC_EHIP, "hipEventCreate");
+    auto mark = [&](int k) { return timed ? hipEventRecord(ev[k], st) : hipSuccess; };
+    BATCH_HIP(b, mark(0));
     BATCH_HIP(b, launch_batch_prepare(B, precision == ELOC_FP32C, st));
+    BATCH_HIP(b, mark(1));
     BATCH_HIP(b, launch_batch_pairs(B, precision, b->schedule.rows_per_wave, launch_blocks(b, precision, true),
                                     launch_blocks(b, precision, false), st));
+    BATCH_HIP(b, mark(2));
     BATCH_HIP(b, launch_batch_finish(B, precision, st));
+    BATCH_HIP(b, mark(3));
+    if (timed) b->prof_ev.insert(b->prof_ev.end(), ev, ev + 4);
     return ELOC_OK;
 }
 
@@ -228,7 +255,7 @@ int run(eloc_batch b, int precision) {
         BATCH_HIP(b, hipGraphLaunch(b->exec[precision], b->stream));
         return ELOC_OK;
     }
-    return enqueue(b, precision, b->stream);
+    return enqueue(b, precision, b->stream, b->prof);
 }
 
 // Group membership tables (LoopOverBatch), built once; a new salt is drawn if
@@ -559,6 +586,8 @@ void eloc_batch_destroy(eloc_batch b) {
                       &b->err_dev, &b->sigmin, &b->sigmax, &b->bitcounts, &b->rad, &b->shift, &b->scal, &b->part, &b->pairs, &b->work,
                       &b->a, &b->b, &b->af, &b->bf, &b->partial};
     for (DevBuf* d : bufs) d->release();
+    for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
     if (b->err_host) (void)hipHostFree(b->err_host);
     delete b;
 }
@@ -581,6 +610,32 @@ int eloc_batch_run(eloc_batch b, int precision) {
     if (!b) return ELOC_EINVAL;
     if (precision != ELOC_FP64 && precision != ELOC_FP32C) return bfail(b, ELOC_EINVAL, "unknown precision");
     return run(b, precision);
+}
+
+int eloc_batch_profile_enable(eloc_batch b, int on) {
+    if (!b) return ELOC_EINVAL;
+    b->prof = on != 0;
+    return ELOC_OK;
+}
+
+int eloc_batch_profile_read(eloc_batch b, double* ms_total, int64_t* count) {
+    if (!b || !ms_total || !count) return ELOC_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+        ms_total[k] = 0.0;
+        count[k] = 0;
+    }
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    for (size_t r = 0; r + 4 <= b->prof_ev.size(); r += 4)
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, b->prof_ev[r + k], b->prof_ev[r + k + 1]) == hipSuccess) {
+                ms_total[k] += ms;
+                count[k] += 1;
+            }
+        }
+    b->ev_pool.insert(b->ev_pool.end(), b->prof_ev.begin(), b->prof_ev.end());
+    b->prof_ev.clear();
+    return ELOC_OK;
 }
 
 int eloc_batch_check(eloc_batch b, int* bad_problem) {

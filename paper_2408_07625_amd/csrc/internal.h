@@ -353,6 +353,10 @@ struct SampleParams {
 
 struct SampleDev {
     int64_t n = 0;
+    int64_t rows = 0;                       // rows the pair kernels evaluate: samples
+                                            // 0 .. rows - 1 (0: all n); the conventional
+                                            // local energy evaluates U's rows over U and
+                                            // its coupled states
     const SampleParams* params = nullptr;   // device
     const uint32_t* prep_err = nullptr;     // device error word of the preparation: the
                                             // pair kernels do nothing while it is non-zero
@@ -566,6 +570,10 @@ hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, 
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
                              uint64_t* nkeys, hipStream_t st);
 int rows_per_block(int variant, int requested);
+// Node pairs (U node, XY node) the LoopOverTrie walk visits over all rows
+// and XY chunks, added to *visits.
+hipError_t launch_trie_visits(const HamDev& H, const SampleDev& S, const Plan& P, unsigned long long* visits,
+                              hipStream_t st);
 
 // Batched pipeline (batch.hip; the persistent pair kernel in pairs.hip).
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
@@ -574,6 +582,53 @@ hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int na
 hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st);
 int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
 
+
+// The conventional local energy's extra states: count (fill = false: one
+// count per (row, chunk) into counts) or write (fill: at offsets, [n][W]
+// keys into out) the x' = x ^ XY_g outside U with |H_xx'| > tol sum |h|.
+hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol, bool fill,
+                         int32_t* counts, const int64_t* offsets, uint64_t* out, hipStream_t st);
+// flags[i] = 1 where sorted key i starts a run of equal keys
+hipError_t launch_unique_flags(int W, const uint64_t* sorted, int64_t n, int32_t* flags, hipStream_t st);
+// out[pos[i]] = sorted[i] where flags[i]
+hipError_t launch_unique_scatter(int W, const uint64_t* sorted, int64_t n, const int32_t* flags, const int64_t* pos,
+                                 uint64_t* out, hipStream_t st);
+
+// Stochastic reconfiguration over the highest-probability samples: the
+// indices of the nsr largest Re log psi (descending, ties to the lower
+// index; sorts all n with the key scratch), and the shifted solve.
+hipError_t launch_sr_select(const double2* logpsi, int64_t n, int nsr, uint64_t* key, uint32_t* val, uint64_t* key2,
+                            uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan, int32_t* out,
+                            hipStream_t st);
+// Scratch: w[2 nsr], mean[2 np], partial[sr_partial_blocks(np)][R16][R16]
+// (R16 = 2 nsr + 1 rounded up to 16), T[R][R], L[(2 nsr)^2], y[2 nsr].
+hipError_t launch_sr_solve(int nsr, int64_t np, const double* ore, const double* oim, const double2* logpsi,
+                           const double* F, double lambda, double* w, double* mean, double* partial, double* T,
+                           double* L, double* y, double* d, uint32_t* err, hipStream_t st);
+int64_t sr_partial_blocks(int64_t np);
+
+// Autoregressive sampling without replacement: the ansatz of per-qudit
+// perceptrons (hidden width 64) and one level of the Gumbel top-K search.
+struct ArModelDev {
+    int n_qubits;
+    int qudit;
+    int n_up, n_down;
+    const double* W1;   // [Q][64][N]
+    const double* b1;   // [Q][64]
+    const double* W2;   // [Q][64][64]
+    const double* b2;   // [Q][64]
+    const double* W3;   // [Q][2^qudit][64]
+    const double* b3;   // [Q][2^qudit]
+};
+hipError_t launch_ar_root(uint64_t* keys, int W, double* l, double* T, hipStream_t st);
+// Candidates of level `level` for the B prefixes (keys, l, T): cand_* [B O],
+// O = 2^(qudit width); *n_allowed += the unmasked ones.
+hipError_t launch_ar_level(const ArModelDev& M, int level, int64_t B, uint64_t seed, const uint64_t* keys,
+                           const double* l, const double* T, double* cand_l, double* cand_T, uint64_t* cand_key,
+                           uint32_t* cand_idx, unsigned long long* n_allowed, hipStream_t st);
+hipError_t launch_ar_gather(const uint64_t* keys, const uint32_t* sorted_idx, int64_t n, int O, int W, int q0,
+                            const double* cand_l, const double* cand_T, uint64_t* out_keys, double* out_l, double* out_T,
+                            hipStream_t st);
 
 int64_t energy_scratch_len();
 int64_t amp_scratch_len();

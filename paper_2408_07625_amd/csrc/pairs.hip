@@ -63,7 +63,8 @@ struct PairArgs {
     uint32_t bloom_mask;
     int kstash;      // stash counts, read at kernel start
     int gstash;
-    int64_t M;
+    int64_t M;       // samples of U (table entries, LoopOverBatch's inner loop)
+    int64_t rows;    // rows evaluated: samples 0 .. rows - 1 (rows <= M)
     int per_chunk;
     int chunks;      // LoopOverBatch forward / adjoint: chunks of the 1-D grid
     // prefix trees
@@ -103,6 +104,7 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.bloom_words = P.bloom_words;
     a.bloom_mask = P.bloom_words ? P.bloom_words - 1u : 0u;
     a.M = S.n;
+    a.rows = S.rows > 0 ? S.rows : S.n;
     a.per_chunk = P.per_chunk;
     a.chunks = P.chunks;
     a.u_keys = S.ut.keys;
@@ -161,16 +163,16 @@ __device__ __forceinline__ bool read_sample_params(PairArgs& A) {
 template <int W, int NR>
 __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey, int64_t tile) {
     R.row0 = tile * NR;
-    R.n = static_cast<int>(min(static_cast<int64_t>(NR), A.M - R.row0));
+    R.n = static_cast<int>(min(static_cast<int64_t>(NR), A.rows - R.row0));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int64_t row = min(R.row0 + r, A.M - 1);
+        const int64_t row = min(R.row0 + r, A.rows - 1);
 #pragma unroll
         for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
         R.hx[r] = A.khash[row];
     }
     if (lane_id() < NR * W) {
-        const int64_t row = min(R.row0 + lane_id() / W, A.M - 1);
+        const int64_t row = min(R.row0 + lane_id() / W, A.rows - 1);
         rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
     }
 }
@@ -384,7 +386,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         const uint32_t meta = cb[on ? lane : 0].x;
         const int r = static_cast<int>(meta & 7u);
         const int j = static_cast<int>(meta >> 3);
-        const int64_t row = min(R.row0 + r, A.M - 1);
+        const int64_t row = min(R.row0 + r, A.rows - 1);
         const HT h = static_cast<HT>((A.khash[row] ^ T.salt) ^ A.khash[j]);
         uint64_t xj[W], m[W];
 #pragma unroll
@@ -646,6 +648,7 @@ struct FillSink {
     int jbits;
     uint64_t* pkey;
     uint32_t* pval;
+    const int32_t* perm = nullptr;   // row slot k is sample perm[row0 + k] (else row0 + k)
     // r may differ between lanes
     __device__ __forceinline__ void hit(int r, bool h, int g, int j, RunRef, uint32_t) {
 #pragma unroll
@@ -653,7 +656,8 @@ struct FillSink {
             const uint64_t m = __ballot(h && r == k);
             if (h && r == k && k < n) {
                 const int64_t p = pos[k] + lanes_below(m);
-                pkey[p] = (static_cast<uint64_t>(row0 + k) << jbits) | static_cast<uint64_t>(j);
+                const int64_t row = perm ? perm[row0 + k] : row0 + k;
+                pkey[p] = (static_cast<uint64_t>(row) << jbits) | static_cast<uint64_t>(j);
                 pval[p] = static_cast<uint32_t>(g);
             }
             pos[k] += __popcll(m);
@@ -711,7 +715,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
         chunk = static_cast<int>(blockIdx.x % static_cast<unsigned>(A.chunks));
         tile = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(A.chunks));
     }
-    if (tile * NR >= A.M) return;   // no block-wide barrier follows
+    if (tile * NR >= A.rows) return;   // no block-wide barrier follows
     uint64_t* rowkey = rowkey_s[wave];
     Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
     Rows<W, NR> R;
@@ -731,7 +735,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     if (lane_id() < R.n) {
         Acc t{};
         for (int l = 0; l < kAccCols; ++l) acc_plus(t, acc[lane_id() * kAccCols + l]);
-        store_acc(partial, static_cast<int64_t>(chunk) * A.M + R.row0 + lane_id(), t);
+        store_acc(partial, static_cast<int64_t>(chunk) * A.rows + R.row0 + lane_id(), t);
     }
 }
 
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
     Rows<W, kRows> R;
     if (!read_sample_params(A)) {   // no pairs while U is invalid
         const int64_t row = static_cast<int64_t>(blockIdx.x) * kRows + lane_id();
-        if (lane_id() < kRows && row < A.M) counts[row * chunks + blockIdx.y] = 0;
+        if (lane_id() < kRows && row < A.rows) counts[row * chunks + blockIdx.y] = 0;
         return;
     }
     load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
@@ -861,6 +865,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         A.khash = B.khash + D.s0;
         A.ktable = D.ktable;
         A.M = D.M;
+        A.rows = D.M;
         A.per_chunk = D.per_chunk;
         const uint32_t smin = B.sigmin[k], smax = B.sigmax[k];
         A.sig_pa = static_cast<int>(smin >> 8);
@@ -999,6 +1004,231 @@ __global__ __launch_bounds__(kTrieBlock) void k_fill_trie(PairArgs A, int chunks
         pval[pos] = static_cast<uint32_t>(A.xy_gid[vbase + vl]);
         ++pos;
     });
+}
+
+// ---------------------------------------------------------------------------
+// LoopOverTrie, wave-cooperative walk.  A workgroup of kTW waves shares one
+// XY chunk tree (staged in LDS when it is small); each wave owns kTRows rows
+// of U taken in sorted key order and walks U's tree against the chunk tree
+// for all of them at once.  The frontier of (row, U node, XY node, bit down
+// to which the pair is verified) entries is a stack in LDS: every step the
+// wave takes up to 64 entries from its top, one per lane, checks the bits
+// between the entry's verified bit and the next branch bit with one masked
+// XOR, and compacts the surviving children back onto the stack with
+// ballot + mbcnt; a pair of leaves is a coupled pair and goes to the sink.
+// Close to a full stack the wave takes one entry per step (a depth-first
+// walk grows the stack by at most one entry per bit), so the stack never
+// overflows.
+// ---------------------------------------------------------------------------
+constexpr int kTW = 4;          // waves per workgroup
+constexpr int kTRows = kRows;   // rows per wave
+constexpr int kTStack = 512;    // stack entries per wave
+constexpr size_t kTrieStageMax = 16 * 1024;
+constexpr int kTrieWaveMaxChunk = 32767;   // XY nodes coded in 16 bits
+
+// entry: x = U node (>= 0 internal, < 0 leaf ~i); y = XY node code (16 bits:
+// leaf i -> i, internal n -> chunk size + n) | verified bit d << 16 | row << 24
+__device__ __forceinline__ uint32_t tenc(int32_t v, int chunk_n, int d, int r) {
+    const uint32_t vc = v >= 0 ? static_cast<uint32_t>(chunk_n + v) : static_cast<uint32_t>(~v);
+    return vc | (static_cast<uint32_t>(d) << 16) | (static_cast<uint32_t>(r) << 24);
+}
+
+template <int W, class Sink>
+__device__ __forceinline__ int64_t trie_wave_walk(const PairArgs& A, const TrieView& U, const TrieView& V,
+                                                  int64_t vbase, const uint64_t* rowkey, int nrows, uint2* stk,
+                                                  Sink& sink) {
+    const int lane = lane_id();
+    const int chunk_n = static_cast<int>(V.n);
+    const int32_t u0 = U.n > 1 ? 0 : ~0;
+    const int32_t v0 = V.n > 1 ? 0 : ~0;
+    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    if (lane < nrows) stk[lane] = make_uint2(static_cast<uint32_t>(u0), tenc(v0, chunk_n, 64 * W, lane));
+    int sp = nrows;   // wave-uniform
+    int64_t visits = 0;
+    constexpr int kSlack = 64 * W + 2;
+    wave_sync();
+    while (sp > 0) {
+        const int n = (sp + kWave <= kTStack - kSlack) ? min(kWave, sp) : 1;
+        const bool on = lane < n;
+        // idle lanes decode the roots (valid indices; their results are discarded)
+        const uint2 e = on ? stk[sp - n + lane] : make_uint2(static_cast<uint32_t>(u0), tenc(v0, chunk_n, 0, 0));
+        sp -= n;
+        visits += n;
+        wave_sync();   // the popped entries are read before the pushes overwrite them
+        const int32_t u = static_cast<int32_t>(e.x);
+        const int vc = static_cast<int>(e.y & 0xFFFFu);
+        const int d = static_cast<int>((e.y >> 16) & 0xFFu);
+        const int r = static_cast<int>(e.y >> 24);
+        const int32_t v = vc >= chunk_n ? vc - chunk_n : ~vc;
+        const uint64_t* x = rowkey + r * W;
+        const TNode nu = u >= 0 ? U.nodes[u] : TNode{0, 0, ~u, -1};
+        const TNode nv = v >= 0 ? V.nodes[v] : TNode{0, 0, ~v, -1};
+        const uint64_t* ku = u >= 0 ? U.nkeys + static_cast<int64_t>(u) * W : U.keys + static_cast<int64_t>(~u) * W;
+        const uint64_t* kv = v >= 0 ? V.nkeys + static_cast<int64_t>(v) * W : V.keys + static_cast<int64_t>(~v) * W;
+        const int b = nu.bit > nv.bit ? nu.bit : nv.bit;
+        const bool agree = on && trie_agree<W>(x, ku, kv, b + 1, d);
+        const bool leaf = agree && b < 0;
+        int32_t a_u = kNoNode, a_v = kNoNode, c_u = kNoNode, c_v = kNoNode;
+        if (agree && b >= 0) {
+            const int xb = trie_bit<W>(x, b);
+            int32_t u_0, u_1, v_0, v_1;
+            if (nu.bit == b) {
+                u_0 = nu.left;
+                u_1 = nu.right;
+            } else {
+                const int ub = trie_bit<W>(ku, b);
+                u_0 = ub ? kNoNode : u;
+                u_1 = ub ? u : kNoNode;
+            }
+            if (nv.bit == b) {
+                v_0 = nv.left;
+                v_1 = nv.right;
+            } else {
+                const int vb = trie_bit<W>(kv, b);
+                v_0 = vb ? kNoNode : v;
+                v_1 = vb ? v : kNoNode;
+            }
+            // x'_b = 0: U child 0 with XY child x_b; x'_b = 1: U child 1 with XY child 1 - x_b
+            a_u = u_0;
+            a_v = xb ? v_1 : v_0;
+            c_u = u_1;
+            c_v = xb ? v_0 : v_1;
+        }
+        const bool a_ok = a_u != kNoNode && a_v != kNoNode;
+        const bool c_ok = c_u != kNoNode && c_v != kNoNode;
+        const uint64_t ma = __ballot(a_ok), mc = __ballot(c_ok);
+        if (a_ok) stk[sp + lanes_below(ma)] = make_uint2(static_cast<uint32_t>(a_u), tenc(a_v, chunk_n, b, r));
+        if (c_ok)
+            stk[sp + __popcll(ma) + lanes_below(mc)] = make_uint2(static_cast<uint32_t>(c_u), tenc(c_v, chunk_n, b, r));
+        sp += __popcll(ma) + __popcll(mc);
+        // a pair of leaves: sample j = U's leaf in caller order, group of XY's leaf
+        int g = 0, j = 0;
+        RunRef run{};
+        uint32_t xp = 0;
+        if (leaf) {
+            g = A.xy_gid[vbase + nv.rep];
+            j = A.u_perm[nu.rep];
+            xp = static_cast<uint32_t>(U.keys[static_cast<int64_t>(nu.rep) * W]);
+            if (Sink::kCarry) run = run_ref(groups[g]);
+        }
+        sink.hit(r, leaf, g, j, run, xp);
+        sink.flush();
+        wave_sync();
+    }
+    return visits;
+}
+
+template <int W>
+__device__ __forceinline__ void stage_chunk_tree(TrieView& V, uint64_t* tsm, int nthreads) {
+    const int64_t nn = V.n > 1 ? V.n - 1 : 0;
+    TNode* ln = reinterpret_cast<TNode*>(tsm);
+    uint64_t* lnk = reinterpret_cast<uint64_t*>(ln + nn);
+    uint64_t* lk = lnk + nn * W;
+    for (int64_t t = threadIdx.x; t < nn; t += nthreads) ln[t] = V.nodes[t];
+    for (int64_t t = threadIdx.x; t < nn * W; t += nthreads) lnk[t] = V.nkeys[t];
+    for (int64_t t = threadIdx.x; t < V.n * W; t += nthreads) lk[t] = V.keys[t];
+    __syncthreads();
+    V.nodes = ln;
+    V.nkeys = lnk;
+    V.keys = lk;
+}
+
+template <int W, int PREC, bool ADJ, bool NW, bool STAGE>
+__global__ __launch_bounds__(kWave * kTW) void k_pairs_trie_w(PairArgs A, const void* __restrict__ vec,
+                                                              void* __restrict__ partial) {
+    using P = Prec<PREC>;
+    using Acc = typename P::Acc;
+    extern __shared__ uint64_t tsm[];
+    __shared__ uint64_t rowkey_s[kTW][kTRows * W];
+    __shared__ QEntry<NW> q_s[kTW][2 * kWave];
+    __shared__ double2 acc_s[kTW][kTRows * kAccCols];
+    __shared__ uint2 stk_s[kTW][kTStack];
+    // no walk over an invalid U (the trees assume unique keys); uniform per block
+    if (__builtin_amdgcn_readfirstlane(static_cast<int>(*A.prep_err)) != 0) return;
+    TrieView U, V;
+    int64_t vbase;
+    trie_views<W>(A, blockIdx.y, U, V, vbase);
+    if constexpr (STAGE) stage_chunk_tree<W>(V, tsm, kWave * kTW);
+    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    const int lane = lane_id();
+    const int64_t srow0 = (static_cast<int64_t>(blockIdx.x) * kTW + wave) * kTRows;
+    if (srow0 >= A.M) return;   // no block-wide barrier follows
+    const int nrows = static_cast<int>(min(static_cast<int64_t>(kTRows), A.M - srow0));
+    uint64_t* rowkey = rowkey_s[wave];
+    if (lane < kTRows * W) rowkey[lane] = A.u_keys[min(srow0 + lane / W, A.M - 1) * W + lane % W];
+    Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
+    for (int i = lane; i < kTRows * kAccCols; i += kWave) acc[i] = Acc{};
+    wave_sync();
+    AccSink<W, PREC, ADJ, kTRows, NW> sink;
+    sink.groups = static_cast<const GroupRec<W>*>(A.groups);
+    sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
+    sink.vec = static_cast<const typename P::Vec*>(vec);
+    sink.q = q_s[wave];
+    sink.acc = acc;
+    sink.rowkey = rowkey;
+    trie_wave_walk<W>(A, U, V, vbase, rowkey, nrows, stk_s[wave], sink);
+    sink.finish();
+    if (lane < nrows) {
+        Acc t{};
+        for (int l = 0; l < kAccCols; ++l) acc_plus(t, acc[lane * kAccCols + l]);
+        store_acc(partial, static_cast<int64_t>(blockIdx.y) * A.M + A.u_perm[srow0 + lane], t);
+    }
+}
+
+// Pair counts (MODE 0), pair emission (MODE 1) or node-pair visits (MODE 2)
+// of the wave-cooperative walk.
+struct NullSink {
+    static constexpr bool kCarry = false;
+    __device__ __forceinline__ void hit(int, bool, int, int, RunRef, uint32_t) {}
+    __device__ __forceinline__ void flush() {}
+};
+
+template <int W, int MODE>
+__global__ __launch_bounds__(kWave) void k_trie_w_list(PairArgs A, int chunks, int jbits,
+                                                       int32_t* __restrict__ counts,
+                                                       const int64_t* __restrict__ offsets,
+                                                       uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval,
+                                                       unsigned long long* __restrict__ visits) {
+    __shared__ uint64_t rowkey[kTRows * W];
+    __shared__ uint2 stk[kTStack];
+    const int lane = lane_id();
+    const int64_t srow0 = static_cast<int64_t>(blockIdx.x) * kTRows;
+    if (srow0 >= A.M) return;
+    const int nrows = static_cast<int>(min(static_cast<int64_t>(kTRows), A.M - srow0));
+    if (*A.prep_err != 0u) {   // no pairs while U is invalid
+        if (MODE == 0 && lane < nrows) counts[static_cast<int64_t>(A.u_perm[srow0 + lane]) * chunks + blockIdx.y] = 0;
+        return;
+    }
+    TrieView U, V;
+    int64_t vbase;
+    trie_views<W>(A, blockIdx.y, U, V, vbase);
+    if (lane < kTRows * W) rowkey[lane] = A.u_keys[min(srow0 + lane / W, A.M - 1) * W + lane % W];
+    wave_sync();
+    if constexpr (MODE == 0) {
+        CountSink sink;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
+        trie_wave_walk<W>(A, U, V, vbase, rowkey, nrows, stk, sink);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            if (lane == r && r < nrows) counts[static_cast<int64_t>(A.u_perm[srow0 + r]) * chunks + blockIdx.y] = sink.cnt[r];
+    } else if constexpr (MODE == 1) {
+        FillSink sink;
+        sink.row0 = srow0;
+        sink.n = nrows;
+        sink.jbits = jbits;
+        sink.pkey = pkey;
+        sink.pval = pval;
+        sink.perm = A.u_perm;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            sink.pos[r] = r < nrows ? offsets[static_cast<int64_t>(A.u_perm[srow0 + r]) * chunks + blockIdx.y] : 0;
+        trie_wave_walk<W>(A, U, V, vbase, rowkey, nrows, stk, sink);
+    } else {
+        NullSink sink;
+        const int64_t n = trie_wave_walk<W>(A, U, V, vbase, rowkey, nrows, stk, sink);
+        if (lane == 0) atomicAdd(visits, static_cast<unsigned long long>(n));
+    }
 }
 
 // MatrixElement for given sample pairs (ket x_j); with cnt / grp also the
@@ -1141,31 +1371,41 @@ __global__ __launch_bounds__(kWave) void k_spmv(int64_t M, const int64_t* __rest
 template <int W, int VARIANT, int PREC, bool ADJ, bool NW>
 hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, void* partial, hipStream_t st) {
     if constexpr (VARIANT == 2) {
-        dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         const size_t lds = trie_chunk_bytes<W>(A.xy_chunk);
-        if (lds <= kTrieLdsMax)
-            hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, true>), grid, dim3(kTrieBlock), lds, st, A, vec, partial);
-        else
-            hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, false>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+        if (A.xy_chunk <= kTrieWaveMaxChunk) {
+            dim3 grid(div_up(A.M, kTRows * kTW), static_cast<unsigned>(P.chunks));
+            if (lds <= kTrieStageMax)
+                hipLaunchKernelGGL((k_pairs_trie_w<W, PREC, ADJ, NW, true>), grid, dim3(kWave * kTW), lds, st, A, vec,
+                                   partial);
+            else
+                hipLaunchKernelGGL((k_pairs_trie_w<W, PREC, ADJ, NW, false>), grid, dim3(kWave * kTW), 0, st, A, vec,
+                                   partial);
+        } else {
+            dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
+            if (lds <= kTrieLdsMax)
+                hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, true>), grid, dim3(kTrieBlock), lds, st, A, vec, partial);
+            else
+                hipLaunchKernelGGL((k_pairs_trie<W, PREC, ADJ, false>), grid, dim3(kTrieBlock), 0, st, A, vec, partial);
+        }
     } else if (VARIANT == 3 && P.bloom_words > 0 && P.waves_per_block == 4) {
         constexpr int kW = 4;
         const size_t lds = sizeof(uint32_t) * P.bloom_words;
         if (P.rows_per_block == 4) {
-            dim3 grid(div_up(div_up(A.M, 4), kW), static_cast<unsigned>(P.chunks));
+            dim3 grid(div_up(div_up(A.rows, 4), kW), static_cast<unsigned>(P.chunks));
             hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW, kW>), grid, dim3(kWave * kW), lds, st, A, vec,
                                partial);
         } else {
-            dim3 grid(div_up(div_up(A.M, kRows), kW), static_cast<unsigned>(P.chunks));
+            dim3 grid(div_up(div_up(A.rows, kRows), kW), static_cast<unsigned>(P.chunks));
             hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, kW>), grid, dim3(kWave * kW), lds, st, A,
                                vec, partial);
         }
     } else if (P.rows_per_block == 4) {
-        dim3 grid(div_up(A.M, 4), static_cast<unsigned>(P.chunks));
-        if (VARIANT == 1) grid = dim3(div_up(A.M, 4) * static_cast<unsigned>(P.chunks));
+        dim3 grid(div_up(A.rows, 4), static_cast<unsigned>(P.chunks));
+        if (VARIANT == 1) grid = dim3(div_up(A.rows, 4) * static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, 4, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     } else {
-        dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
-        if (VARIANT == 1) grid = dim3(div_up(A.M, kRows) * static_cast<unsigned>(P.chunks));
+        dim3 grid(div_up(A.rows, kRows), static_cast<unsigned>(P.chunks));
+        if (VARIANT == 1) grid = dim3(div_up(A.rows, kRows) * static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();
@@ -1200,6 +1440,20 @@ hipError_t dispatch_width(const HamDev& H, int variant, int precision, const Pai
 int rows_per_block(int variant, int requested) {
     if (variant == 2) return kTrieBlock;
     return requested == 4 ? 4 : kRows;
+}
+
+hipError_t launch_trie_visits(const HamDev& H, const SampleDev& S, const Plan& P, unsigned long long* visits,
+                              hipStream_t st) {
+    const PairArgs A = make_args(H, S, P);
+    if (A.xy_chunk > kTrieWaveMaxChunk) return hipErrorInvalidValue;
+    dim3 grid(div_up(A.M, kTRows), static_cast<unsigned>(P.chunks));
+    if (H.W == 2)
+        hipLaunchKernelGGL((k_trie_w_list<2, 2>), grid, dim3(kWave), 0, st, A, P.chunks, 0, nullptr, nullptr, nullptr,
+                           nullptr, visits);
+    else
+        hipLaunchKernelGGL((k_trie_w_list<1, 2>), grid, dim3(kWave), 0, st, A, P.chunks, 0, nullptr, nullptr, nullptr,
+                           nullptr, visits);
+    return hipGetLastError();
 }
 
 hipError_t launch_pairs(bool adjoint, int variant, int precision, const HamDev& H, const SampleDev& S, const Plan& P,
@@ -1253,7 +1507,11 @@ hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int na
 
 template <int W, bool NW>
 static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t* counts, hipStream_t st) {
-    if (variant == 2) {
+    if (variant == 2 && A.xy_chunk <= kTrieWaveMaxChunk) {
+        dim3 grid(div_up(A.M, kTRows), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL((k_trie_w_list<W, 0>), grid, dim3(kWave), 0, st, A, P.chunks, 0, counts, nullptr, nullptr,
+                           nullptr, nullptr);
+    } else if (variant == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL(k_count_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, counts);
     } else {
@@ -1271,7 +1529,11 @@ static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t
 template <int W, bool NW>
 static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbits, const int64_t* offsets,
                          uint64_t* pkey, uint32_t* pval, hipStream_t st) {
-    if (variant == 2) {
+    if (variant == 2 && A.xy_chunk <= kTrieWaveMaxChunk) {
+        dim3 grid(div_up(A.M, kTRows), static_cast<unsigned>(P.chunks));
+        hipLaunchKernelGGL((k_trie_w_list<W, 1>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, nullptr, offsets, pkey,
+                           pval, nullptr);
+    } else if (variant == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL(k_fill_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
     } else {

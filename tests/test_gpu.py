@@ -360,9 +360,11 @@ def test_phase_exponents(eng, small_workload, case):
         kk = torch.full((ref_k.size,), 7, dtype=torch.uint8, device="cuda")
         offs = torch.empty(i.size + 1, dtype=torch.int64, device="cuda")
         hh = torch.empty(i.size, dtype=torch.complex128, device="cuda")
-        rc = eng.lib.eloc_pair_elements(eng.handle, i.size, pe._ptr(dev(i, torch.int32)),
-                                        pe._ptr(dev(j, torch.int32)), pe._ptr(hh), pe._ptr(offs), pe._ptr(kk),
-                                        ref_k.size - 1)
+        # the index tensors stay referenced until the call has run (a freed
+        # temporary's memory can be handed to the next one)
+        i_dev, j_dev = dev(i, torch.int32), dev(j, torch.int32)
+        rc = eng.lib.eloc_pair_elements(eng.handle, i.size, pe._ptr(i_dev), pe._ptr(j_dev), pe._ptr(hh),
+                                        pe._ptr(offs), pe._ptr(kk), ref_k.size - 1)
         assert rc == 0
         with pytest.raises(pe.ElocError) as ex:
             eng.check()
@@ -408,9 +410,10 @@ def test_errors(eng, small_workload):
     with pytest.raises(pe.ElocError) as ex:
         eng.set_samples(keys_dev(bad))
     assert ex.value.status == "EINVAL"
+    # the rejected samples stay latched: every synchronising call reports them
     with pytest.raises(pe.ElocError) as ex:
         eng.local_energy(dev(w.logpsi[:10]))
-    assert ex.value.status == "ESTATE"
+    assert ex.value.status == "EINVAL"
     eng.set_samples(keys_dev(w.keys[:10]))
     negw = np.ones(10)
     negw[2] = -1.0
