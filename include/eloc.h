@@ -149,6 +149,26 @@ int eloc_samples_info(eloc_ctx ctx, int64_t* n_unique, int64_t* table_slots, int
 int eloc_local_energy(eloc_ctx ctx, int variant, int precision, const eloc_c64* logpsi_dev,
                       const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev);
 
+/* The forward pass of eloc_local_energy, allocating nothing: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and deferred errors as eloc_local_energy, bit for bit.  The amplitudes,
+ * partial row sums and reduction scratch live in a fixed workspace of
+ * 64 MiB per device that the library holds from its first eloc_create on
+ * that device until the process ends; about 64 bytes per sample (FP32C) or
+ * 32 (FP64) plus 16 per sample and inner-loop chunk must fit (2^18 samples
+ * do at the 100-qubit workload; ECAPACITY, with the size needed in
+ * eloc_last_error, when they do not).  Every context on a device shares
+ * that device's workspace: calls that overlap on one device (several
+ * contexts or streams) race.  Variants ELOC_TERMS, ELOC_BATCH, ELOC_AUTO
+ * and ELOC_STORED; ELOC_TRIE is EINVAL (its sorted copy of U is built on
+ * first use).  U's Bloom filter is not used.  The context's own buffers
+ * (Hamiltonian, U's tables) come from eloc_set_hamiltonian and
+ * eloc_set_samples, which allocate only when U grows.
+ * Errors (immediate): EINVAL, ESTATE, ECAPACITY, EHIP. */
+int eloc_local_energy_noalloc(eloc_ctx ctx, int variant, int precision, const eloc_c64* logpsi_dev,
+                              const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev);
+
 /* Wait for the context's stream and report a deferred device-side error:
  * first of the current samples (EINVAL, EDUP, EAGAIN as in
  * eloc_set_samples), then of the last eloc_local_energy / adjoint /

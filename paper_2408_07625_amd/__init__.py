@@ -75,6 +75,7 @@ def library() -> ctypes.CDLL:
             "eloc_set_samples": (i32, [P, i64, P]),
             "eloc_samples_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "eloc_local_energy": (i32, [P, i32, i32, P, P, P, P]),
+            "eloc_local_energy_noalloc": (i32, [P, i32, i32, P, P, P, P]),
             "eloc_find_misses": (i32, [P, ctypes.c_double, i64, P, ctypes.POINTER(i64)]),
             "eloc_local_energy_full": (i32, [P, i32, P, P, i64, P, P, P, P]),
             "eloc_sr_select": (i32, [P, i64, P, i32, P]),
@@ -120,7 +121,7 @@ def exported_symbols() -> list[str]:
     lib = library()
     return [n for n in ("eloc_create", "eloc_destroy", "eloc_last_error", "eloc_set_stream",
                         "eloc_set_hamiltonian", "eloc_hamiltonian_info", "eloc_set_samples", "eloc_samples_info",
-                        "eloc_local_energy", "eloc_find_misses",
+                        "eloc_local_energy", "eloc_local_energy_noalloc", "eloc_find_misses",
                         "eloc_local_energy_full", "eloc_sr_select", "eloc_sr_solve", "eloc_sample", "eloc_trie_visits", "eloc_check", "eloc_count_pairs", "eloc_find_pairs",
                         "eloc_pair_elements", "eloc_local_energy_adjoint", "eloc_store_pairs", "eloc_set_tuning",
                         "eloc_get_tuning",

@@ -48,6 +48,7 @@ struct eloc_ctx_s {
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
     DevBuf partial, energy_scratch, err_run, err_prep;
     uint32_t* err_host = nullptr;    // pinned words for synchronous read-backs
+    void* ws = nullptr;              // this device's fixed workspace (eloc_local_energy_noalloc)
 
     DevBuf counts, offsets, scan_scratch, pkey, pval, pkey2, pval2, hist, hist_off, hist_scratch;
 
@@ -488,7 +489,8 @@ int eloc_create(eloc_ctx* out, int device, void* hip_stream) {
         c->err_run.ensure(sizeof(uint32_t)) != hipSuccess || c->err_prep.ensure(sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->err_run.p, 0, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->err_prep.p, 0, sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess ||
+        noalloc_workspace(device, &c->ws) != hipSuccess) {
         eloc_destroy(c);
         return ELOC_EHIP;
     }
@@ -662,6 +664,68 @@ int eloc_local_energy(eloc_ctx c, int variant, int precision, const eloc_c64* lo
                               weights_dev, c->shift.as<double>(), M, stats_dev, c->energy_scratch.as<double>(),
                               c->err_run.as<uint32_t>(), c->stream));
     prof_end(c, pm);
+    return ELOC_OK;
+}
+
+int eloc_local_energy_noalloc(eloc_ctx c, int variant, int precision, const eloc_c64* logpsi_dev,
+                              const double* weights_dev, eloc_c64* eloc_dev, double* stats_dev) {
+    if (!c) return ELOC_EINVAL;
+    if (!c->ham_set) return fail(c, ELOC_ESTATE, "no Hamiltonian set");
+    if (!c->samples_set) return fail(c, ELOC_ESTATE, "no samples set");
+    if (precision != ELOC_FP64 && precision != ELOC_FP32C) return fail(c, ELOC_EINVAL, "unknown precision");
+    if (!logpsi_dev || !eloc_dev || !stats_dev) return fail(c, ELOC_EINVAL, "null pointer");
+    if (variant == ELOC_TRIE)
+        return fail(c, ELOC_EINVAL, "LoopOverTrie builds U's sorted copy on first use, which allocates; "
+                                    "use ELOC_TERMS, ELOC_BATCH, ELOC_AUTO or ELOC_STORED");
+    if (variant == ELOC_STORED) {
+        if (!c->st_valid) return fail(c, ELOC_ESTATE, "no stored pair list for these samples (eloc_store_pairs)");
+    } else {
+        if (!valid_variant(variant)) return fail(c, ELOC_EINVAL, "unknown variant");
+        variant = resolve_variant(c, variant);
+    }
+    if (!c->ws) return fail(c, ELOC_EHIP, "no fixed workspace on this device");
+    const int64_t M = c->S.n;
+    const bool fp32 = precision == ELOC_FP32C;
+    Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant);
+    P.bloom_words = 0;   // U's Bloom filter is built on first use (it allocates)
+    // workspace layout, every part 256-byte aligned
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_a = take(sizeof(double2) * M), o_b = take(sizeof(double2) * M);
+    const size_t o_af = take(fp32 ? sizeof(float4) * M : 0), o_bf = take(fp32 ? sizeof(float4) * M : 0);
+    const size_t o_shift = take(sizeof(double) * 2);
+    const size_t o_amp = take(sizeof(double) * amp_scratch_len());
+    const size_t o_part = take((fp32 ? sizeof(float4) : sizeof(double2)) * static_cast<size_t>(P.chunks) * M);
+    const size_t o_en = take(sizeof(double) * energy_scratch_len());
+    if (off > kNoAllocBytes)
+        return fail(c, ELOC_ECAPACITY,
+                    "the allocation-free forward pass needs " + std::to_string(off) + " bytes of workspace for " +
+                        std::to_string(M) + " samples; the fixed workspace holds " + std::to_string(kNoAllocBytes));
+    unsigned char* ws = static_cast<unsigned char*>(c->ws);
+    double2* a = reinterpret_cast<double2*>(ws + o_a);
+    double2* b = reinterpret_cast<double2*>(ws + o_b);
+    float4* af = fp32 ? reinterpret_cast<float4*>(ws + o_af) : nullptr;
+    float4* bf = fp32 ? reinterpret_cast<float4*>(ws + o_bf) : nullptr;
+    double* shift = reinterpret_cast<double*>(ws + o_shift);
+    void* partial = ws + o_part;
+    ELOC_HIP(c, launch_fill_u32(c->err_run.as<uint32_t>(), 1, 0u, c->stream));
+    ELOC_HIP(c, launch_amp_prep(reinterpret_cast<const double2*>(logpsi_dev), M, fp32, a, b, af, bf, shift,
+                                reinterpret_cast<double*>(ws + o_amp), c->err_run.as<uint32_t>(), c->stream));
+    if (variant == ELOC_STORED) {
+        const void* v = fp32 ? static_cast<const void*>(af) : static_cast<const void*>(a);
+        ELOC_HIP(c, launch_spmv(false, precision, M, c->st_rowptr.as<int64_t>(), c->st_col.as<int32_t>(),
+                                c->st_h.as<double2>(), v, partial, c->stream));
+    } else {
+        ELOC_HIP(c, launch_pairs(false, variant, precision, c->H, c->S, P, a, af, partial, c->stream));
+    }
+    ELOC_HIP(c, launch_finish(precision, M, P, partial, b, bf, reinterpret_cast<double2*>(eloc_dev), c->stream));
+    ELOC_HIP(c, launch_energy(reinterpret_cast<const double2*>(eloc_dev), reinterpret_cast<const double2*>(logpsi_dev),
+                              weights_dev, shift, M, stats_dev, reinterpret_cast<double*>(ws + o_en),
+                              c->err_run.as<uint32_t>(), c->stream));
     return ELOC_OK;
 }
 

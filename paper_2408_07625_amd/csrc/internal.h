@@ -630,6 +630,14 @@ hipError_t launch_ar_gather(const uint64_t* keys, const uint32_t* sorted_idx, in
                             const double* cand_l, const double* cand_T, uint64_t* out_keys, double* out_l, double* out_T,
                             hipStream_t st);
 
+// Fixed workspace of the allocation-free forward pass (one per device).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+// Device address of this device's workspace (`device` must be current on
+// the first call for it); cached per device.
+hipError_t noalloc_workspace(int device, void** out);
+// p[0..n) = v (a kernel, so that code under stream capture records no memset)
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+
 int64_t energy_scratch_len();
 int64_t amp_scratch_len();
 int64_t scan_scratch_len(int64_t n);

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 namespace eloc {
 
@@ -677,6 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_trie_build(const uint64_t* __restric
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -887,6 +893,41 @@ hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, 
         pv = alt2 ? other : pv;
     }
     hipLaunchKernelGGL(k_gather_keys, dim3(blocks_for(n)), dim3(kBlock), 0, st, keys, W, pv, n, sorted, perm);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device workspace of eloc_local_energy_noalloc: amplitudes, partial
+// row sums and reduction scratch of the forward pass, for callers that cannot
+// allocate device memory.  Every GPU the library runs on holds its own copy
+// of this array (kNoAllocBytes) until the process ends.  Host code never uses
+// the array's name as an address: its device address is taken once per
+// device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mu;
+void* g_ws_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_workspace(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    if (!g_ws_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_ws_ptr[device] = ptr;
+    }
+    *out = g_ws_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, v);
     return hipGetLastError();
 }
 
