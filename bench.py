@@ -110,6 +110,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint measurement")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the conventional local energy, SR and sampler measurements")
+    ap.add_argument("--partition", type=int, default=0,
+                    help="LoopOverTerms by U's table partitions: 0 automatic, 1 on, -1 off")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reads and writes it once), "
                          "the reference kernel for scaling hardware byte counters")
@@ -198,6 +200,8 @@ def main():
     w = configs.by_name(args.workload)
     M, N, W = w.n_unique, w.n_qubits, w.ham.n_words
     eng = pe.Engine(0)
+    if args.partition:
+        eng.set_tuning(partition=args.partition)
     eng.set_hamiltonian(N, w.ham.coeff, w.ham.xy, w.ham.yz)
     info = eng.info()
     G, NT = info["n_groups"], info["n_terms"]

@@ -363,6 +363,10 @@ typedef struct {
                             in LDS, when U is small enough to have one; 0: off  */
     int waves_per_block; /* waves sharing a workgroup (and its Bloom filter):
                             1 or 4 (0 = automatic)                              */
+    int partition;       /* forward / adjoint LoopOverTerms by partitions of U's
+                            membership table, one per XCD, so that each XCD's
+                            L2 holds its eighth of the table: 0 = automatic
+                            (tables of 8 MB and more), 1 = on, -1 = off       */
 } eloc_tuning;
 int eloc_set_tuning(eloc_ctx ctx, const eloc_tuning* tuning);
 int eloc_get_tuning(eloc_ctx ctx, eloc_tuning* tuning);

@@ -21,6 +21,10 @@ using namespace eloc;
 
 namespace {
 
+// U tables of at least this many bytes are probed by partition (an XCD's L2
+// is 4 MB)
+constexpr uint64_t kPartAutoBytes = uint64_t(8) << 20;
+
 }  // namespace
 
 struct eloc_ctx_s {
@@ -33,6 +37,8 @@ struct eloc_ctx_s {
     bool ham_set = false;
     HamDev H;
     DevBuf groups, terms, terms_f, term_src, term_ny, ghash, gkeys, gslots, gstash;
+    DevBuf groups_b, ghash_b;   // group records bucketed by the partition of their hash
+    DevBuf gbucket;             // their bucket starts [kParts + 1] (int32)
     DevBuf pe_cnt, pe_grp;   // pair_elements: term counts and groups of the pairs
     DevBuf xyt_keys, xyt_gid, xyt_nodes, xyt_nkeys;
 
@@ -43,6 +49,8 @@ struct eloc_ctx_s {
     bool bloom_built = false;   // built on first use by a kernel that reads it
     DevBuf ut_keys, ut_perm, ut_nodes, ut_nkeys;
     bool ut_valid = false;
+    DevBuf part_perm, part_class, part_tile;   // U's rows by partition class
+    bool part_ok = false;                      // U's table is partitioned and its rows classed
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
 
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
@@ -73,6 +81,7 @@ struct eloc_ctx_s {
     int tune_rows = 0;       // 0 = automatic
     int tune_bloom = 0;      // the LDS Bloom filter is slower on MI355X (occupancy); opt-in
     int tune_waves = 0;      // 0 = automatic
+    int tune_part = 0;       // 0 automatic, 1 on where possible, -1 off
     uint64_t kslots_n = 0;   // slots of U's membership table
     uint64_t salt_state = 0x5EED2408ull;
 
@@ -119,7 +128,7 @@ int resolve_variant(const eloc_ctx c, int v) {
 // inner loop (groups / samples) split into chunks of whole 64-lane steps so
 // that the grid has about `target` waves.  TRIE: one lane per row, one chunk
 // per XY tree.
-Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1) {
+Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1, bool allow_part = false) {
     Plan P;
     const int64_t M = n_rows >= 0 ? n_rows : c->S.n;
     // LoopOverTerms with the prefilters reads U's Bloom filter from LDS when
@@ -156,6 +165,18 @@ Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1) {
     const int64_t per = per_steps * 64;
     P.chunks = static_cast<int>((span + per - 1) / per);
     P.per_chunk = static_cast<int>(per);
+    // LoopOverTerms over a large U table: one XCD per table partition (the
+    // partition of a candidate is linear in the row's and the group's hashes),
+    // so that each XCD's L2 holds its eighth of the table
+    if (allow_part && variant == ELOC_TERMS && c->part_ok && c->tune_part >= 0 && P.rows_per_block == kPartRows &&
+        P.waves_per_block == 1 && n_rows < 0 &&
+        (c->tune_part > 0 || slot_bytes(table_kind(c->H.W, c->H.narrow)) * c->kslots_n >= kPartAutoBytes)) {
+        const int64_t items = ((M + kPartRows - 1) / kPartRows + kParts) * kParts;
+        P.part = true;
+        P.part_sub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (target + items - 1) / items)));
+        P.chunks = kParts * P.part_sub;
+        P.bloom_words = 0;
+    }
     return P;
 }
 
@@ -164,7 +185,8 @@ Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1) {
 int build_sample_table(eloc_ctx c) {
     const int64_t n = c->S.n;
     const int tk = table_kind(c->H.W, c->H.narrow);
-    c->S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), c->kslots_n, n, splitmix64(c->salt_state));
+    c->S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), c->kslots_n, n, splitmix64(c->salt_state),
+                            c->H.part.shift);
     ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(tk) * c->kslots_n, c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(Stash), c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
@@ -289,6 +311,33 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->term_ny.p, hh.term_ny.data(), sizeof(uint8_t) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
+    // the group records bucketed by the partition of their hash (stable)
+    {
+        std::vector<GroupRec<W>> gb;
+        std::vector<uint64_t> hb;
+        gb.reserve(static_cast<size_t>(G));
+        hb.reserve(static_cast<size_t>(G));
+        int bucket[kParts + 1] = {};
+        // a context tuned to partition every table partitions small ones by
+        // runs of 32 slots, else by blocks of 64K slots
+        c->H.part.shift = c->tune_part > 0 ? kPartShiftSmall : kPartShiftLarge;
+        for (int b = 0; b < kParts; ++b) {
+            bucket[b] = static_cast<int>(gb.size());
+            for (int64_t g = 0; g < G; ++g)
+                if (hash_part(ghash[static_cast<size_t>(g)], c->H.part.shift) == b) {
+                    gb.push_back(groups[static_cast<size_t>(g)]);
+                    hb.push_back(ghash[static_cast<size_t>(g)]);
+                }
+        }
+        bucket[kParts] = static_cast<int>(G);
+        ELOC_HIP(c, c->groups_b.ensure(sizeof(GroupRec<W>) * G));
+        ELOC_HIP(c, c->ghash_b.ensure(sizeof(uint64_t) * G));
+        ELOC_HIP(c, hipMemcpy(c->groups_b.p, gb.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
+        ELOC_HIP(c, hipMemcpy(c->ghash_b.p, hb.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
+        for (int b = 0; b <= kParts; ++b) c->H.part.bucket[b] = bucket[b];
+        ELOC_HIP(c, c->gbucket.ensure(sizeof(int32_t) * (kParts + 1)));
+        ELOC_HIP(c, hipMemcpy(c->gbucket.p, bucket, sizeof(int32_t) * (kParts + 1), hipMemcpyHostToDevice));
+    }
     ELOC_HIP(c, c->gstash.ensure(sizeof(Stash)));
     Table T;
     int rc = build_table(c, tk, c->ghash.as<uint64_t>(), G, c->gslots.p, c->gstash.as<Stash>(), cap, &T);
@@ -310,6 +359,11 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.group_hash = c->ghash.as<uint64_t>();
     H.group_keys = c->gkeys.as<uint64_t>();
     H.group_table = T;
+    H.part.groups = c->groups_b.p;
+    H.part.shift = c->H.part.shift;
+    H.part.ghash = c->ghash_b.as<uint64_t>();
+    for (int b = 0; b <= kParts; ++b) H.part.bucket[b] = c->H.part.bucket[b];
+    H.part.bucket_dev = c->gbucket.as<int32_t>();
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
     H.xyt.gid = c->xyt_gid.as<int32_t>();
     H.xyt.nodes = c->xyt_nodes.as<TNode>();
@@ -424,7 +478,7 @@ int amp_prep(eloc_ctx c, const eloc_c64* logpsi, bool fp32) {
 int row_sums(eloc_ctx c, bool adjoint, int variant, int precision, const double2* vec, const float4* vecf, Plan* plan) {
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
-    const Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant);
+    const Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant, -1, true);
     ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
     const int pm = prof_begin(c, adjoint ? ELOC_STAGE_ADJOINT_PAIRS : ELOC_STAGE_PAIRS);
     if (variant == ELOC_STORED) {
@@ -513,6 +567,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
                       &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->st_rowptr, &c->st_col, &c->st_h,
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
+                      &c->groups_b, &c->ghash_b, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
                       &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
                       &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt};
     for (DevBuf* b : bufs) b->release();
@@ -631,6 +686,31 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     // stay latched in the preparation error word until a synchronising call
     const int rc = build_sample_table(c);
     if (rc) return rc;
+    c->part_ok = false;
+    if (cap >= part_min_slots(c->H.part.shift) &&
+        (c->tune_part > 0 || (c->tune_part == 0 && slot_bytes(tk) * cap >= kPartAutoBytes))) {
+        const int64_t tiles = radix_tiles(n_unique);
+        ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * n_unique));
+        ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * n_unique));
+        ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * n_unique));
+        ELOC_HIP(c, c->s_val2.ensure(sizeof(uint32_t) * n_unique));
+        ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+        ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+        ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+        ELOC_HIP(c, c->part_perm.ensure(sizeof(int32_t) * n_unique));
+        ELOC_HIP(c, c->part_class.ensure(sizeof(int64_t) * (kParts + 1)));
+        ELOC_HIP(c, c->part_tile.ensure(sizeof(int64_t) * (kParts + 1)));
+        ELOC_HIP(c, launch_row_classes(c->khash.as<uint64_t>(), n_unique, c->H.part.shift, c->s_key.as<uint64_t>(),
+                                       c->s_val.as<uint32_t>(),
+                                       c->s_key2.as<uint64_t>(), c->s_val2.as<uint32_t>(), c->hist.as<uint32_t>(),
+                                       c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(),
+                                       c->part_perm.as<int32_t>(), c->part_class.as<int64_t>(),
+                                       c->part_tile.as<int64_t>(), c->stream));
+        c->S.part.row_perm = c->part_perm.as<int32_t>();
+        c->S.part.class_off = c->part_class.as<int64_t>();
+        c->S.part.tile_off = c->part_tile.as<int64_t>();
+        c->part_ok = true;
+    }
     prof_end(c, pm);
     c->ut_valid = false;
     c->st_valid = false;
@@ -686,7 +766,7 @@ int eloc_local_energy_noalloc(eloc_ctx c, int variant, int precision, const eloc
     if (!c->ws) return fail(c, ELOC_EHIP, "no fixed workspace on this device");
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
-    Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant);
+    Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant, -1, true);
     P.bloom_words = 0;   // U's Bloom filter is built on first use (it allocates)
     // workspace layout, every part 256-byte aligned
     size_t off = 0;
@@ -1216,6 +1296,7 @@ int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
     c->tune_rows = t->rows_per_wave;
     c->tune_bloom = t->bloom;
     c->tune_waves = t->waves_per_block;
+    c->tune_part = t->partition;
     return ELOC_OK;
 }
 
@@ -1226,6 +1307,7 @@ int eloc_get_tuning(eloc_ctx c, eloc_tuning* t) {
     t->rows_per_wave = c->tune_rows;
     t->bloom = c->tune_bloom;
     t->waves_per_block = c->tune_waves;
+    t->partition = c->tune_part;
     return ELOC_OK;
 }
 

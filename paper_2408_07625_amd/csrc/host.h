@@ -55,7 +55,8 @@ inline uint64_t pow2_at_least(uint64_t v) {
     return c;
 }
 
-inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n, uint64_t salt) {
+inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n, uint64_t salt,
+                        int part_shift = kPartShiftLarge) {
     Table T;
     T.stash = stash;
     T.slots = slots;
@@ -64,6 +65,7 @@ inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n,
     T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
     T.fpshift = 32 + T.ibits;
     T.capbits = bits_for(capacity - 1);
+    T.pmask = capacity >= part_min_slots(part_shift) ? (7u << part_shift) : 0u;
     T.salt = salt;
     return T;
 }

@@ -116,9 +116,28 @@ struct Table {
     uint32_t imask;     // (1 << ibits) - 1
     int fpshift;        // two-word keys: fingerprint = hs >> fpshift
     int capbits;        // log2(capacity)
+    uint32_t pmask;     // partition bits of a slot index (7 << shift, or 0: not partitioned)
     uint64_t salt;
     const Stash* stash;
 };
+
+// A table of at least 8 << shift slots is split into eight partitions by
+// bits shift .. shift + 2 of the slot index; both slots of a key lie in the
+// partition of the key's salted hash.  The hash is GF(2)-linear, so the
+// partition of a candidate x ^ XY is part(x) ^ part(XY) ^ part(salt): a
+// kernel can give each XCD the candidates of one partition, whose slots then
+// stay in that XCD's L2.  Large tables use shift 16 (partitions made of
+// blocks of 64K slots, so that every L2 channel and memory channel serves
+// every partition: with low shift bits a partition would fall on a few
+// channels only); shift 5 (runs of 32 slots) lets small tables exercise the
+// same path.
+constexpr int kPartShiftLarge = 16;
+constexpr int kPartShiftSmall = 5;
+constexpr int kParts = 8;
+__host__ __device__ __forceinline__ int hash_part(uint64_t h, int shift) {
+    return static_cast<int>((h >> shift) & 7u);
+}
+__host__ __device__ __forceinline__ uint64_t part_min_slots(int shift) { return uint64_t(8) << shift; }
 
 template <int TK>
 __host__ __device__ __forceinline__ typename TabT<TK>::hash salted(const Table& T, uint64_t h) {
@@ -128,9 +147,13 @@ template <class HT>
 __host__ __device__ __forceinline__ uint32_t slot1(const Table& T, HT hs) {
     return static_cast<uint32_t>(hs) & T.mask;
 }
+// The second slot keeps the first slot's partition bits; the other bits mix
+// in the hash bits above the slot index (always odd, so the slots differ).
+// Position and stored tag still determine the hash exactly.
 template <class HT>
 __host__ __device__ __forceinline__ uint32_t slot2(const Table& T, HT hs) {
-    return (static_cast<uint32_t>(hs) ^ (static_cast<uint32_t>(hs >> T.capbits) | 1u)) & T.mask;
+    const uint32_t s = (static_cast<uint32_t>(hs) ^ (static_cast<uint32_t>(hs >> T.capbits) | 1u)) & T.mask;
+    return (s & ~T.pmask) | (static_cast<uint32_t>(hs) & T.pmask);
 }
 // two-word keys; never 0, so an empty slot cannot match
 __host__ __device__ __forceinline__ uint32_t fingerprint(const Table& T, uint64_t hs) {
@@ -256,8 +279,9 @@ __device__ __forceinline__ void table_insert_one(const uint64_t* __restrict__ ha
         for (int k = 0; k < kMaxKicks; ++k) {
             const ST old = atomicExch(slots + s, v);
             if (old == 0) return;
-            // the evicted key moves to its other slot (the same XOR in both directions)
-            s ^= (static_cast<uint32_t>(old >> (T.ibits + 1)) | 1u) & T.mask;
+            // the evicted key moves to its other slot (the same XOR in both
+            // directions; the partition bits are kept, as slot2 keeps them)
+            s ^= (static_cast<uint32_t>(old >> (T.ibits + 1)) | 1u) & T.mask & ~T.pmask;
             v = old ^ (static_cast<ST>(1) << T.ibits);
         }
         held = static_cast<int64_t>(v & T.imask) - 1;
@@ -335,6 +359,15 @@ struct HamDev {
     const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
     Table group_table{};               // XY -> group id
     XYTrieDev xyt{};
+    // the group records again, bucketed by hash_part of their hash (stable),
+    // for LoopOverTerms over a partitioned U table
+    struct {
+        const void* groups = nullptr;
+        const uint64_t* ghash = nullptr;
+        int bucket[kParts + 1] = {};           // bucket starts (host copy)
+        const int32_t* bucket_dev = nullptr;   // the same [kParts + 1] on the device
+        int shift = kPartShiftLarge;   // partition bits of U's tables for this Hamiltonian
+    } part;
 };
 
 // Prefilter parameters of U for LoopOverTerms, derived on the device by
@@ -365,6 +398,13 @@ struct SampleDev {
     Table table{};
     const uint64_t* sig = nullptr;     // [kSigWords] signature bitmap
     UTrieDev ut{};                     // valid once built for this batch
+    // rows ordered by hash_part of their (unsalted) hash, for the partitioned
+    // LoopOverTerms: built with U's table when the table is partitioned
+    struct {
+        const int32_t* row_perm = nullptr;
+        const int64_t* class_off = nullptr;   // [kParts + 1] (device)
+        const int64_t* tile_off = nullptr;    // [kParts + 1] (device), tiles of kRows rows
+    } part;
 };
 
 // Amplitudes relative to the largest |psi|: a_i = exp(L_i - c), c = max Re L.
@@ -389,6 +429,8 @@ struct Plan {
     int waves_per_block = 1;   // waves of a TERMS / BATCH workgroup
     const uint32_t* bloom = nullptr;   // U's Bloom filter (LoopOverTerms), staged in LDS
     uint32_t bloom_words = 0;          // its size in words, a power of two (0: not used)
+    bool part = false;                 // LoopOverTerms by U's table partitions (one per XCD)
+    int part_sub = 1;                  // chunks of a group bucket (chunks = 8 part_sub)
 };
 
 // Error bits latched in a device word, read by eloc_check / synchronising calls.
@@ -570,6 +612,13 @@ hipError_t launch_sort_keys(int W, int n_bits, const uint64_t* keys, int64_t n, 
 hipError_t launch_trie_build(int W, const uint64_t* keys, int64_t n_total, int64_t per, TNode* nodes,
                              uint64_t* nkeys, hipStream_t st);
 int rows_per_block(int variant, int requested);
+constexpr int kPartRows = 8;   // rows of a tile of the partitioned LoopOverTerms
+// Rows ordered by the partition class of their hash (stable), the first
+// position and the first tile (kPartRows rows, classes padded to whole tiles)
+// of every class: perm[n], class_off[9], tile_off[9]; scratch as for the sort.
+hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, uint64_t* key, uint32_t* val, uint64_t* key2,
+                              uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan, int32_t* perm,
+                              int64_t* class_off, int64_t* tile_off, hipStream_t st);
 // Node pairs (U node, XY node) the LoopOverTrie walk visits over all rows
 // and XY chunks, added to *visits.
 hipError_t launch_trie_visits(const HamDev& H, const SampleDev& S, const Plan& P, unsigned long long* visits,

@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kRows = 8;                 // rows per wave (TERMS / BATCH)
+static_assert(kRows == kPartRows, "the partitioned LoopOverTerms tiles are whole waves of rows");
 constexpr int kLongRun = 16;             // longer term runs are split over the wave
 constexpr int kTrieBlock = 256;
 
@@ -77,6 +78,21 @@ struct PairArgs {
     const TNode* xy_nodes;
     const uint64_t* xy_nkeys;
     int xy_chunk;
+    // LoopOverTerms split by U's table partitions (large tables): workgroup w
+    // serves XCD w % 8, which probes only partition w % 8; a tile's rows share
+    // one partition class, so its groups are the bucket class ^ part ^ salt's
+    bool part;
+    int part_salt;              // partition bits of U's table salt
+    const int32_t* row_perm;    // rows ordered by class (stable)
+    const int64_t* class_off;   // [9] first position of each class in row_perm
+    const int64_t* tile_off;    // [9] first tile of each class
+    const void* groups_b;       // group records bucketed by the partition of their hash
+    const uint64_t* ghash_b;
+    // bucket starts in groups_b [kParts + 1], in device memory: a kernel
+    // argument array indexed at run time would move the whole argument
+    // block to the stack
+    const int32_t* gbucket;
+    int part_sub;               // chunks of a bucket
 };
 
 PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
@@ -116,6 +132,15 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.xy_nodes = H.xyt.nodes;
     a.xy_nkeys = H.xyt.nkeys;
     a.xy_chunk = H.xyt.chunk;
+    a.part = P.part;
+    a.part_salt = hash_part(S.table.salt, H.part.shift);
+    a.row_perm = S.part.row_perm;
+    a.class_off = S.part.class_off;
+    a.tile_off = S.part.tile_off;
+    a.groups_b = H.part.groups;
+    a.ghash_b = H.part.ghash;
+    a.gbucket = H.part.bucket_dev;
+    a.part_sub = P.part_sub;
     return a;
 }
 
@@ -129,6 +154,7 @@ struct Rows {
     static constexpr int kN = NR;
     int n;
     int64_t row0;
+    int64_t id[NR];      // sample index of each row slot (clamped copies past n)
     uint64_t x[NR][W];
     uint64_t hx[NR];
 };
@@ -167,12 +193,33 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int64_t row = min(R.row0 + r, A.rows - 1);
+        R.id[r] = row;
 #pragma unroll
         for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
         R.hx[r] = A.khash[row];
     }
     if (lane_id() < NR * W) {
         const int64_t row = min(R.row0 + lane_id() / W, A.rows - 1);
+        rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
+    }
+}
+
+// Rows of a tile taken through a row order: positions [p0, p0 + n) of perm.
+template <int W, int NR>
+__device__ __forceinline__ void load_rows_perm(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey, int64_t p0,
+                                               int n, const int32_t* __restrict__ perm) {
+    R.row0 = p0;
+    R.n = n;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int64_t row = perm[p0 + min(r, n - 1)];
+        R.id[r] = row;
+#pragma unroll
+        for (int w = 0; w < W; ++w) R.x[r][w] = A.keys[row * W + w];
+        R.hx[r] = A.khash[row];
+    }
+    if (lane_id() < NR * W) {
+        const int64_t row = perm[p0 + min(lane_id() / W, n - 1)];
         rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
     }
 }
@@ -199,15 +246,15 @@ template <bool NW>
 using CEntry = std::conditional_t<NW, uint2, uint4>;
 
 template <int W, int SIG, int NR, bool NW, bool BL, class Sink>
-__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
+__device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int g0, int g1,
+                                           const void* groups_v, const uint64_t* __restrict__ ghash, Sink& sink,
                                            const uint32_t* lfilt, CEntry<NW>* cb, const uint64_t* rowkey) {
     constexpr int TK = table_kind(W, NW);
     using HT = typename TabT<TK>::hash;
-    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
+    const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(groups_v);
     const Table& T = A.ktable;
     const SlotReader<TK> slots(T);
-    const int g0 = chunk * A.per_chunk;
-    const int g1 = min(A.n_groups, g0 + A.per_chunk);
+    if (g0 >= g1) return;
     const int lane = lane_id();
     // the step's group fields live in plain registers (mask words, term
     // run, hash)
@@ -219,7 +266,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
 #pragma unroll
         for (int w = 0; w < W; ++w) gxy[w] = gr.xy[w];
         run = run_ref(gr);
-        gh = A.ghash[min(g0 + lane, g1 - 1)];
+        gh = ghash[min(g0 + lane, g1 - 1)];
     }
     for (int base = g0; base < g1; base += kWave) {
         const int g = base + lane;
@@ -236,7 +283,7 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
 #pragma unroll
             for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
             nrun = run_ref(gr);
-            ngh = A.ghash[ng];
+            ngh = ghash[ng];
         }
         // the exact prefilters of candidate x ^ XY for row r: U's single
         // popcount signature (unless sig_all), U's radius around its majority
@@ -672,10 +719,12 @@ struct FillSink {
 template <int W, int VARIANT, int NR, bool NW, bool BL = false, class Sink>
 __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, int chunk, Sink& sink,
                                      CEntry<NW>* cb, const uint64_t* rowkey, const uint32_t* lfilt = nullptr) {
+    const int g0 = chunk * A.per_chunk;
+    const int g1 = min(A.n_groups, g0 + A.per_chunk);
     if constexpr (VARIANT == 0)
-        find_terms<W, 0, NR, NW, false>(A, R, chunk, sink, lfilt, cb, rowkey);
+        find_terms<W, 0, NR, NW, false>(A, R, g0, g1, A.groups, A.ghash, sink, lfilt, cb, rowkey);
     else if constexpr (VARIANT == 3)
-        find_terms<W, 1, NR, NW, BL>(A, R, chunk, sink, lfilt, cb, rowkey);
+        find_terms<W, 1, NR, NW, BL>(A, R, g0, g1, A.groups, A.ghash, sink, lfilt, cb, rowkey);
     else
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
 }
@@ -690,8 +739,9 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 // (dynamic shared memory) once per workgroup.  LoopOverBatch runs on a 1-D
 // grid with chunk = workgroup id mod chunks: workgroups go to the eight XCDs
 // in turn, so with a multiple of eight chunks each XCD streams only its own
-// chunks of U through its L2.
-template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB>
+// chunks of U through its L2.  PART: LoopOverTerms by U's table partitions
+// (a separate instantiation, so that the plain kernel keeps its registers).
+template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB, bool PART = false>
 __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                        void* __restrict__ partial) {
     using P = Prec<PREC>;
@@ -715,27 +765,63 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
         chunk = static_cast<int>(blockIdx.x % static_cast<unsigned>(A.chunks));
         tile = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(A.chunks));
     }
-    if (tile * NR >= A.rows) return;   // no block-wide barrier follows
     uint64_t* rowkey = rowkey_s[wave];
     Acc* acc = reinterpret_cast<Acc*>(acc_s[wave]);
     Rows<W, NR> R;
-    load_rows<W, NR>(A, R, rowkey, tile);
+    int g0 = 0, g1 = 0;
+    static_assert(!PART || (VARIANT != 1 && WPB == 1 && NR == kPartRows), "partitioned LoopOverTerms tiles");
+    constexpr bool part = PART;
+    if constexpr (part) {
+        // 1-D grid: workgroup w serves XCD w % 8 (partition k), then
+        // (tile, sub-chunk); the tile's class c gives the group bucket
+        // c ^ k ^ part(salt), whose candidates all fall in partition k
+        const int k = static_cast<int>(blockIdx.x % kParts);
+        const int64_t item = blockIdx.x / kParts;
+        const int sub = static_cast<int>(item % A.part_sub);
+        const int64_t t = item / A.part_sub;
+        if (t >= A.tile_off[kParts]) return;
+        int c = 0;
+#pragma unroll
+        for (int q = 1; q < kParts; ++q) c += t >= A.tile_off[q] ? 1 : 0;
+        const int64_t p0 = A.class_off[c] + (t - A.tile_off[c]) * NR;
+        const int n = static_cast<int>(min(static_cast<int64_t>(NR), A.class_off[c + 1] - p0));
+        load_rows_perm<W, NR>(A, R, rowkey, p0, n, A.row_perm);
+        const int b = c ^ k ^ A.part_salt;
+        const int bs = A.gbucket[b], be = A.gbucket[b + 1];
+        const int per = (be - bs + A.part_sub - 1) / A.part_sub;
+        g0 = min(be, bs + sub * per);
+        g1 = min(be, g0 + per);
+        chunk = k * A.part_sub + sub;
+    } else {
+        if (tile * NR >= A.rows) return;   // no block-wide barrier follows
+        load_rows<W, NR>(A, R, rowkey, tile);
+    }
     for (int i = lane_id(); i < NR * kAccCols; i += kWave) acc[i] = Acc{};
     wave_sync();
     AccSink<W, PREC, ADJ, NR, NW> sink;
-    sink.groups = static_cast<const GroupRec<W>*>(A.groups);
+    sink.groups = static_cast<const GroupRec<W>*>(part ? A.groups_b : A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
     sink.vec = static_cast<const typename P::Vec*>(vec);
     sink.q = q_s[wave];
     sink.acc = acc;
     sink.rowkey = rowkey;
-    find<W, VARIANT, NR, NW, BL>(A, R, chunk, sink, cb_s[wave], rowkey, lfilt);
+    if constexpr (part)
+        find_terms<W, VARIANT == 3 ? 1 : 0, NR, NW, BL>(A, R, g0, g1, A.groups_b, A.ghash_b, sink, lfilt, cb_s[wave],
+                                                         rowkey);
+    else
+        find<W, VARIANT, NR, NW, BL>(A, R, chunk, sink, cb_s[wave], rowkey, lfilt);
     sink.finish();
     // per-row totals: lane r adds the columns of row r in order
     if (lane_id() < R.n) {
         Acc t{};
         for (int l = 0; l < kAccCols; ++l) acc_plus(t, acc[lane_id() * kAccCols + l]);
-        store_acc(partial, static_cast<int64_t>(chunk) * A.rows + R.row0 + lane_id(), t);
+        int64_t id = R.row0 + lane_id();
+        if constexpr (part) {
+            id = R.id[0];
+#pragma unroll
+            for (int r = 1; r < NR; ++r) id = lane_id() == r ? R.id[r] : id;
+        }
+        store_acc(partial, static_cast<int64_t>(chunk) * A.rows + id, t);
     }
 }
 
@@ -814,7 +900,8 @@ __device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, N
     if (D.variant == 1)
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
     else
-        find_terms<W, 1, NR, NW, false>(A, R, chunk, sink, nullptr, cb, rowkey);
+        find_terms<W, 1, NR, NW, false>(A, R, chunk * A.per_chunk, min(A.n_groups, (chunk + 1) * A.per_chunk),
+                                        A.groups, A.ghash, sink, nullptr, cb, rowkey);
     sink.finish();
     return sink.hits;
 }
@@ -1406,6 +1493,17 @@ hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, voi
     } else {
         dim3 grid(div_up(A.rows, kRows), static_cast<unsigned>(P.chunks));
         if (VARIANT == 1) grid = dim3(div_up(A.rows, kRows) * static_cast<unsigned>(P.chunks));
+        if constexpr (VARIANT != 1) {
+            if (A.part) {
+                // partitioned LoopOverTerms: at most rows / 8 + 8 tiles
+                // (classes padded to whole tiles), eight partitions,
+                // part_sub chunks each
+                grid = dim3((div_up(A.rows, kRows) + kParts) * kParts * static_cast<unsigned>(A.part_sub));
+                hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1, true>), grid, dim3(kWave), 0, st, A,
+                                   vec, partial);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1>), grid, dim3(kWave), 0, st, A, vec, partial);
     }
     return hipGetLastError();

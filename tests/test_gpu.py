@@ -630,3 +630,47 @@ def test_backward_after_state_change_raises(eng, small_workload):
         eng.adjoint(dev(w.logpsi), e, st[:3], 1.0)
     with pytest.raises(ValueError):
         eng.adjoint(dev(w.logpsi), e, st, 1.0, weights=dev(np.ones(5)))
+
+
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("wl", ["small", "medium", "odd_y"])
+def test_partitioned_terms(eng, wl, small_workload, medium_workload):
+    """LoopOverTerms by U's table partitions (one XCD per partition; on by
+    default only for tables of 8 MB and more, forced here): forward and
+    adjoint against the oracle in both precisions, bitwise reproducible, and
+    the pair list of the variant unchanged."""
+    if wl == "odd_y":
+        rng = np.random.default_rng(21)
+        ham = jw.random_pauli(11, 500, rng, max_flip=3)
+        keys = rng.choice(2 ** 11, 1500, replace=False).astype(np.uint64)[:, None]
+        lp = rng.normal(scale=0.5, size=1500) + 1j * rng.uniform(0, 6, 1500)
+    else:
+        w = small_workload if wl == "small" else medium_workload
+        ham, keys, lp = w.ham, w.keys, w.logpsi
+    M = keys.shape[0]
+    rows = (0, min(M, 1500))
+    eng.set_tuning(partition=1)
+    try:
+        load(eng, ham, keys)
+        ref = oracle.local_energy(ham, keys, lp, rows=rows)
+        L = dev(lp)
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, st = eng.local_energy(L, variant="terms", precision=prec)
+            e1, st1 = e.clone(), st.clone()
+            err = np.abs(e.cpu().numpy()[rows[0]:rows[1]] - ref).max()
+            print(f"partitioned {wl} {prec}: max |dE_loc| = {err:.2e}")
+            assert err <= tol * max(1.0, np.abs(ref).max())
+            e2, st2 = eng.local_energy(L, variant="terms", precision=prec)
+            assert torch.equal(e1, e2) and torch.equal(st1, st2)
+            if M <= 2000:
+                E, var, _ = oracle.energy(oracle.local_energy(ham, keys, lp), lp)
+                s = st.cpu().numpy()
+                assert abs(s[0] - E.real) <= tol and abs(s[2] - var) <= tol * max(1.0, var)
+                g = eng.adjoint(L, e, st, 0.3 - 0.4j, None, variant="terms", precision=prec).cpu().numpy()
+                gr = oracle.adjoint(ham, keys, lp, oracle.local_energy(ham, keys, lp), 0.3 - 0.4j, energy_value=E)
+                assert np.abs(g - gr).max() <= tol * max(1.0, np.abs(gr).max())
+        if M <= 2000:
+            for a, b in zip(gpu_pairs(eng, "terms"), oracle_pairs(ham, keys)):
+                np.testing.assert_array_equal(a, b)
+    finally:
+        eng.set_tuning()
