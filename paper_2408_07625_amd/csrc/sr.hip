@@ -16,8 +16,10 @@
 //                 eight waves accumulate 16 x 16 tiles of the upper triangle
 //                 with FP64 MFMA (v_mfma_f64_16x16x4f64); one partial Gram
 //                 per workgroup, added in fixed order by k_sr_reduce
-//   k_sr_chol     Cholesky of X X^T + lambda I and the two triangular solves
-//                 for y = (X X^T + lambda I)^{-1} X F, one workgroup
+//   k_sr_chol_reg Cholesky of X X^T + lambda I and the two triangular solves
+//                 for y = (X X^T + lambda I)^{-1} X F: one workgroup whose
+//                 threads hold the lower triangle in registers (N_SR <= 127)
+//   k_sr_chol     the same from global memory, one wave (larger sets)
 //   k_sr_update   d_p = (F_p - sum_r X_rp y_r) / lambda
 #include "device.h"
 
@@ -242,6 +244,104 @@ __global__ __launch_bounds__(64) void k_sr_chol(const double* __restrict__ T, in
     }
 }
 
+// The factorisation of the augmented matrix [[A, b], [b^T, *]] (A = T[0..n)^2
+// + lambda I, b = T[n][0..n)): its last row of L is z = L^{-1} b, so the
+// forward substitution comes with the factorisation.  The lower triangle
+// (rows 0..n) is held in registers, cyclically over a 32 x 32 grid of
+// threads: thread (tr, tc) owns the elements (tr + 32 p, tc + 32 q), p >= q.
+// Step k publishes column k unnormalised (a_ik, i >= k) in LDS,
+// double-buffered so that one barrier per step suffices; then a_ij -= a_ik
+// a_jk / a_kk for j > k, and column k becomes L's (a_ik / sqrt(a_kk)).  The
+// back substitution L^T y = z runs over the rows j of L from the last: the
+// owners of (j, i < j) take L_ji y_j off z_i.
+constexpr int kCholThreads = 1024;
+constexpr int kCholMaxRows = 256;   // rows of the augmented matrix (n + 1) the register form takes
+
+template <int P>
+__global__ __launch_bounds__(kCholThreads) void k_sr_chol_reg(const double* __restrict__ T, int n, int R, double lambda,
+                                                             double* __restrict__ y, uint32_t* __restrict__ err) {
+    static_assert(32 * P <= kCholMaxRows, "rows of the register grid");
+    __shared__ double col[2][kCholMaxRows];
+    __shared__ double zbuf[kCholMaxRows];
+    __shared__ double diag[kCholMaxRows];
+    const int tid = static_cast<int>(threadIdx.x);
+    const int tr = tid >> 5, tc = tid & 31;
+    double a[P][P];   // [p][q], p >= q used
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int q = 0; q <= p; ++q) {
+            const int i = tr + 32 * p, j = tc + 32 * q;
+            a[p][q] = (i <= n && j <= i) ? T[static_cast<int64_t>(i) * R + j] + (i == j && i < n ? lambda : 0.0) : 0.0;
+        }
+    for (int k = 0; k < n; ++k) {
+        double* c = col[k & 1];
+        const int qk = k >> 5;
+        if (tc == (k & 31)) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int q = 0; q <= p; ++q) {
+                    const int i = tr + 32 * p;
+                    if (q == qk && i >= k && i <= n) c[i] = a[p][q];
+                }
+        }
+        __syncthreads();
+        const double akk = c[k];
+        if (tid == 0 && !(akk > 0.0)) atomicOr(err, static_cast<uint32_t>(kErrRange));
+        const double dk = fmax(akk, 1e-300);
+        const double piv = sqrt(dk);
+        const double inv = 1.0 / dk;
+        if (tid == 0) diag[k] = piv;
+        double cr[P], cc[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            cr[p] = c[tr + 32 * p];
+            cc[p] = c[tc + 32 * p];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q <= p; ++q) {
+                const int i = tr + 32 * p, j = tc + 32 * q;
+                if (i > n || j > i) continue;
+                if (j == k)
+                    a[p][q] = i == k ? piv : a[p][q] / piv;
+                else if (j > k)
+                    a[p][q] -= cr[p] * cc[q] * inv;
+            }
+    }
+    if (tr == (n & 31)) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q <= p; ++q) {
+                const int j = tc + 32 * q;
+                if (p == (n >> 5) && j < n) zbuf[j] = a[p][q];
+            }
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+        const double yj = zbuf[j] / diag[j];
+        if (tr == (j & 31)) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int q = 0; q <= p; ++q) {
+                    const int i = tc + 32 * q;
+                    if (p == (j >> 5) && i < j) zbuf[i] -= a[p][q] * yj;
+                }
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < n; j += kCholThreads) y[j] = zbuf[j] / diag[j];
+}
+
+template <int P>
+void launch_chol_reg(const double* T, int n, int R, double lambda, double* y, uint32_t* err, hipStream_t st) {
+    hipLaunchKernelGGL((k_sr_chol_reg<P>), dim3(1), dim3(kCholThreads), 0, st, T, n, R, lambda, y, err);
+}
+
 __global__ __launch_bounds__(256) void k_sr_update(SrArgs A, const double* __restrict__ y, double lambda,
                                                    double* __restrict__ d) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -315,7 +415,20 @@ hipError_t launch_sr_solve(int nsr, int64_t np, const double* ore, const double*
     const int64_t RR = static_cast<int64_t>(A.R) * A.R;
     hipLaunchKernelGGL(k_sr_reduce, dim3(blocks256(RR)), dim3(256), 0, st, partial, static_cast<int>(nb), A.R16, A.R,
                        T);
-    hipLaunchKernelGGL(k_sr_chol, dim3(1), dim3(64), 0, st, T, 2 * nsr, A.R, lambda, L, y, err);
+    const int n = 2 * nsr;
+    const int P = (n + 1 + 31) / 32;   // row blocks of the augmented matrix
+    if (P > kCholMaxRows / 32)
+        hipLaunchKernelGGL(k_sr_chol, dim3(1), dim3(64), 0, st, T, n, A.R, lambda, L, y, err);
+    else if (P <= 2)
+        launch_chol_reg<2>(T, n, A.R, lambda, y, err, st);
+    else if (P <= 4)
+        launch_chol_reg<4>(T, n, A.R, lambda, y, err, st);
+    else if (P <= 6)
+        launch_chol_reg<6>(T, n, A.R, lambda, y, err, st);
+    else if (P == 7)
+        launch_chol_reg<7>(T, n, A.R, lambda, y, err, st);
+    else
+        launch_chol_reg<8>(T, n, A.R, lambda, y, err, st);
     hipLaunchKernelGGL(k_sr_update, dim3(blocks256(np)), dim3(256), 0, st, A, y, lambda, d);
     return hipGetLastError();
 }
