@@ -112,6 +112,7 @@ def parse():
                     help="skip the conventional local energy, SR and sampler measurements")
     ap.add_argument("--partition", type=int, default=0,
                     help="LoopOverTerms by U's table partitions: 0 automatic, 1 on, -1 off")
+    ap.add_argument("--partition-count", type=int, default=0, help="table partitions: 8, 16, 32 (0 automatic)")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reads and writes it once), "
                          "the reference kernel for scaling hardware byte counters")
@@ -200,8 +201,8 @@ def main():
     w = configs.by_name(args.workload)
     M, N, W = w.n_unique, w.n_qubits, w.ham.n_words
     eng = pe.Engine(0)
-    if args.partition:
-        eng.set_tuning(partition=args.partition)
+    if args.partition or args.partition_count:
+        eng.set_tuning(partition=args.partition, partition_count=args.partition_count)
     eng.set_hamiltonian(N, w.ham.coeff, w.ham.xy, w.ham.yz)
     info = eng.info()
     G, NT = info["n_groups"], info["n_terms"]

@@ -364,9 +364,14 @@ typedef struct {
     int waves_per_block; /* waves sharing a workgroup (and its Bloom filter):
                             1 or 4 (0 = automatic)                              */
     int partition;       /* forward / adjoint LoopOverTerms by partitions of U's
-                            membership table, one per XCD, so that each XCD's
-                            L2 holds its eighth of the table: 0 = automatic
-                            (tables of 8 MB and more), 1 = on, -1 = off       */
+                            membership table, each XCD probing its own
+                            partitions one after another, so that its L2 holds
+                            the partition it works on: 0 = automatic (tables
+                            of 8 MB and more), 1 = on (any size), -1 = off.
+                            Takes effect at the next eloc_set_hamiltonian /
+                            eloc_set_samples.                                 */
+    int partition_count; /* partitions: 8, 16 or 32; 0 = automatic (enough to
+                            bring one partition to 1 MB)                      */
 } eloc_tuning;
 int eloc_set_tuning(eloc_ctx ctx, const eloc_tuning* tuning);
 int eloc_get_tuning(eloc_ctx ctx, eloc_tuning* tuning);

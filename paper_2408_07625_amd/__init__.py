@@ -37,7 +37,8 @@ class C64(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
-                ("bloom", ctypes.c_int), ("waves_per_block", ctypes.c_int), ("partition", ctypes.c_int)]
+                ("bloom", ctypes.c_int), ("waves_per_block", ctypes.c_int), ("partition", ctypes.c_int),
+                ("partition_count", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -229,18 +230,21 @@ class Engine:
         return {"n_unique": n.value, "table_slots": slots.value, "table_stash": stash.value}
 
     def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = False,
-                   waves_per_block: int = 0, partition: int = 0):
+                   waves_per_block: int = 0, partition: int = 0, partition_count: int = 0):
         """partition: 0 automatic (U tables of 8 MB and more), 1 on, -1 off;
-        set before set_samples (U's rows are classed when its table is built)."""
+        partition_count: 8, 16 or 32 (0 automatic).  Set before
+        set_hamiltonian and set_samples (the group records are bucketed at
+        ingest, U's rows classed when its table is built)."""
         t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave), 1 if bloom else 0, int(waves_per_block),
-                   int(partition))
+                   int(partition), int(partition_count))
         self._call(self.lib.eloc_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         self._call(self.lib.eloc_get_tuning(self.handle, ctypes.byref(t)))
         return {"chunks": t.chunks, "sig_filter": bool(t.sig_filter), "rows_per_wave": t.rows_per_wave,
-                "bloom": bool(t.bloom), "waves_per_block": t.waves_per_block, "partition": t.partition}
+                "bloom": bool(t.bloom), "waves_per_block": t.waves_per_block, "partition": t.partition,
+                "partition_count": t.partition_count}
 
     STAGES = ("samples", "amplitudes", "pairs", "finish", "energy", "adjoint_pairs", "adjoint_finish")
 

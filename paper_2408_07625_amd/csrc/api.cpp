@@ -22,8 +22,10 @@ using namespace eloc;
 namespace {
 
 // U tables of at least this many bytes are probed by partition (an XCD's L2
-// is 4 MB)
+// is 4 MB), in as many partitions (8, 16 or 32) as it takes to bring one
+// partition down to kPartTargetBytes
 constexpr uint64_t kPartAutoBytes = uint64_t(8) << 20;
+constexpr uint64_t kPartTargetBytes = uint64_t(1) << 20;
 
 }  // namespace
 
@@ -38,7 +40,7 @@ struct eloc_ctx_s {
     HamDev H;
     DevBuf groups, terms, terms_f, term_src, term_ny, ghash, gkeys, gslots, gstash;
     DevBuf groups_b, ghash_b;   // group records bucketed by the partition of their hash
-    DevBuf gbucket;             // their bucket starts [kParts + 1] (int32)
+    DevBuf gbucket;             // their bucket starts [kMaxParts + 1] (int32)
     DevBuf pe_cnt, pe_grp;   // pair_elements: term counts and groups of the pairs
     DevBuf xyt_keys, xyt_gid, xyt_nodes, xyt_nkeys;
 
@@ -51,6 +53,7 @@ struct eloc_ctx_s {
     bool ut_valid = false;
     DevBuf part_perm, part_class, part_tile;   // U's rows by partition class
     bool part_ok = false;                      // U's table is partitioned and its rows classed
+    int part_bits = 0;                         // 2^part_bits partitions of U's table (0: none)
     DevBuf s_key, s_val, s_key2, s_val2;   // sort scratch
 
     DevBuf a, b, af, bf, v, vf, shift, amp_scratch;
@@ -82,6 +85,7 @@ struct eloc_ctx_s {
     int tune_bloom = 0;      // the LDS Bloom filter is slower on MI355X (occupancy); opt-in
     int tune_waves = 0;      // 0 = automatic
     int tune_part = 0;       // 0 automatic, 1 on where possible, -1 off
+    int tune_part_count = 0; // partitions: 0 automatic, 8, 16 or 32
     uint64_t kslots_n = 0;   // slots of U's membership table
     uint64_t salt_state = 0x5EED2408ull;
 
@@ -165,19 +169,36 @@ Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1, bool allow_pa
     const int64_t per = per_steps * 64;
     P.chunks = static_cast<int>((span + per - 1) / per);
     P.per_chunk = static_cast<int>(per);
-    // LoopOverTerms over a large U table: one XCD per table partition (the
-    // partition of a candidate is linear in the row's and the group's hashes),
-    // so that each XCD's L2 holds its eighth of the table
-    if (allow_part && variant == ELOC_TERMS && c->part_ok && c->tune_part >= 0 && P.rows_per_block == kPartRows &&
-        P.waves_per_block == 1 && n_rows < 0 &&
-        (c->tune_part > 0 || slot_bytes(table_kind(c->H.W, c->H.narrow)) * c->kslots_n >= kPartAutoBytes)) {
-        const int64_t items = ((M + kPartRows - 1) / kPartRows + kParts) * kParts;
+    // LoopOverTerms over a large U table: each XCD probes its own table
+    // partitions, one at a time (the partition of a candidate is linear in
+    // the row's and the group's hashes), so that the XCD's L2 holds the
+    // partition it works on
+    if (allow_part && variant == ELOC_TERMS && c->part_ok && P.rows_per_block == kPartRows &&
+        P.waves_per_block == 1 && n_rows < 0) {
+        const int64_t nparts = int64_t(1) << c->part_bits;
+        const int64_t items = ((M + kPartRows - 1) / kPartRows + nparts) * nparts;
         P.part = true;
         P.part_sub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (target + items - 1) / items)));
-        P.chunks = kParts * P.part_sub;
+        P.chunks = static_cast<int>(nparts) * P.part_sub;
         P.bloom_words = 0;
     }
     return P;
+}
+
+// Partition bits of U's table of `bytes` bytes and `cap` slots (0: not
+// partitioned): automatic for tables of kPartAutoBytes or more, enough
+// partitions (8 to 32) to bring one down to kPartTargetBytes; a tuned count
+// otherwise.  Never more than the table's slots allow.
+int part_bits_for(const eloc_ctx c, uint64_t bytes, uint64_t cap) {
+    if (c->tune_part < 0 || (c->tune_part == 0 && bytes < kPartAutoBytes)) return 0;
+    int bits = 3;
+    if (c->tune_part_count >= 8) {
+        while ((1 << bits) < c->tune_part_count) ++bits;
+    } else {
+        while (bits < kMaxPartBits && (bytes >> bits) > kPartTargetBytes) ++bits;
+    }
+    while (bits >= 3 && cap < part_min_slots(c->H.part.shift, bits)) --bits;
+    return bits >= 3 ? bits : 0;
 }
 
 // One cuckoo table of U with a fresh salt, its verification (duplicates,
@@ -186,7 +207,7 @@ int build_sample_table(eloc_ctx c) {
     const int64_t n = c->S.n;
     const int tk = table_kind(c->H.W, c->H.narrow);
     c->S.table = make_table(c->kslots.p, c->kstash.as<Stash>(), c->kslots_n, n, splitmix64(c->salt_state),
-                            c->H.part.shift);
+                            c->H.part.shift, c->part_bits);
     ELOC_HIP(c, hipMemsetAsync(c->kslots.p, 0, slot_bytes(tk) * c->kslots_n, c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->kstash.p, 0, sizeof(Stash), c->stream));
     ELOC_HIP(c, hipMemsetAsync(c->sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
@@ -317,26 +338,27 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
         std::vector<uint64_t> hb;
         gb.reserve(static_cast<size_t>(G));
         hb.reserve(static_cast<size_t>(G));
-        int bucket[kParts + 1] = {};
+        int bucket[kMaxParts + 1] = {};
         // a context tuned to partition every table partitions small ones by
         // runs of 32 slots, else by blocks of 64K slots
         c->H.part.shift = c->tune_part > 0 ? kPartShiftSmall : kPartShiftLarge;
-        for (int b = 0; b < kParts; ++b) {
+        for (int b = 0; b < kMaxParts; ++b) {
             bucket[b] = static_cast<int>(gb.size());
             for (int64_t g = 0; g < G; ++g)
-                if (hash_part(ghash[static_cast<size_t>(g)], c->H.part.shift) == b) {
+                if (rev_bits(hash_part(ghash[static_cast<size_t>(g)], c->H.part.shift, kMaxPartBits), kMaxPartBits) ==
+                    b) {
                     gb.push_back(groups[static_cast<size_t>(g)]);
                     hb.push_back(ghash[static_cast<size_t>(g)]);
                 }
         }
-        bucket[kParts] = static_cast<int>(G);
+        bucket[kMaxParts] = static_cast<int>(G);
         ELOC_HIP(c, c->groups_b.ensure(sizeof(GroupRec<W>) * G));
         ELOC_HIP(c, c->ghash_b.ensure(sizeof(uint64_t) * G));
         ELOC_HIP(c, hipMemcpy(c->groups_b.p, gb.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
         ELOC_HIP(c, hipMemcpy(c->ghash_b.p, hb.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
-        for (int b = 0; b <= kParts; ++b) c->H.part.bucket[b] = bucket[b];
-        ELOC_HIP(c, c->gbucket.ensure(sizeof(int32_t) * (kParts + 1)));
-        ELOC_HIP(c, hipMemcpy(c->gbucket.p, bucket, sizeof(int32_t) * (kParts + 1), hipMemcpyHostToDevice));
+        for (int b = 0; b <= kMaxParts; ++b) c->H.part.bucket[b] = bucket[b];
+        ELOC_HIP(c, c->gbucket.ensure(sizeof(int32_t) * (kMaxParts + 1)));
+        ELOC_HIP(c, hipMemcpy(c->gbucket.p, bucket, sizeof(int32_t) * (kMaxParts + 1), hipMemcpyHostToDevice));
     }
     ELOC_HIP(c, c->gstash.ensure(sizeof(Stash)));
     Table T;
@@ -362,7 +384,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.part.groups = c->groups_b.p;
     H.part.shift = c->H.part.shift;
     H.part.ghash = c->ghash_b.as<uint64_t>();
-    for (int b = 0; b <= kParts; ++b) H.part.bucket[b] = c->H.part.bucket[b];
+    for (int b = 0; b <= kMaxParts; ++b) H.part.bucket[b] = c->H.part.bucket[b];
     H.part.bucket_dev = c->gbucket.as<int32_t>();
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
     H.xyt.gid = c->xyt_gid.as<int32_t>();
@@ -681,14 +703,15 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
     S.prep_err = c->err_prep.as<uint32_t>();
     c->S = S;
     c->kslots_n = cap;
+    c->part_bits = part_bits_for(c, slot_bytes(tk) * cap, cap);
     // table insert, verification and prefilter parameters, all on the
     // device: errors (duplicates, bits >= N, a table that did not settle)
     // stay latched in the preparation error word until a synchronising call
     const int rc = build_sample_table(c);
     if (rc) return rc;
     c->part_ok = false;
-    if (cap >= part_min_slots(c->H.part.shift) &&
-        (c->tune_part > 0 || (c->tune_part == 0 && slot_bytes(tk) * cap >= kPartAutoBytes))) {
+    c->S.part.bits = 0;
+    if (c->part_bits > 0) {
         const int64_t tiles = radix_tiles(n_unique);
         ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * n_unique));
         ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * n_unique));
@@ -698,9 +721,10 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
         ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
         ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
         ELOC_HIP(c, c->part_perm.ensure(sizeof(int32_t) * n_unique));
-        ELOC_HIP(c, c->part_class.ensure(sizeof(int64_t) * (kParts + 1)));
-        ELOC_HIP(c, c->part_tile.ensure(sizeof(int64_t) * (kParts + 1)));
-        ELOC_HIP(c, launch_row_classes(c->khash.as<uint64_t>(), n_unique, c->H.part.shift, c->s_key.as<uint64_t>(),
+        ELOC_HIP(c, c->part_class.ensure(sizeof(int64_t) * (kMaxParts + 1)));
+        ELOC_HIP(c, c->part_tile.ensure(sizeof(int64_t) * (kMaxParts + 1)));
+        ELOC_HIP(c, launch_row_classes(c->khash.as<uint64_t>(), n_unique, c->H.part.shift, c->part_bits,
+                                       c->s_key.as<uint64_t>(),
                                        c->s_val.as<uint32_t>(),
                                        c->s_key2.as<uint64_t>(), c->s_val2.as<uint32_t>(), c->hist.as<uint32_t>(),
                                        c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(),
@@ -709,6 +733,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
         c->S.part.row_perm = c->part_perm.as<int32_t>();
         c->S.part.class_off = c->part_class.as<int64_t>();
         c->S.part.tile_off = c->part_tile.as<int64_t>();
+        c->S.part.bits = c->part_bits;
         c->part_ok = true;
     }
     prof_end(c, pm);
@@ -767,6 +792,11 @@ int eloc_local_energy_noalloc(eloc_ctx c, int variant, int precision, const eloc
     const int64_t M = c->S.n;
     const bool fp32 = precision == ELOC_FP32C;
     Plan P = variant == ELOC_STORED ? Plan{} : make_plan(c, variant, -1, true);
+    // the partitioned LoopOverTerms keeps one partial sum per partition and
+    // row: where that outgrows the workspace, the plain loop serves
+    const size_t acc_bytes = fp32 ? sizeof(float4) : sizeof(double2);
+    if (P.part && acc_bytes * static_cast<size_t>(P.chunks) * M > kNoAllocBytes / 2)
+        P = make_plan(c, variant, -1, false);
     P.bloom_words = 0;   // U's Bloom filter is built on first use (it allocates)
     // workspace layout, every part 256-byte aligned
     size_t off = 0;
@@ -779,7 +809,7 @@ int eloc_local_energy_noalloc(eloc_ctx c, int variant, int precision, const eloc
     const size_t o_af = take(fp32 ? sizeof(float4) * M : 0), o_bf = take(fp32 ? sizeof(float4) * M : 0);
     const size_t o_shift = take(sizeof(double) * 2);
     const size_t o_amp = take(sizeof(double) * amp_scratch_len());
-    const size_t o_part = take((fp32 ? sizeof(float4) : sizeof(double2)) * static_cast<size_t>(P.chunks) * M);
+    const size_t o_part = take(acc_bytes * static_cast<size_t>(P.chunks) * M);
     const size_t o_en = take(sizeof(double) * energy_scratch_len());
     if (off > kNoAllocBytes)
         return fail(c, ELOC_ECAPACITY,
@@ -1288,8 +1318,10 @@ int eloc_store_pairs(eloc_ctx c, int variant, size_t budget_bytes, int64_t* n_pa
 }
 
 int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
+    const int tp = t ? t->partition : 0, tc = t ? t->partition_count : 0;
     if (!c || !t || t->chunks < 0 || (t->rows_per_wave != 0 && t->rows_per_wave != 4 && t->rows_per_wave != 8) ||
-        (t->waves_per_block != 0 && t->waves_per_block != 1 && t->waves_per_block != 4))
+        (t->waves_per_block != 0 && t->waves_per_block != 1 && t->waves_per_block != 4) || tp < -1 || tp > 1 ||
+        !(tc == 0 || tc == 8 || tc == 16 || tc == 32))
         return c ? fail(c, ELOC_EINVAL, "bad tuning") : ELOC_EINVAL;
     c->tune_chunks = t->chunks;
     c->tune_sig = t->sig_filter;
@@ -1297,6 +1329,7 @@ int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
     c->tune_bloom = t->bloom;
     c->tune_waves = t->waves_per_block;
     c->tune_part = t->partition;
+    c->tune_part_count = t->partition_count;
     return ELOC_OK;
 }
 
@@ -1308,6 +1341,7 @@ int eloc_get_tuning(eloc_ctx c, eloc_tuning* t) {
     t->bloom = c->tune_bloom;
     t->waves_per_block = c->tune_waves;
     t->partition = c->tune_part;
+    t->partition_count = c->tune_part_count;
     return ELOC_OK;
 }
 

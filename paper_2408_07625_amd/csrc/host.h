@@ -55,8 +55,9 @@ inline uint64_t pow2_at_least(uint64_t v) {
     return c;
 }
 
+// part_bits = 0: not partitioned.
 inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n, uint64_t salt,
-                        int part_shift = kPartShiftLarge) {
+                        int part_shift = kPartShiftLarge, int part_bits = 0) {
     Table T;
     T.stash = stash;
     T.slots = slots;
@@ -65,7 +66,9 @@ inline Table make_table(void* slots, Stash* stash, uint64_t capacity, int64_t n,
     T.imask = (T.ibits >= 32) ? 0xFFFFFFFFu : ((1u << T.ibits) - 1u);
     T.fpshift = 32 + T.ibits;
     T.capbits = bits_for(capacity - 1);
-    T.pmask = capacity >= part_min_slots(part_shift) ? (7u << part_shift) : 0u;
+    T.pmask = part_bits > 0 && capacity >= part_min_slots(part_shift, part_bits)
+                  ? (((1u << part_bits) - 1u) << part_shift)
+                  : 0u;
     T.salt = salt;
     return T;
 }

@@ -116,28 +116,39 @@ struct Table {
     uint32_t imask;     // (1 << ibits) - 1
     int fpshift;        // two-word keys: fingerprint = hs >> fpshift
     int capbits;        // log2(capacity)
-    uint32_t pmask;     // partition bits of a slot index (7 << shift, or 0: not partitioned)
+    uint32_t pmask;     // partition bits of a slot index ((2^bits - 1) << shift, or 0: not partitioned)
     uint64_t salt;
     const Stash* stash;
 };
 
-// A table of at least 8 << shift slots is split into eight partitions by
-// bits shift .. shift + 2 of the slot index; both slots of a key lie in the
-// partition of the key's salted hash.  The hash is GF(2)-linear, so the
-// partition of a candidate x ^ XY is part(x) ^ part(XY) ^ part(salt): a
-// kernel can give each XCD the candidates of one partition, whose slots then
-// stay in that XCD's L2.  Large tables use shift 16 (partitions made of
-// blocks of 64K slots, so that every L2 channel and memory channel serves
-// every partition: with low shift bits a partition would fall on a few
-// channels only); shift 5 (runs of 32 slots) lets small tables exercise the
-// same path.
+// A table of at least 2^(shift + bits) slots is split into 2^bits
+// partitions (bits = 3..5) by bits shift .. shift + bits - 1 of the slot
+// index; both slots of a key lie in the partition of the key's salted hash.
+// The hash is GF(2)-linear, so the partition of a candidate x ^ XY is part(x)
+// ^ part(XY) ^ part(salt): a kernel can give each XCD the candidates of its
+// partitions, one after another, whose slots then stay in that XCD's L2.
+// Large tables use shift 16 (partitions made of blocks of 64K slots, so that
+// every L2 channel and memory channel serves every partition: with low shift
+// bits a partition would fall on a few channels only); shift 5 (runs of 32
+// slots) lets small tables exercise the same path.
 constexpr int kPartShiftLarge = 16;
 constexpr int kPartShiftSmall = 5;
-constexpr int kParts = 8;
-__host__ __device__ __forceinline__ int hash_part(uint64_t h, int shift) {
-    return static_cast<int>((h >> shift) & 7u);
+constexpr int kXcds = 8;
+constexpr int kMaxPartBits = 5;
+constexpr int kMaxParts = 1 << kMaxPartBits;
+__host__ __device__ __forceinline__ int hash_part(uint64_t h, int shift, int bits) {
+    return static_cast<int>((h >> shift) & ((1u << bits) - 1u));
 }
-__host__ __device__ __forceinline__ uint64_t part_min_slots(int shift) { return uint64_t(8) << shift; }
+__host__ __device__ __forceinline__ uint64_t part_min_slots(int shift, int bits) { return uint64_t(1) << (shift + bits); }
+// Group buckets are ordered by the bit-reversed kMaxPartBits-bit partition
+// field, so that for any bits the groups of one partition value p form one
+// range: the buckets [r << (kMaxPartBits - bits), (r + 1) << (kMaxPartBits -
+// bits)) with r = p reversed in bits bits.
+__host__ __device__ __forceinline__ int rev_bits(int v, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+    return r;
+}
 
 template <int TK>
 __host__ __device__ __forceinline__ typename TabT<TK>::hash salted(const Table& T, uint64_t h) {
@@ -359,14 +370,15 @@ struct HamDev {
     const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
     Table group_table{};               // XY -> group id
     XYTrieDev xyt{};
-    // the group records again, bucketed by hash_part of their hash (stable),
-    // for LoopOverTerms over a partitioned U table
+    // the group records again, bucketed by the reversed kMaxPartBits-bit
+    // partition field of their hash (stable), for LoopOverTerms over a
+    // partitioned U table
     struct {
         const void* groups = nullptr;
         const uint64_t* ghash = nullptr;
-        int bucket[kParts + 1] = {};           // bucket starts (host copy)
-        const int32_t* bucket_dev = nullptr;   // the same [kParts + 1] on the device
-        int shift = kPartShiftLarge;   // partition bits of U's tables for this Hamiltonian
+        int bucket[kMaxParts + 1] = {};        // bucket starts (host copy)
+        const int32_t* bucket_dev = nullptr;   // the same [kMaxParts + 1] on the device
+        int shift = kPartShiftLarge;   // first partition bit of U's tables for this Hamiltonian
     } part;
 };
 
@@ -401,9 +413,10 @@ struct SampleDev {
     // rows ordered by hash_part of their (unsalted) hash, for the partitioned
     // LoopOverTerms: built with U's table when the table is partitioned
     struct {
+        int bits = 0;                         // 2^bits partitions (0: not partitioned)
         const int32_t* row_perm = nullptr;
-        const int64_t* class_off = nullptr;   // [kParts + 1] (device)
-        const int64_t* tile_off = nullptr;    // [kParts + 1] (device), tiles of kRows rows
+        const int64_t* class_off = nullptr;   // [2^bits + 1] (device)
+        const int64_t* tile_off = nullptr;    // [2^bits + 1] (device), tiles of kRows rows
     } part;
 };
 
@@ -429,8 +442,8 @@ struct Plan {
     int waves_per_block = 1;   // waves of a TERMS / BATCH workgroup
     const uint32_t* bloom = nullptr;   // U's Bloom filter (LoopOverTerms), staged in LDS
     uint32_t bloom_words = 0;          // its size in words, a power of two (0: not used)
-    bool part = false;                 // LoopOverTerms by U's table partitions (one per XCD)
-    int part_sub = 1;                  // chunks of a group bucket (chunks = 8 part_sub)
+    bool part = false;                 // LoopOverTerms by U's table partitions (2^bits, kXcds at a time)
+    int part_sub = 1;                  // chunks of a group bucket (chunks = 2^bits part_sub)
 };
 
 // Error bits latched in a device word, read by eloc_check / synchronising calls.
@@ -615,8 +628,10 @@ int rows_per_block(int variant, int requested);
 constexpr int kPartRows = 8;   // rows of a tile of the partitioned LoopOverTerms
 // Rows ordered by the partition class of their hash (stable), the first
 // position and the first tile (kPartRows rows, classes padded to whole tiles)
-// of every class: perm[n], class_off[9], tile_off[9]; scratch as for the sort.
-hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, uint64_t* key, uint32_t* val, uint64_t* key2,
+// of every class: perm[n], class_off[2^bits + 1], tile_off[2^bits + 1];
+// scratch as for the sort.
+hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, int bits, uint64_t* key, uint32_t* val,
+                              uint64_t* key2,
                               uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan, int32_t* perm,
                               int64_t* class_off, int64_t* tile_off, hipStream_t st);
 // Node pairs (U node, XY node) the LoopOverTrie walk visits over all rows

@@ -684,24 +684,24 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 }
 
 // Partition classes of U's rows (hash_part of the unsalted hash).
-__global__ void k_class_keys(const uint64_t* __restrict__ hash, int64_t n, int shift, uint64_t* __restrict__ key,
-                             uint32_t* __restrict__ val) {
+__global__ void k_class_keys(const uint64_t* __restrict__ hash, int64_t n, int shift, int bits,
+                             uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    key[i] = static_cast<uint64_t>(hash_part(hash[i], shift));
+    key[i] = static_cast<uint64_t>(hash_part(hash[i], shift, bits));
     val[i] = static_cast<uint32_t>(i);
 }
 
 // class_off[c] = first sorted position with class >= c; tile_off[c] = tiles
 // of kPartRows rows before class c; perm = the sorted row indices.
 __global__ void k_class_bounds(const uint64_t* __restrict__ key, const uint32_t* __restrict__ val, int64_t n,
-                               int32_t* __restrict__ perm, int64_t* __restrict__ class_off,
+                               int nparts, int32_t* __restrict__ perm, int64_t* __restrict__ class_off,
                                int64_t* __restrict__ tile_off) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) perm[i] = static_cast<int32_t>(val[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int64_t off[kParts + 1];
-        for (int c = 0; c <= kParts; ++c) {
+        int64_t off[kMaxParts + 1];
+        for (int c = 0; c <= nparts; ++c) {
             int64_t lo = 0, hi = n;   // first position with key >= c
             while (lo < hi) {
                 const int64_t mid = (lo + hi) / 2;
@@ -713,10 +713,10 @@ __global__ void k_class_bounds(const uint64_t* __restrict__ key, const uint32_t*
             off[c] = lo;
         }
         int64_t t = 0;
-        for (int c = 0; c <= kParts; ++c) {
+        for (int c = 0; c <= nparts; ++c) {
             class_off[c] = off[c];
             tile_off[c] = t;
-            if (c < kParts) t += (off[c + 1] - off[c] + kPartRows - 1) / kPartRows;
+            if (c < nparts) t += (off[c + 1] - off[c] + kPartRows - 1) / kPartRows;
         }
     }
 }
@@ -783,15 +783,16 @@ hipError_t launch_sample_params(const uint64_t* sig, const unsigned long long* r
     return hipGetLastError();
 }
 
-hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, uint64_t* key, uint32_t* val, uint64_t* key2,
-                              uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan, int32_t* perm,
-                              int64_t* class_off, int64_t* tile_off, hipStream_t st) {
-    hipLaunchKernelGGL(k_class_keys, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, shift, key, val);
+hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, int bits, uint64_t* key, uint32_t* val,
+                              uint64_t* key2, uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan,
+                              int32_t* perm, int64_t* class_off, int64_t* tile_off, hipStream_t st) {
+    if (bits < 1 || bits > kMaxPartBits) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_class_keys, dim3(blocks_for(n)), dim3(kBlock), 0, st, hash, n, shift, bits, key, val);
     int alt = 0;
     const hipError_t e = launch_radix_sort_pairs(key, val, key2, val2, n, 8, hist, hist_off, scan, &alt, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_class_bounds, dim3(blocks_for(n)), dim3(kBlock), 0, st, alt ? key2 : key, alt ? val2 : val, n,
-                       perm, class_off, tile_off);
+                       1 << bits, perm, class_off, tile_off);
     return hipGetLastError();
 }
 

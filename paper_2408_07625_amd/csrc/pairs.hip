@@ -79,16 +79,19 @@ struct PairArgs {
     const uint64_t* xy_nkeys;
     int xy_chunk;
     // LoopOverTerms split by U's table partitions (large tables): workgroup w
-    // serves XCD w % 8, which probes only partition w % 8; a tile's rows share
-    // one partition class, so its groups are the bucket class ^ part ^ salt's
+    // serves XCD w % 8, which probes only partitions w % 8 + 8 p, pass p
+    // after pass; a tile's rows share one partition class, so its groups are
+    // the bucket class ^ part ^ salt's
     bool part;
+    int part_bits;              // 2^part_bits partitions
     int part_salt;              // partition bits of U's table salt
+    int64_t part_tiles;         // workgroup rows of one pass (>= the tiles of all classes)
     const int32_t* row_perm;    // rows ordered by class (stable)
-    const int64_t* class_off;   // [9] first position of each class in row_perm
-    const int64_t* tile_off;    // [9] first tile of each class
+    const int64_t* class_off;   // [2^bits + 1] first position of each class in row_perm
+    const int64_t* tile_off;    // [2^bits + 1] first tile of each class
     const void* groups_b;       // group records bucketed by the partition of their hash
     const uint64_t* ghash_b;
-    // bucket starts in groups_b [kParts + 1], in device memory: a kernel
+    // bucket starts in groups_b [kMaxParts + 1], in device memory: a kernel
     // argument array indexed at run time would move the whole argument
     // block to the stack
     const int32_t* gbucket;
@@ -133,7 +136,9 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.xy_nkeys = H.xyt.nkeys;
     a.xy_chunk = H.xyt.chunk;
     a.part = P.part;
-    a.part_salt = hash_part(S.table.salt, H.part.shift);
+    a.part_bits = P.part ? S.part.bits : 0;
+    a.part_salt = hash_part(S.table.salt, H.part.shift, a.part_bits);
+    a.part_tiles = P.part ? (a.rows + kPartRows - 1) / kPartRows + (int64_t(1) << a.part_bits) : 0;
     a.row_perm = S.part.row_perm;
     a.class_off = S.part.class_off;
     a.tile_off = S.part.tile_off;
@@ -772,22 +777,26 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     static_assert(!PART || (VARIANT != 1 && WPB == 1 && NR == kPartRows), "partitioned LoopOverTerms tiles");
     constexpr bool part = PART;
     if constexpr (part) {
-        // 1-D grid: workgroup w serves XCD w % 8 (partition k), then
-        // (tile, sub-chunk); the tile's class c gives the group bucket
-        // c ^ k ^ part(salt), whose candidates all fall in partition k
-        const int k = static_cast<int>(blockIdx.x % kParts);
-        const int64_t item = blockIdx.x / kParts;
+        // 1-D grid: workgroup w serves XCD w % 8; the rest of w gives the
+        // pass p (partition k = w % 8 + 8 p), then (tile, sub-chunk); the
+        // tile's class c gives the group bucket c ^ k ^ part(salt), whose
+        // candidates all fall in partition k
+        const int nparts = 1 << A.part_bits;
+        const int64_t rest = blockIdx.x / kXcds;
+        const int64_t per_pass = A.part_tiles * A.part_sub;
+        const int k = static_cast<int>(blockIdx.x % kXcds) + kXcds * static_cast<int>(rest / per_pass);
+        const int64_t item = rest % per_pass;
         const int sub = static_cast<int>(item % A.part_sub);
         const int64_t t = item / A.part_sub;
-        if (t >= A.tile_off[kParts]) return;
-        int c = 0;
-#pragma unroll
-        for (int q = 1; q < kParts; ++q) c += t >= A.tile_off[q] ? 1 : 0;
+        if (k >= nparts || t >= A.tile_off[nparts]) return;
+        int c = 0;   // the tile's class: the last class starting at or before t
+        for (int q = 1; q < nparts; ++q) c += t >= A.tile_off[q] ? 1 : 0;
         const int64_t p0 = A.class_off[c] + (t - A.tile_off[c]) * NR;
         const int n = static_cast<int>(min(static_cast<int64_t>(NR), A.class_off[c + 1] - p0));
         load_rows_perm<W, NR>(A, R, rowkey, p0, n, A.row_perm);
-        const int b = c ^ k ^ A.part_salt;
-        const int bs = A.gbucket[b], be = A.gbucket[b + 1];
+        const int r = rev_bits(c ^ k ^ A.part_salt, A.part_bits);
+        const int bs = A.gbucket[r << (kMaxPartBits - A.part_bits)];
+        const int be = A.gbucket[(r + 1) << (kMaxPartBits - A.part_bits)];
         const int per = (be - bs + A.part_sub - 1) / A.part_sub;
         g0 = min(be, bs + sub * per);
         g1 = min(be, g0 + per);
@@ -1495,10 +1504,10 @@ hipError_t launch_pairs_t(const PairArgs& A, const Plan& P, const void* vec, voi
         if (VARIANT == 1) grid = dim3(div_up(A.rows, kRows) * static_cast<unsigned>(P.chunks));
         if constexpr (VARIANT != 1) {
             if (A.part) {
-                // partitioned LoopOverTerms: at most rows / 8 + 8 tiles
-                // (classes padded to whole tiles), eight partitions,
-                // part_sub chunks each
-                grid = dim3((div_up(A.rows, kRows) + kParts) * kParts * static_cast<unsigned>(A.part_sub));
+                // partitioned LoopOverTerms: at most rows / 8 + 2^bits tiles
+                // (classes padded to whole tiles) per partition, part_sub
+                // chunks each; 8 partitions per pass
+                grid = dim3(static_cast<unsigned>(A.part_tiles * A.part_sub * (int64_t(1) << A.part_bits)));
                 hipLaunchKernelGGL((k_pairs<W, VARIANT, PREC, ADJ, kRows, NW, 1, true>), grid, dim3(kWave), 0, st, A,
                                    vec, partial);
                 return hipGetLastError();

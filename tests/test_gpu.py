@@ -633,12 +633,15 @@ def test_backward_after_state_change_raises(eng, small_workload):
 
 
 # ----------------------------------------------------------------------------
+@pytest.mark.parametrize("count", [0, 16, 32])
 @pytest.mark.parametrize("wl", ["small", "medium", "odd_y"])
-def test_partitioned_terms(eng, wl, small_workload, medium_workload):
-    """LoopOverTerms by U's table partitions (one XCD per partition; on by
-    default only for tables of 8 MB and more, forced here): forward and
-    adjoint against the oracle in both precisions, bitwise reproducible, and
-    the pair list of the variant unchanged."""
+def test_partitioned_terms(eng, wl, count, small_workload, medium_workload):
+    """LoopOverTerms by U's table partitions (each XCD probing its own
+    partitions, one pass after another; on by default only for tables of 8 MB
+    and more, forced here, with the automatic count (8 for these tables), 16
+    and 32 partitions): forward and adjoint against the oracle in both
+    precisions, bitwise reproducible, and the pair list of the variant
+    unchanged."""
     if wl == "odd_y":
         rng = np.random.default_rng(21)
         ham = jw.random_pauli(11, 500, rng, max_flip=3)
@@ -649,7 +652,7 @@ def test_partitioned_terms(eng, wl, small_workload, medium_workload):
         ham, keys, lp = w.ham, w.keys, w.logpsi
     M = keys.shape[0]
     rows = (0, min(M, 1500))
-    eng.set_tuning(partition=1)
+    eng.set_tuning(partition=1, partition_count=count)
     try:
         load(eng, ham, keys)
         ref = oracle.local_energy(ham, keys, lp, rows=rows)
