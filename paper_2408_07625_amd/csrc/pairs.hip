@@ -191,6 +191,11 @@ __device__ __forceinline__ bool read_sample_params(PairArgs& A) {
     return true;
 }
 
+// A wave's row buffer in LDS: the NR rows' keys [NR][W], then their
+// unsalted hashes [NR].
+template <int W, int NR>
+constexpr int kRowBuf = NR * (W + 1);
+
 template <int W, int NR>
 __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey, int64_t tile) {
     R.row0 = tile * NR;
@@ -207,6 +212,7 @@ __device__ __forceinline__ void load_rows(const PairArgs& A, Rows<W, NR>& R, uin
         const int64_t row = min(R.row0 + lane_id() / W, A.rows - 1);
         rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
     }
+    if (lane_id() < NR) rowkey[NR * W + lane_id()] = A.khash[min(R.row0 + lane_id(), A.rows - 1)];
 }
 
 // Rows of a tile taken through a row order: positions [p0, p0 + n) of perm.
@@ -227,6 +233,7 @@ __device__ __forceinline__ void load_rows_perm(const PairArgs& A, Rows<W, NR>& R
         const int64_t row = perm[p0 + min(lane_id() / W, n - 1)];
         rowkey[lane_id()] = A.keys[row * W + lane_id() % W];
     }
+    if (lane_id() < NR) rowkey[NR * W + lane_id()] = A.khash[perm[p0 + min(lane_id(), n - 1)]];
 }
 
 // A group's term run as the hit queue carries it for narrow keys: first
@@ -245,10 +252,11 @@ __device__ __forceinline__ RunRef run_ref(const GroupRec<W>& gr) {
 // candidate must have U's single (even-qubit, total) popcount signature.
 // Rows past the end of U are clamped copies of the last row; their results
 // are discarded by the caller.
-// Compaction buffer entries of LoopOverTerms (exact tables): the salted
-// hash of a candidate that passed the prefilters and its (row, lane).
+// Compaction buffer entries: a candidate that passed the prefilters as row |
+// lane << 3 (LoopOverTerms, exact tables) or row | sample << 3
+// (LoopOverBatch).
 template <bool NW>
-using CEntry = std::conditional_t<NW, uint2, uint4>;
+using CEntry = uint32_t;
 
 template <int W, int SIG, int NR, bool NW, bool BL, class Sink>
 __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int g0, int g1,
@@ -261,6 +269,15 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
     const SlotReader<TK> slots(T);
     if (g0 >= g1) return;
     const int lane = lane_id();
+    const uint32_t lane8 = static_cast<uint32_t>(lane) << 3;
+    // the signature (even-qubit popcount << 8 | popcount) of U, and the mask
+    // of its compare (0: U has no single signature, everything passes)
+    // (bit 16 marks lanes past the end of the bucket and is always compared;
+    // the mask lives in a vector register: the compare's three-operand
+    // logic op can read only one scalar register)
+    const uint32_t sig_key = (static_cast<uint32_t>(A.sig_pa) << 8) | static_cast<uint32_t>(A.sig_n);
+    uint32_t sig_mask = A.sig_all ? 0x10000u : 0x1FFFFu;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(sig_mask) : "s"(sig_mask));
     // the step's group fields live in plain registers (mask words, term
     // run, hash)
     uint64_t gxy[W];
@@ -292,55 +309,62 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         }
         // the exact prefilters of candidate x ^ XY for row r: U's single
         // popcount signature (unless sig_all), U's radius around its majority
-        // key, U's Bloom filter (BL); returns the salted hash
-        auto filter = [&](int r, uint64_t (&xpr)[W], bool& ok) -> HT {
-            ok = valid;
-            int pa = 0, n = 0, d = 0;
-            if constexpr (NW) {
-                const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
-                xpr[0] = x32;
-                if (SIG) {
+        // key, U's Bloom filter (BL).  All of them fold into one unsigned
+        // compare, d + 256 t <= rad_max, with d the distance from the
+        // reference key and t the masked mismatch of (even popcount << 8 |
+        // popcount | 2^16 on lanes past the bucket) against U's signature,
+        // so that the lane mask stays the compare's own.
+        const uint32_t vpen = valid ? 0u : 0x10000u;
+        auto filter = [&](int r) -> bool {
+            bool ok = valid;
+            if constexpr (SIG) {
+                uint32_t pa = 0, n = vpen, d = 0;
+                if constexpr (NW) {
+                    const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
                     pa = __popc(x32 & static_cast<uint32_t>(kEven));
-                    n = __popc(x32);
+                    n += __popc(x32);
                     d = __popc(x32 ^ static_cast<uint32_t>(A.rad_ref[0]));
-                }
-            } else {
+                } else {
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    xpr[w] = R.x[r][w] ^ gxy[w];
-                    if (SIG) {
-                        pa += popc64(xpr[w] & kEven);
-                        n += popc64(xpr[w]);
-                        d += popc64(xpr[w] ^ A.rad_ref[w]);
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t xp = R.x[r][w] ^ gxy[w];
+                        pa += popc64(xp & kEven);
+                        n += popc64(xp);
+                        d += popc64(xp ^ A.rad_ref[w]);
                     }
                 }
+                const uint32_t t = ((pa << 8) | n) ^ sig_key;
+                ok = (d + ((t & sig_mask) << 8)) <= static_cast<uint32_t>(A.rad_max);
             }
-            if (SIG) ok = ok & (A.sig_all | ((pa == A.sig_pa) & (n == A.sig_n))) & (d <= A.rad_max);
             if constexpr (BL) {
                 const uint32_t hf = static_cast<uint32_t>(R.hx[r] >> 32) ^ static_cast<uint32_t>(gh >> 32);
                 const uint32_t bits = bloom_bits(hf);
                 ok = ok & ((lfilt[bloom_word(hf, A.bloom_mask)] & bits) == bits);
             }
-            return static_cast<HT>((R.hx[r] ^ T.salt) ^ gh);
+            return ok;
         };
+        auto salted = [&](int r) -> HT { return static_cast<HT>((R.hx[r] ^ T.salt) ^ gh); };
         if constexpr (TK != kTabVerify) {
             // exact tables: the candidates that pass are compacted into dense
             // lanes (LDS, ballot + mbcnt), and only those are probed, 64 at a
             // time; a probe's group fields come from its source lane
             auto probe_round = [&](int n) {
                 const bool on = lane < n;
-                const CEntry<NW> e = cb[on ? lane : 0];
-                HT h;
-                uint32_t meta;
-                if constexpr (NW) {
-                    h = e.x;
-                    meta = e.y;
-                } else {
-                    h = (static_cast<uint64_t>(e.y) << 32) | e.x;
-                    meta = e.z;
-                }
+                const uint32_t meta = cb[on ? lane : 0];
                 const int r = static_cast<int>(meta & 7u);
                 const int src = static_cast<int>(meta >> 3);
+                // the candidate's salted hash: the row's (LDS) ^ the group's
+                // (source lane)
+                const uint64_t hrow = rowkey[NR * W + r] ^ T.salt;
+                HT h;
+                if constexpr (NW) {
+                    h = static_cast<HT>(static_cast<uint32_t>(hrow) ^
+                                        static_cast<uint32_t>(__shfl(static_cast<int>(gh), src, kWave)));
+                } else {
+                    const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(gh), src, kWave));
+                    const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(gh >> 32), src, kWave));
+                    h = static_cast<HT>(hrow ^ ((static_cast<uint64_t>(hi) << 32) | lo));
+                }
                 const auto s1 = slots.load(slot1(T, h), on);
                 const auto s2 = slots.load(slot2(T, h), need_slot2<TK>(T, s1, h));
                 const int jj = table_settle<TK, W>(T, A.keys, s1, s2, h, nullptr, A.kstash, on);
@@ -353,19 +377,9 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             int cn = 0;   // entries in cb (wave-uniform)
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                uint64_t xpr[W];
-                bool ok;
-                const HT h = filter(r, xpr, ok);
-                const uint64_t m = __ballot(ok);
-                if (ok) {
-                    const uint32_t meta = static_cast<uint32_t>(r) | (static_cast<uint32_t>(lane) << 3);
-                    if constexpr (NW)
-                        cb[cn + lanes_below(m)] = make_uint2(static_cast<uint32_t>(h), meta);
-                    else
-                        cb[cn + lanes_below(m)] = make_uint4(static_cast<uint32_t>(h),
-                                                             static_cast<uint32_t>(static_cast<uint64_t>(h) >> 32),
-                                                             meta, 0u);
-                }
+                const bool ok = filter(r);
+                const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
+                if (ok) cb[cn + lanes_below(m)] = static_cast<uint32_t>(r) | lane8;
                 cn += __popcll(m);
                 if (cn >= kWave) {
                     wave_sync();
@@ -391,7 +405,10 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
             bool okr[NR];
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                hs[r] = filter(r, xp[r], okr[r]);
+                okr[r] = filter(r);
+#pragma unroll
+                for (int w = 0; w < W; ++w) xp[r][w] = R.x[r][w] ^ gxy[w];
+                hs[r] = salted(r);
                 v1[r] = slots.load(slot1(T, hs[r]), okr[r]);
             }
             // second slots only where the first leaves the lookup open
@@ -435,7 +452,7 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
     // entries [0, n) of cb: row | sample << 3 in the first word
     auto probe_round = [&](int n) {
         const bool on = lane < n;
-        const uint32_t meta = cb[on ? lane : 0].x;
+        const uint32_t meta = cb[on ? lane : 0];
         const int r = static_cast<int>(meta & 7u);
         const int j = static_cast<int>(meta >> 3);
         const int64_t row = min(R.row0 + r, A.rows - 1);
@@ -462,26 +479,29 @@ __device__ __forceinline__ void find_batch(const PairArgs& A, const Rows<W, NR>&
         uint64_t xj[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) xj[w] = A.keys[jj * W + w];
-        int pc[NR];
+        // popcount of x ^ x', plus 256 on lanes past the chunk: one compare
+        const uint32_t vpen = valid ? 0u : 256u;
+        uint32_t pc[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if constexpr (NW) {
-                pc[r] = __popc(static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]));
+                pc[r] = vpen + __popc(static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(xj[0]));
             } else {
-                pc[r] = 0;
+                pc[r] = vpen;
 #pragma unroll
                 for (int w = 0; w < W; ++w) pc[r] += popc64(R.x[r][w] ^ xj[w]);
             }
         }
+        const uint32_t jm = static_cast<uint32_t>(j) << 3;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const bool ok = valid & (pc[r] <= A.maxpop);
-            const uint64_t mk = __ballot(ok);
+            const bool ok = pc[r] <= static_cast<uint32_t>(A.maxpop);
+            const uint64_t mk = __builtin_amdgcn_ballot_w64(ok);
             if (ok) {
-                const uint32_t meta = static_cast<uint32_t>(r) | (static_cast<uint32_t>(j) << 3);
-                CEntry<NW> ce{};
-                ce.x = meta;
-                cb[cn + lanes_below(mk)] = ce;
+                const uint32_t at = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mk >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mk),
+                                                                                        static_cast<uint32_t>(cn)));
+                cb[at] = static_cast<uint32_t>(r) | jm;
             }
             cn += __popcll(mk);
             if (cn >= kWave) {
@@ -752,7 +772,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
     constexpr bool BL = WPB > 1;
-    __shared__ uint64_t rowkey_s[WPB][NR * W];
+    __shared__ uint64_t rowkey_s[WPB][kRowBuf<W, NR>];
     __shared__ QEntry<NW> q_s[WPB][2 * kWave];
     __shared__ CEntry<NW> cb_s[WPB][2 * kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
@@ -836,7 +856,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
 
 template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
-    __shared__ uint64_t rowkey[kRows * W];
+    __shared__ uint64_t rowkey[kRowBuf<W, kRows>];
     __shared__ CEntry<NW> cb[2 * kWave];
     Rows<W, kRows> R;
     if (!read_sample_params(A)) {   // no pairs while U is invalid
@@ -858,7 +878,7 @@ __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t
 template <int W, int VARIANT, bool NW>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
-    __shared__ uint64_t rowkey[kRows * W];
+    __shared__ uint64_t rowkey[kRowBuf<W, kRows>];
     __shared__ CEntry<NW> cb[2 * kWave];
     if (!read_sample_params(A)) return;
     Rows<W, kRows> R;
@@ -922,7 +942,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
                                                          void* __restrict__ partial_all) {
     using P = Prec<PREC>;
     using Acc = typename P::Acc;
-    __shared__ uint64_t rowkey[NR * W];
+    __shared__ uint64_t rowkey[kRowBuf<W, NR>];
     __shared__ QEntry<NW> q[2 * kWave];
     __shared__ CEntry<NW> cb[2 * kWave];
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
