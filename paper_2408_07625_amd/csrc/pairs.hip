@@ -907,26 +907,53 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 // problem's partial offset.  Every wave leaves the loop when the counter
 // passes the last item.
 // ---------------------------------------------------------------------------
+// Wave-uniform copies of values read from memory at a uniform address: the
+// first lane's, so that they live in scalar registers (the compiler cannot
+// tell that a descriptor read through a pointer is the same in every lane).
+__device__ __forceinline__ uint32_t rfl32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int32_t rfl32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+    return (static_cast<uint64_t>(rfl32(static_cast<uint32_t>(v >> 32))) << 32) | rfl32(static_cast<uint32_t>(v));
+}
+__device__ __forceinline__ int64_t rfl64(int64_t v) { return static_cast<int64_t>(rfl64(static_cast<uint64_t>(v))); }
+template <class T>
+__device__ __forceinline__ T* rflp(T* p) {
+    return reinterpret_cast<T*>(rfl64(reinterpret_cast<uint64_t>(p)));
+}
+__device__ __forceinline__ Table rfl_table(const Table& t) {
+    Table u;
+    u.slots = rflp(t.slots);
+    u.mask = rfl32(t.mask);
+    u.ibits = rfl32(t.ibits);
+    u.imask = rfl32(t.imask);
+    u.fpshift = rfl32(t.fpshift);
+    u.capbits = rfl32(t.capbits);
+    u.pmask = rfl32(t.pmask);
+    u.salt = rfl64(t.salt);
+    u.stash = rflp(t.stash);
+    return u;
+}
+
 // One work item of the batched kernel: the forward row kernel over a row
 // tile and chunk of problem D, with the problem's own tables, variant and
 // signature filter (NW: the problem's narrow format).  Returns the coupled
 // pairs of the tile's rows inside U.
 template <int W, int PREC, int NR, bool NW>
-__device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, NR>& R, const BatchProb& D, int chunk,
-                                              const void* vec_all, typename Prec<PREC>::Acc* acc,
+__device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, NR>& R, int variant, int64_t s0,
+                                              int chunk, const void* vec_all, typename Prec<PREC>::Acc* acc,
                                               QEntry<NW>* q, CEntry<NW>* cb, const uint64_t* rowkey) {
     using P = Prec<PREC>;
     AccSink<W, PREC, false, NR, NW> sink;
     sink.groups = static_cast<const GroupRec<W>*>(A.groups);
     sink.terms = static_cast<const typename P::template Term<W>*>(PREC == 0 ? A.terms : A.terms_f);
-    sink.vec = static_cast<const typename P::Vec*>(vec_all) + D.s0;
+    sink.vec = static_cast<const typename P::Vec*>(vec_all) + s0;
     sink.q = q;
     sink.acc = acc;
     sink.rowkey = rowkey;
     sink.nrows = R.n;
     // one LoopOverTerms body: without a usable prefilter the problem has
     // sig_all set and rad_max 128, which every candidate passes
-    if (D.variant == 1)
+    if (variant == 1)
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
     else
         find_terms<W, 1, NR, NW, false>(A, R, chunk * A.per_chunk, min(A.n_groups, (chunk + 1) * A.per_chunk),
@@ -966,45 +993,48 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         int pos = -1;
 #pragma unroll
         for (int c = 0; c < kSlices; ++c) pos += __popcll(__ballot(istart[c] <= t));
-        const int k = B.sched[pos];
+        // the problem's descriptor, every field wave-uniform
+        const int k = rfl32(B.sched[pos]);
         const BatchProb& D = B.probs[k];
+        const int64_t s0 = rfl64(D.s0), M = rfl64(D.M), item0 = rfl64(D.item0), pbase = rfl64(D.pbase);
+        const int chunks = rfl32(D.chunks), variant = rfl32(D.variant);
         PairArgs A;
-        A.groups = D.groups;
-        A.ghash = D.ghash;
-        A.terms = D.terms;
-        A.terms_f = D.terms_f;
-        A.gkeys = D.gkeys;
-        A.gtable = D.gtable;
-        A.n_groups = D.n_groups;
-        A.maxpop = D.maxpop;
-        A.keys = B.keys + D.s0 * W;
-        A.khash = B.khash + D.s0;
-        A.ktable = D.ktable;
-        A.M = D.M;
-        A.rows = D.M;
-        A.per_chunk = D.per_chunk;
-        const uint32_t smin = B.sigmin[k], smax = B.sigmax[k];
+        A.groups = rflp(D.groups);
+        A.ghash = rflp(D.ghash);
+        A.terms = rflp(D.terms);
+        A.terms_f = rflp(D.terms_f);
+        A.gkeys = rflp(D.gkeys);
+        A.gtable = rfl_table(D.gtable);
+        A.n_groups = rfl32(D.n_groups);
+        A.maxpop = rfl32(D.maxpop);
+        A.keys = B.keys + s0 * W;
+        A.khash = B.khash + s0;
+        A.ktable = rfl_table(D.ktable);
+        A.M = M;
+        A.rows = M;
+        A.per_chunk = rfl32(D.per_chunk);
+        const uint32_t smin = rfl32(B.sigmin[k]), smax = rfl32(B.sigmax[k]);
         A.sig_pa = static_cast<int>(smin >> 8);
         A.sig_n = static_cast<int>(smin & 255u);
         A.sig_all = smin != smax;
-        A.rad_ref[0] = B.rad[3 * k];
-        A.rad_ref[1] = B.rad[3 * k + 1];
-        const int rmax = static_cast<int>(B.rad[3 * k + 2]);
-        A.rad_max = 2 * rmax < D.n_qubits ? rmax : 128;
+        A.rad_ref[0] = rfl64(static_cast<uint64_t>(B.rad[3 * k]));
+        A.rad_ref[1] = rfl64(static_cast<uint64_t>(B.rad[3 * k + 1]));
+        const int rmax = static_cast<int>(rfl64(static_cast<uint64_t>(B.rad[3 * k + 2])));
+        A.rad_max = 2 * rmax < rfl32(D.n_qubits) ? rmax : 128;
         read_stash_counts(A);
-        const int64_t u = t - D.item0;
-        const int64_t tile = u / D.chunks;
-        const int chunk = static_cast<int>(u - tile * D.chunks);
+        const int64_t u = t - item0;
+        const int64_t tile = u / chunks;
+        const int chunk = static_cast<int>(u - tile * chunks);
         Rows<W, NR> R;
         load_rows<W, NR>(A, R, rowkey, tile);
         for (int i = lane; i < NR * kAccCols; i += kWave) acc[i] = Acc{};
         wave_sync();
-        const int64_t hits = batch_item<W, PREC, NR, NW>(A, R, D, chunk, vec_all, acc, q, cb, rowkey);
+        const int64_t hits = batch_item<W, PREC, NR, NW>(A, R, variant, s0, chunk, vec_all, acc, q, cb, rowkey);
         if (lane < R.n) {
             Acc s{};
             for (int l = 0; l < kAccCols; ++l) acc_plus(s, acc[lane * kAccCols + l]);
-            auto* part = static_cast<double2*>(partial_all) + D.pbase;
-            store_acc(part, static_cast<int64_t>(chunk) * D.M + R.row0 + lane, s);
+            auto* part = static_cast<double2*>(partial_all) + pbase;
+            store_acc(part, static_cast<int64_t>(chunk) * M + R.row0 + lane, s);
         }
         if (lane == 0) atomicAdd(B.pairs + k, static_cast<unsigned long long>(hits));
         wave_sync();
