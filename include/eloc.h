@@ -283,7 +283,7 @@ int eloc_sr_select(eloc_ctx ctx, int64_t n, const eloc_c64* logpsi_dev, int n_sr
  * 2 n_sr x 2 n_sr Gram matrix of the centred, weighted rows (no n_params^2
  * matrix is formed).  1 <= n_sr <= 256.  Asynchronous; a shifted matrix
  * that is not positive definite in FP64 is reported by eloc_check as
- * ERANGE.  Scratch: about 8 (2 n_params + 512 (2 n_sr + 16)^2) bytes. */
+ * ERANGE.  Scratch: about 8 (2 n_params + 520 (2 n_sr + 16)^2) bytes. */
 int eloc_sr_solve(eloc_ctx ctx, int n_sr, int64_t n_params, const double* o_re_dev, const double* o_im_dev,
                   const eloc_c64* logpsi_set_dev, const double* grad_dev, double lambda, double* d_dev);
 

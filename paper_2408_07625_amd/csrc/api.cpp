@@ -72,6 +72,7 @@ struct eloc_ctx_s {
     DevBuf sr_w, sr_mean, sr_part, sr_T, sr_L, sr_y;
     // sampler: two prefix beams, the candidates of a level, the allowed count
     DevBuf ar_keys[2], ar_l[2], ar_T[2], ar_cl, ar_cT, ar_ck, ar_ci, ar_ck2, ar_ci2, ar_cnt;
+    DevBuf ar_hist, ar_sel, ar_keep, ar_off;   // top-K selection scratch
 
     // stored pair list (CSR by row of (column, H_ij)), valid until the
     // samples or the Hamiltonian change
@@ -591,7 +592,8 @@ void eloc_destroy(eloc_ctx c) {
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
                       &c->groups_b, &c->ghash_b, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
                       &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
-                      &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt};
+                      &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt,
+                      &c->ar_hist, &c->ar_sel, &c->ar_keep, &c->ar_off};
     for (DevBuf* b : bufs) b->release();
     for (auto& m : c->marks) {
         c->ev_pool.push_back(m.a);
@@ -1042,7 +1044,7 @@ int eloc_sr_solve(eloc_ctx c, int n_sr, int64_t n_params, const double* o_re_dev
     const int64_t n = 2 * n_sr;
     ELOC_HIP(c, c->sr_w.ensure(sizeof(double) * 2 * n_sr));
     ELOC_HIP(c, c->sr_mean.ensure(sizeof(double) * 2 * n_params));
-    ELOC_HIP(c, c->sr_part.ensure(sizeof(double) * sr_partial_blocks(n_params) * R16 * R16));
+    ELOC_HIP(c, c->sr_part.ensure(sizeof(double) * sr_partial_len(n_params, static_cast<int>(R16), R)));
     ELOC_HIP(c, c->sr_T.ensure(sizeof(double) * R * R));
     ELOC_HIP(c, c->sr_L.ensure(sizeof(double) * n * n));
     ELOC_HIP(c, c->sr_y.ensure(sizeof(double) * n));
@@ -1083,7 +1085,11 @@ int eloc_sample(eloc_ctx c, const eloc_ar_model* m, int64_t k, uint64_t seed, ui
     const int64_t tiles = radix_tiles(maxc);
     ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
     ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
-    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+    ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * std::max(scan_scratch_len(256 * tiles), scan_scratch_len(maxc))));
+    ELOC_HIP(c, c->ar_hist.ensure(sizeof(uint32_t) * 4096));
+    ELOC_HIP(c, c->ar_sel.ensure(sizeof(int64_t) * 4));
+    ELOC_HIP(c, c->ar_keep.ensure(sizeof(int32_t) * maxc));
+    ELOC_HIP(c, c->ar_off.ensure(sizeof(int64_t) * (maxc + 1)));
     ELOC_HIP(c, launch_ar_root(c->ar_keys[0].as<uint64_t>(), W, c->ar_l[0].as<double>(), c->ar_T[0].as<double>(),
                                c->stream));
     int cur = 0;
@@ -1102,12 +1108,34 @@ int eloc_sample(eloc_ctx c, const eloc_ar_model* m, int64_t k, uint64_t seed, ui
         ELOC_HIP(c, hipStreamSynchronize(c->stream));
         const int64_t Bn = std::min<int64_t>(k, static_cast<int64_t>(allowed));
         if (Bn == 0) return ELOC_OK;   // no allowed state
-        int alt = 0;
-        ELOC_HIP(c, launch_radix_sort_pairs(c->ar_ck.as<uint64_t>(), c->ar_ci.as<uint32_t>(), c->ar_ck2.as<uint64_t>(),
-                                            c->ar_ci2.as<uint32_t>(), n, 64, c->hist.as<uint32_t>(),
-                                            c->hist_off.as<int64_t>(), c->hist_scratch.as<int64_t>(), &alt, c->stream));
+        // the first Bn candidates in (key, index) order: large levels sort
+        // only the candidates a two-digit selection keeps, small ones all
+        uint32_t* sorted = nullptr;
+        if (n >= (int64_t(1) << 16) && n > 4 * Bn) {
+            ELOC_HIP(c, launch_ar_select(c->ar_ck.as<uint64_t>(), n, Bn, c->ar_hist.as<uint32_t>(),
+                                         c->ar_sel.as<int64_t>(), c->ar_keep.as<int32_t>(), c->ar_off.as<int64_t>(),
+                                         c->hist_scratch.as<int64_t>(), c->ar_ck2.as<uint64_t>(),
+                                         c->ar_ci2.as<uint32_t>(), c->stream));
+            int64_t m = 0;
+            ELOC_HIP(c, hipMemcpyAsync(&m, c->ar_off.as<int64_t>() + n, sizeof(m), hipMemcpyDeviceToHost, c->stream));
+            ELOC_HIP(c, hipStreamSynchronize(c->stream));
+            if (m < Bn || m > n) return fail(c, ELOC_EHIP, "top-K selection kept " + std::to_string(m) + " candidates");
+            int alt = 0;
+            ELOC_HIP(c, launch_radix_sort_pairs(c->ar_ck2.as<uint64_t>(), c->ar_ci2.as<uint32_t>(),
+                                                c->ar_ck.as<uint64_t>(), c->ar_ci.as<uint32_t>(), m, 64,
+                                                c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(),
+                                                c->hist_scratch.as<int64_t>(), &alt, c->stream));
+            sorted = alt ? c->ar_ci.as<uint32_t>() : c->ar_ci2.as<uint32_t>();
+        } else {
+            int alt = 0;
+            ELOC_HIP(c, launch_radix_sort_pairs(c->ar_ck.as<uint64_t>(), c->ar_ci.as<uint32_t>(),
+                                                c->ar_ck2.as<uint64_t>(), c->ar_ci2.as<uint32_t>(), n, 64,
+                                                c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(),
+                                                c->hist_scratch.as<int64_t>(), &alt, c->stream));
+            sorted = alt ? c->ar_ci2.as<uint32_t>() : c->ar_ci.as<uint32_t>();
+        }
         const int nxt = cur ^ 1;
-        ELOC_HIP(c, launch_ar_gather(c->ar_keys[cur].as<uint64_t>(), alt ? c->ar_ci2.as<uint32_t>() : c->ar_ci.as<uint32_t>(),
+        ELOC_HIP(c, launch_ar_gather(c->ar_keys[cur].as<uint64_t>(), sorted,
                                      Bn, O, W, level * D, c->ar_cl.as<double>(), c->ar_cT.as<double>(),
                                      c->ar_keys[nxt].as<uint64_t>(), c->ar_l[nxt].as<double>(),
                                      c->ar_T[nxt].as<double>(), c->stream));

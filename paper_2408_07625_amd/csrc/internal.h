@@ -664,12 +664,14 @@ hipError_t launch_unique_scatter(int W, const uint64_t* sorted, int64_t n, const
 hipError_t launch_sr_select(const double2* logpsi, int64_t n, int nsr, uint64_t* key, uint32_t* val, uint64_t* key2,
                             uint32_t* val2, uint32_t* hist, int64_t* hist_off, int64_t* scan, int32_t* out,
                             hipStream_t st);
-// Scratch: w[2 nsr], mean[2 np], partial[sr_partial_blocks(np)][R16][R16]
+// Scratch: w[2 nsr], mean[2 np], partial[sr_partial_len(np, R16, R)] (per-block
+// Gram partials [sr_partial_blocks(np)][R16][R16], then the reduction passes)
 // (R16 = 2 nsr + 1 rounded up to 16), T[R][R], L[(2 nsr)^2], y[2 nsr].
 hipError_t launch_sr_solve(int nsr, int64_t np, const double* ore, const double* oim, const double2* logpsi,
                            const double* F, double lambda, double* w, double* mean, double* partial, double* T,
                            double* L, double* y, double* d, uint32_t* err, hipStream_t st);
 int64_t sr_partial_blocks(int64_t np);
+int64_t sr_partial_len(int64_t np, int R16, int R);   // doubles of `partial`
 
 // Autoregressive sampling without replacement: the ansatz of per-qudit
 // perceptrons (hidden width 64) and one level of the Gumbel top-K search.
@@ -692,6 +694,15 @@ hipError_t launch_ar_level(const ArModelDev& M, int level, int64_t B, uint64_t s
                            uint32_t* cand_idx, unsigned long long* n_allowed, hipStream_t st);
 hipError_t launch_ar_gather(const uint64_t* keys, const uint32_t* sorted_idx, int64_t n, int O, int W, int q0,
                             const double* cand_l, const double* cand_T, uint64_t* out_keys, double* out_l, double* out_T,
+                            hipStream_t st);
+// The candidates that can be among the first `need` (1 <= need <= n) in
+// (key, index) order: every candidate whose 24-bit key prefix is at most the
+// need-th's, in index order, into okey / oidx (their count in off[n]).
+// Scratch: hist[4096] (digit totals), sel[4], keep[n], off[n + 1],
+// scan as for launch_scan_i32.
+int64_t ar_select_blocks(int64_t n);
+hipError_t launch_ar_select(const uint64_t* key, int64_t n, int64_t need, uint32_t* hist, int64_t* sel,
+                            int32_t* keep, int64_t* off, int64_t* scan, uint64_t* okey, uint32_t* oidx,
                             hipStream_t st);
 
 // Fixed workspace of the allocation-free forward pass (one per device).

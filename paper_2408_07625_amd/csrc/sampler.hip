@@ -16,8 +16,14 @@
 //                its Gumbel perturbation, the siblings' maximum Z and the
 //                conditioned value Ltil; a sort key (descending Ltil, masked
 //                outcomes last) and the candidate index b O_k + c.
-//   sort         the B O_k candidates by key (stable radix sort on 64 bits, so
-//                equal values keep the (prefix, outcome) order)
+//   select       the first min(K, allowed) candidates in (key, index) order:
+//                for large levels, two 12-bit digit histograms of the keys
+//                (k_sel_hist, k_sel_pick) find the 24-bit key prefix that
+//                holds the K-th candidate, the candidates at or below it are
+//                compacted in index order (k_sel_flags, scan, k_sel_scatter)
+//                and only those are sorted; small levels sort all candidates.
+//                The sort is a stable radix sort on 64 bits, so equal values
+//                keep the (prefix, outcome) order either way.
 //   k_ar_gather  the first min(K, allowed) candidates become the next level's
 //                prefixes (key with the outcome's bits set, l, Ltil).
 #include "device.h"
@@ -182,13 +188,14 @@ __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const ui
         const double a = 2.0 * (z - mean);
         bool ok = live;
         if (A.n_up >= 0 && live) {
+            // electrons of the prefix: even qubits spin up, odd spin down
+            // (word boundaries are even, so a bit's parity is its qubit's)
             int up = 0, dn = 0;
-            for (int q = 0; q < A.q0; ++q) {
-                const int bit = key_bit(key, q);
-                if (q & 1)
-                    dn += bit;
-                else
-                    up += bit;
+            for (int w = 0; w < A.W && 64 * w < A.q0; ++w) {
+                const int nb = A.q0 - 64 * w;
+                const uint64_t v = key[w] & (nb >= 64 ? ~0ull : ((1ull << nb) - 1ull));
+                up += __popcll(v & kEven);
+                dn += __popcll(v & kOdd);
             }
             for (int t = 0; t < A.Dk; ++t)
                 if ((lane >> t) & 1) {
@@ -251,9 +258,116 @@ __global__ void k_ar_root(uint64_t* keys, int W, double* l, double* T) {
     }
 }
 
+// Top-K selection.  Histogram of the 12-bit digit (key >> shift) & 4095
+// over the candidates whose key agrees above the digit with the digit chosen
+// by the previous pass (prev[0]; all candidates for the top digit, shift
+// 52): per block in LDS, then its non-zero counts added to total[4096]
+// (integer counts: the order of the additions does not matter).
+constexpr int kSelBuckets = 4096;
+constexpr int kSelPerBlock = 16384;
+
+__global__ __launch_bounds__(256) void k_sel_hist(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                  const int64_t* __restrict__ prev, uint32_t* __restrict__ total) {
+    __shared__ uint32_t h[kSelBuckets];
+    for (int t = threadIdx.x; t < kSelBuckets; t += 256) h[t] = 0u;
+    __syncthreads();
+    const bool filt = shift + 12 < 64;
+    const uint64_t prefix = filt ? static_cast<uint64_t>(prev[0]) : 0ull;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kSelPerBlock;
+    const int64_t i1 = min(n, i0 + kSelPerBlock);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const uint64_t k = key[i];
+        if (!filt || (k >> (shift + 12)) == prefix) atomicAdd(&h[(k >> shift) & (kSelBuckets - 1)], 1u);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSelBuckets; t += 256)
+        if (h[t]) atomicAdd(total + t, h[t]);
+}
+
+__global__ void k_sel_clear(uint32_t* __restrict__ total) {
+    for (int t = threadIdx.x; t < kSelBuckets; t += blockDim.x) total[t] = 0u;
+}
+
+// The digit in which the running count over ascending digits reaches `need`
+// = need_total - prev[1] (the candidates before the previous pass's digit):
+// sel[0] = the digit, sel[1] = the candidates before it over both passes.
+// One workgroup, four digits per thread; need >= 1 and at most the total.
+// The totals are cleared for the next pass as they are read.
+__global__ __launch_bounds__(1024) void k_sel_pick(uint32_t* __restrict__ total, int64_t need_total,
+                                                   const int64_t* __restrict__ prev, int64_t* __restrict__ sel) {
+    __shared__ int64_t part[1024];
+    const int t = static_cast<int>(threadIdx.x);
+    int64_t c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c[q] = total[4 * t + q];
+        total[4 * t + q] = 0u;
+    }
+    part[t] = c[0] + c[1] + c[2] + c[3];
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const int64_t base = prev ? prev[1] : 0;
+    const int64_t need = need_total - base;
+    const int64_t before = t ? part[t - 1] : 0;
+    if (before < need && need <= part[t]) {
+        int64_t run = before;
+        int q = 0;
+        for (; q < 3; ++q) {
+            if (run + c[q] >= need) break;
+            run += c[q];
+        }
+        sel[0] = 4 * t + q;
+        sel[1] = base + run;
+    }
+}
+
+// keep[i] = 1 for the candidates whose 24-bit key prefix is at most the
+// selected one (sel1: top digit, sel2: next digit).
+__global__ void k_sel_flags(const uint64_t* __restrict__ key, int64_t n, const int64_t* __restrict__ sel1,
+                            const int64_t* __restrict__ sel2, int32_t* __restrict__ keep) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t thr = (static_cast<uint64_t>(sel1[0]) << 12) | static_cast<uint64_t>(sel2[0]);
+    keep[i] = (key[i] >> 40) <= thr ? 1 : 0;
+}
+
+// The kept candidates, in index order, with their candidate index.
+__global__ void k_sel_scatter(const uint64_t* __restrict__ key, int64_t n, const int32_t* __restrict__ keep,
+                              const int64_t* __restrict__ off, uint64_t* __restrict__ okey,
+                              uint32_t* __restrict__ oidx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    okey[off[i]] = key[i];
+    oidx[off[i]] = static_cast<uint32_t>(i);
+}
+
 inline unsigned blocks256(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
 
 }  // namespace
+
+int64_t ar_select_blocks(int64_t n) { return (n + kSelPerBlock - 1) / kSelPerBlock; }
+
+hipError_t launch_ar_select(const uint64_t* key, int64_t n, int64_t need, uint32_t* hist, int64_t* sel,
+                            int32_t* keep, int64_t* off, int64_t* scan, uint64_t* okey, uint32_t* oidx,
+                            hipStream_t st) {
+    const int nb = static_cast<int>(ar_select_blocks(n));
+    uint32_t* total = hist;
+    hipLaunchKernelGGL(k_sel_clear, dim3(1), dim3(1024), 0, st, total);
+    hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, st, key, n, 52, static_cast<const int64_t*>(nullptr), total);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, st, total, need, static_cast<const int64_t*>(nullptr), sel);
+    hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, st, key, n, 40, sel, total);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, st, total, need, sel, sel + 2);
+    hipLaunchKernelGGL(k_sel_flags, dim3(blocks256(n)), dim3(256), 0, st, key, n, sel, sel + 2, keep);
+    const hipError_t e = launch_scan_i32(keep, n, off, scan, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sel_scatter, dim3(blocks256(n)), dim3(256), 0, st, key, n, keep, off, okey, oidx);
+    return hipGetLastError();
+}
 
 hipError_t launch_ar_root(uint64_t* keys, int W, double* l, double* T, hipStream_t st) {
     hipLaunchKernelGGL(k_ar_root, dim3(1), dim3(64), 0, st, keys, W, l, T);

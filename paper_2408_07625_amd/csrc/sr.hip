@@ -179,12 +179,16 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_sr_gram(SrArgs A, int64_t col
     }
 }
 
-// T[r][c] (r <= c by tiles) = sum over blocks of the partials, fixed order;
-// mirrored into the lower triangle.
+// T[r][c] (r <= c by tiles) = sum over blocks of the partials in a fixed
+// order, mirrored into the lower triangle: pass 1 (blockIdx.y = g) adds the
+// partials of blocks g, g + kSrRed, ... into tmp[g], pass 2 adds tmp[0..kSrRed).
+constexpr int kSrRed = 8;
+
 __global__ __launch_bounds__(256) void k_sr_reduce(const double* __restrict__ partial, int nblocks, int R16, int R,
-                                                   double* __restrict__ T) {
+                                                   double* __restrict__ tmp) {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= static_cast<int64_t>(R) * R) return;
+    const int64_t RR = static_cast<int64_t>(R) * R;
+    if (e >= RR) return;
     const int r = static_cast<int>(e / R), c = static_cast<int>(e % R);
     // the upper tile holding (min, max) carries both orders inside a
     // diagonal tile; off the diagonal tiles only the tile with row <= column
@@ -194,7 +198,17 @@ __global__ __launch_bounds__(256) void k_sr_reduce(const double* __restrict__ pa
         cc = r;
     }
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[static_cast<int64_t>(b) * R16 * R16 + static_cast<int64_t>(rr) * R16 + cc];
+    for (int b = static_cast<int>(blockIdx.y); b < nblocks; b += kSrRed)
+        s += partial[static_cast<int64_t>(b) * R16 * R16 + static_cast<int64_t>(rr) * R16 + cc];
+    tmp[static_cast<int64_t>(blockIdx.y) * RR + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sr_reduce2(const double* __restrict__ tmp, int64_t RR, double* __restrict__ T) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= RR) return;
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < kSrRed; ++g) s += tmp[g * RR + e];
     T[e] = s;
 }
 
@@ -263,9 +277,19 @@ __global__ __launch_bounds__(kCholThreads) void k_sr_chol_reg(const double* __re
     static_assert(32 * P <= kCholMaxRows, "rows of the register grid");
     __shared__ double col[2][kCholMaxRows];
     __shared__ double zbuf[kCholMaxRows];
-    __shared__ double diag[kCholMaxRows];
+    // pivot terms of step k: sqrt(a_kk), 1 / a_kk, 1 / sqrt(a_kk), written by
+    // the owner of (k, k) as soon as a_kk is final (the step before)
+    __shared__ double prm[kCholMaxRows][3];
     const int tid = static_cast<int>(threadIdx.x);
     const int tr = tid >> 5, tc = tid & 31;
+    auto pivot = [&](int k, double akk) {
+        if (!(akk > 0.0)) atomicOr(err, static_cast<uint32_t>(kErrRange));
+        const double dk = fmax(akk, 1e-300);
+        const double piv = sqrt(dk);
+        prm[k][0] = piv;
+        prm[k][1] = 1.0 / dk;
+        prm[k][2] = 1.0 / piv;
+    };
     double a[P][P];   // [p][q], p >= q used
 #pragma unroll
     for (int p = 0; p < P; ++p)
@@ -274,42 +298,43 @@ __global__ __launch_bounds__(kCholThreads) void k_sr_chol_reg(const double* __re
             const int i = tr + 32 * p, j = tc + 32 * q;
             a[p][q] = (i <= n && j <= i) ? T[static_cast<int64_t>(i) * R + j] + (i == j && i < n ? lambda : 0.0) : 0.0;
         }
+    if (tid == 0) pivot(0, a[0][0]);
     for (int k = 0; k < n; ++k) {
         double* c = col[k & 1];
-        const int qk = k >> 5;
+        const int kb = k >> 5;   // row / column blocks below kb hold nothing left to do (uniform)
         if (tc == (k & 31)) {
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
                 for (int q = 0; q <= p; ++q) {
                     const int i = tr + 32 * p;
-                    if (q == qk && i >= k && i <= n) c[i] = a[p][q];
+                    if (q == kb && i >= k && i <= n) c[i] = a[p][q];
                 }
         }
         __syncthreads();
-        const double akk = c[k];
-        if (tid == 0 && !(akk > 0.0)) atomicOr(err, static_cast<uint32_t>(kErrRange));
-        const double dk = fmax(akk, 1e-300);
-        const double piv = sqrt(dk);
-        const double inv = 1.0 / dk;
-        if (tid == 0) diag[k] = piv;
-        double cr[P], cc[P];
+        const double piv = prm[k][0], inv = prm[k][1], rpiv = prm[k][2];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            cr[p] = c[tr + 32 * p];
-            cc[p] = c[tc + 32 * p];
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p)
+            if (p < kb) continue;
+            const double cr = c[tr + 32 * p];
 #pragma unroll
             for (int q = 0; q <= p; ++q) {
+                if (q < kb) continue;
                 const int i = tr + 32 * p, j = tc + 32 * q;
                 if (i > n || j > i) continue;
                 if (j == k)
-                    a[p][q] = i == k ? piv : a[p][q] / piv;
+                    a[p][q] = i == k ? piv : a[p][q] * rpiv;
                 else if (j > k)
-                    a[p][q] -= cr[p] * cc[q] * inv;
+                    a[p][q] -= cr * c[j] * inv;
             }
+        }
+        // the next pivot, from its owner's final a_{k+1,k+1}
+        const int k1 = k + 1;
+        if (k1 < n && tr == (k1 & 31) && tc == (k1 & 31)) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (p == (k1 >> 5)) pivot(k1, a[p][p]);
+        }
     }
     if (tr == (n & 31)) {
 #pragma unroll
@@ -322,7 +347,7 @@ __global__ __launch_bounds__(kCholThreads) void k_sr_chol_reg(const double* __re
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
-        const double yj = zbuf[j] / diag[j];
+        const double yj = zbuf[j] * prm[j][2];
         if (tr == (j & 31)) {
 #pragma unroll
             for (int p = 0; p < P; ++p)
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(kCholThreads) void k_sr_chol_reg(const double* __re
         }
         __syncthreads();
     }
-    for (int j = tid; j < n; j += kCholThreads) y[j] = zbuf[j] / diag[j];
+    for (int j = tid; j < n; j += kCholThreads) y[j] = zbuf[j] * prm[j][2];
 }
 
 template <int P>
@@ -373,6 +398,12 @@ inline unsigned blocks256(int64_t n) { return static_cast<unsigned>((n + 255) / 
 }  // namespace
 
 int64_t sr_partial_blocks(int64_t np) { return std::max<int64_t>(1, std::min<int64_t>(512, (np + 255) / 256)); }
+
+// Doubles of the Gram scratch: the per-block partials, then kSrRed R^2 of the
+// first reduction pass.
+int64_t sr_partial_len(int64_t np, int R16, int R) {
+    return sr_partial_blocks(np) * R16 * R16 + static_cast<int64_t>(kSrRed) * R * R;
+}
 
 // LDS slab of the Gram kernel under 64 KB: R16 rows of KS + 1 doubles
 size_t sr_gram_slab_cols(int R16) { return R16 <= 240 ? 32 : (R16 <= 480 ? 16 : 8); }
@@ -413,8 +444,10 @@ hipError_t launch_sr_solve(int nsr, int64_t np, const double* ore, const double*
     hipLaunchKernelGGL(k_sr_gram, dim3(static_cast<unsigned>(nb), static_cast<unsigned>(groups)), dim3(64 * kSrWaves),
                        lds, st, A, cols, partial);
     const int64_t RR = static_cast<int64_t>(A.R) * A.R;
-    hipLaunchKernelGGL(k_sr_reduce, dim3(blocks256(RR)), dim3(256), 0, st, partial, static_cast<int>(nb), A.R16, A.R,
-                       T);
+    double* tmp = partial + nb * A.R16 * A.R16;   // kSrRed R^2 doubles after the partials
+    hipLaunchKernelGGL(k_sr_reduce, dim3(blocks256(RR), kSrRed), dim3(256), 0, st, partial, static_cast<int>(nb), A.R16,
+                       A.R, tmp);
+    hipLaunchKernelGGL(k_sr_reduce2, dim3(blocks256(RR)), dim3(256), 0, st, tmp, RR, T);
     const int n = 2 * nsr;
     const int P = (n + 1 + 31) / 32;   // row blocks of the augmented matrix
     if (P > kCholMaxRows / 32)
