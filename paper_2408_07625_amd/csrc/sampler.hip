@@ -88,23 +88,31 @@ __device__ __forceinline__ double log1mexp(double a) {
 
 __device__ __forceinline__ int key_bit(const uint64_t* k, int q) { return static_cast<int>((k[q >> 6] >> (q & 63)) & 1ull); }
 
-// C[16 x 16 tile] += A[rows][k..] * Bw[cols][k..]^T over k in [0, kend), A
-// from a callback (row, k), B from global weights row-major [out][in].  Lane
-// l feeds A[l % 16][k + l / 16] and B[k + l / 16][l % 16]; register c of lane
-// l holds D[4 c + l / 16][l % 16] (measured layout of v_mfma_f64_16x16x4f64
-// on gfx950).
-template <class AF>
-__device__ __forceinline__ d4 tile_mma(AF a_of, const double* __restrict__ Bw, int ldb, int col0, int ncols, int kend,
-                                       int lane) {
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    const int col = col0 + (lane & 15);
+// acc[t] (the 16 x 16 output tile of columns 16 t ..) = A[rows][0..kend) *
+// B[cols][0..kend)^T for t < nt, A from a callback (row, k) read once per
+// k step for all tiles, B row-major [out][in] with row pitch ldb (global or
+// LDS).  Lane l feeds A[l % 16][k + l / 16] and B[k + l / 16][l % 16];
+// register c of lane l holds D[4 c + l / 16][l % 16] (measured layout of
+// v_mfma_f64_16x16x4f64 on gfx950).
+template <int NT, class AF>
+__device__ __forceinline__ void tiles_mma(d4 (&acc)[NT], AF a_of, const double* __restrict__ Bw, int ldb, int ncols,
+                                          int kend, int nt, int lane) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < kend; k += 4) {
         const int kk = k + (lane >> 4);
-        const double a = kk < kend ? a_of(lane & 15, kk) : 0.0;
-        const double b = (kk < kend && col < ncols) ? Bw[col * ldb + kk] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        const bool kin = kk < kend;
+        const double a = kin ? a_of(lane & 15, kk) : 0.0;
+        double b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int col = 16 * t + (lane & 15);
+            b[t] = (t < nt && kin && col < ncols) ? Bw[col * ldb + kk] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t], 0, 0, 0);
     }
-    return acc;
 }
 
 __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const uint64_t* __restrict__ keys,
@@ -114,6 +122,7 @@ __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const ui
                                                   unsigned long long* __restrict__ n_allowed) {
     __shared__ uint64_t kbuf[kArRows * kMaxWords];
     __shared__ double h[kArRows][kArH + 1];   // h1, then h2, then z (per wave's own rows)
+    __shared__ double wb[kArMaxOut][kArH + 1];   // W2, then W3 ([out][in], padded rows)
     const int wave = static_cast<int>(threadIdx.x) / 64;
     const int lane = lane_id();
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kArRows;
@@ -129,8 +138,7 @@ __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const ui
             return key_bit(kbuf + (r0 + r) * A.W, q) ? 1.0 : -1.0;
         };
         d4 acc[kArH / 16];
-#pragma unroll
-        for (int t = 0; t < kArH / 16; ++t) acc[t] = tile_mma(a_of, A.W1, A.N, 16 * t, kArH, A.q0, lane);
+        tiles_mma(acc, a_of, A.W1, A.N, kArH, A.q0, kArH / 16, lane);
 #pragma unroll
         for (int t = 0; t < kArH / 16; ++t)
 #pragma unroll
@@ -139,13 +147,13 @@ __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const ui
                 h[row][col] = tanh(acc[t][c] + A.b1[col]);
             }
     }
+    for (int e = threadIdx.x; e < kArH * kArH; e += 256) wb[e / kArH][e % kArH] = A.W2[e];
     __syncthreads();
     // layer 2 with the residual of layer 1
     {
         auto a_of = [&](int r, int k) -> double { return h[r0 + r][k]; };
         d4 acc[kArH / 16];
-#pragma unroll
-        for (int t = 0; t < kArH / 16; ++t) acc[t] = tile_mma(a_of, A.W2, kArH, 16 * t, kArH, kArH, lane);
+        tiles_mma(acc, a_of, &wb[0][0], kArH + 1, kArH, kArH, kArH / 16, lane);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kArH / 16; ++t)
@@ -155,15 +163,14 @@ __global__ __launch_bounds__(256) void k_ar_level(ArLevel A, int64_t B, const ui
                 h[row][col] = tanh(acc[t][c] + A.b2[col] + h[row][col]);
             }
     }
+    for (int e = threadIdx.x; e < A.O * kArH; e += 256) wb[e / kArH][e % kArH] = A.W3[e];
     __syncthreads();
     // output layer: z for the O outcomes
     {
         auto a_of = [&](int r, int k) -> double { return h[r0 + r][k]; };
         d4 acc[kArMaxOut / 16];
         const int nt = (A.O + 15) / 16;
-#pragma unroll
-        for (int t = 0; t < kArMaxOut / 16; ++t)
-            if (t < nt) acc[t] = tile_mma(a_of, A.W3, kArH, 16 * t, A.O, kArH, lane);
+        tiles_mma(acc, a_of, &wb[0][0], kArH + 1, A.O, kArH, nt, lane);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kArMaxOut / 16; ++t) {
