@@ -434,14 +434,18 @@ def bench_full(args):
     eng.set_samples(keys)
     L = torch.from_numpy(w.logpsi).cuda()
     steps = max(1, min(args.steps, args.other_steps))
-    t_find = _timed(lambda: eng.find_misses(), steps, 1)
+    # the library keeps the last list for unchanged samples: time the list
+    # from fresh samples (set_samples + find_misses) less set_samples alone
+    t_set = _timed(lambda: eng.set_samples(keys), steps, 1)
+    t_set_find = _timed(lambda: (eng.set_samples(keys), eng.find_misses()), steps, 1)
+    t_find = t_set_find - t_set
     V = eng.find_misses()
     Vn = V.cpu().numpy().view(np.uint64)
     rank = samples.excitation_rank(Vn, w.n_qubits, w.n_electrons)
     rng = np.random.default_rng(11)
     Lv = torch.from_numpy(samples.log_amplitudes(rank, rng)).cuda()
     res = {"workload": f"medium: {w.n_qubits} qubits, {w.n_unique} samples; {V.shape[0]} coupled states outside U",
-           "extra_states": int(V.shape[0]), "find_ms": t_find}
+           "extra_states": int(V.shape[0]), "find_ms": t_find, "set_samples_plus_find_ms": t_set_find}
     for prec in ("fp64", "fp32c"):
         res[prec] = {"ms": _timed(lambda: eng.local_energy_full(L, V, Lv, None, prec), steps, 1)}
     e_full, st_full = eng.local_energy_full(L, V, Lv, None, "fp64")

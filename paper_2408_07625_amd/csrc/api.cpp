@@ -65,7 +65,12 @@ struct eloc_ctx_s {
 
     // conventional local energy: the extra states' list (raw, sorted, run
     // flags and positions) and the set X = U followed by the extra states
-    DevBuf m_raw, m_sorted, m_perm, m_flags, m_pos;
+    DevBuf m_raw, m_sorted, m_perm, m_flags, m_pos, m_count;
+    // the last eloc_find_misses result (m_sorted / m_flags / m_pos), valid
+    // for these samples, this Hamiltonian and tolerance
+    bool miss_valid = false;
+    double miss_tol = 0.0;
+    int64_t miss_total = 0, miss_uniq = 0;
     DevBuf x_keys, x_hash, x_slots, x_stash, x_sig, x_bitcounts, x_rad, x_params, x_err, x_logpsi;
     DevBuf x_a, x_b, x_af, x_bf, x_shift;
     // stochastic reconfiguration scratch
@@ -586,7 +591,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->counts, &c->offsets, &c->scan_scratch, &c->pkey, &c->pval, &c->pkey2, &c->pval2,
                       &c->hist, &c->hist_off, &c->hist_scratch, &c->gstash, &c->kstash, &c->xyt_keys, &c->xyt_gid, &c->xyt_nodes, &c->xyt_nkeys,
                       &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->ut_nkeys, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2,
-                      &c->m_raw, &c->m_sorted, &c->m_perm, &c->m_flags, &c->m_pos, &c->x_keys, &c->x_hash, &c->x_slots,
+                      &c->m_raw, &c->m_sorted, &c->m_perm, &c->m_flags, &c->m_pos, &c->m_count, &c->x_keys, &c->x_hash, &c->x_slots,
                       &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
                       &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->st_rowptr, &c->st_col, &c->st_h,
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
@@ -632,6 +637,7 @@ int eloc_set_hamiltonian(eloc_ctx c, int n_qubits, int64_t n_terms, const double
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, ELOC_EHIP, "hipSetDevice");
     c->ham_set = false;
     c->samples_set = false;    // sample tables depend on the qubit count
+    c->miss_valid = false;
     c->st_valid = false;
     return W == 1 ? ingest<1>(c, n_qubits, n_terms, coeff, xy, yz) : ingest<2>(c, n_qubits, n_terms, coeff, xy, yz);
 }
@@ -666,6 +672,7 @@ int eloc_set_samples(eloc_ctx c, int64_t n_unique, const uint64_t* keys_dev) {
         return fail(c, ELOC_EINVAL, "n_unique must be in 1..2^24-1 with a key pointer");
     const int W = c->H.W;
     c->samples_set = false;
+    c->miss_valid = false;
     ELOC_HIP(c, c->keys.ensure(sizeof(uint64_t) * n_unique * W));
     ELOC_HIP(c, c->khash.ensure(sizeof(uint64_t) * n_unique));
     const uint64_t cap = table_capacity(n_unique);
@@ -849,28 +856,33 @@ int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_de
     if (capacity < 0) return fail(c, ELOC_EINVAL, "negative capacity");
     rc = samples_verdict(c, nullptr);
     if (rc) return rc;
-    const int64_t M = c->S.n;
     const int W = c->H.W;
-    const Plan P = make_plan(c, ELOC_TERMS);
-    const int64_t n = M * P.chunks;
-    ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
-    ELOC_HIP(c, c->offsets.ensure(sizeof(int64_t) * (n + 1)));
-    ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(n)));
-    ELOC_HIP(c, launch_misses(c->H, c->S, P.chunks, P.per_chunk, tol, false, c->counts.as<int32_t>(), nullptr,
-                              nullptr, c->stream));
-    ELOC_HIP(c, launch_scan_i32(c->counts.as<int32_t>(), n, c->offsets.as<int64_t>(), c->scan_scratch.as<int64_t>(),
-                                c->stream));
-    int64_t total = 0;
-    ELOC_HIP(c, hipMemcpyAsync(&total, c->offsets.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost,
-                               c->stream));
-    ELOC_HIP(c, hipStreamSynchronize(c->stream));
-    if (total >= (int64_t(1) << 31))
-        return fail(c, ELOC_ECAPACITY, "more than 2^31 coupled states outside U before deduplication");
-    int64_t uniq = 0;
-    if (total > 0) {
-        ELOC_HIP(c, c->m_raw.ensure(sizeof(uint64_t) * total * W));
-        ELOC_HIP(c, launch_misses(c->H, c->S, P.chunks, P.per_chunk, tol, true, nullptr, c->offsets.as<int64_t>(),
-                                  c->m_raw.as<uint64_t>(), c->stream));
+    int64_t total = c->miss_total, uniq = c->miss_uniq;
+    if (!(c->miss_valid && c->miss_tol == tol)) {
+        c->miss_valid = false;
+        const Plan P = make_plan(c, ELOC_TERMS);
+        // one append pass into the buffer as it stands; when the states
+        // outnumber it, a second pass into one of the counted size
+        ELOC_HIP(c, c->m_count.ensure(sizeof(unsigned long long)));
+        total = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int64_t room = static_cast<int64_t>(c->m_raw.p ? c->m_raw.bytes / (sizeof(uint64_t) * W) : 0);
+            ELOC_HIP(c, hipMemsetAsync(c->m_count.p, 0, sizeof(unsigned long long), c->stream));
+            ELOC_HIP(c, launch_misses(c->H, c->S, P.chunks, P.per_chunk, tol, c->m_count.as<unsigned long long>(),
+                                      room, c->m_raw.as<uint64_t>(), c->stream));
+            unsigned long long cnt = 0;
+            ELOC_HIP(c, hipMemcpyAsync(&cnt, c->m_count.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+            ELOC_HIP(c, hipStreamSynchronize(c->stream));
+            total = static_cast<int64_t>(cnt);
+            if (total >= (int64_t(1) << 31))
+                return fail(c, ELOC_ECAPACITY, "more than 2^31 coupled states outside U before deduplication");
+            if (total <= room) break;
+            if (pass == 1) return fail(c, ELOC_EHIP, "the coupled states outside U changed between two passes");
+            ELOC_HIP(c, c->m_raw.ensure(sizeof(uint64_t) * (total + total / 4) * W));
+        }
+        uniq = 0;
+    }
+    if (!c->miss_valid && total > 0) {
         // sort (W-word keys, most significant word last) and keep the first of every run
         const int64_t tiles = radix_tiles(total);
         ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * total));
@@ -897,6 +909,10 @@ int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_de
                                    c->stream));
         ELOC_HIP(c, hipStreamSynchronize(c->stream));
     }
+    c->miss_valid = true;
+    c->miss_tol = tol;
+    c->miss_total = total;
+    c->miss_uniq = uniq;
     *n_misses_host = uniq;
     if (uniq > capacity) return fail(c, ELOC_ECAPACITY, "capacity too small for the coupled states outside U");
     if (uniq > 0) {

@@ -647,11 +647,13 @@ hipError_t launch_batch_finish(const BatchDev& B, int precision, hipStream_t st)
 int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
 
 
-// The conventional local energy's extra states: count (fill = false: one
-// count per (row, chunk) into counts) or write (fill: at offsets, [n][W]
-// keys into out) the x' = x ^ XY_g outside U with |H_xx'| > tol sum |h|.
-hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol, bool fill,
-                         int32_t* counts, const int64_t* offsets, uint64_t* out, hipStream_t st);
+// The conventional local energy's extra states: the x' = x ^ XY_g outside U
+// with |H_xx'| > tol sum |h|, appended (in no particular order, duplicates
+// included) as [n][W] keys to out at positions taken from *counter (which
+// must start at 0 and ends at their number); those at positions >= capacity
+// are counted but not written.
+hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
+                         unsigned long long* counter, int64_t capacity, uint64_t* out, hipStream_t st);
 // flags[i] = 1 where sorted key i starts a run of equal keys
 hipError_t launch_unique_flags(int W, const uint64_t* sorted, int64_t n, int32_t* flags, hipStream_t st);
 // out[pos[i]] = sorted[i] where flags[i]

@@ -8,9 +8,11 @@
 // table; one that is absent has its matrix element evaluated over the
 // group's run, and is a miss when |H| > tol * sum |h_l| (strings that cancel
 // exactly, e.g. hopping strings between particle-number sectors, give no
-// state).  The count pass writes one count per (row, chunk); the fill pass
-// writes the misses at the scanned offsets, in the same order (ballot +
-// mbcnt per row and step).  The list is then sorted and made unique.
+// state).  The misses of a step (all rows) take one range of the output
+// from an atomic counter and are written there (ballot + mbcnt), those past
+// the capacity only counted; the caller reruns with a larger buffer when the
+// count exceeds it.  The list is then sorted and made unique, so the order
+// in which waves append does not show in the result.
 #include "device.h"
 
 #include <hip/hip_runtime.h>
@@ -62,18 +64,15 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
-template <int W, int TK, bool FILL>
-__global__ __launch_bounds__(64) void k_misses(MissArgs A, int32_t* __restrict__ counts,
-                                               const int64_t* __restrict__ offsets, uint64_t* __restrict__ out) {
+template <int W, int TK>
+__global__ __launch_bounds__(64) void k_misses(MissArgs A, unsigned long long* __restrict__ counter, int64_t capacity,
+                                               uint64_t* __restrict__ out) {
     const int lane = lane_id();
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kMissRows;
     const int chunk = static_cast<int>(blockIdx.y);
     if (row0 >= A.M) return;
     const int nr = static_cast<int>(min(static_cast<int64_t>(kMissRows), A.M - row0));
-    if (__builtin_amdgcn_readfirstlane(static_cast<int>(*A.prep_err)) != 0) {   // U invalid: no states
-        if (!FILL && lane < nr) counts[(row0 + lane) * A.chunks + chunk] = 0;
-        return;
-    }
+    if (__builtin_amdgcn_readfirstlane(static_cast<int>(*A.prep_err)) != 0) return;   // U invalid: no states
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(A.groups);
     const TermRec<W>* __restrict__ terms = static_cast<const TermRec<W>*>(A.terms);
     uint64_t x[kMissRows][W];
@@ -85,13 +84,6 @@ __global__ __launch_bounds__(64) void k_misses(MissArgs A, int32_t* __restrict__
         for (int w = 0; w < W; ++w) x[r][w] = A.keys[row * W + w];
         hx[r] = A.khash[row];
     }
-    int64_t pos[kMissRows];
-    int cnt[kMissRows];
-#pragma unroll
-    for (int r = 0; r < kMissRows; ++r) {
-        cnt[r] = 0;
-        pos[r] = (FILL && r < nr) ? offsets[(row0 + r) * A.chunks + chunk] : 0;
-    }
     const int nstash = __builtin_amdgcn_readfirstlane(static_cast<int>(A.ktable.stash->count));
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
@@ -100,35 +92,43 @@ __global__ __launch_bounds__(64) void k_misses(MissArgs A, int32_t* __restrict__
         const bool valid = g < g1;
         const GroupRec<W> gr = groups[min(g, g1 - 1)];
         const uint64_t gh = A.ghash[min(g, g1 - 1)];
+        uint64_t m[kMissRows];
+        bool miss[kMissRows];
+        int total = 0;
 #pragma unroll
         for (int r = 0; r < kMissRows; ++r) {
             uint64_t xp[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) xp[w] = x[r][w] ^ gr.xy[w];
-            bool miss = false;
+            miss[r] = false;
             if (valid && r < nr) {
                 const auto hs = salted<TK>(A.ktable, hx[r] ^ gh);
                 const int j = table_settle<TK, W>(A.ktable, A.keys, load_slot<TK>(A.ktable, slot1(A.ktable, hs)),
                                                   load_slot<TK>(A.ktable, slot2(A.ktable, hs)), hs, xp, nstash);
-                if (j < 0) miss = nonzero_element<W>(terms, gr, xp, A.tol);
+                if (j < 0) miss[r] = nonzero_element<W>(terms, gr, xp, A.tol);
             }
-            const uint64_t m = __ballot(miss);
-            if constexpr (FILL) {
-                if (miss) {
-                    const int64_t at = pos[r] + lanes_below(m);
-#pragma unroll
-                    for (int w = 0; w < W; ++w) out[at * W + w] = xp[w];
-                }
-                pos[r] += __popcll(m);
-            } else {
-                cnt[r] += __popcll(m);
-            }
+            m[r] = __ballot(miss[r]);
+            total += __popcll(m[r]);
         }
-    }
-    if constexpr (!FILL) {
+        if (total == 0) continue;   // wave-uniform
+        unsigned long long first = 0ull;
+        if (lane == 0) first = atomicAdd(counter, static_cast<unsigned long long>(total));
+        const int64_t at0 = static_cast<int64_t>(
+            (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(first >> 32))))
+             << 32) |
+            static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(first))));
+        int64_t run = 0;
 #pragma unroll
-        for (int r = 0; r < kMissRows; ++r)
-            if (lane == r && r < nr) counts[(row0 + r) * A.chunks + chunk] = cnt[r];
+        for (int r = 0; r < kMissRows; ++r) {
+            if (miss[r]) {
+                const int64_t at = at0 + run + lanes_below(m[r]);
+                if (at < capacity) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) out[at * W + w] = x[r][w] ^ gr.xy[w];
+                }
+            }
+            run += __popcll(m[r]);
+        }
     }
 }
 
@@ -158,20 +158,17 @@ __global__ void k_scatter_unique(const uint64_t* __restrict__ sorted, int64_t n,
 inline unsigned blocks256(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
 
 template <int W, int TK>
-hipError_t launch_misses_t(const MissArgs& A, bool fill, int32_t* counts, const int64_t* offsets, uint64_t* out,
+hipError_t launch_misses_t(const MissArgs& A, unsigned long long* counter, int64_t capacity, uint64_t* out,
                            hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((A.M + kMissRows - 1) / kMissRows), static_cast<unsigned>(A.chunks));
-    if (fill)
-        hipLaunchKernelGGL((k_misses<W, TK, true>), grid, dim3(64), 0, st, A, counts, offsets, out);
-    else
-        hipLaunchKernelGGL((k_misses<W, TK, false>), grid, dim3(64), 0, st, A, counts, offsets, out);
+    hipLaunchKernelGGL((k_misses<W, TK>), grid, dim3(64), 0, st, A, counter, capacity, out);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol, bool fill,
-                         int32_t* counts, const int64_t* offsets, uint64_t* out, hipStream_t st) {
+hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
+                         unsigned long long* counter, int64_t capacity, uint64_t* out, hipStream_t st) {
     MissArgs A;
     A.groups = H.groups;
     A.ghash = H.group_hash;
@@ -186,9 +183,9 @@ hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int pe
     A.prep_err = S.prep_err;
     A.tol = tol;
     const int tk = table_kind(H.W, H.narrow);
-    if (H.W == 2) return launch_misses_t<2, kTabVerify>(A, fill, counts, offsets, out, st);
-    if (tk == kTabNarrow) return launch_misses_t<1, kTabNarrow>(A, fill, counts, offsets, out, st);
-    return launch_misses_t<1, kTabWide>(A, fill, counts, offsets, out, st);
+    if (H.W == 2) return launch_misses_t<2, kTabVerify>(A, counter, capacity, out, st);
+    if (tk == kTabNarrow) return launch_misses_t<1, kTabNarrow>(A, counter, capacity, out, st);
+    return launch_misses_t<1, kTabWide>(A, counter, capacity, out, st);
 }
 
 hipError_t launch_unique_flags(int W, const uint64_t* sorted, int64_t n, int32_t* flags, hipStream_t st) {

@@ -163,3 +163,23 @@ def test_full_errors(eng):
     ref = oracle.local_energy_full(ham, keys, np.zeros(20, complex), V.cpu().numpy().view(np.uint64),
                                    np.zeros(n, complex))
     np.testing.assert_allclose(e.cpu().numpy(), ref, atol=1e-9)
+
+
+def test_miss_list_follows_samples_and_tolerance(eng):
+    """The library keeps its last miss list for unchanged samples: a second
+    call returns the same list; new samples give the oracle's new list,
+    whether the raw list outgrows the kept buffer (a second pass into a
+    larger one) or shrinks inside it; a new tolerance recomputes it."""
+    rng = np.random.default_rng(31)
+    ham = jw.random_pauli(10, 300, rng, max_flip=3)
+    keys = rng.choice(2 ** 10, 600, replace=False).astype(np.uint64)[:, None]
+    _load(eng, ham, keys[:100])
+    for sub in (keys[:100], keys[:600], keys[:250]):
+        eng.set_samples(torch.from_numpy(np.ascontiguousarray(sub).view(np.int64)).cuda())
+        got = eng.find_misses().cpu().numpy().view(np.uint64)
+        np.testing.assert_array_equal(got, oracle.find_misses(ham, sub))
+        np.testing.assert_array_equal(eng.find_misses().cpu().numpy().view(np.uint64), got)
+    # a tolerance that drops every state: recomputed, empty; then the default again
+    assert eng.find_misses(tol=1e300).shape[0] == 0
+    np.testing.assert_array_equal(eng.find_misses().cpu().numpy().view(np.uint64),
+                                  oracle.find_misses(ham, keys[:250]))
