@@ -634,7 +634,7 @@ def test_backward_after_state_change_raises(eng, small_workload):
 
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("count", [0, 16, 32])
-@pytest.mark.parametrize("wl", ["small", "medium", "odd_y"])
+@pytest.mark.parametrize("wl", ["small", "medium", "odd_y", "two_words"])
 def test_partitioned_terms(eng, wl, count, small_workload, medium_workload):
     """LoopOverTerms by U's table partitions (each XCD probing its own
     partitions, one pass after another; on by default only for tables of 8 MB
@@ -647,6 +647,22 @@ def test_partitioned_terms(eng, wl, count, small_workload, medium_workload):
         ham = jw.random_pauli(11, 500, rng, max_flip=3)
         keys = rng.choice(2 ** 11, 1500, replace=False).astype(np.uint64)[:, None]
         lp = rng.normal(scale=0.5, size=1500) + 1j * rng.uniform(0, 6, 1500)
+    elif wl == "two_words":
+        # 70 qubits (two-word keys, membership by fingerprint and key
+        # compare): keys within three flips of one base key, so that many
+        # pairs couple across both words
+        rng = np.random.default_rng(22)
+        N = 70
+        ham = jw.random_pauli(N, 400, rng, max_flip=2)
+        base = np.array([rng.integers(0, 2 ** 62), rng.integers(0, 2 ** (N - 64))], dtype=np.uint64)
+        rows = set()
+        while len(rows) < 1500:
+            k = base.copy()
+            for q in rng.choice(N, size=rng.integers(0, 4), replace=False):
+                k[q // 64] ^= np.uint64(1) << np.uint64(q % 64)
+            rows.add((int(k[0]), int(k[1])))
+        keys = np.array(sorted(rows), dtype=np.uint64)[rng.permutation(len(rows))]
+        lp = rng.normal(scale=0.5, size=keys.shape[0]) + 1j * rng.uniform(0, 6, keys.shape[0])
     else:
         w = small_workload if wl == "small" else medium_workload
         ham, keys, lp = w.ham, w.keys, w.logpsi
