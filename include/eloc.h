@@ -37,8 +37,8 @@
  *    GPU finishes unless documented as synchronising.  A context is not
  *    thread-safe; use one per host thread.
  *  - Many problems at once: the eloc_batch_* calls at the end evaluate a
- *    set of (Hamiltonian, U) problems of uneven size in one persistent
- *    launch replayed from a HIP graph.
+ *    set of (Hamiltonian, U) problems of uneven size in one pipeline
+ *    replayed from a HIP graph.
  */
 #ifndef ELOC_H
 #define ELOC_H
@@ -402,8 +402,8 @@ int eloc_profile_read(eloc_ctx ctx, double* ms_total, int64_t* count);
  * Batched evaluation: many problems (H_k, U_k) of uneven size in one
  * pipeline.  Per problem the result is the forward pass above
  * (E_loc^var over U_k and the weighted statistics); the pair stage of all
- * problems is one persistent kernel whose workgroups take work items
- * (problem, row tile, chunk of the inner loop) from an atomic counter, and
+ * problems is one kernel per key format over the work items (problem, row
+ * tile, chunk of the inner loop) of all problems in the schedule's order, and
  * the whole pipeline (sample tables, amplitudes, pairs, row sums,
  * reductions) is captured once per precision into a HIP graph and replayed
  * by eloc_batch_run.  Every problem uses LoopOverTerms or LoopOverBatch as
@@ -434,11 +434,12 @@ typedef struct {
     double* stats_dev;
 } eloc_problem;
 
-/* Schedule of the persistent pair kernel. */
+/* Schedule of the batched pair kernel. */
 typedef struct {
     int rows_per_wave;       /* 4 or 8 rows owned by one wave per work item        */
-    int blocks_per_cu;       /* resident workgroups per compute unit; 0 = as many
-                                as fit                                              */
+    int blocks_per_cu;       /* 0: one workgroup per work item; else that many
+                                per compute unit (at most what fits), striding
+                                over the items                                     */
     int64_t item_candidates; /* target candidates (row x inner index) per item;
                                 sets the chunk length of every problem             */
     int order;               /* 0: problems with most candidates first; 1: as given */
@@ -469,7 +470,7 @@ int eloc_batch_set_graph(eloc_batch batch, int on);
 /* Stage timing of the batched pipeline with HIP events on the batch's
  * stream (for roofline figures): while enabled, every eloc_batch_run with
  * the graph off records events around its three stages - per-sample
- * preparation, the persistent pair kernels, row sums and reductions.
+ * preparation, the batched pair kernels, row sums and reductions.
  * eloc_batch_profile_read writes HOST ms_total[3] and count[3] (totals since
  * the last read) and resets them; synchronising.  Graph replays are not
  * timed. */

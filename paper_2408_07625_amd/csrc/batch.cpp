@@ -1,6 +1,6 @@
 // Batched launch (C ABI eloc_batch_*): many (Hamiltonian, U) problems of
-// uneven size evaluated by one pipeline whose pair stage is a single
-// persistent kernel fed from a work counter.  The pipeline is captured once
+// uneven size evaluated by one pipeline whose pair stage is one kernel per
+// key format over all problems' work items.  The pipeline is captured once
 // per precision into a HIP graph and replayed; the schedule (rows per wave,
 // workgroups per compute unit, candidates per work item, problem order, and
 // the LoopOverTerms / LoopOverBatch choice per problem) is set directly or
@@ -55,7 +55,7 @@ struct eloc_batch_s {
 
     DevBuf R_dev, groups, terms, terms_f, ghash, gkeys, gslots, gstash;
     DevBuf probs, pid, tiles_dev, sched, keys, khash, kslots, kstash;
-    DevBuf err_dev, sigmin, sigmax, bitcounts, rad, shift, scal, part, pairs, work, a, b, af, bf, partial;
+    DevBuf err_dev, sigmin, sigmax, bitcounts, rad, shift, scal, part, pairs, a, b, af, bf, partial;
     uint32_t* err_host = nullptr;
 
     eloc_batch_schedule schedule{};
@@ -121,7 +121,6 @@ BatchDev dev_view(const eloc_batch b) {
     B.scal = b->scal.as<double>();
     B.part = b->part.as<double>();
     B.pairs = b->pairs.as<unsigned long long>();
-    B.work = b->work.as<unsigned int>();
     B.a = b->a.as<double2>();
     B.b = b->b.as<double2>();
     B.af = b->af.as<float4>();
@@ -190,11 +189,18 @@ int apply_schedule(eloc_batch b, const eloc_batch_schedule& s) {
     return ELOC_OK;
 }
 
+// Workgroups of a batched pair kernel: one per work item (blocks_per_cu <= 0),
+// or blocks_per_cu per CU (at most what fits) striding over the items.
 int launch_blocks(eloc_batch b, int precision, bool narrow) {
-    int per_cu = b->schedule.blocks_per_cu;
-    const int fit = batch_blocks_per_cu(b->W, narrow, precision, b->schedule.rows_per_wave);
-    if (per_cu <= 0 || (fit > 0 && per_cu > fit)) per_cu = fit > 0 ? fit : 1;
-    return std::max(1, per_cu * b->n_cu);
+    const int64_t items = narrow ? b->narrow_items : b->total_items - b->narrow_items;
+    int64_t blocks = items;
+    if (b->schedule.blocks_per_cu > 0) {
+        int per_cu = b->schedule.blocks_per_cu;
+        const int fit = batch_blocks_per_cu(b->W, narrow, precision, b->schedule.rows_per_wave);
+        if (fit > 0 && per_cu > fit) per_cu = fit;
+        blocks = std::min<int64_t>(items, static_cast<int64_t>(per_cu) * b->n_cu);
+    }
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(blocks, int64_t(1) << 30)));
 }
 
 hipEvent_t batch_event(eloc_batch b) {
@@ -560,7 +566,6 @@ int eloc_batch_create(eloc_batch* out, int device, void* hip_stream, int n, cons
     BATCH_HIP(b, b->scal.ensure(sizeof(double) * 3 * n));
     BATCH_HIP(b, b->part.ensure(sizeof(double) * 3 * nt));
     BATCH_HIP(b, b->pairs.ensure(sizeof(unsigned long long) * n));
-    BATCH_HIP(b, b->work.ensure(2 * sizeof(unsigned int)));
     BATCH_HIP(b, b->a.ensure(sizeof(double2) * S));
     BATCH_HIP(b, b->b.ensure(sizeof(double2) * S));
     BATCH_HIP(b, b->af.ensure(sizeof(float4) * S));
@@ -583,7 +588,7 @@ void eloc_batch_destroy(eloc_batch b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     DevBuf* bufs[] = {&b->R_dev, &b->groups, &b->terms, &b->terms_f, &b->ghash, &b->gkeys, &b->gslots, &b->gstash,
                       &b->probs, &b->pid, &b->tiles_dev, &b->sched, &b->keys, &b->khash, &b->kslots, &b->kstash,
-                      &b->err_dev, &b->sigmin, &b->sigmax, &b->bitcounts, &b->rad, &b->shift, &b->scal, &b->part, &b->pairs, &b->work,
+                      &b->err_dev, &b->sigmin, &b->sigmax, &b->bitcounts, &b->rad, &b->shift, &b->scal, &b->part, &b->pairs,
                       &b->a, &b->b, &b->af, &b->bf, &b->partial};
     for (DevBuf* d : bufs) d->release();
     for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);

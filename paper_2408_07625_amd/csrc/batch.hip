@@ -1,4 +1,4 @@
-// Kernels of the batched pipeline around the persistent pair kernel: one
+// Kernels of the batched pipeline around the batched pair kernel: one
 // launch of each covers every problem of the batch.  Per-sample kernels run
 // over the global sample index and find their problem through the pid map;
 // reductions run over tiles that never straddle two problems and are then
@@ -36,7 +36,6 @@ __global__ __launch_bounds__(kBlock) void k_bt_clear(BatchDev B) {
         B.sigmax[t0] = 0u;
         B.pairs[t0] = 0ull;
     }
-    if (t0 < 2) B.work[t0] = 0u;
 }
 
 // Copy of the caller keys (words beyond the problem's own are zero), linear

@@ -461,9 +461,9 @@ enum ErrBits : uint32_t {
 // Batched launch: many (Hamiltonian, U) problems in one pipeline.  Samples of
 // all problems share one global index space (problem k owns [s0, s0 + M));
 // a per-problem descriptor holds the offsets into the concatenated buffers
-// and the caller's own input / output pointers.  The pair kernel is
-// persistent: work items (problem, row tile, chunk) are taken from one
-// atomic counter in the order of the schedule.
+// and the caller's own input / output pointers.  The pair kernel runs over
+// work items (problem, row tile, chunk) in the order of the schedule: one
+// workgroup per item, or a grid of a few per compute unit striding over them.
 // ---------------------------------------------------------------------------
 constexpr int kMaxBatch = 256;   // problems per batch (four lane registers of item starts)
 constexpr int kBTile = 2048;     // samples per reduction tile
@@ -536,7 +536,6 @@ struct BatchDev {
     double* scal;              // [n][3] E re, E im, sum w
     double* part;              // [n_tiles][3] reduction partials
     unsigned long long* pairs; // [n] coupled pairs found
-    unsigned int* work;        // work-item counters [2]: narrow items, wide items
     int64_t narrow_items;      // items [0, narrow_items) belong to narrow problems
     double2* a;
     double2* b;
@@ -639,7 +638,7 @@ hipError_t launch_row_classes(const uint64_t* hash, int64_t n, int shift, int bi
 hipError_t launch_trie_visits(const HamDev& H, const SampleDev& S, const Plan& P, unsigned long long* visits,
                               hipStream_t st);
 
-// Batched pipeline (batch.hip; the persistent pair kernel in pairs.hip).
+// Batched pipeline (batch.hip; the batched pair kernel in pairs.hip).
 hipError_t launch_batch_prepare(const BatchDev& B, bool fp32, hipStream_t st);
 hipError_t launch_batch_pairs(const BatchDev& B, int precision, int rows, int narrow_blocks, int wide_blocks,
                               hipStream_t st);

@@ -897,15 +897,16 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
 }
 
 // ---------------------------------------------------------------------------
-// Batched persistent kernel.  Each workgroup (one wave) takes work items
-// from the batch's atomic counter until the schedule is exhausted; item t
-// belongs to the problem whose [item0, item0 + items) holds it (found by a
-// ballot over the item starts, kept in four lane registers), and is the
-// (row tile, chunk) pair u / chunks, u % chunks of that problem.  The item
-// body is the forward row kernel above with the problem's own tables,
-// variant and signature filter; a row's chunk partials land at the
-// problem's partial offset.  Every wave leaves the loop when the counter
-// passes the last item.
+// Batched pair kernel.  Workgroup w (one wave) takes work items w, w + grid,
+// ... of its key format's range (one item per workgroup unless the schedule
+// asks for a few workgroups per compute unit; the hardware hands workgroups
+// to free slots in order, which balances uneven items as a work counter
+// would, without its round trip); item t belongs to the problem whose
+// [item0, item0 + items) holds it (found by a ballot over the item starts,
+// kept in four lane registers), and is the (row tile, chunk) pair
+// u / chunks, u % chunks of that problem.  The item body is the forward row
+// kernel above with the problem's own tables, variant and signature filter;
+// a row's chunk partials land at the problem's partial offset.
 // ---------------------------------------------------------------------------
 // Wave-uniform copies of values read from memory at a uniform address: the
 // first lane's, so that they live in scalar registers (the compiler cannot
@@ -985,11 +986,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
     }
     const int64_t first = NW ? 0 : B.narrow_items;
     const int64_t last = NW ? B.narrow_items : B.total_items;
-    for (;;) {
-        unsigned int t0 = 0u;
-        if (lane == 0) t0 = atomicAdd(B.work + (NW ? 0 : 1), 1u);
-        const int64_t t = first + static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(t0)));
-        if (t >= last) break;
+    for (int64_t t = first + blockIdx.x; t < last; t += gridDim.x) {
         int pos = -1;
 #pragma unroll
         for (int c = 0; c < kSlices; ++c) pos += __popcll(__ballot(istart[c] <= t));
