@@ -351,6 +351,17 @@ def cpu_baseline(w, res_head):
     oracle.set_threads(threads)
     a, b = rows_all
     acc = {p: float(np.abs(res_head[p]["eloc"][a:b] - ref).max()) for p in ("fp64", "fp32c")}
+    # the oracle on the other workloads (all host threads, bounded row samples)
+    from synth import configs
+    others = {}
+    for name, rows in (("small", None), ("medium", 4096), ("wide", 128)):
+        wo = getattr(configs, name)()
+        r = (0, wo.n_unique if rows is None else min(wo.n_unique, rows))
+        t0 = time.perf_counter()
+        _, np_o = oracle.local_energy(wo.ham, wo.keys, wo.logpsi, rows=r, with_pairs=True)
+        t_o = time.perf_counter() - t0
+        others[name] = {"pairs_per_s": float(np_o.sum()) / t_o, "samples_per_s": (r[1] - r[0]) / t_o,
+                        "sample": f"rows [{r[0]}, {r[1]}) of {wo.n_unique} ({wo.n_qubits} qubits), {t_o:.2f} s wall"}
     return {"value": float(npairs.sum()) / t_all, "unit": "coupled pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"rows [{a}, {b}) of the workload ({b - a} of {M} samples, {int(npairs.sum())} coupled "
                       f"pairs), one forward pass, {t_all:.2f} s wall on {threads} threads",
@@ -359,7 +370,7 @@ def cpu_baseline(w, res_head):
                               "sample": f"rows [{rows_one[0]}, {rows_one[1]}), {t_one:.2f} s wall",
                               "samples_per_s": (rows_one[1] - rows_one[0]) / t_one},
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-            "gpu_vs_oracle_max_abs_dE_loc": acc}
+            "gpu_vs_oracle_max_abs_dE_loc": acc, "other_workloads": others}
 
 
 def bench_medium(args):
