@@ -372,6 +372,10 @@ typedef struct {
                             eloc_set_samples.                                 */
     int partition_count; /* partitions: 8, 16 or 32; 0 = automatic (enough to
                             bring one partition to 1 MB)                      */
+    int trie_chunk;      /* XY masks per chunk tree of LoopOverTrie (2..32767);
+                            0 = automatic (about 2^25 / n_unique chunks, at
+                            least 64 masks each).  The trees are built at the
+                            first LoopOverTrie use after eloc_set_samples.   */
 } eloc_tuning;
 int eloc_set_tuning(eloc_ctx ctx, const eloc_tuning* tuning);
 int eloc_get_tuning(eloc_ctx ctx, eloc_tuning* tuning);

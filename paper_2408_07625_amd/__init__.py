@@ -38,7 +38,7 @@ class C64(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("chunks", ctypes.c_int), ("sig_filter", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
                 ("bloom", ctypes.c_int), ("waves_per_block", ctypes.c_int), ("partition", ctypes.c_int),
-                ("partition_count", ctypes.c_int)]
+                ("partition_count", ctypes.c_int), ("trie_chunk", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -230,13 +230,15 @@ class Engine:
         return {"n_unique": n.value, "table_slots": slots.value, "table_stash": stash.value}
 
     def set_tuning(self, chunks: int = 0, sig_filter: bool = True, rows_per_wave: int = 0, bloom: bool = False,
-                   waves_per_block: int = 0, partition: int = 0, partition_count: int = 0):
+                   waves_per_block: int = 0, partition: int = 0, partition_count: int = 0, trie_chunk: int = 0):
         """partition: 0 automatic (U tables of 8 MB and more), 1 on, -1 off;
         partition_count: 8, 16 or 32 (0 automatic).  Set before
         set_hamiltonian and set_samples (the group records are bucketed at
-        ingest, U's rows classed when its table is built)."""
+        ingest, U's rows classed when its table is built).  trie_chunk: XY
+        masks per LoopOverTrie chunk tree (0 automatic; used from the next
+        set_samples)."""
         t = Tuning(int(chunks), 1 if sig_filter else 0, int(rows_per_wave), 1 if bloom else 0, int(waves_per_block),
-                   int(partition), int(partition_count))
+                   int(partition), int(partition_count), int(trie_chunk))
         self._call(self.lib.eloc_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -244,7 +246,7 @@ class Engine:
         self._call(self.lib.eloc_get_tuning(self.handle, ctypes.byref(t)))
         return {"chunks": t.chunks, "sig_filter": bool(t.sig_filter), "rows_per_wave": t.rows_per_wave,
                 "bloom": bool(t.bloom), "waves_per_block": t.waves_per_block, "partition": t.partition,
-                "partition_count": t.partition_count}
+                "partition_count": t.partition_count, "trie_chunk": t.trie_chunk}
 
     STAGES = ("samples", "amplitudes", "pairs", "finish", "energy", "adjoint_pairs", "adjoint_finish")
 

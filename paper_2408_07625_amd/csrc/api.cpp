@@ -92,6 +92,7 @@ struct eloc_ctx_s {
     int tune_waves = 0;      // 0 = automatic
     int tune_part = 0;       // 0 automatic, 1 on where possible, -1 off
     int tune_part_count = 0; // partitions: 0 automatic, 8, 16 or 32
+    int tune_trie_chunk = 0; // XY masks per LoopOverTrie chunk tree (0: automatic)
     uint64_t kslots_n = 0;   // slots of U's membership table
     uint64_t salt_state = 0x5EED2408ull;
 
@@ -303,21 +304,13 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     const std::vector<int32_t>& order = hh.order;
     const std::vector<uint64_t>& xsorted = hh.xsorted;
     const int maxpop = hh.maxpop, diag = hh.diag;
-    // LoopOverTrie walks U against one XY chunk tree per workgroup column:
-    // about 128 chunks of at least 64 masks (measured at the medium workload:
-    // 16 chunks 24 ms, 32: 19, 64: 16, 128 and 256: 14)
-    const int64_t xy_chunks_target = 128;
-    const int64_t xy_chunk = std::max<int64_t>(
-        2, std::max<int64_t>(std::min<int64_t>(G, 64), (G + xy_chunks_target - 1) / xy_chunks_target));
-    const int64_t xy_chunks = (G + xy_chunk - 1) / xy_chunk;
+    // the sorted XY masks and their group ids; LoopOverTrie's chunk trees
+    // over them are built at its first use on a sample set (their size
+    // depends on the number of rows)
     ELOC_HIP(c, c->xyt_keys.ensure(sizeof(uint64_t) * G * W));
     ELOC_HIP(c, c->xyt_gid.ensure(sizeof(int32_t) * G));
-    ELOC_HIP(c, c->xyt_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, xy_chunks * (xy_chunk - 1))));
-    ELOC_HIP(c, c->xyt_nkeys.ensure(sizeof(uint64_t) * W * std::max<int64_t>(1, xy_chunks * (xy_chunk - 1))));
     ELOC_HIP(c, hipMemcpy(c->xyt_keys.p, xsorted.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->xyt_gid.p, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice));
-    ELOC_HIP(c, launch_trie_build(W, c->xyt_keys.as<uint64_t>(), G, xy_chunk, c->xyt_nodes.as<TNode>(),
-                                  c->xyt_nkeys.as<uint64_t>(), c->stream));
     ELOC_HIP(c, c->groups.ensure(sizeof(GroupRec<W>) * G));
     ELOC_HIP(c, c->terms.ensure(sizeof(TermRec<W>) * n_terms));
     ELOC_HIP(c, c->terms_f.ensure(sizeof(TermRecF<W>) * n_terms));
@@ -394,10 +387,10 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.part.bucket_dev = c->gbucket.as<int32_t>();
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
     H.xyt.gid = c->xyt_gid.as<int32_t>();
-    H.xyt.nodes = c->xyt_nodes.as<TNode>();
-    H.xyt.nkeys = c->xyt_nkeys.as<uint64_t>();
-    H.xyt.chunk = static_cast<int>(xy_chunk);
-    H.xyt.chunks = static_cast<int>(xy_chunks);
+    H.xyt.nodes = nullptr;   // chunk trees not built yet
+    H.xyt.nkeys = nullptr;
+    H.xyt.chunk = 0;
+    H.xyt.chunks = 0;
     c->H = H;
     c->ham_set = true;
     return ELOC_OK;
@@ -446,10 +439,48 @@ int check_ready(eloc_ctx c) {
 
 // Sorted copy of U with its radix tree, built on first use by LoopOverTrie
 // after every eloc_set_samples.
+// XY masks per chunk tree of LoopOverTrie for M rows: about 2^25 (row,
+// chunk) walks (measured: 2^16 rows fastest with about 128 chunks, 2^20
+// rows with 32: 382 ms against 425 with 128 and 406 with 16), at least 64
+// masks a chunk and at most what the walk's 16-bit node codes allow; or the
+// tuned size.
+int64_t trie_chunk_for(const eloc_ctx c, int64_t M) {
+    const int64_t G = c->H.n_groups;
+    if (c->tune_trie_chunk > 0) return std::max<int64_t>(2, std::min<int64_t>(c->tune_trie_chunk, std::max<int64_t>(G, 2)));
+    const int64_t chunks = std::max<int64_t>(1, ((int64_t(1) << 25) + M - 1) / std::max<int64_t>(M, 1));
+    int64_t chunk = (G + chunks - 1) / chunks;
+    chunk = std::max<int64_t>(chunk, std::min<int64_t>(G, 64));
+    return std::max<int64_t>(2, std::min<int64_t>(chunk, 32767));
+}
+
+// The XY chunk trees for chunks of `chunk` masks (synchronous with respect
+// to the stream: later work on it sees them).
+int build_xy_trie(eloc_ctx c, int64_t chunk) {
+    const int64_t G = c->H.n_groups;
+    const int W = c->H.W;
+    const int64_t chunks = (G + chunk - 1) / chunk;
+    ELOC_HIP(c, c->xyt_nodes.ensure(sizeof(TNode) * std::max<int64_t>(1, chunks * (chunk - 1))));
+    ELOC_HIP(c, c->xyt_nkeys.ensure(sizeof(uint64_t) * W * std::max<int64_t>(1, chunks * (chunk - 1))));
+    ELOC_HIP(c, launch_trie_build(W, c->xyt_keys.as<uint64_t>(), G, chunk, c->xyt_nodes.as<TNode>(),
+                                  c->xyt_nkeys.as<uint64_t>(), c->stream));
+    c->H.xyt.nodes = c->xyt_nodes.as<TNode>();
+    c->H.xyt.nkeys = c->xyt_nkeys.as<uint64_t>();
+    c->H.xyt.chunk = static_cast<int>(chunk);
+    c->H.xyt.chunks = static_cast<int>(chunks);
+    return ELOC_OK;
+}
+
 int ensure_utrie(eloc_ctx c) {
     if (c->ut_valid) return ELOC_OK;
     const int64_t M = c->S.n;
     const int W = c->H.W;
+    {
+        const int64_t chunk = trie_chunk_for(c, M);
+        if (chunk != c->H.xyt.chunk) {
+            const int rc = build_xy_trie(c, chunk);
+            if (rc) return rc;
+        }
+    }
     const int64_t tiles = radix_tiles(M);
     ELOC_HIP(c, c->ut_keys.ensure(sizeof(uint64_t) * M * W));
     ELOC_HIP(c, c->ut_perm.ensure(sizeof(int32_t) * M));
@@ -1365,7 +1396,7 @@ int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
     const int tp = t ? t->partition : 0, tc = t ? t->partition_count : 0;
     if (!c || !t || t->chunks < 0 || (t->rows_per_wave != 0 && t->rows_per_wave != 4 && t->rows_per_wave != 8) ||
         (t->waves_per_block != 0 && t->waves_per_block != 1 && t->waves_per_block != 4) || tp < -1 || tp > 1 ||
-        !(tc == 0 || tc == 8 || tc == 16 || tc == 32))
+        !(tc == 0 || tc == 8 || tc == 16 || tc == 32) || t->trie_chunk < 0 || t->trie_chunk > 32767)
         return c ? fail(c, ELOC_EINVAL, "bad tuning") : ELOC_EINVAL;
     c->tune_chunks = t->chunks;
     c->tune_sig = t->sig_filter;
@@ -1374,6 +1405,7 @@ int eloc_set_tuning(eloc_ctx c, const eloc_tuning* t) {
     c->tune_waves = t->waves_per_block;
     c->tune_part = t->partition;
     c->tune_part_count = t->partition_count;
+    c->tune_trie_chunk = t->trie_chunk;
     return ELOC_OK;
 }
 
@@ -1386,6 +1418,7 @@ int eloc_get_tuning(eloc_ctx c, eloc_tuning* t) {
     t->waves_per_block = c->tune_waves;
     t->partition = c->tune_part;
     t->partition_count = c->tune_part_count;
+    t->trie_chunk = c->tune_trie_chunk;
     return ELOC_OK;
 }
 
