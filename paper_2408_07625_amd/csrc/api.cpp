@@ -39,7 +39,8 @@ struct eloc_ctx_s {
     bool ham_set = false;
     HamDev H;
     DevBuf groups, terms, terms_f, term_src, term_ny, ghash, gkeys, gslots, gstash;
-    DevBuf groups_b, ghash_b;   // group records bucketed by the partition of their hash
+    DevBuf groups_b, ghash_b, gsplit_b;   // group records bucketed by the partition of their hash
+    DevBuf gsplit;              // spin_split of every group's XY mask
     DevBuf gbucket;             // their bucket starts [kMaxParts + 1] (int32)
     DevBuf pe_cnt, pe_grp;   // pair_elements: term counts and groups of the pairs
     DevBuf xyt_keys, xyt_gid, xyt_nodes, xyt_nkeys;
@@ -331,12 +332,18 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     ELOC_HIP(c, hipMemcpy(c->term_ny.p, hh.term_ny.data(), sizeof(uint8_t) * n_terms, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->ghash.p, ghash.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
     ELOC_HIP(c, hipMemcpy(c->gkeys.p, gkeys.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
+    // the XY masks in spin-split form, for the LoopOverTerms prefilter
+    std::vector<uint64_t> gsplit(gkeys.size());
+    for (size_t i = 0; i < gkeys.size(); ++i) gsplit[i] = spin_split(gkeys[i]);
+    ELOC_HIP(c, c->gsplit.ensure(sizeof(uint64_t) * G * W));
+    ELOC_HIP(c, hipMemcpy(c->gsplit.p, gsplit.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
     // the group records bucketed by the partition of their hash (stable)
     {
         std::vector<GroupRec<W>> gb;
-        std::vector<uint64_t> hb;
+        std::vector<uint64_t> hb, sb;
         gb.reserve(static_cast<size_t>(G));
         hb.reserve(static_cast<size_t>(G));
+        sb.reserve(static_cast<size_t>(G * W));
         int bucket[kMaxParts + 1] = {};
         // a context tuned to partition every table partitions small ones by
         // runs of 32 slots, else by blocks of 64K slots
@@ -348,6 +355,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
                     b) {
                     gb.push_back(groups[static_cast<size_t>(g)]);
                     hb.push_back(ghash[static_cast<size_t>(g)]);
+                    for (int w = 0; w < W; ++w) sb.push_back(gsplit[static_cast<size_t>(g * W + w)]);
                 }
         }
         bucket[kMaxParts] = static_cast<int>(G);
@@ -355,6 +363,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
         ELOC_HIP(c, c->ghash_b.ensure(sizeof(uint64_t) * G));
         ELOC_HIP(c, hipMemcpy(c->groups_b.p, gb.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
         ELOC_HIP(c, hipMemcpy(c->ghash_b.p, hb.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
+        ELOC_HIP(c, c->gsplit_b.ensure(sizeof(uint64_t) * G * W));
+        ELOC_HIP(c, hipMemcpy(c->gsplit_b.p, sb.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
         for (int b = 0; b <= kMaxParts; ++b) c->H.part.bucket[b] = bucket[b];
         ELOC_HIP(c, c->gbucket.ensure(sizeof(int32_t) * (kMaxParts + 1)));
         ELOC_HIP(c, hipMemcpy(c->gbucket.p, bucket, sizeof(int32_t) * (kMaxParts + 1), hipMemcpyHostToDevice));
@@ -379,10 +389,12 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.term_ny = c->term_ny.as<uint8_t>();
     H.group_hash = c->ghash.as<uint64_t>();
     H.group_keys = c->gkeys.as<uint64_t>();
+    H.group_split = c->gsplit.as<uint64_t>();
     H.group_table = T;
     H.part.groups = c->groups_b.p;
     H.part.shift = c->H.part.shift;
     H.part.ghash = c->ghash_b.as<uint64_t>();
+    H.part.gsplit = c->gsplit_b.as<uint64_t>();
     for (int b = 0; b <= kMaxParts; ++b) H.part.bucket[b] = c->H.part.bucket[b];
     H.part.bucket_dev = c->gbucket.as<int32_t>();
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
@@ -626,7 +638,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
                       &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->st_rowptr, &c->st_col, &c->st_h,
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
-                      &c->groups_b, &c->ghash_b, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
+                      &c->groups_b, &c->ghash_b, &c->gsplit_b, &c->gsplit, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
                       &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
                       &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt,
                       &c->ar_hist, &c->ar_sel, &c->ar_keep, &c->ar_off};

@@ -53,7 +53,7 @@ struct eloc_batch_s {
     std::vector<RTile> tiles;
     std::vector<uint64_t> kcap;      // key-table capacity per problem
 
-    DevBuf R_dev, groups, terms, terms_f, ghash, gkeys, gslots, gstash;
+    DevBuf R_dev, groups, terms, terms_f, ghash, gkeys, gsplit, gslots, gstash;
     DevBuf probs, pid, tiles_dev, sched, keys, khash, kslots, kstash;
     DevBuf err_dev, sigmin, sigmax, bitcounts, rad, shift, scal, part, pairs, a, b, af, bf, partial;
     uint32_t* err_host = nullptr;
@@ -329,6 +329,7 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
     BATCH_HIP(b, b->groups.ensure(sizeof(GroupRec<W>) * ng));
     BATCH_HIP(b, b->ghash.ensure(sizeof(uint64_t) * ng));
     BATCH_HIP(b, b->gkeys.ensure(sizeof(uint64_t) * ng * W));
+    BATCH_HIP(b, b->gsplit.ensure(sizeof(uint64_t) * ng * W));
     BATCH_HIP(b, b->terms.ensure(sizeof(TermRec<W>) * nt));
     BATCH_HIP(b, b->terms_f.ensure(sizeof(TermRecF<W>) * nt));
     BATCH_HIP(b, b->gslots.ensure(static_cast<size_t>(gcap)));
@@ -348,12 +349,17 @@ int ingest_all(eloc_batch b, const eloc_problem* probs) {
                                hipMemcpyHostToDevice));
         BATCH_HIP(b, hipMemcpy(b->gkeys.as<uint64_t>() + go * W, h.gkeys.data(), sizeof(uint64_t) * h.G * W,
                                hipMemcpyHostToDevice));
+        std::vector<uint64_t> split(h.gkeys.size());
+        for (size_t i = 0; i < split.size(); ++i) split[i] = spin_split(h.gkeys[i]);
+        BATCH_HIP(b, hipMemcpy(b->gsplit.as<uint64_t>() + go * W, split.data(), sizeof(uint64_t) * h.G * W,
+                               hipMemcpyHostToDevice));
         BATCH_HIP(b, hipMemcpy(terms + to, h.terms.data(), sizeof(TermRec<W>) * h.n_terms, hipMemcpyHostToDevice));
         BATCH_HIP(b, hipMemcpy(terms_f + to, h.terms_f.data(), sizeof(TermRecF<W>) * h.n_terms,
                                hipMemcpyHostToDevice));
         BatchProb& D = b->desc[static_cast<size_t>(k)];
         D.groups = groups + go;
         D.ghash = b->ghash.as<uint64_t>() + go;
+        D.gsplit = b->gsplit.as<uint64_t>() + go * W;
         D.terms = terms + to;
         D.terms_f = terms_f + to;
         D.gkeys = b->gkeys.as<uint64_t>() + go * W;
@@ -586,7 +592,7 @@ void eloc_batch_destroy(eloc_batch b) {
     else (void)hipDeviceSynchronize();
     drop_graphs(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    DevBuf* bufs[] = {&b->R_dev, &b->groups, &b->terms, &b->terms_f, &b->ghash, &b->gkeys, &b->gslots, &b->gstash,
+    DevBuf* bufs[] = {&b->R_dev, &b->groups, &b->terms, &b->terms_f, &b->ghash, &b->gkeys, &b->gsplit, &b->gslots, &b->gstash,
                       &b->probs, &b->pid, &b->tiles_dev, &b->sched, &b->keys, &b->khash, &b->kslots, &b->kstash,
                       &b->err_dev, &b->sigmin, &b->sigmax, &b->bitcounts, &b->rad, &b->shift, &b->scal, &b->part, &b->pairs,
                       &b->a, &b->b, &b->af, &b->bf, &b->partial};

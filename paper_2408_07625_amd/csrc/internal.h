@@ -150,6 +150,27 @@ __host__ __device__ __forceinline__ int rev_bits(int v, int bits) {
     return r;
 }
 
+// Spin-split form of a key word: its even bits (spin-up orbitals under the
+// interleaved Jordan-Wigner order) in order in the low half, its odd bits in
+// the high half (an outer perfect unshuffle by five delta swaps).  A bit
+// permutation commutes with XOR and keeps popcounts, so the LoopOverTerms
+// prefilter can count both spin sectors of x ^ XY with one popcount per half
+// word instead of a mask and two popcounts.
+__host__ __device__ __forceinline__ uint64_t spin_split(uint64_t x) {
+    uint64_t t;
+    t = (x ^ (x >> 1)) & 0x2222222222222222ull;
+    x ^= t ^ (t << 1);
+    t = (x ^ (x >> 2)) & 0x0C0C0C0C0C0C0C0Cull;
+    x ^= t ^ (t << 2);
+    t = (x ^ (x >> 4)) & 0x00F000F000F000F0ull;
+    x ^= t ^ (t << 4);
+    t = (x ^ (x >> 8)) & 0x0000FF000000FF00ull;
+    x ^= t ^ (t << 8);
+    t = (x ^ (x >> 16)) & 0x00000000FFFF0000ull;
+    x ^= t ^ (t << 16);
+    return x;
+}
+
 template <int TK>
 __host__ __device__ __forceinline__ typename TabT<TK>::hash salted(const Table& T, uint64_t h) {
     return static_cast<typename TabT<TK>::hash>(h ^ T.salt);
@@ -368,6 +389,7 @@ struct HamDev {
     const uint8_t* term_ny = nullptr;      // its |Y| mod 4 [T]
     const uint64_t* group_hash = nullptr;  // lin(XY_g) [G]
     const uint64_t* group_keys = nullptr;  // XY_g [G][W] (table key array)
+    const uint64_t* group_split = nullptr; // spin_split(XY_g) [G][W]
     Table group_table{};               // XY -> group id
     XYTrieDev xyt{};
     // the group records again, bucketed by the reversed kMaxPartBits-bit
@@ -376,6 +398,7 @@ struct HamDev {
     struct {
         const void* groups = nullptr;
         const uint64_t* ghash = nullptr;
+        const uint64_t* gsplit = nullptr;
         int bucket[kMaxParts + 1] = {};        // bucket starts (host copy)
         const int32_t* bucket_dev = nullptr;   // the same [kMaxParts + 1] on the device
         int shift = kPartShiftLarge;   // first partition bit of U's tables for this Hamiltonian
@@ -472,6 +495,7 @@ struct BatchProb {
     // Hamiltonian (run and group indices local to the problem)
     const void* groups;
     const uint64_t* ghash;
+    const uint64_t* gsplit;   // spin_split of the XY masks [G][W]
     const void* terms;
     const void* terms_f;
     const uint64_t* gkeys;

@@ -41,6 +41,7 @@ constexpr int kTrieBlock = 256;
 struct PairArgs {
     const void* groups;
     const uint64_t* ghash;
+    const uint64_t* gsplit;     // spin_split of the groups' XY masks [G][W]
     const void* terms;
     const void* terms_f;
     const uint64_t* gkeys;
@@ -91,6 +92,7 @@ struct PairArgs {
     const int64_t* tile_off;    // [2^bits + 1] first tile of each class
     const void* groups_b;       // group records bucketed by the partition of their hash
     const uint64_t* ghash_b;
+    const uint64_t* gsplit_b;
     // bucket starts in groups_b [kMaxParts + 1], in device memory: a kernel
     // argument array indexed at run time would move the whole argument
     // block to the stack
@@ -102,6 +104,7 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     PairArgs a;
     a.groups = H.groups;
     a.ghash = H.group_hash;
+    a.gsplit = H.group_split;
     a.terms = H.terms;
     a.terms_f = H.terms_f;
     a.gkeys = H.group_keys;
@@ -144,9 +147,18 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.tile_off = S.part.tile_off;
     a.groups_b = H.part.groups;
     a.ghash_b = H.part.ghash;
+    a.gsplit_b = H.part.gsplit;
     a.gbucket = H.part.bucket_dev;
     a.part_sub = P.part_sub;
     return a;
+}
+
+// popcount(x) + c in one instruction (the optimizer would otherwise turn an
+// addend that is a negated signature into a separate subtraction)
+__device__ __forceinline__ uint32_t popc_plus(uint32_t x, uint32_t c) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "s"(c));
+    return r;
 }
 
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
@@ -260,35 +272,50 @@ using CEntry = uint32_t;
 
 template <int W, int SIG, int NR, bool NW, bool BL, class Sink>
 __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>& R, int g0, int g1,
-                                           const void* groups_v, const uint64_t* __restrict__ ghash, Sink& sink,
-                                           const uint32_t* lfilt, CEntry<NW>* cb, const uint64_t* rowkey) {
+                                           const void* groups_v, const uint64_t* __restrict__ ghash,
+                                           const uint64_t* __restrict__ gsplit, Sink& sink, const uint32_t* lfilt,
+                                           CEntry<NW>* cb, const uint64_t* rowkey) {
     constexpr int TK = table_kind(W, NW);
     using HT = typename TabT<TK>::hash;
+    // wide keys on an exact table need the XY masks only in the prefilter,
+    // which then takes rows, masks and reference key in spin-split form
+    constexpr bool SPLIT = SIG && !NW && TK != kTabVerify;
     const GroupRec<W>* __restrict__ groups = static_cast<const GroupRec<W>*>(groups_v);
     const Table& T = A.ktable;
     const SlotReader<TK> slots(T);
     if (g0 >= g1) return;
     const int lane = lane_id();
     const uint32_t lane8 = static_cast<uint32_t>(lane) << 3;
-    // the signature (even-qubit popcount << 8 | popcount) of U, and the mask
-    // of its compare (0: U has no single signature, everything passes)
-    // (bit 16 marks lanes past the end of the bucket and is always compared;
-    // the mask lives in a vector register: the compare's three-operand
-    // logic op can read only one scalar register)
-    const uint32_t sig_key = (static_cast<uint32_t>(A.sig_pa) << 8) | static_cast<uint32_t>(A.sig_n);
-    uint32_t sig_mask = A.sig_all ? 0x10000u : 0x1FFFFu;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(sig_mask) : "s"(sig_mask));
+    // U's signature: even-qubit popcount and the other one (odd qubits, or
+    // all qubits for narrow keys).  A candidate's mismatch is the OR of its
+    // two counts less U's (each popcount's own addend) and of 2^16 on lanes
+    // past the bucket; it may be at most sig_tol.  When U has several
+    // signatures nothing is subtracted and every valid lane passes.
+    const uint32_t sig_a = A.sig_all ? 0u : static_cast<uint32_t>(A.sig_pa);
+    const uint32_t sig_b = A.sig_all ? 0u : static_cast<uint32_t>(SPLIT ? A.sig_n - A.sig_pa : A.sig_n);
+    const uint32_t sig_tol = A.sig_all ? 0xFFFFu : 0u;
+    const uint32_t neg_a = 0u - sig_a, neg_b = 0u - sig_b;
+    uint64_t rx[NR][W], ref[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) ref[w] = SPLIT ? spin_split(A.rad_ref[w]) : A.rad_ref[w];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int w = 0; w < W; ++w) rx[r][w] = SPLIT ? spin_split(R.x[r][w]) : R.x[r][w];
     // the step's group fields live in plain registers (mask words, term
     // run, hash)
+    auto mask_word = [&](int g, int w) -> uint64_t {
+        return SPLIT ? gsplit[static_cast<int64_t>(g) * W + w] : groups[g].xy[w];
+    };
     uint64_t gxy[W];
     RunRef run;
     uint64_t gh;
     {
-        const GroupRec<W>& gr = groups[min(g0 + lane, g1 - 1)];
+        const int g = min(g0 + lane, g1 - 1);
 #pragma unroll
-        for (int w = 0; w < W; ++w) gxy[w] = gr.xy[w];
-        run = run_ref(gr);
-        gh = ghash[min(g0 + lane, g1 - 1)];
+        for (int w = 0; w < W; ++w) gxy[w] = mask_word(g, w);
+        run = run_ref(groups[g]);
+        gh = ghash[g];
     }
     for (int base = g0; base < g1; base += kWave) {
         const int g = base + lane;
@@ -301,47 +328,65 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
         uint64_t ngh;
         {
             const int ng = min(base + kWave + lane, g1 - 1);
-            const GroupRec<W>& gr = groups[ng];
 #pragma unroll
-            for (int w = 0; w < W; ++w) nxy[w] = gr.xy[w];
-            nrun = run_ref(gr);
+            for (int w = 0; w < W; ++w) nxy[w] = mask_word(ng, w);
+            nrun = run_ref(groups[ng]);
             ngh = ghash[ng];
         }
-        // the exact prefilters of candidate x ^ XY for row r: U's single
-        // popcount signature (unless sig_all), U's radius around its majority
-        // key, U's Bloom filter (BL).  All of them fold into one unsigned
-        // compare, d + 256 t <= rad_max, with d the distance from the
-        // reference key and t the masked mismatch of (even popcount << 8 |
-        // popcount | 2^16 on lanes past the bucket) against U's signature,
-        // so that the lane mask stays the compare's own.
+        // the exact prefilters of candidate x ^ XY for row r: U's radius
+        // around its majority key, U's single popcount signature (unless
+        // sig_all; lanes past the bucket carry 2^16 in the mismatch), U's
+        // Bloom filter (BL).  Each test is one compare, kept as two lane
+        // conditions (a, b) so that their ballots are the compares' own
+        // masks, combined in scalar registers.
         const uint32_t vpen = valid ? 0u : 0x10000u;
-        auto filter = [&](int r) -> bool {
-            bool ok = valid;
+        auto filter2 = [&](int r, bool& ok_a, bool& ok_b) {
+            ok_a = valid;
+            ok_b = true;
             if constexpr (SIG) {
-                uint32_t pa = 0, n = vpen, d = 0;
+                uint32_t pa = 0, pb = 0, d = 0;
                 if constexpr (NW) {
-                    const uint32_t x32 = static_cast<uint32_t>(R.x[r][0]) ^ static_cast<uint32_t>(gxy[0]);
-                    pa = __popc(x32 & static_cast<uint32_t>(kEven));
-                    n += __popc(x32);
-                    d = __popc(x32 ^ static_cast<uint32_t>(A.rad_ref[0]));
+                    const uint32_t x32 = static_cast<uint32_t>(rx[r][0]) ^ static_cast<uint32_t>(gxy[0]);
+                    pa = popc_plus(x32 & static_cast<uint32_t>(kEven), neg_a);
+                    pb = popc_plus(x32, neg_b);
+                    d += __popc(x32 ^ static_cast<uint32_t>(ref[0]));
                 } else {
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const uint64_t xp = R.x[r][w] ^ gxy[w];
-                        pa += popc64(xp & kEven);
-                        n += popc64(xp);
-                        d += popc64(xp ^ A.rad_ref[w]);
+                        const uint64_t xp = rx[r][w] ^ gxy[w];
+                        if constexpr (SPLIT) {
+                            if (w == 0) {
+                                pa = popc_plus(static_cast<uint32_t>(xp), neg_a);
+                                pb = popc_plus(static_cast<uint32_t>(xp >> 32), neg_b);
+                            } else {
+                                pa += __popc(static_cast<uint32_t>(xp));
+                                pb += __popc(static_cast<uint32_t>(xp >> 32));
+                            }
+                        } else {
+                            if (w == 0) {
+                                pa = neg_a;
+                                pb = neg_b;
+                            }
+                            pa += popc64(xp & kEven);
+                            pb += popc64(xp);
+                        }
+                        d += popc64(xp ^ ref[w]);
                     }
                 }
-                const uint32_t t = ((pa << 8) | n) ^ sig_key;
-                ok = (d + ((t & sig_mask) << 8)) <= static_cast<uint32_t>(A.rad_max);
+                const uint32_t t = pa | pb | vpen;
+                ok_a = d <= static_cast<uint32_t>(A.rad_max);
+                ok_b = t <= sig_tol;
             }
             if constexpr (BL) {
                 const uint32_t hf = static_cast<uint32_t>(R.hx[r] >> 32) ^ static_cast<uint32_t>(gh >> 32);
                 const uint32_t bits = bloom_bits(hf);
-                ok = ok & ((lfilt[bloom_word(hf, A.bloom_mask)] & bits) == bits);
+                ok_b = ok_b & ((lfilt[bloom_word(hf, A.bloom_mask)] & bits) == bits);
             }
-            return ok;
+        };
+        auto filter = [&](int r) -> bool {
+            bool a, b;
+            filter2(r, a, b);
+            return a & b;
         };
         auto salted = [&](int r) -> HT { return static_cast<HT>((R.hx[r] ^ T.salt) ^ gh); };
         if constexpr (TK != kTabVerify) {
@@ -370,16 +415,19 @@ __device__ __forceinline__ void find_terms(const PairArgs& A, const Rows<W, NR>&
                 const int jj = table_settle<TK, W>(T, A.keys, s1, s2, h, nullptr, A.kstash, on);
                 const RunRef rr{static_cast<uint32_t>(__shfl(static_cast<int>(run.begin), src, kWave)),
                                 static_cast<uint32_t>(__shfl(static_cast<int>(run.lens), src, kWave))};
-                const uint32_t gx = static_cast<uint32_t>(__shfl(static_cast<int>(gxy[0]), src, kWave));
+                // low word of x ^ XY, which only the narrow hit queue carries
+                // (wide keys hold the masks in spin-split form here)
+                const uint32_t gx = NW ? static_cast<uint32_t>(__shfl(static_cast<int>(gxy[0]), src, kWave)) : 0u;
                 sink.hit(r, on && jj >= 0, base + src, jj, rr, static_cast<uint32_t>(rowkey[r * W]) ^ gx);
                 sink.flush();   // the queue never holds more than two waves of hits
             };
             int cn = 0;   // entries in cb (wave-uniform)
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const bool ok = filter(r);
-                const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
-                if (ok) cb[cn + lanes_below(m)] = static_cast<uint32_t>(r) | lane8;
+                bool a, b;
+                filter2(r, a, b);
+                const uint64_t m = __builtin_amdgcn_ballot_w64(a) & __builtin_amdgcn_ballot_w64(b);
+                if (a & b) (cb + cn)[lanes_below(m)] = static_cast<uint32_t>(r) | lane8;
                 cn += __popcll(m);
                 if (cn >= kWave) {
                     wave_sync();
@@ -747,9 +795,9 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
     const int g0 = chunk * A.per_chunk;
     const int g1 = min(A.n_groups, g0 + A.per_chunk);
     if constexpr (VARIANT == 0)
-        find_terms<W, 0, NR, NW, false>(A, R, g0, g1, A.groups, A.ghash, sink, lfilt, cb, rowkey);
+        find_terms<W, 0, NR, NW, false>(A, R, g0, g1, A.groups, A.ghash, A.gsplit, sink, lfilt, cb, rowkey);
     else if constexpr (VARIANT == 3)
-        find_terms<W, 1, NR, NW, BL>(A, R, g0, g1, A.groups, A.ghash, sink, lfilt, cb, rowkey);
+        find_terms<W, 1, NR, NW, BL>(A, R, g0, g1, A.groups, A.ghash, A.gsplit, sink, lfilt, cb, rowkey);
     else
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
 }
@@ -778,7 +826,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     static_assert(sizeof(Acc) == sizeof(double2), "accumulators are 16 bytes");
     __shared__ double2 acc_s[WPB][NR * kAccCols];
     extern __shared__ uint32_t lfilt[];
-    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
     if (!read_sample_params(A)) return;   // the same for every thread of the block
     if constexpr (BL) {
         for (uint32_t t = threadIdx.x; t < A.bloom_words; t += kWave * WPB) lfilt[t] = A.bloom[t];
@@ -835,7 +883,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     sink.acc = acc;
     sink.rowkey = rowkey;
     if constexpr (part)
-        find_terms<W, VARIANT == 3 ? 1 : 0, NR, NW, BL>(A, R, g0, g1, A.groups_b, A.ghash_b, sink, lfilt, cb_s[wave],
+        find_terms<W, VARIANT == 3 ? 1 : 0, NR, NW, BL>(A, R, g0, g1, A.groups_b, A.ghash_b, A.gsplit_b, sink, lfilt, cb_s[wave],
                                                          rowkey);
     else
         find<W, VARIANT, NR, NW, BL>(A, R, chunk, sink, cb_s[wave], rowkey, lfilt);
@@ -958,7 +1006,7 @@ __device__ __forceinline__ int64_t batch_item(const PairArgs& A, const Rows<W, N
         find_batch<W, NR, NW>(A, R, chunk, sink, cb, rowkey);
     else
         find_terms<W, 1, NR, NW, false>(A, R, chunk * A.per_chunk, min(A.n_groups, (chunk + 1) * A.per_chunk),
-                                        A.groups, A.ghash, sink, nullptr, cb, rowkey);
+                                        A.groups, A.ghash, A.gsplit, sink, nullptr, cb, rowkey);
     sink.finish();
     return sink.hits;
 }
@@ -998,6 +1046,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_batched(BatchDev B, const void*
         PairArgs A;
         A.groups = rflp(D.groups);
         A.ghash = rflp(D.ghash);
+        A.gsplit = rflp(D.gsplit);
         A.terms = rflp(D.terms);
         A.terms_f = rflp(D.terms_f);
         A.gkeys = rflp(D.gkeys);
