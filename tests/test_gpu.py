@@ -304,6 +304,40 @@ def test_random_pauli_odd_y(eng):
     np.testing.assert_allclose(h, oracle.matrix_elements(ham, keys[i], keys[j]), atol=1e-12)
 
 
+@pytest.mark.parametrize("partition", [-1, 1])
+def test_one_word_wide_keys_mixed_signatures(eng, partition):
+    """46 qubits in one key word, so the LoopOverTerms prefilter runs on
+    spin-split keys, with keys within three flips of a base key: U has many
+    popcount signatures (signature test off) and a small radius around its
+    majority key (radius test on).  Pair list bit-exact and E_loc within the
+    tolerances against the oracle, unpartitioned and partitioned."""
+    rng = np.random.default_rng(31)
+    N = 46
+    ham = jw.random_pauli(N, 600, rng, max_flip=3)
+    base = int(rng.integers(0, 2 ** N))
+    rows = set()
+    while len(rows) < 2000:
+        k = base
+        for q in rng.choice(N, size=rng.integers(0, 4), replace=False):
+            k ^= 1 << int(q)
+        rows.add(k)
+    keys = np.array(sorted(rows), dtype=np.uint64)[rng.permutation(len(rows))][:, None]
+    lp = rng.normal(scale=0.5, size=keys.shape[0]) + 1j * rng.uniform(0, 6, keys.shape[0])
+    eng.set_tuning(partition=partition)
+    try:
+        load(eng, ham, keys)
+        ref_p = oracle_pairs(ham, keys)
+        assert ref_p[0].size > 1000
+        for a, b in zip(gpu_pairs(eng, "terms"), ref_p):
+            np.testing.assert_array_equal(a, b)
+        ref = oracle.local_energy(ham, keys, lp)
+        for prec, tol in (("fp64", TOL64), ("fp32c", TOL32)):
+            e, _ = eng.local_energy(dev(lp), variant="terms", precision=prec)
+            assert np.abs(e.cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
+    finally:
+        eng.set_tuning()
+
+
 def test_long_group_part_uses_wide_format(eng):
     """A diagonal group of 70 000 Z strings on 20 qubits: its real part is too
     long for the 16-bit run lengths of the narrow hit queue, so the engine
