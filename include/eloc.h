@@ -242,7 +242,10 @@ int eloc_local_energy_adjoint(eloc_ctx ctx, int variant, int precision,
  * W-word integers (word W-1 most significant); *n_misses_host receives
  * their count, ECAPACITY (nothing written) if it exceeds capacity (call with
  * capacity 0 to learn it).  Synchronising; EDUP / EINVAL for invalid
- * samples, ECAPACITY beyond 2^31 states before deduplication. */
+ * samples.  One-word keys of at most 30 qubits are deduplicated in a bitmap
+ * over the key space (2^(N-3) bytes of device memory); other keys are
+ * listed, sorted and deduplicated, with ECAPACITY beyond 2^31 states before
+ * deduplication. */
 int eloc_find_misses(eloc_ctx ctx, double tol, int64_t capacity, uint64_t* keys_dev, int64_t* n_misses_host);
 
 /* Conventional local energy of Eq. local_energy for every sample of U:

@@ -901,7 +901,29 @@ int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_de
     if (rc) return rc;
     const int W = c->H.W;
     int64_t total = c->miss_total, uniq = c->miss_uniq;
-    if (!(c->miss_valid && c->miss_tol == tol)) {
+    // one-word keys of at most kMissBitmapQubits qubits: the states are
+    // marked in a bitmap over the key space, whose set bits are the unique
+    // states in ascending order (no list, no sort)
+    const bool bitmap = W == 1 && c->H.n_qubits <= kMissBitmapQubits;
+    const int64_t nwords = int64_t(1) << std::max(0, c->H.n_qubits - 5);
+    if (bitmap && !(c->miss_valid && c->miss_tol == tol)) {
+        c->miss_valid = false;
+        const Plan P = make_plan(c, ELOC_TERMS);
+        ELOC_HIP(c, c->m_raw.ensure(sizeof(uint32_t) * nwords));
+        ELOC_HIP(c, c->m_flags.ensure(sizeof(int32_t) * nwords));
+        ELOC_HIP(c, c->m_pos.ensure(sizeof(int64_t) * (nwords + 1)));
+        ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(nwords)));
+        uint32_t* bits = static_cast<uint32_t*>(c->m_raw.p);
+        ELOC_HIP(c, hipMemsetAsync(bits, 0, sizeof(uint32_t) * nwords, c->stream));
+        ELOC_HIP(c, launch_misses_bitmap(c->H, c->S, P.chunks, P.per_chunk, tol, bits, c->stream));
+        ELOC_HIP(c, launch_bitmap_counts(bits, nwords, c->m_flags.as<int32_t>(), c->stream));
+        ELOC_HIP(c, launch_scan_i32(c->m_flags.as<int32_t>(), nwords, c->m_pos.as<int64_t>(),
+                                    c->scan_scratch.as<int64_t>(), c->stream));
+        ELOC_HIP(c, hipMemcpyAsync(&uniq, c->m_pos.as<int64_t>() + nwords, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   c->stream));
+        ELOC_HIP(c, hipStreamSynchronize(c->stream));
+        total = uniq;
+    } else if (!(c->miss_valid && c->miss_tol == tol)) {
         c->miss_valid = false;
         const Plan P = make_plan(c, ELOC_TERMS);
         // one append pass into the buffer as it stands; when the states
@@ -925,7 +947,7 @@ int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_de
         }
         uniq = 0;
     }
-    if (!c->miss_valid && total > 0) {
+    if (!bitmap && !c->miss_valid && total > 0) {
         // sort (W-word keys, most significant word last) and keep the first of every run
         const int64_t tiles = radix_tiles(total);
         ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * total));
@@ -960,8 +982,12 @@ int eloc_find_misses(eloc_ctx c, double tol, int64_t capacity, uint64_t* keys_de
     if (uniq > capacity) return fail(c, ELOC_ECAPACITY, "capacity too small for the coupled states outside U");
     if (uniq > 0) {
         if (!keys_dev) return fail(c, ELOC_EINVAL, "null pointer");
-        ELOC_HIP(c, launch_unique_scatter(W, c->m_sorted.as<uint64_t>(), total, c->m_flags.as<int32_t>(),
-                                          c->m_pos.as<int64_t>(), keys_dev, c->stream));
+        if (bitmap)
+            ELOC_HIP(c, launch_bitmap_keys(static_cast<const uint32_t*>(c->m_raw.p), nwords, c->m_pos.as<int64_t>(),
+                                           keys_dev, c->stream));
+        else
+            ELOC_HIP(c, launch_unique_scatter(W, c->m_sorted.as<uint64_t>(), total, c->m_flags.as<int32_t>(),
+                                              c->m_pos.as<int64_t>(), keys_dev, c->stream));
     }
     ELOC_HIP(c, hipStreamSynchronize(c->stream));
     return ELOC_OK;

@@ -677,6 +677,17 @@ int batch_blocks_per_cu(int W, bool narrow, int precision, int rows);
 // are counted but not written.
 hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
                          unsigned long long* counter, int64_t capacity, uint64_t* out, hipStream_t st);
+// One-word keys of at most kMissBitmapQubits qubits: the same states marked
+// instead in a bitmap over the whole key space (bit x' of word x' >> 5; the
+// bitmap must start cleared), which makes them unique and sorted at once.
+constexpr int kMissBitmapQubits = 30;
+hipError_t launch_misses_bitmap(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
+                                uint32_t* bitmap, hipStream_t st);
+// counts[w] = popcount(bitmap[w]); keys of the set bits in ascending order
+// to out at the exclusive prefix sums pos of those counts
+hipError_t launch_bitmap_counts(const uint32_t* bitmap, int64_t nwords, int32_t* counts, hipStream_t st);
+hipError_t launch_bitmap_keys(const uint32_t* bitmap, int64_t nwords, const int64_t* pos, uint64_t* out,
+                              hipStream_t st);
 // flags[i] = 1 where sorted key i starts a run of equal keys
 hipError_t launch_unique_flags(int W, const uint64_t* sorted, int64_t n, int32_t* flags, hipStream_t st);
 // out[pos[i]] = sorted[i] where flags[i]

@@ -12,7 +12,10 @@
 // from an atomic counter and are written there (ballot + mbcnt), those past
 // the capacity only counted; the caller reruns with a larger buffer when the
 // count exceeds it.  The list is then sorted and made unique, so the order
-// in which waves append does not show in the result.
+// in which waves append does not show in the result.  For one-word keys of
+// at most 30 qubits the misses instead set their bit in a bitmap over the
+// key space (one atomic OR each); the set bits, read in order, are the
+// unique states already sorted.
 #include "device.h"
 
 #include <hip/hip_runtime.h>
@@ -66,7 +69,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 
 template <int W, int TK>
 __global__ __launch_bounds__(64) void k_misses(MissArgs A, unsigned long long* __restrict__ counter, int64_t capacity,
-                                               uint64_t* __restrict__ out) {
+                                               uint64_t* __restrict__ out, uint32_t* __restrict__ bitmap) {
     const int lane = lane_id();
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kMissRows;
     const int chunk = static_cast<int>(blockIdx.y);
@@ -111,6 +114,16 @@ __global__ __launch_bounds__(64) void k_misses(MissArgs A, unsigned long long* _
             total += __popcll(m[r]);
         }
         if (total == 0) continue;   // wave-uniform
+        if (W == 1 && bitmap) {   // uniform
+#pragma unroll
+            for (int r = 0; r < kMissRows; ++r) {
+                if (miss[r]) {
+                    const uint64_t key = x[r][0] ^ gr.xy[0];
+                    atomicOr(bitmap + (key >> 5), 1u << static_cast<uint32_t>(key & 31u));
+                }
+            }
+            continue;
+        }
         unsigned long long first = 0ull;
         if (lane == 0) first = atomicAdd(counter, static_cast<unsigned long long>(total));
         const int64_t at0 = static_cast<int64_t>(
@@ -157,18 +170,33 @@ __global__ void k_scatter_unique(const uint64_t* __restrict__ sorted, int64_t n,
 
 inline unsigned blocks256(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
 
+__global__ void k_bitmap_counts(const uint32_t* __restrict__ bitmap, int64_t nwords, int32_t* __restrict__ counts) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nwords) counts[i] = __popc(bitmap[i]);
+}
+
+__global__ void k_bitmap_keys(const uint32_t* __restrict__ bitmap, int64_t nwords, const int64_t* __restrict__ pos,
+                              uint64_t* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nwords) return;
+    uint32_t b = bitmap[i];
+    int64_t o = pos[i];
+    while (b) {
+        const int k = __builtin_ctz(b);
+        out[o++] = (static_cast<uint64_t>(i) << 5) | static_cast<uint64_t>(k);
+        b &= b - 1u;
+    }
+}
+
 template <int W, int TK>
 hipError_t launch_misses_t(const MissArgs& A, unsigned long long* counter, int64_t capacity, uint64_t* out,
-                           hipStream_t st) {
+                           uint32_t* bitmap, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>((A.M + kMissRows - 1) / kMissRows), static_cast<unsigned>(A.chunks));
-    hipLaunchKernelGGL((k_misses<W, TK>), grid, dim3(64), 0, st, A, counter, capacity, out);
+    hipLaunchKernelGGL((k_misses<W, TK>), grid, dim3(64), 0, st, A, counter, capacity, out, bitmap);
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
-                         unsigned long long* counter, int64_t capacity, uint64_t* out, hipStream_t st) {
+MissArgs miss_args(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol) {
     MissArgs A;
     A.groups = H.groups;
     A.ghash = H.group_hash;
@@ -182,10 +210,38 @@ hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int pe
     A.M = S.n;
     A.prep_err = S.prep_err;
     A.tol = tol;
+    return A;
+}
+
+}  // namespace
+
+hipError_t launch_misses(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
+                         unsigned long long* counter, int64_t capacity, uint64_t* out, hipStream_t st) {
+    const MissArgs A = miss_args(H, S, chunks, per_chunk, tol);
     const int tk = table_kind(H.W, H.narrow);
-    if (H.W == 2) return launch_misses_t<2, kTabVerify>(A, counter, capacity, out, st);
-    if (tk == kTabNarrow) return launch_misses_t<1, kTabNarrow>(A, counter, capacity, out, st);
-    return launch_misses_t<1, kTabWide>(A, counter, capacity, out, st);
+    if (H.W == 2) return launch_misses_t<2, kTabVerify>(A, counter, capacity, out, nullptr, st);
+    if (tk == kTabNarrow) return launch_misses_t<1, kTabNarrow>(A, counter, capacity, out, nullptr, st);
+    return launch_misses_t<1, kTabWide>(A, counter, capacity, out, nullptr, st);
+}
+
+hipError_t launch_misses_bitmap(const HamDev& H, const SampleDev& S, int chunks, int per_chunk, double tol,
+                                uint32_t* bitmap, hipStream_t st) {
+    if (H.W != 1 || H.n_qubits > kMissBitmapQubits || !bitmap) return hipErrorInvalidValue;
+    const MissArgs A = miss_args(H, S, chunks, per_chunk, tol);
+    if (table_kind(H.W, H.narrow) == kTabNarrow)
+        return launch_misses_t<1, kTabNarrow>(A, nullptr, 0, nullptr, bitmap, st);
+    return launch_misses_t<1, kTabWide>(A, nullptr, 0, nullptr, bitmap, st);
+}
+
+hipError_t launch_bitmap_counts(const uint32_t* bitmap, int64_t nwords, int32_t* counts, hipStream_t st) {
+    hipLaunchKernelGGL(k_bitmap_counts, dim3(blocks256(nwords)), dim3(256), 0, st, bitmap, nwords, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_bitmap_keys(const uint32_t* bitmap, int64_t nwords, const int64_t* pos, uint64_t* out,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_bitmap_keys, dim3(blocks256(nwords)), dim3(256), 0, st, bitmap, nwords, pos, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_unique_flags(int W, const uint64_t* sorted, int64_t n, int32_t* flags, hipStream_t st) {

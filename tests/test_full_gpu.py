@@ -109,6 +109,25 @@ def test_full_excitations_20_qubits(eng):
     _check(eng, ham, keys, L_of)
 
 
+@pytest.mark.parametrize("N", [30, 31, 44])
+def test_full_one_word_list_and_bitmap(eng, N):
+    """One-word keys on both sides of the 30-qubit bound: up to it the
+    misses are marked in a bitmap over the key space (unique and sorted at
+    once), above it appended and sorted; both must give the oracle's list."""
+    rng = np.random.default_rng(40 + N)
+    ham = jw.random_pauli(N, 80, rng, max_flip=2)
+    base = int(rng.integers(0, 2 ** N))
+    rows = set()
+    while len(rows) < 400:
+        k = base
+        for q in rng.choice(N, size=rng.integers(0, 4), replace=False):
+            k ^= 1 << int(q)
+        rows.add(k)
+    keys = np.array(sorted(rows), dtype=np.uint64)[rng.permutation(len(rows))][:, None]
+    got = _check(eng, ham, keys, _random_L(N, 41))
+    assert got.shape[0] > 1000
+
+
 def test_full_two_words(eng):
     rng = np.random.default_rng(8)
     N = 70
