@@ -74,6 +74,7 @@ struct eloc_ctx_s {
     int64_t miss_total = 0, miss_uniq = 0;
     DevBuf x_keys, x_hash, x_slots, x_stash, x_sig, x_bitcounts, x_rad, x_params, x_err, x_logpsi;
     DevBuf x_a, x_b, x_af, x_bf, x_shift;
+    DevBuf x_part_perm, x_part_class, x_part_tile;   // U's rows by partition class of the U-and-extra table
     // stochastic reconfiguration scratch
     DevBuf sr_w, sr_mean, sr_part, sr_T, sr_L, sr_y;
     // sampler: two prefix beams, the candidates of a level, the allowed count
@@ -140,6 +141,22 @@ int resolve_variant(const eloc_ctx c, int v) {
 // inner loop (groups / samples) split into chunks of whole 64-lane steps so
 // that the grid has about `target` waves.  TRIE: one lane per row, one chunk
 // per XY tree.
+// LoopOverTerms by the 2^bits partitions of the membership table, over M
+// rows, where the launch shape allows it (one wave of kPartRows rows per
+// workgroup): each XCD probes its own partitions, one at a time, so that
+// the XCD's L2 holds the partition it works on (the partition of a
+// candidate is linear in the row's and the group's hashes).
+void set_part_plan(Plan& P, int64_t M, int bits) {
+    if (bits <= 0 || P.rows_per_block != kPartRows || P.waves_per_block != 1) return;
+    const int64_t target = 65536;   // (row tile, chunk) waves, as the unpartitioned plan
+    const int64_t nparts = int64_t(1) << bits;
+    const int64_t items = ((M + kPartRows - 1) / kPartRows + nparts) * nparts;
+    P.part = true;
+    P.part_sub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (target + items - 1) / items)));
+    P.chunks = static_cast<int>(nparts) * P.part_sub;
+    P.bloom_words = 0;
+}
+
 Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1, bool allow_part = false) {
     Plan P;
     const int64_t M = n_rows >= 0 ? n_rows : c->S.n;
@@ -177,19 +194,8 @@ Plan make_plan(const eloc_ctx c, int variant, int64_t n_rows = -1, bool allow_pa
     const int64_t per = per_steps * 64;
     P.chunks = static_cast<int>((span + per - 1) / per);
     P.per_chunk = static_cast<int>(per);
-    // LoopOverTerms over a large U table: each XCD probes its own table
-    // partitions, one at a time (the partition of a candidate is linear in
-    // the row's and the group's hashes), so that the XCD's L2 holds the
-    // partition it works on
-    if (allow_part && variant == ELOC_TERMS && c->part_ok && P.rows_per_block == kPartRows &&
-        P.waves_per_block == 1 && n_rows < 0) {
-        const int64_t nparts = int64_t(1) << c->part_bits;
-        const int64_t items = ((M + kPartRows - 1) / kPartRows + nparts) * nparts;
-        P.part = true;
-        P.part_sub = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (target + items - 1) / items)));
-        P.chunks = static_cast<int>(nparts) * P.part_sub;
-        P.bloom_words = 0;
-    }
+    // LoopOverTerms over a large U table: by its partitions
+    if (allow_part && variant == ELOC_TERMS && c->part_ok && n_rows < 0) set_part_plan(P, M, c->part_bits);
     return P;
 }
 
@@ -636,7 +642,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->ut_keys, &c->ut_perm, &c->ut_nodes, &c->ut_nkeys, &c->s_key, &c->s_val, &c->s_key2, &c->s_val2,
                       &c->m_raw, &c->m_sorted, &c->m_perm, &c->m_flags, &c->m_pos, &c->m_count, &c->x_keys, &c->x_hash, &c->x_slots,
                       &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
-                      &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->st_rowptr, &c->st_col, &c->st_h,
+                      &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->x_part_perm, &c->x_part_class, &c->x_part_tile, &c->st_rowptr, &c->st_col, &c->st_h,
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
                       &c->groups_b, &c->ghash_b, &c->gsplit_b, &c->gsplit, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
                       &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
@@ -1047,9 +1053,13 @@ int eloc_local_energy_full(eloc_ctx c, int precision, const eloc_c64* logpsi_dev
     S.prep_err = c->x_err.as<uint32_t>();
     // membership table of X (a new salt if an insertion does not settle),
     // duplicate and bit checks, prefilter parameters; verdict before use
+    // a large table is split into partitions as U's is (the group records are
+    // bucketed for the same partition shift at ingest)
+    const int xbits = part_bits_for(c, slot_bytes(tk) * cap, cap);
     uint32_t bits = kErrTable;
     for (int attempt = 0; attempt < 8 && (bits & kErrTable) && !(bits & kErrBits); ++attempt) {
-        S.table = make_table(c->x_slots.p, c->x_stash.as<Stash>(), cap, X, splitmix64(c->salt_state));
+        S.table = make_table(c->x_slots.p, c->x_stash.as<Stash>(), cap, X, splitmix64(c->salt_state),
+                             c->H.part.shift, xbits);
         ELOC_HIP(c, hipMemsetAsync(c->x_slots.p, 0, slot_bytes(tk) * cap, c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->x_stash.p, 0, sizeof(Stash), c->stream));
         ELOC_HIP(c, hipMemsetAsync(c->x_sig.p, 0, sizeof(uint64_t) * kSigWords, c->stream));
@@ -1080,6 +1090,32 @@ int eloc_local_energy_full(eloc_ctx c, int precision, const eloc_c64* logpsi_dev
                                 c->amp_scratch.as<double>(), c->err_run.as<uint32_t>(), c->stream));
     Plan P = make_plan(c, ELOC_TERMS, M);
     P.bloom_words = 0;
+    S.part.bits = 0;
+    if (xbits > 0) {
+        // U's rows (the first M of X) in classes by their hashes' partition
+        // field, as eloc_set_samples orders them for U's own table
+        const int64_t tiles = radix_tiles(M);
+        ELOC_HIP(c, c->s_key.ensure(sizeof(uint64_t) * M));
+        ELOC_HIP(c, c->s_key2.ensure(sizeof(uint64_t) * M));
+        ELOC_HIP(c, c->s_val.ensure(sizeof(uint32_t) * M));
+        ELOC_HIP(c, c->s_val2.ensure(sizeof(uint32_t) * M));
+        ELOC_HIP(c, c->hist.ensure(sizeof(uint32_t) * 256 * tiles));
+        ELOC_HIP(c, c->hist_off.ensure(sizeof(int64_t) * (256 * tiles + 1)));
+        ELOC_HIP(c, c->hist_scratch.ensure(sizeof(int64_t) * scan_scratch_len(256 * tiles)));
+        ELOC_HIP(c, c->x_part_perm.ensure(sizeof(int32_t) * M));
+        ELOC_HIP(c, c->x_part_class.ensure(sizeof(int64_t) * (kMaxParts + 1)));
+        ELOC_HIP(c, c->x_part_tile.ensure(sizeof(int64_t) * (kMaxParts + 1)));
+        ELOC_HIP(c, launch_row_classes(c->x_hash.as<uint64_t>(), M, c->H.part.shift, xbits, c->s_key.as<uint64_t>(),
+                                       c->s_val.as<uint32_t>(), c->s_key2.as<uint64_t>(), c->s_val2.as<uint32_t>(),
+                                       c->hist.as<uint32_t>(), c->hist_off.as<int64_t>(),
+                                       c->hist_scratch.as<int64_t>(), c->x_part_perm.as<int32_t>(),
+                                       c->x_part_class.as<int64_t>(), c->x_part_tile.as<int64_t>(), c->stream));
+        S.part.row_perm = c->x_part_perm.as<int32_t>();
+        S.part.class_off = c->x_part_class.as<int64_t>();
+        S.part.tile_off = c->x_part_tile.as<int64_t>();
+        S.part.bits = xbits;
+        set_part_plan(P, M, xbits);
+    }
     ELOC_HIP(c, c->partial.ensure((fp32 ? sizeof(float4) : sizeof(double2)) * P.chunks * M));
     ELOC_HIP(c, launch_pairs(false, ELOC_TERMS, precision, c->H, S, P, c->x_a.as<double2>(), c->x_af.as<float4>(),
                              c->partial.p, c->stream));

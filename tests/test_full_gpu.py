@@ -128,6 +128,34 @@ def test_full_one_word_list_and_bitmap(eng, N):
     assert got.shape[0] > 1000
 
 
+@pytest.mark.parametrize("count", [0, 32])
+@pytest.mark.parametrize("case", ["excitations", "odd_y"])
+def test_full_partitioned_table(eng, case, count):
+    """The membership table of U and the extra states split into partitions
+    (automatic for tables of 8 MB and more, forced here with the automatic
+    count and with 32), U's rows in partition classes: same misses, E_loc
+    and energies as the oracle."""
+    eng.set_tuning(partition=1, partition_count=count)
+    try:
+        if case == "excitations":
+            N, ne = 20, 10
+            ham, _, _ = jw.random_jw(N, np.random.default_rng(5))
+            keys, _ = samples.excitation_batch(N, ne, 4096, np.random.default_rng(6))
+            rng = np.random.default_rng(7)
+
+            def L_of(k):
+                rank = samples.excitation_rank(k, N, ne)
+                return -0.7 * rank + rng.normal(scale=0.3, size=k.shape[0]) + 1j * rng.uniform(0, 2 * np.pi, k.shape[0])
+            _check(eng, ham, keys, L_of)
+        else:
+            rng = np.random.default_rng(3)
+            ham = jw.random_pauli(11, 300, rng, max_flip=3)
+            keys = rng.choice(2 ** 11, 150, replace=False).astype(np.uint64)[:, None]
+            _check(eng, ham, keys, _random_L(11, 4), weights=rng.integers(1, 9, 150).astype(np.float64))
+    finally:
+        eng.set_tuning()
+
+
 def test_full_two_words(eng):
     rng = np.random.default_rng(8)
     N = 70
