@@ -39,7 +39,7 @@ struct eloc_ctx_s {
     bool ham_set = false;
     HamDev H;
     DevBuf groups, terms, terms_f, term_src, term_ny, ghash, gkeys, gslots, gstash;
-    DevBuf groups_b, ghash_b, gsplit_b;   // group records bucketed by the partition of their hash
+    DevBuf groups_b, ghash_b, gsplit_b, gid_b;   // group records bucketed by the partition of their hash
     DevBuf gsplit;              // spin_split of every group's XY mask
     DevBuf gbucket;             // their bucket starts [kMaxParts + 1] (int32)
     DevBuf pe_cnt, pe_grp;   // pair_elements: term counts and groups of the pairs
@@ -347,6 +347,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     {
         std::vector<GroupRec<W>> gb;
         std::vector<uint64_t> hb, sb;
+        std::vector<int32_t> ib;
+        ib.reserve(static_cast<size_t>(G));
         gb.reserve(static_cast<size_t>(G));
         hb.reserve(static_cast<size_t>(G));
         sb.reserve(static_cast<size_t>(G * W));
@@ -361,6 +363,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
                     b) {
                     gb.push_back(groups[static_cast<size_t>(g)]);
                     hb.push_back(ghash[static_cast<size_t>(g)]);
+                    ib.push_back(static_cast<int32_t>(g));
                     for (int w = 0; w < W; ++w) sb.push_back(gsplit[static_cast<size_t>(g * W + w)]);
                 }
         }
@@ -369,6 +372,8 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
         ELOC_HIP(c, c->ghash_b.ensure(sizeof(uint64_t) * G));
         ELOC_HIP(c, hipMemcpy(c->groups_b.p, gb.data(), sizeof(GroupRec<W>) * G, hipMemcpyHostToDevice));
         ELOC_HIP(c, hipMemcpy(c->ghash_b.p, hb.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice));
+        ELOC_HIP(c, c->gid_b.ensure(sizeof(int32_t) * G));
+        ELOC_HIP(c, hipMemcpy(c->gid_b.p, ib.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice));
         ELOC_HIP(c, c->gsplit_b.ensure(sizeof(uint64_t) * G * W));
         ELOC_HIP(c, hipMemcpy(c->gsplit_b.p, sb.data(), sizeof(uint64_t) * G * W, hipMemcpyHostToDevice));
         for (int b = 0; b <= kMaxParts; ++b) c->H.part.bucket[b] = bucket[b];
@@ -401,6 +406,7 @@ int ingest(eloc_ctx c, int n_qubits, int64_t n_terms, const double* coeff, const
     H.part.shift = c->H.part.shift;
     H.part.ghash = c->ghash_b.as<uint64_t>();
     H.part.gsplit = c->gsplit_b.as<uint64_t>();
+    H.part.gid = c->gid_b.as<int32_t>();
     for (int b = 0; b <= kMaxParts; ++b) H.part.bucket[b] = c->H.part.bucket[b];
     H.part.bucket_dev = c->gbucket.as<int32_t>();
     H.xyt.keys = c->xyt_keys.as<uint64_t>();
@@ -588,6 +594,8 @@ int count_into_offsets(eloc_ctx c, int variant, const Plan& P, int64_t* total) {
     ELOC_HIP(c, c->counts.ensure(sizeof(int32_t) * n));
     ELOC_HIP(c, c->offsets.ensure(sizeof(int64_t) * (n + 1)));
     ELOC_HIP(c, c->scan_scratch.ensure(sizeof(int64_t) * scan_scratch_len(n)));
+    // the partitioned count skips its writes while U is invalid
+    if (P.part) ELOC_HIP(c, hipMemsetAsync(c->counts.p, 0, sizeof(int32_t) * n, c->stream));
     ELOC_HIP(c, launch_pairs_count(variant, c->H, c->S, P, c->counts.as<int32_t>(), c->stream));
     ELOC_HIP(c, launch_scan_i32(c->counts.as<int32_t>(), n, c->offsets.as<int64_t>(),
                                 c->scan_scratch.as<int64_t>(), c->stream));
@@ -644,7 +652,7 @@ void eloc_destroy(eloc_ctx c) {
                       &c->x_stash, &c->x_sig, &c->x_bitcounts, &c->x_rad, &c->x_params, &c->x_err, &c->x_logpsi,
                       &c->x_a, &c->x_b, &c->x_af, &c->x_bf, &c->x_shift, &c->x_part_perm, &c->x_part_class, &c->x_part_tile, &c->st_rowptr, &c->st_col, &c->st_h,
                       &c->sr_w, &c->sr_mean, &c->sr_part, &c->sr_T, &c->sr_L, &c->sr_y,
-                      &c->groups_b, &c->ghash_b, &c->gsplit_b, &c->gsplit, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
+                      &c->groups_b, &c->ghash_b, &c->gsplit_b, &c->gid_b, &c->gsplit, &c->gbucket, &c->part_perm, &c->part_class, &c->part_tile,
                       &c->ar_keys[0], &c->ar_keys[1], &c->ar_l[0], &c->ar_l[1], &c->ar_T[0], &c->ar_T[1],
                       &c->ar_cl, &c->ar_cT, &c->ar_ck, &c->ar_ci, &c->ar_ck2, &c->ar_ci2, &c->ar_cnt,
                       &c->ar_hist, &c->ar_sel, &c->ar_keep, &c->ar_off};
@@ -1315,7 +1323,7 @@ int eloc_count_pairs(eloc_ctx c, int variant, int64_t* n_pairs_host) {
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
     rc = prepare_variant(c, variant);
     if (rc) return rc;
-    const Plan P = make_plan(c, variant);
+    const Plan P = make_plan(c, variant, -1, true);
     return count_into_offsets(c, variant, P, n_pairs_host);
 }
 
@@ -1328,7 +1336,7 @@ int eloc_find_pairs(eloc_ctx c, int variant, int64_t capacity, int32_t* i_dev, i
     if (!n_pairs_host) return fail(c, ELOC_EINVAL, "null pointer");
     rc = prepare_variant(c, variant);
     if (rc) return rc;
-    const Plan P = make_plan(c, variant);
+    const Plan P = make_plan(c, variant, -1, true);
     int64_t total = 0;
     rc = count_into_offsets(c, variant, P, &total);
     if (rc) return rc;
@@ -1434,7 +1442,7 @@ int eloc_store_pairs(eloc_ctx c, int variant, size_t budget_bytes, int64_t* n_pa
     rc = prepare_variant(c, variant);
     if (rc) return rc;
     c->st_valid = false;
-    const Plan P = make_plan(c, variant);
+    const Plan P = make_plan(c, variant, -1, true);
     int64_t total = 0;
     rc = count_into_offsets(c, variant, P, &total);
     if (rc) return rc;

@@ -399,6 +399,7 @@ struct HamDev {
         const void* groups = nullptr;
         const uint64_t* ghash = nullptr;
         const uint64_t* gsplit = nullptr;
+        const int32_t* gid = nullptr;          // group id of every record in bucket order
         int bucket[kMaxParts + 1] = {};        // bucket starts (host copy)
         const int32_t* bucket_dev = nullptr;   // the same [kMaxParts + 1] on the device
         int shift = kPartShiftLarge;   // first partition bit of U's tables for this Hamiltonian

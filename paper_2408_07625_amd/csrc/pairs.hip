@@ -93,6 +93,7 @@ struct PairArgs {
     const void* groups_b;       // group records bucketed by the partition of their hash
     const uint64_t* ghash_b;
     const uint64_t* gsplit_b;
+    const int32_t* gid_b;       // group id of every record in bucket order
     // bucket starts in groups_b [kMaxParts + 1], in device memory: a kernel
     // argument array indexed at run time would move the whole argument
     // block to the stack
@@ -148,6 +149,7 @@ PairArgs make_args(const HamDev& H, const SampleDev& S, const Plan& P) {
     a.groups_b = H.part.groups;
     a.ghash_b = H.part.ghash;
     a.gsplit_b = H.part.gsplit;
+    a.gid_b = H.part.gid;
     a.gbucket = H.part.bucket_dev;
     a.part_sub = P.part_sub;
     return a;
@@ -769,6 +771,7 @@ struct FillSink {
     uint64_t* pkey;
     uint32_t* pval;
     const int32_t* perm = nullptr;   // row slot k is sample perm[row0 + k] (else row0 + k)
+    const int32_t* gmap = nullptr;   // group g is gmap[g] (records in bucket order; else g)
     // r may differ between lanes
     __device__ __forceinline__ void hit(int r, bool h, int g, int j, RunRef, uint32_t) {
 #pragma unroll
@@ -778,7 +781,7 @@ struct FillSink {
                 const int64_t p = pos[k] + lanes_below(m);
                 const int64_t row = perm ? perm[row0 + k] : row0 + k;
                 pkey[p] = (static_cast<uint64_t>(row) << jbits) | static_cast<uint64_t>(j);
-                pval[p] = static_cast<uint32_t>(g);
+                pval[p] = static_cast<uint32_t>(gmap ? gmap[g] : g);
             }
             pos[k] += __popcll(m);
         }
@@ -814,6 +817,39 @@ __device__ __forceinline__ void find(const PairArgs& A, const Rows<W, NR>& R, in
 // in turn, so with a multiple of eight chunks each XCD streams only its own
 // chunks of U through its L2.  PART: LoopOverTerms by U's table partitions
 // (a separate instantiation, so that the plain kernel keeps its registers).
+// The work item of workgroup blockIdx.x in the partitioned LoopOverTerms
+// (1-D grid): workgroup w serves XCD w % 8; the rest of w gives the pass p
+// (partition k = w % 8 + 8 p), then (tile, sub-chunk); the tile's class c
+// gives the group bucket c ^ k ^ part(salt), whose candidates all fall in
+// partition k.  Loads the tile's rows and sets the bucket range [g0, g1) of
+// the records in bucket order and the chunk index k * part_sub + sub; false
+// for a workgroup past the items.
+template <int W, int NR>
+__device__ __forceinline__ bool part_item(const PairArgs& A, Rows<W, NR>& R, uint64_t* rowkey, int& g0, int& g1,
+                                          int& chunk) {
+    const int nparts = 1 << A.part_bits;
+    const int64_t rest = blockIdx.x / kXcds;
+    const int64_t per_pass = A.part_tiles * A.part_sub;
+    const int k = static_cast<int>(blockIdx.x % kXcds) + kXcds * static_cast<int>(rest / per_pass);
+    const int64_t item = rest % per_pass;
+    const int sub = static_cast<int>(item % A.part_sub);
+    const int64_t t = item / A.part_sub;
+    if (k >= nparts || t >= A.tile_off[nparts]) return false;
+    int c = 0;   // the tile's class: the last class starting at or before t
+    for (int q = 1; q < nparts; ++q) c += t >= A.tile_off[q] ? 1 : 0;
+    const int64_t p0 = A.class_off[c] + (t - A.tile_off[c]) * NR;
+    const int n = static_cast<int>(min(static_cast<int64_t>(NR), A.class_off[c + 1] - p0));
+    load_rows_perm<W, NR>(A, R, rowkey, p0, n, A.row_perm);
+    const int r = rev_bits(c ^ k ^ A.part_salt, A.part_bits);
+    const int bs = A.gbucket[r << (kMaxPartBits - A.part_bits)];
+    const int be = A.gbucket[(r + 1) << (kMaxPartBits - A.part_bits)];
+    const int per = (be - bs + A.part_sub - 1) / A.part_sub;
+    g0 = min(be, bs + sub * per);
+    g1 = min(be, g0 + per);
+    chunk = k * A.part_sub + sub;
+    return true;
+}
+
 template <int W, int VARIANT, int PREC, bool ADJ, int NR, bool NW, int WPB, bool PART = false>
 __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* __restrict__ vec,
                                                        void* __restrict__ partial) {
@@ -845,30 +881,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     static_assert(!PART || (VARIANT != 1 && WPB == 1 && NR == kPartRows), "partitioned LoopOverTerms tiles");
     constexpr bool part = PART;
     if constexpr (part) {
-        // 1-D grid: workgroup w serves XCD w % 8; the rest of w gives the
-        // pass p (partition k = w % 8 + 8 p), then (tile, sub-chunk); the
-        // tile's class c gives the group bucket c ^ k ^ part(salt), whose
-        // candidates all fall in partition k
-        const int nparts = 1 << A.part_bits;
-        const int64_t rest = blockIdx.x / kXcds;
-        const int64_t per_pass = A.part_tiles * A.part_sub;
-        const int k = static_cast<int>(blockIdx.x % kXcds) + kXcds * static_cast<int>(rest / per_pass);
-        const int64_t item = rest % per_pass;
-        const int sub = static_cast<int>(item % A.part_sub);
-        const int64_t t = item / A.part_sub;
-        if (k >= nparts || t >= A.tile_off[nparts]) return;
-        int c = 0;   // the tile's class: the last class starting at or before t
-        for (int q = 1; q < nparts; ++q) c += t >= A.tile_off[q] ? 1 : 0;
-        const int64_t p0 = A.class_off[c] + (t - A.tile_off[c]) * NR;
-        const int n = static_cast<int>(min(static_cast<int64_t>(NR), A.class_off[c + 1] - p0));
-        load_rows_perm<W, NR>(A, R, rowkey, p0, n, A.row_perm);
-        const int r = rev_bits(c ^ k ^ A.part_salt, A.part_bits);
-        const int bs = A.gbucket[r << (kMaxPartBits - A.part_bits)];
-        const int be = A.gbucket[(r + 1) << (kMaxPartBits - A.part_bits)];
-        const int per = (be - bs + A.part_sub - 1) / A.part_sub;
-        g0 = min(be, bs + sub * per);
-        g1 = min(be, g0 + per);
-        chunk = k * A.part_sub + sub;
+        if (!part_item<W, NR>(A, R, rowkey, g0, g1, chunk)) return;
     } else {
         if (tile * NR >= A.rows) return;   // no block-wide barrier follows
         load_rows<W, NR>(A, R, rowkey, tile);
@@ -902,35 +915,54 @@ __global__ __launch_bounds__(kWave * WPB) void k_pairs(PairArgs A, const void* _
     }
 }
 
-template <int W, int VARIANT, bool NW>
+// Pair counts per (row, chunk) and the pair list (FillSink), LoopOverTerms
+// and LoopOverBatch; PART: LoopOverTerms by U's table partitions (1-D grid,
+// as the partitioned pair kernel; rows through the class order, groups in
+// bucket order, reported under their own ids).
+template <int W, int VARIANT, bool NW, bool PART = false>
 __global__ __launch_bounds__(kWave) void k_count(PairArgs A, int chunks, int32_t* __restrict__ counts) {
     __shared__ uint64_t rowkey[kRowBuf<W, kRows>];
     __shared__ CEntry<NW> cb[2 * kWave];
     Rows<W, kRows> R;
-    if (!read_sample_params(A)) {   // no pairs while U is invalid
+    if (!read_sample_params(A)) {   // no pairs while U is invalid (PART: the caller clears the counts)
         const int64_t row = static_cast<int64_t>(blockIdx.x) * kRows + lane_id();
-        if (lane_id() < kRows && row < A.rows) counts[row * chunks + blockIdx.y] = 0;
+        if (!PART && lane_id() < kRows && row < A.rows) counts[row * chunks + blockIdx.y] = 0;
         return;
     }
-    load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
-    wave_sync();
     CountSink sink;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) sink.cnt[r] = 0;
-    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
+    int chunk = static_cast<int>(blockIdx.y);
+    if constexpr (PART) {
+        int g0 = 0, g1 = 0;
+        if (!part_item<W, kRows>(A, R, rowkey, g0, g1, chunk)) return;
+        wave_sync();
+        find_terms<W, VARIANT == 3 ? 1 : 0, kRows, NW, false>(A, R, g0, g1, A.groups_b, A.ghash_b, A.gsplit_b,
+                                                              sink, nullptr, cb, rowkey);
+    } else {
+        load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
+        wave_sync();
+        find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
+    }
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
-        if (lane_id() == r && r < R.n) counts[(R.row0 + r) * chunks + blockIdx.y] = sink.cnt[r];
+        if (lane_id() == r && r < R.n) counts[R.id[r] * chunks + chunk] = sink.cnt[r];
 }
 
-template <int W, int VARIANT, bool NW>
+template <int W, int VARIANT, bool NW, bool PART = false>
 __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbits, const int64_t* __restrict__ offsets,
                                                 uint64_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
     __shared__ uint64_t rowkey[kRowBuf<W, kRows>];
     __shared__ CEntry<NW> cb[2 * kWave];
     if (!read_sample_params(A)) return;
     Rows<W, kRows> R;
-    load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
+    int chunk = static_cast<int>(blockIdx.y);
+    int g0 = 0, g1 = 0;
+    if constexpr (PART) {
+        if (!part_item<W, kRows>(A, R, rowkey, g0, g1, chunk)) return;
+    } else {
+        load_rows<W, kRows>(A, R, rowkey, blockIdx.x);
+    }
     wave_sync();
     FillSink sink;
     sink.row0 = R.row0;
@@ -938,10 +970,17 @@ __global__ __launch_bounds__(kWave) void k_fill(PairArgs A, int chunks, int jbit
     sink.jbits = jbits;
     sink.pkey = pkey;
     sink.pval = pval;
+    if constexpr (PART) {
+        sink.perm = A.row_perm;
+        sink.gmap = A.gid_b;
+    }
 #pragma unroll
-    for (int r = 0; r < kRows; ++r)
-        sink.pos[r] = r < R.n ? offsets[(R.row0 + r) * chunks + blockIdx.y] : 0;
-    find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
+    for (int r = 0; r < kRows; ++r) sink.pos[r] = r < R.n ? offsets[R.id[r] * chunks + chunk] : 0;
+    if constexpr (PART)
+        find_terms<W, VARIANT == 3 ? 1 : 0, kRows, NW, false>(A, R, g0, g1, A.groups_b, A.ghash_b, A.gsplit_b,
+                                                              sink, nullptr, cb, rowkey);
+    else
+        find<W, VARIANT, kRows, NW>(A, R, blockIdx.y, sink, cb, rowkey);
 }
 
 // ---------------------------------------------------------------------------
@@ -1717,6 +1756,12 @@ static hipError_t count_w(int variant, const PairArgs& A, const Plan& P, int32_t
     } else if (variant == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL(k_count_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, counts);
+    } else if (variant == 0 && A.part) {
+        const dim3 grid(static_cast<unsigned>(A.part_tiles * A.part_sub * (int64_t(1) << A.part_bits)));
+        if (P.sig_filter)
+            hipLaunchKernelGGL((k_count<W, 3, NW, true>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
+        else
+            hipLaunchKernelGGL((k_count<W, 0, NW, true>), grid, dim3(kWave), 0, st, A, P.chunks, counts);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
         if (variant == 0 && P.sig_filter)
@@ -1739,6 +1784,14 @@ static hipError_t fill_w(int variant, const PairArgs& A, const Plan& P, int jbit
     } else if (variant == 2) {
         dim3 grid(div_up(A.M, kTrieBlock), static_cast<unsigned>(P.chunks));
         hipLaunchKernelGGL(k_fill_trie<W>, grid, dim3(kTrieBlock), 0, st, A, P.chunks, jbits, offsets, pkey, pval);
+    } else if (variant == 0 && A.part) {
+        const dim3 grid(static_cast<unsigned>(A.part_tiles * A.part_sub * (int64_t(1) << A.part_bits)));
+        if (P.sig_filter)
+            hipLaunchKernelGGL((k_fill<W, 3, NW, true>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey,
+                               pval);
+        else
+            hipLaunchKernelGGL((k_fill<W, 0, NW, true>), grid, dim3(kWave), 0, st, A, P.chunks, jbits, offsets, pkey,
+                               pval);
     } else {
         dim3 grid(div_up(A.M, kRows), static_cast<unsigned>(P.chunks));
         if (variant == 0 && P.sig_filter)
